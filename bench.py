@@ -1,0 +1,238 @@
+"""Benchmark of the DCT-domain block filter on one MI355X.
+
+Workload (default): 64 seeded uint8 images of 2048 x 2048 cut into 8 x 8
+blocks (4,194,304 blocks), a pool of 16 sum-1 masks with K in {3, 5, 7}
+(symmetric or asymmetric, border replication), each image filtered with one
+mask drawn from the pool, split-BF16 precision.  One step = the FP64 builder
+launch for the 16 operators + one persistent filter launch over all 64 jobs.
+Inputs (FP32 coefficients, from the library's forward DCT) are resident in HBM
+before timing starts.
+
+Prints one JSON line (see the keys below).  ``--gpus`` above 1 is refused: the
+path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DCT-domain filtered 8×8 blocks/sec (5×5 mask), % HBM roofline, p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--images", type=int, default=64)
+    ap.add_argument("--side", type=int, default=2048)
+    ap.add_argument("--prec", choices=["split", "fp32"], default="split")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1710_07193_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_key, src_hash):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_inputs(dctf, torch, images, side, N=8, seed0=1000):
+    import synthetic as syn
+    nblk = (side // N) * (side // N)
+    X = torch.empty(images * nblk * N * N, dtype=torch.float32, device="cuda")
+    for i in range(images):
+        img = torch.from_numpy(syn.image_u8(seed0 + i, side, side)).cuda()
+        dctf.dctf_forward_dct_u8(img, N, X[i * nblk * N * N:(i + 1) * nblk * N * N])
+    torch.cuda.synchronize()
+    return X, nblk
+
+
+def timed_steps(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(images, side, pool, draws, seconds, N=8):
+    """The FP64 oracle (IDCT -> block filter -> DCT per block, all host threads)
+    on a bounded sample of the same workload: the first blocks of image 0,
+    with image 0's mask, sized to about `seconds` of CPU work."""
+    import numpy as np
+
+    import oracle
+    import synthetic as syn
+    img = syn.image_u8(1000, side, side)
+    px = oracle.tile_u8(img, N)
+    X = oracle.dct_pixels(px)
+    spec = pool[draws[0]]
+    probe = min(len(X), 4096)
+    t0 = time.perf_counter()
+    oracle.filter_coeffs(X[:probe], spec.mask, spec.border)
+    t_probe = time.perf_counter() - t0
+    n = int(min(len(X), max(probe, probe * seconds / max(t_probe, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.filter_coeffs(X[:n], spec.mask, spec.border)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "blocks/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d blocks of image 0 (%dx%d, N=%d), mask %dx%d %s, FP64 IDCT->filter->DCT per block, %.1f s"
+                      % (n, side, side, N, spec.mask.shape[0], spec.mask.shape[1],
+                         "replicate" if spec.border else "zero", dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this path runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1710_07193_amd as dctf
+    import synthetic as syn
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    N = 8
+    prec = dctf.DCTF_PREC_SPLIT_BF16 if args.prec == "split" else dctf.DCTF_PREC_FP32
+    t_setup = time.perf_counter()
+    X, nblk = make_inputs(dctf, torch, args.images, args.side, N)
+    Y = torch.empty_like(X)
+    B = args.images * nblk
+    pool = syn.mask_pool_16()
+    draws = np.random.default_rng(17).integers(0, len(pool), size=args.images)
+    ops = dctf.dctf_build_operators([(m.mask, N, m.border) for m in pool])
+    per = nblk * N * N
+    jobs = [(ops[draws[i]], X[i * per:(i + 1) * per], Y[i * per:(i + 1) * per]) for i in range(args.images)]
+    batch = dctf.dctf_batch_create(jobs, prec)
+    setup_s = time.perf_counter() - t_setup
+
+    stream = torch.cuda.current_stream()
+    step = lambda: dctf.dctf_batch_run(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, stream)
+    dctf.dctf_timing_enable(True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dctf.dctf_timing_read()           # drop the warm-up launches
+    ms = timed_steps(torch, step, args.steps, 0, stream)
+    kernel_ms, n_timed = dctf.dctf_timing_read()
+    dctf.dctf_timing_enable(False)
+
+    value = B / (ms * 1e-3)
+    alg_bytes = B * N * N * 4 * 2          # FP32 coefficients in + out
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    src_hash = kernel_source_hash()
+    wl_key = "batch64x2048_n8_%s" % args.prec
+    traffic = load_traffic(wl_key, src_hash)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if prec == dctf.DCTF_PREC_SPLIT_BF16 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%d seeded %dx%d uint8 images, %d 8x8 blocks, 16-mask pool K in {3,5,7} "
+                        "sym/asym replicate, one mask per image, one persistent launch (+ FP64 operator "
+                        "rebuild) per step" % (args.images, args.side, args.side, B),
+            "images": args.images, "side": args.side, "N": N, "blocks": B, "masks": len(pool),
+            "border": "replicate",
+            "precision": "split-bf16: BF16 hi/lo x3 MFMA products, FP32 accumulate, 16 low-frequency "
+                         "inputs in FP32 MFMA" if prec else "fp32 MFMA, FP32 DC column in VALU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_batch (persistent filter)", "kernel_ms": kernel_ms, "kernel_launches": n_timed,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+        "setup_s": round(setup_s, 2),
+        "source_hash": src_hash,
+    }
+
+    if not args.no_extras:
+        extras = {}
+        # the same step replayed from a captured HIP graph
+        side_stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side_stream):
+            dctf.dctf_batch_capture(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, side_stream)
+            gms = timed_steps(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
+                              args.steps, args.warmup, side_stream)
+        extras["graph_replay"] = {"ms_per_step": gms, "blocks_per_s": B / (gms * 1e-3)}
+        # the other precision on the same jobs (split-BF16 vs FP32 speedup)
+        other = dctf.DCTF_PREC_FP32 if prec == dctf.DCTF_PREC_SPLIT_BF16 else dctf.DCTF_PREC_SPLIT_BF16
+        ob = dctf.dctf_batch_create(jobs, other)
+        oms = timed_steps(torch, lambda: dctf.dctf_batch_run(ob, dctf.DCTF_RUN_REBUILD_OPERATORS, stream),
+                          args.steps, args.warmup, stream)
+        extras["fp32" if other == dctf.DCTF_PREC_FP32 else "split_bf16"] = {
+            "ms_per_step": oms, "blocks_per_s": B / (oms * 1e-3),
+            "split_over_fp32_speedup": (oms / ms) if other == dctf.DCTF_PREC_FP32 else (ms / oms)}
+        del ob
+        # all blocks through the single 5x5 asymmetric inseparable mask (one operator)
+        op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, dctf.DCTF_BORDER_REPLICATE)
+        for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+            sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
+                              args.steps, args.warmup, stream)
+            extras["mask5x5_single_op_" + pname] = {
+                "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
+                "GBps": alg_bytes / (sms * 1e-3) / 1e9, "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
+        # optional verify kernel: inverse DCT + uint8 of every output block
+        pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
+        vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)
+        extras["verify_kernel_ms"] = vms
+        out["extras"] = extras
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.images, args.side, pool, draws, args.cpu_seconds, N)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * dctf.h — C ABI of the MI355X (gfx950) block-DCT filtering library.
+ *
+ * Method: Amin-Naji & Aghagolzadeh, "Block DCT filtering using vector
+ * processing".  An image stored as N x N blocks of orthonormal DCT-II
+ * coefficients (BLOCK = C.block.C^t, Sec. II.A eq. 1-3) is filtered without
+ * leaving the DCT domain.  The paper turns a custom mask (eq. 4) into
+ * constant DCT-domain matrices once per mask (Sec. II.B) and applies them to
+ * every block as matrix products (eq. 8-11 for zero padding, eq. 13-20 for
+ * border replication).  This library folds those products into one
+ * N^2 x N^2 operator per mask,
+ *
+ *     H_dct = (C (x) C) . H_sp . (C (x) C)^t
+ *           = sum_{p,q} W[p][q] (C S_p C^t) (x) (C S_q C^t),
+ *
+ * and filters a block by one matrix-vector product Y = H_dct . X of its
+ * row-major coefficient vector (vec index u*N + v).  S_d is the block-local
+ * row (or column) shift by d = p - a (a = floor((K-1)/2)) with zero fill
+ * (Sec. II.B) or with clamping to the block edge (Sec. II.C, Fig. 1).
+ *
+ * Conventions for every call:
+ *   - Blocks are x[i][j], i = row, j = column.  Coefficient blocks are stored
+ *     block-contiguous: block b occupies N*N consecutive floats, row-major
+ *     (u*N + v), i.e. a column-major N^2 x B matrix.
+ *   - Masks are row-major kh x kw doubles and are CORRELATED: W[p][q] weights
+ *     the pixel at (i + p - a_h, j + q - a_w).  This is the orientation the
+ *     paper's matrices a..e fix (w11 weights block(i-1, j-1), Sec. II.B);
+ *     eq. 5 as printed swaps the indices.  Pass a 180-degree rotated mask for
+ *     a convolution.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls that take a
+ *     stream are asynchronous on it; argument validation happens on the host
+ *     before anything is enqueued.  Device faults surface as DCTF_EHIP from a
+ *     later call that synchronises.
+ *   - Device pointers must be 16-byte aligned.  The library never aborts,
+ *     throws or prints; every call returns a dctf_status.
+ */
+#ifndef DCTF_H
+#define DCTF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DCTF_OK = 0,
+    DCTF_EINVAL = -1,        /* bad argument (null, misaligned, overlap, range) */
+    DCTF_EUNSUPPORTED = -2,  /* N or precision not supported by this build */
+    DCTF_ENOMEM = -3,        /* device or host allocation failed */
+    DCTF_EHIP = -4,          /* a HIP runtime call failed */
+    DCTF_EBUSY = -5,         /* resource budget exhausted (server admission) */
+} dctf_status;
+
+typedef enum {
+    DCTF_BORDER_ZERO = 0,       /* zero padding at the block edge (Sec. II.B) */
+    DCTF_BORDER_REPLICATE = 1,  /* nearest-pixel replication (Sec. II.C, Fig. 1) */
+} dctf_border;
+
+typedef enum {
+    DCTF_PREC_FP32 = 0,        /* FP32 MFMA, FP32 accumulate */
+    DCTF_PREC_SPLIT_BF16 = 1,  /* X and H split into BF16 hi + lo, three BF16 MFMA
+                                  products hi.hi + hi.lo + lo.hi, FP32 accumulate */
+} dctf_precision;
+
+typedef void *dctf_stream;                 /* hipStream_t */
+typedef struct dctf_operator_s *dctf_operator;
+typedef struct dctf_batch_s *dctf_batch;
+
+/* Supported block sizes N: 2, 4, 8, 16.  Mask sides: 1 <= kh, kw <= 2N + 1. */
+
+/* ------------------------------------------------------------------ operators */
+
+/*
+ * Build the operator of one mask (Sec. II.B-C: the paper prepares the
+ * DCT-domain matrices once per mask and reuses them as constants).
+ * The operator is formed on the GPU in FP64: C from its closed form, the
+ * shift / clamp factors C S_d C^t, and H_dct as the sum above.  From the FP64
+ * operator the build derives, by round-to-nearest-even, the FP32 operator,
+ * its BF16 hi/lo split (hi = bf16(fp32(H)), lo = bf16(fp32(H - hi))) and the
+ * FP32 DC column H[:, 0], all in the layouts the filter kernels read.
+ *   mask_host  kh*kw doubles, row-major, host memory; copied before return.
+ *   N          block size (2, 4, 8 or 16).
+ *   border     dctf_border.
+ *   out        receives a handle owning device memory until destroyed.
+ * Errors: DCTF_EINVAL (null, kh/kw out of [1, 2N+1], non-finite entry, bad
+ * border), DCTF_EUNSUPPORTED (N), DCTF_ENOMEM, DCTF_EHIP.
+ * Asynchronous on `stream`: wait on it before dctf_operator_fp64 reads back.
+ */
+dctf_status dctf_build_operator(const double *mask_host, int kh, int kw, int N, int border,
+                                dctf_stream stream, dctf_operator *out);
+
+/* Mask description for dctf_build_operators. */
+typedef struct {
+    const double *mask_host; /* kh*kw doubles, row-major */
+    int kh, kw, N, border;
+} dctf_mask_desc;
+
+/*
+ * Build n operators with one builder launch (same result, bit for bit, as n
+ * calls of dctf_build_operator).  out[i] receives the i-th handle.  On error
+ * no handle is returned.
+ */
+dctf_status dctf_build_operators(const dctf_mask_desc *masks, int n, dctf_stream stream,
+                                 dctf_operator *out);
+
+/*
+ * Re-run the builder for existing operators from their device-resident masks
+ * (one launch, no host transfer; may be captured in a HIP graph).
+ */
+dctf_status dctf_rebuild_operators(const dctf_operator *ops, int n, dctf_stream stream);
+
+/* Copy the FP64 operator (N^2 x N^2, row-major, row = output coefficient
+ * u*N+v, column = input coefficient) to host memory.  Synchronous. */
+dctf_status dctf_operator_fp64(dctf_operator op, double *host_out);
+
+/* Block size, mask size and border of an operator (any pointer may be NULL). */
+dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *border);
+
+/* Free an operator.  The caller must ensure no queued work still uses it. */
+void dctf_operator_destroy(dctf_operator op);
+
+/* ------------------------------------------------------------------- filter */
+
+/*
+ * Y[b] = H_dct . X[b] for b = 0..B-1 (eq. 11 / eq. 20 for every block at
+ * once).  in_dev, out_dev: device, B * N*N floats each, block-contiguous,
+ * 16-byte aligned, non-overlapping (in-place is not supported).
+ * prec: dctf_precision.  The DC column H[:,0] is always applied in FP32
+ * VALU arithmetic; the MFMA sums over the other columns.
+ * For N <= 4 both precisions run one FP32 kernel (the operator is at most
+ * 16 x 16).  B = 0 is a no-op.  Each block's result depends only on that
+ * block and the operator: it is bit-identical whatever B, the tuning variant
+ * or the batch the block belongs to.
+ * Errors: DCTF_EINVAL, DCTF_EUNSUPPORTED, DCTF_EHIP (launch failure).
+ */
+dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, float *out_dev,
+                               int64_t B, dctf_stream stream);
+
+/* ---------------------------------------------------------- batched launch */
+
+/* One filter job: B blocks of in -> out with operator op. */
+typedef struct {
+    dctf_operator op;
+    const float *in;
+    float *out;
+    int64_t B;
+} dctf_job;
+
+/*
+ * Plan a batch: many jobs (images), operators (masks) and block sizes (N = 8
+ * and N = 16 may be mixed) that run in ONE persistent kernel launch.  The plan
+ * copies the job list into a device work table (jobs grouped by operator) and
+ * records the distinct operators.  Jobs with N <= 4 are rejected
+ * (DCTF_EUNSUPPORTED).  Outputs of different jobs must not overlap any input
+ * or output of another job.  The plan owns device memory until destroyed;
+ * operators must outlive it.
+ */
+dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out);
+
+/* Flags for dctf_batch_run / dctf_batch_capture. */
+#define DCTF_RUN_REBUILD_OPERATORS 1u /* re-run the FP64 builder for the plan's
+                                         operators first (one extra launch) */
+
+/* Enqueue the plan on `stream`: [builder launch] + one persistent filter launch. */
+dctf_status dctf_batch_run(dctf_batch batch, unsigned flags, dctf_stream stream);
+
+/* Capture dctf_batch_run(batch, flags, stream) into a HIP graph held by the
+ * plan (replaces any previous capture).  Nothing is executed. */
+dctf_status dctf_batch_capture(dctf_batch batch, unsigned flags, dctf_stream stream);
+
+/* Launch the captured graph on `stream` (DCTF_EINVAL if none was captured). */
+dctf_status dctf_batch_launch_graph(dctf_batch batch, dctf_stream stream);
+
+/* Grid shape of the plan's persistent launch (workgroups for N = 8 work,
+ * workgroups for N = 16 work, threads per workgroup).  Any pointer may be NULL. */
+dctf_status dctf_batch_info(dctf_batch batch, int *groups_n8, int *groups_n16, int *threads);
+
+void dctf_batch_destroy(dctf_batch batch);
+
+/* Convenience: create, run and destroy a plan.  Synchronises `stream`. */
+dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int prec, dctf_stream stream);
+
+/* --------------------------------------------------------- around the path */
+
+/*
+ * Forward DCT of a uint8 image into coefficient blocks (eq. 1), FP64
+ * arithmetic rounded once to FP32.  The h x w image (row pitch `pitch` bytes,
+ * device memory) is cut into N x N blocks in raster order; sides that are not
+ * multiples of N are extended by repeating the last row / column.
+ * coeffs_dev receives ceil(h/N)*ceil(w/N) blocks of N*N floats.
+ */
+dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w, int64_t pitch, int N,
+                                float *coeffs_dev, dctf_stream stream);
+
+/*
+ * Verify kernel: inverse DCT (eq. 3) of each coefficient block in FP32, then
+ * the uint8 conversion of Sec. III (round half up, saturate to [0, 255]).
+ *   pix_dev      B*N*N bytes out (block-contiguous, row-major inside a block).
+ *   expected_dev B*N*N bytes or NULL.
+ *   counters_dev two unsigned 64-bit device counters, ADDED to (zero them first):
+ *                [0] pixels that differ from expected_dev while their FP32
+ *                    value is not within 1e-3 of a .5 boundary,
+ *                [1] pixels within 1e-3 of a .5 boundary.
+ *                NULL skips counting.
+ */
+dctf_status dctf_idct_u8_verify(int N, const float *coeffs_dev, int64_t B, uint8_t *pix_dev,
+                                const uint8_t *expected_dev, unsigned long long *counters_dev,
+                                dctf_stream stream);
+
+/* ----------------------------------------------------------------- tuning */
+
+/*
+ * Kernel variants for (N, precision): a variant fixes the blocks each wave
+ * carries per iteration and the persistent grid size.  Every variant
+ * computes bit-identical results.  dctf_autotune times each variant on the
+ * caller's buffers (in_dev/out_dev, B blocks, operator op) with HIP events
+ * and selects the fastest for subsequent calls; the choice can be read and
+ * set explicitly so that a table persisted by the caller can be re-applied.
+ */
+int dctf_variant_count(int N, int prec);
+const char *dctf_variant_name(int N, int prec, int variant);
+dctf_status dctf_get_variant(int N, int prec, int *variant);
+dctf_status dctf_set_variant(int N, int prec, int variant);
+dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float *out_dev,
+                          int64_t B, int iters, dctf_stream stream, int *best_variant,
+                          float *best_ms);
+
+/* ------------------------------------------------------------------ misc */
+
+const char *dctf_status_string(dctf_status s);
+const char *dctf_version(void);
+
+/* Kernel-only timing: the average duration (ms) of the last `n` persistent
+ * filter launches of dctf_batch_run on this device, measured with HIP events
+ * recorded on the launch stream around each launch.  Enable with
+ * dctf_timing_enable(1) (events cost a few microseconds per launch). */
+dctf_status dctf_timing_enable(int on);
+dctf_status dctf_timing_read(double *avg_ms, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCTF_H */

@@ -1,0 +1,342 @@
+"""Python binding of libdctf, the MI355X (gfx950) block-DCT filtering library.
+
+Argument marshalling only: every step of the filtering path runs in the HIP
+kernels of ``libdctf.so`` (declared in ``include/dctf.h``).  PyTorch supplies
+device memory and streams.  The functions carry the C names; tensors stand in
+for device pointers and ``stream`` defaults to torch's current stream.
+
+Importing this module fails loudly when the library has not been built
+(``python -m paper_1710_07193_amd.build`` or ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first: libdctf binds to the HIP runtime torch has loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdctf.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdctf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+DCTF_OK, DCTF_EINVAL, DCTF_EUNSUPPORTED, DCTF_ENOMEM, DCTF_EHIP, DCTF_EBUSY = 0, -1, -2, -3, -4, -5
+DCTF_BORDER_ZERO, DCTF_BORDER_REPLICATE = 0, 1
+DCTF_PREC_FP32, DCTF_PREC_SPLIT_BF16 = 0, 1
+DCTF_RUN_REBUILD_OPERATORS = 1
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+
+class _MaskDesc(ctypes.Structure):
+    _fields_ = [("mask_host", _P), ("kh", _I), ("kw", _I), ("N", _I), ("border", _I)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("op", _P), ("in_", _P), ("out", _P), ("B", _I64)]
+
+
+_SIGS = {
+    "dctf_build_operator": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
+    "dctf_build_operators": ([ctypes.POINTER(_MaskDesc), _I, _P, ctypes.POINTER(_P)], _I),
+    "dctf_rebuild_operators": ([ctypes.POINTER(_P), _I, _P], _I),
+    "dctf_operator_fp64": ([_P, _P], _I),
+    "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
+    "dctf_operator_destroy": ([_P], None),
+    "dctf_filter_blocks": ([_P, _I, _P, _P, _I64, _P], _I),
+    "dctf_batch_create": ([ctypes.POINTER(_Job), _I, _I, ctypes.POINTER(_P)], _I),
+    "dctf_batch_run": ([_P, ctypes.c_uint, _P], _I),
+    "dctf_batch_capture": ([_P, ctypes.c_uint, _P], _I),
+    "dctf_batch_launch_graph": ([_P, _P], _I),
+    "dctf_batch_info": ([_P, _P, _P, _P], _I),
+    "dctf_batch_destroy": ([_P], None),
+    "dctf_filter_batch": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
+    "dctf_forward_dct_u8": ([_P, _I, _I, _I64, _I, _P, _P], _I),
+    "dctf_idct_u8_verify": ([_I, _P, _I64, _P, _P, _P, _P], _I),
+    "dctf_variant_count": ([_I, _I], _I),
+    "dctf_variant_name": ([_I, _I, _I], ctypes.c_char_p),
+    "dctf_get_variant": ([_I, _I, _P], _I),
+    "dctf_set_variant": ([_I, _I, _I], _I),
+    "dctf_autotune": ([_P, _I, _P, _P, _I64, _I, _P, _P, _P], _I),
+    "dctf_status_string": ([_I], ctypes.c_char_p),
+    "dctf_version": ([], ctypes.c_char_p),
+    "dctf_timing_enable": ([_I], _I),
+    "dctf_timing_read": ([_P, _P], _I),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+class DctfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = _lib.dctf_status_string(status).decode()
+        super().__init__("%s: %s (status %d)" % (what, msg, status))
+
+
+def _check(status: int, what: str):
+    if status != DCTF_OK:
+        raise DctfError(status, what)
+
+
+def _stream(stream):
+    if stream is None:
+        return _P(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return _P(stream.cuda_stream)
+    return _P(int(stream))
+
+
+def _dptr(t, dtype, what):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % what)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return _P(t.data_ptr())
+
+
+class Operator:
+    """Owning handle of a device-resident DCT-domain operator."""
+
+    def __init__(self, handle: int, N: int, kh: int, kw: int, border: int):
+        self.handle = handle
+        self.N, self.kh, self.kw, self.border = N, kh, kw, border
+
+    @property
+    def _as_parameter_(self):
+        return _P(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            _lib.dctf_operator_destroy(_P(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _mask_array(mask):
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.float64))
+    if m.ndim == 1:
+        m = m.reshape(1, -1)
+    if m.ndim != 2:
+        raise ValueError("mask must be 1-D or 2-D")
+    return m
+
+
+def dctf_build_operator(mask, N: int, border: int, stream=None) -> Operator:
+    m = _mask_array(mask)
+    h = _P()
+    _check(_lib.dctf_build_operator(m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, border,
+                                    _stream(stream), ctypes.byref(h)), "dctf_build_operator")
+    return Operator(h.value, N, m.shape[0], m.shape[1], border)
+
+
+def dctf_build_operators(specs, stream=None) -> list:
+    """``specs``: iterable of (mask, N, border); one builder launch for all."""
+    arrays, descs = [], []
+    for mask, N, border in specs:
+        m = _mask_array(mask)
+        arrays.append(m)
+        descs.append(_MaskDesc(m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, border))
+    n = len(descs)
+    arr = (_MaskDesc * max(n, 1))(*descs)
+    out = (_P * max(n, 1))()
+    _check(_lib.dctf_build_operators(arr, n, _stream(stream), out), "dctf_build_operators")
+    return [Operator(out[i], descs[i].N, descs[i].kh, descs[i].kw, descs[i].border) for i in range(n)]
+
+
+def dctf_rebuild_operators(ops, stream=None):
+    arr = (_P * max(len(ops), 1))(*[o.handle for o in ops])
+    _check(_lib.dctf_rebuild_operators(arr, len(ops), _stream(stream)), "dctf_rebuild_operators")
+
+
+def dctf_operator_fp64(op: Operator) -> np.ndarray:
+    nn = op.N * op.N
+    H = np.empty((nn, nn), np.float64)
+    _check(_lib.dctf_operator_fp64(op, H.ctypes.data_as(_P)), "dctf_operator_fp64")
+    return H
+
+
+def dctf_operator_info(op: Operator):
+    vals = [ctypes.c_int() for _ in range(4)]
+    _check(_lib.dctf_operator_info(op, *[ctypes.byref(v) for v in vals]), "dctf_operator_info")
+    return tuple(v.value for v in vals)
+
+
+def dctf_filter_blocks(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    """Y[b] = H_dct . X[b]; X, Y: float32 device tensors of B*N*N elements."""
+    nn = op.N * op.N
+    if X.numel() % nn or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold the same whole number of N*N blocks")
+    _check(_lib.dctf_filter_blocks(op, prec, _dptr(X, torch.float32, "X"),
+                                   _dptr(Y, torch.float32, "Y"), X.numel() // nn, _stream(stream)),
+           "dctf_filter_blocks")
+
+
+def filter_blocks(op: Operator, X: torch.Tensor, prec: int = DCTF_PREC_SPLIT_BF16, stream=None):
+    Y = torch.empty_like(X)
+    dctf_filter_blocks(op, prec, X, Y, stream)
+    return Y
+
+
+def _jobs(jobs):
+    descs = []
+    keep = []
+    for op, X, Y in jobs:
+        nn = op.N * op.N
+        if X.numel() % nn or Y.numel() != X.numel():
+            raise ValueError("job tensors must hold the same whole number of N*N blocks")
+        keep.append(op)
+        descs.append(_Job(op.handle, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
+                          X.numel() // nn))
+    return (_Job * max(len(descs), 1))(*descs), len(descs), keep
+
+
+class Batch:
+    """Owning handle of a batch plan (work table + optional captured graph)."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = handle
+        self._keep = keep   # operators and tensors the plan points into
+
+    @property
+    def _as_parameter_(self):
+        return _P(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            _lib.dctf_batch_destroy(_P(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def dctf_batch_create(jobs, prec: int) -> Batch:
+    """``jobs``: list of (Operator, X, Y)."""
+    arr, n, keep = _jobs(jobs)
+    h = _P()
+    _check(_lib.dctf_batch_create(arr, n, prec, ctypes.byref(h)), "dctf_batch_create")
+    return Batch(h.value, (keep, [j[1] for j in jobs], [j[2] for j in jobs]))
+
+
+def dctf_batch_run(batch: Batch, flags: int = 0, stream=None):
+    _check(_lib.dctf_batch_run(batch, flags, _stream(stream)), "dctf_batch_run")
+
+
+def dctf_batch_capture(batch: Batch, flags: int = 0, stream=None):
+    _check(_lib.dctf_batch_capture(batch, flags, _stream(stream)), "dctf_batch_capture")
+
+
+def dctf_batch_launch_graph(batch: Batch, stream=None):
+    _check(_lib.dctf_batch_launch_graph(batch, _stream(stream)), "dctf_batch_launch_graph")
+
+
+def dctf_batch_info(batch: Batch):
+    vals = [ctypes.c_int() for _ in range(3)]
+    _check(_lib.dctf_batch_info(batch, *[ctypes.byref(v) for v in vals]), "dctf_batch_info")
+    return tuple(v.value for v in vals)
+
+
+def dctf_filter_batch(jobs, prec: int, stream=None):
+    arr, n, _ = _jobs(jobs)
+    _check(_lib.dctf_filter_batch(arr, n, prec, _stream(stream)), "dctf_filter_batch")
+
+
+def dctf_forward_dct_u8(img: torch.Tensor, N: int, coeffs: torch.Tensor, stream=None):
+    """uint8 image (h, w) on the device -> coefficient blocks (raster order)."""
+    if img.dim() != 2:
+        raise ValueError("img must be 2-D")
+    h, w = img.shape
+    nblk = -(-h // N) * -(-w // N)
+    if coeffs.numel() != nblk * N * N:
+        raise ValueError("coeffs must hold %d blocks" % nblk)
+    _check(_lib.dctf_forward_dct_u8(_dptr(img, torch.uint8, "img"), h, w, img.stride(0), N,
+                                    _dptr(coeffs, torch.float32, "coeffs"), _stream(stream)),
+           "dctf_forward_dct_u8")
+
+
+def dctf_idct_u8_verify(N: int, Y: torch.Tensor, pix: torch.Tensor, expected=None, counters=None,
+                        stream=None):
+    nn = N * N
+    if Y.numel() % nn or pix.numel() != Y.numel():
+        raise ValueError("Y and pix must hold the same number of N*N blocks")
+    if expected is not None and expected.numel() != pix.numel():
+        raise ValueError("expected has the wrong size")
+    if counters is not None and (counters.numel() != 2 or counters.dtype != torch.int64):
+        raise ValueError("counters must be two int64 values")
+    _check(_lib.dctf_idct_u8_verify(N, _dptr(Y, torch.float32, "Y"), Y.numel() // nn,
+                                    _dptr(pix, torch.uint8, "pix"),
+                                    _dptr(expected, torch.uint8, "expected"),
+                                    _dptr(counters, torch.int64, "counters"), _stream(stream)),
+           "dctf_idct_u8_verify")
+
+
+def dctf_variant_count(N: int, prec: int) -> int:
+    return int(_lib.dctf_variant_count(N, prec))
+
+
+def dctf_variant_name(N: int, prec: int, v: int):
+    r = _lib.dctf_variant_name(N, prec, v)
+    return r.decode() if r else None
+
+
+def dctf_get_variant(N: int, prec: int) -> int:
+    v = ctypes.c_int()
+    _check(_lib.dctf_get_variant(N, prec, ctypes.byref(v)), "dctf_get_variant")
+    return v.value
+
+
+def dctf_set_variant(N: int, prec: int, v: int):
+    _check(_lib.dctf_set_variant(N, prec, v), "dctf_set_variant")
+
+
+def dctf_autotune(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor, iters: int = 10,
+                  stream=None):
+    """Time every variant on (X -> Y) and select the fastest; returns (variant, ms)."""
+    nn = op.N * op.N
+    v, ms = ctypes.c_int(), ctypes.c_float()
+    _check(_lib.dctf_autotune(op, prec, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
+                              X.numel() // nn, iters, _stream(stream), ctypes.byref(v),
+                              ctypes.byref(ms)), "dctf_autotune")
+    return v.value, ms.value
+
+
+def dctf_status_string(s: int) -> str:
+    return _lib.dctf_status_string(s).decode()
+
+
+def dctf_version() -> str:
+    return _lib.dctf_version().decode()
+
+
+def dctf_timing_enable(on: bool):
+    _check(_lib.dctf_timing_enable(1 if on else 0), "dctf_timing_enable")
+
+
+def dctf_timing_read():
+    avg, n = ctypes.c_double(), ctypes.c_int()
+    _check(_lib.dctf_timing_read(ctypes.byref(avg), ctypes.byref(n)), "dctf_timing_read")
+    return avg.value, n.value
+
+
+def raw_library():
+    """The ctypes handle of libdctf (for symbol checks)."""
+    return _lib

@@ -1,0 +1,759 @@
+// Host side of the C ABI declared in include/dctf.h: argument validation,
+// operator lifetime, dispatch to the kernels, batch plans (work tables,
+// persistent launch, HIP graph capture), variant selection and timing.
+#include "dctf_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <vector>
+
+namespace dctf {
+
+int batch_occupancy(int prec);   // batch.hip
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cu[kMaxDevices];
+
+std::mutex g_variant_mu;
+int g_variant[17][2];   // [N][prec]; zero-initialised = default variant 0
+
+bool supported_n(int N) { return N == 2 || N == 4 || N == 8 || N == 16; }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return na > 0 && nb > 0 && a0 < b0 + nb && b0 < a0 + na;
+}
+
+dctf_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess)
+        return DCTF_OK;
+    if (e == hipErrorOutOfMemory)
+        return DCTF_ENOMEM;
+    return DCTF_EHIP;
+}
+
+int current_variant(int N, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_variant_mu);
+    return g_variant[N][prec];
+}
+
+// ------------------------------------------------------------- timing
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // pairs
+    int used = 0;                 // pairs recorded since the last read
+};
+Timing g_timing;
+constexpr int kTimingPairs = 512;
+
+void timing_begin(hipStream_t s, int *slot)
+{
+    *slot = -1;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.on || g_timing.used >= kTimingPairs)
+        return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return;
+    if (g_timing.ev.empty()) {
+        g_timing.ev.resize(2 * kTimingPairs);
+        for (auto &e : g_timing.ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                e = nullptr;
+    }
+    *slot = g_timing.used++;
+    hipEventRecord(g_timing.ev[2 * *slot], s);
+}
+
+void timing_end(hipStream_t s, int slot)
+{
+    if (slot < 0)
+        return;
+    hipEventRecord(g_timing.ev[2 * slot + 1], s);
+}
+
+}  // namespace
+
+int cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return 256;
+    int v = g_cu[dev].load();
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        g_cu[dev].store(v);
+    }
+    return v;
+}
+
+}  // namespace dctf
+
+using namespace dctf;
+
+// ================================================================ operators
+
+static dctf_status validate_mask(const double *mask, int kh, int kw, int N, int border)
+{
+    if (!supported_n(N))
+        return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
+    if (mask == nullptr || kh < 1 || kw < 1 || kh > 2 * N + 1 || kw > 2 * N + 1)
+        return DCTF_EINVAL;
+    if (border != DCTF_BORDER_ZERO && border != DCTF_BORDER_REPLICATE)
+        return DCTF_EINVAL;
+    for (int i = 0; i < kh * kw; ++i)
+        if (!isfinite(mask[i]))
+            return DCTF_EINVAL;
+    return DCTF_OK;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static dctf_status alloc_operator(int N, int kh, int kw, int border, dctf_operator *out)
+{
+    const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
+    size_t off = 0;
+    const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
+    const size_t o_h64 = off;  off = align_up(off + sizeof(double) * N4);
+    const size_t o_h32 = off;  off = align_up(off + sizeof(float) * N4);
+    const size_t o_f32 = off;  off = align_up(off + sizeof(float) * F);
+    const size_t o_fhi = off;  off = align_up(off + sizeof(uint16_t) * F);
+    const size_t o_flo = off;  off = align_up(off + sizeof(uint16_t) * F);
+    const size_t o_flf = off;  off = align_up(off + sizeof(float) * frag_lf_elems(N));
+    const size_t o_h0 = off;   off = align_up(off + sizeof(float) * NN);
+
+    dctf_operator op = new (std::nothrow) dctf_operator_s();
+    if (!op)
+        return DCTF_ENOMEM;
+    void *base = nullptr;
+    hipError_t e = hipMalloc(&base, off);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_status(e);
+    }
+    char *b = static_cast<char *>(base);
+    op->N = N;
+    op->kh = kh;
+    op->kw = kw;
+    op->border = border;
+    hipGetDevice(&op->device);
+    op->base = base;
+    op->bytes = off;
+    op->img.mask = reinterpret_cast<double *>(b + o_mask);
+    op->img.H64 = reinterpret_cast<double *>(b + o_h64);
+    op->img.H32 = reinterpret_cast<float *>(b + o_h32);
+    op->img.frag32 = F ? reinterpret_cast<float *>(b + o_f32) : nullptr;
+    op->img.frag_hi = F ? reinterpret_cast<uint16_t *>(b + o_fhi) : nullptr;
+    op->img.frag_lo = F ? reinterpret_cast<uint16_t *>(b + o_flo) : nullptr;
+    op->img.frag_lf = F ? reinterpret_cast<float *>(b + o_flf) : nullptr;
+    op->img.h0 = reinterpret_cast<float *>(b + o_h0);
+    *out = op;
+    return DCTF_OK;
+}
+
+static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s)
+{
+    for (int first = 0; first < n; first += kMaxBuildPerLaunch) {
+        BuildArgs args;
+        memset(&args, 0, sizeof(args));
+        args.n = std::min(kMaxBuildPerLaunch, n - first);
+        for (int i = 0; i < args.n; ++i) {
+            const dctf_operator op = ops[first + i];
+            args.d[i].img = op->img;
+            args.d[i].N = op->N;
+            args.d[i].kh = op->kh;
+            args.d[i].kw = op->kw;
+            args.d[i].border = op->border;
+        }
+        dctf_status st = hip_status(launch_build(args, s));
+        if (st != DCTF_OK)
+            return st;
+    }
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_build_operators(const dctf_mask_desc *masks, int n, dctf_stream stream,
+                                            dctf_operator *out)
+{
+    if (n < 0 || (n > 0 && (masks == nullptr || out == nullptr)))
+        return DCTF_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        dctf_status st = validate_mask(masks[i].mask_host, masks[i].kh, masks[i].kw, masks[i].N,
+                                       masks[i].border);
+        if (st != DCTF_OK)
+            return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<dctf_operator> ops(n, nullptr);
+    dctf_status st = DCTF_OK;
+    for (int i = 0; i < n && st == DCTF_OK; ++i) {
+        st = alloc_operator(masks[i].N, masks[i].kh, masks[i].kw, masks[i].border, &ops[i]);
+        if (st == DCTF_OK)
+            st = hip_status(hipMemcpyAsync(ops[i]->img.mask, masks[i].mask_host,
+                                           sizeof(double) * masks[i].kh * masks[i].kw,
+                                           hipMemcpyHostToDevice, s));
+    }
+    if (st == DCTF_OK)
+        st = launch_rebuild(ops.data(), n, s);
+    // The mask copies are from pageable memory: make them complete before the
+    // caller may free its masks.
+    if (st == DCTF_OK)
+        st = hip_status(hipStreamSynchronize(s));
+    if (st != DCTF_OK) {
+        for (auto op : ops)
+            dctf_operator_destroy(op);
+        return st;
+    }
+    for (int i = 0; i < n; ++i)
+        out[i] = ops[i];
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_build_operator(const double *mask_host, int kh, int kw, int N, int border,
+                                           dctf_stream stream, dctf_operator *out)
+{
+    if (out == nullptr)
+        return DCTF_EINVAL;
+    dctf_mask_desc d = {mask_host, kh, kw, N, border};
+    return dctf_build_operators(&d, 1, stream, out);
+}
+
+extern "C" dctf_status dctf_rebuild_operators(const dctf_operator *ops, int n, dctf_stream stream)
+{
+    if (n < 0 || (n > 0 && ops == nullptr))
+        return DCTF_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (ops[i] == nullptr)
+            return DCTF_EINVAL;
+    return launch_rebuild(ops, n, static_cast<hipStream_t>(stream));
+}
+
+extern "C" dctf_status dctf_operator_fp64(dctf_operator op, double *host_out)
+{
+    if (op == nullptr || host_out == nullptr)
+        return DCTF_EINVAL;
+    const size_t NN = (size_t)op->N * op->N;
+    return hip_status(hipMemcpy(host_out, op->img.H64, sizeof(double) * NN * NN, hipMemcpyDeviceToHost));
+}
+
+extern "C" dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *border)
+{
+    if (op == nullptr)
+        return DCTF_EINVAL;
+    if (N)
+        *N = op->N;
+    if (kh)
+        *kh = op->kh;
+    if (kw)
+        *kw = op->kw;
+    if (border)
+        *border = op->border;
+    return DCTF_OK;
+}
+
+extern "C" void dctf_operator_destroy(dctf_operator op)
+{
+    if (op == nullptr)
+        return;
+    if (op->base)
+        hipFree(op->base);
+    delete op;
+}
+
+// =================================================================== filter
+
+static dctf_status validate_io(int N, const float *in, const float *out, int64_t B)
+{
+    if (B < 0)
+        return DCTF_EINVAL;
+    if (B == 0)
+        return DCTF_OK;
+    if (in == nullptr || out == nullptr || !aligned16(in) || !aligned16(out))
+        return DCTF_EINVAL;
+    const size_t bytes = (size_t)B * N * N * sizeof(float);
+    if (ranges_overlap(in, bytes, out, bytes))
+        return DCTF_EINVAL;
+    return DCTF_OK;
+}
+
+static FilterArgs filter_args(dctf_operator op, const float *in, float *out, int64_t B)
+{
+    FilterArgs a;
+    a.in = in;
+    a.out = out;
+    a.B = B;
+    a.frag32 = op->img.frag32;
+    a.frag_hi = op->img.frag_hi;
+    a.frag_lo = op->img.frag_lo;
+    a.frag_lf = op->img.frag_lf;
+    a.h0 = op->img.h0;
+    a.H32 = op->img.H32;
+    return a;
+}
+
+extern "C" dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, float *out_dev,
+                                          int64_t B, dctf_stream stream)
+{
+    if (op == nullptr)
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
+        return DCTF_EINVAL;
+    dctf_status st = validate_io(op->N, in_dev, out_dev, B);
+    if (st != DCTF_OK || B == 0)
+        return st;
+    const FilterArgs a = filter_args(op, in_dev, out_dev, B);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
+    timing_end(s, slot);
+    return st;
+}
+
+// ==================================================================== batch
+
+struct dctf_batch_s {
+    int prec = 0;
+    std::vector<dctf_operator> ops;   // distinct operators, in table order
+    void *dev = nullptr;              // JobDesc[njobs8] | JobDesc[njobs16] | OpDesc[nops]
+    BatchArgs args{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct Interval {
+    uintptr_t a, b;
+    bool out;
+};
+
+bool jobs_conflict(const dctf_job *jobs, int n)
+{
+    std::vector<Interval> iv;
+    iv.reserve(2 * n);
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].B == 0)
+            continue;
+        const size_t bytes = (size_t)jobs[i].B * jobs[i].op->N * jobs[i].op->N * sizeof(float);
+        iv.push_back({(uintptr_t)jobs[i].in, (uintptr_t)jobs[i].in + bytes, false});
+        iv.push_back({(uintptr_t)jobs[i].out, (uintptr_t)jobs[i].out + bytes, true});
+    }
+    std::sort(iv.begin(), iv.end(), [](const Interval &x, const Interval &y) { return x.a < y.a; });
+    uintptr_t end_all = 0, end_out = 0;
+    for (const auto &v : iv) {
+        if (v.out ? v.a < end_all : v.a < end_out)
+            return true;
+        end_all = std::max(end_all, v.b);
+        if (v.out)
+            end_out = std::max(end_out, v.b);
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out)
+{
+    if (out == nullptr || njobs < 0 || (njobs > 0 && jobs == nullptr))
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
+        return DCTF_EINVAL;
+    for (int i = 0; i < njobs; ++i) {
+        const dctf_job &j = jobs[i];
+        if (j.op == nullptr)
+            return DCTF_EINVAL;
+        if (j.op->N != 8 && j.op->N != 16)
+            return DCTF_EUNSUPPORTED;
+        dctf_status st = validate_io(j.op->N, j.in, j.out, j.B);
+        if (st != DCTF_OK)
+            return st;
+    }
+    if (jobs_conflict(jobs, njobs))
+        return DCTF_EINVAL;
+
+    dctf_batch b = new (std::nothrow) dctf_batch_s();
+    if (!b)
+        return DCTF_ENOMEM;
+    b->prec = prec;
+
+    // Group by N, then operator (stable in the caller's order otherwise).
+    std::vector<int> order;
+    for (int i = 0; i < njobs; ++i)
+        if (jobs[i].B > 0)
+            order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (jobs[x].op->N != jobs[y].op->N)
+            return jobs[x].op->N < jobs[y].op->N;
+        return jobs[x].op < jobs[y].op;
+    });
+    std::vector<JobDesc> j8, j16;
+    std::vector<OpDesc> od;
+    int64_t u8 = 0, u16 = 0, blocks8 = 0, blocks16 = 0;
+    for (int idx : order) {
+        const dctf_job &j = jobs[idx];
+        int opi = -1;
+        for (size_t k = 0; k < b->ops.size(); ++k)
+            if (b->ops[k] == j.op)
+                opi = (int)k;
+        if (opi < 0) {
+            opi = (int)b->ops.size();
+            b->ops.push_back(j.op);
+            od.push_back({j.op->img.frag32, j.op->img.frag_hi, j.op->img.frag_lo, j.op->img.frag_lf,
+                          j.op->img.h0});
+        }
+        JobDesc d;
+        d.in = j.in;
+        d.out = j.out;
+        d.B = j.B;
+        d.op = opi;
+        d.N = j.op->N;
+        if (d.N == 8) {
+            d.unit_begin = u8;
+            u8 += (j.B + kUnitBlocks8 - 1) / kUnitBlocks8;
+            blocks8 += j.B;
+            j8.push_back(d);
+        } else {
+            d.unit_begin = u16;
+            u16 += (j.B + kUnitBlocks16 - 1) / kUnitBlocks16;
+            blocks16 += j.B;
+            j16.push_back(d);
+        }
+    }
+
+    const size_t bytes = sizeof(JobDesc) * (j8.size() + j16.size()) + sizeof(OpDesc) * od.size();
+    if (bytes > 0) {
+        hipError_t e = hipMalloc(&b->dev, bytes);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_status(e);
+        }
+        std::vector<char> host(bytes);
+        char *p = host.data();
+        memcpy(p, j8.data(), sizeof(JobDesc) * j8.size());
+        memcpy(p + sizeof(JobDesc) * j8.size(), j16.data(), sizeof(JobDesc) * j16.size());
+        memcpy(p + sizeof(JobDesc) * (j8.size() + j16.size()), od.data(), sizeof(OpDesc) * od.size());
+        e = hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(b->dev);
+            delete b;
+            return hip_status(e);
+        }
+    }
+    char *dp = static_cast<char *>(b->dev);
+    BatchArgs &a = b->args;
+    a.jobs8 = reinterpret_cast<const JobDesc *>(dp);
+    a.njobs8 = (int)j8.size();
+    a.units8 = u8;
+    a.jobs16 = reinterpret_cast<const JobDesc *>(dp + sizeof(JobDesc) * j8.size());
+    a.njobs16 = (int)j16.size();
+    a.units16 = u16;
+    a.ops = reinterpret_cast<const OpDesc *>(dp + sizeof(JobDesc) * (j8.size() + j16.size()));
+    a.prec = prec;
+
+    // Split the persistent grid between the two block sizes in proportion to
+    // their estimated time (bytes for the HBM-bound cases, MFMA work for
+    // N = 16 in FP32).
+    const int occ = std::max(1, batch_occupancy(prec));
+    const int G = std::max(1, cu_count() * occ);
+    const double c16 = (prec == DCTF_PREC_FP32) ? 16.0 : 4.0;
+    const double w8 = (double)blocks8, w16 = c16 * (double)blocks16;
+    int g16 = 0;
+    if (u16 > 0)
+        g16 = (u8 > 0) ? (int)std::lround(G * w16 / (w8 + w16)) : G;
+    if (u16 > 0 && g16 < 1)
+        g16 = 1;
+    if (u8 > 0 && g16 > G - 1)
+        g16 = G - 1;
+    int g8 = (u8 > 0) ? G - g16 : 0;
+    const int64_t waves8 = kBatchThreads / 64;
+    g8 = (int)std::min<int64_t>(g8, (u8 + waves8 - 1) / waves8);
+    g16 = (int)std::min<int64_t>(g16, u16);
+    a.groups8 = g8;
+    a.groups16 = g16;
+    *out = b;
+    return DCTF_OK;
+}
+
+static dctf_status batch_enqueue(dctf_batch b, unsigned flags, hipStream_t s)
+{
+    if (flags & DCTF_RUN_REBUILD_OPERATORS) {
+        dctf_status st = launch_rebuild(b->ops.data(), (int)b->ops.size(), s);
+        if (st != DCTF_OK)
+            return st;
+    }
+    int slot;
+    timing_begin(s, &slot);
+    dctf_status st = hip_status(launch_batch(b->args, s));
+    timing_end(s, slot);
+    return st;
+}
+
+extern "C" dctf_status dctf_batch_run(dctf_batch b, unsigned flags, dctf_stream stream)
+{
+    if (b == nullptr || (flags & ~DCTF_RUN_REBUILD_OPERATORS))
+        return DCTF_EINVAL;
+    return batch_enqueue(b, flags, static_cast<hipStream_t>(stream));
+}
+
+extern "C" dctf_status dctf_batch_capture(dctf_batch b, unsigned flags, dctf_stream stream)
+{
+    if (b == nullptr || stream == nullptr || (flags & ~DCTF_RUN_REBUILD_OPERATORS))
+        return DCTF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_status(e);
+    dctf_status st = batch_enqueue(b, flags, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st != DCTF_OK || e != hipSuccess) {
+        if (g)
+            hipGraphDestroy(g);
+        return st != DCTF_OK ? st : hip_status(e);
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return hip_status(e);
+    }
+    b->graph = g;
+    b->exec = x;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_batch_launch_graph(dctf_batch b, dctf_stream stream)
+{
+    if (b == nullptr || b->exec == nullptr)
+        return DCTF_EINVAL;
+    return hip_status(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+}
+
+extern "C" dctf_status dctf_batch_info(dctf_batch b, int *groups_n8, int *groups_n16, int *threads)
+{
+    if (b == nullptr)
+        return DCTF_EINVAL;
+    if (groups_n8)
+        *groups_n8 = b->args.groups8;
+    if (groups_n16)
+        *groups_n16 = b->args.groups16;
+    if (threads)
+        *threads = kBatchThreads;
+    return DCTF_OK;
+}
+
+extern "C" void dctf_batch_destroy(dctf_batch b)
+{
+    if (b == nullptr)
+        return;
+    if (b->exec)
+        hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        hipGraphDestroy(b->graph);
+    if (b->dev)
+        hipFree(b->dev);
+    delete b;
+}
+
+extern "C" dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int prec, dctf_stream stream)
+{
+    dctf_batch b = nullptr;
+    dctf_status st = dctf_batch_create(jobs, njobs, prec, &b);
+    if (st != DCTF_OK)
+        return st;
+    st = dctf_batch_run(b, 0, stream);
+    dctf_status st2 = hip_status(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    dctf_batch_destroy(b);
+    return st != DCTF_OK ? st : st2;
+}
+
+// ============================================================ around the path
+
+extern "C" dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w, int64_t pitch, int N,
+                                           float *coeffs_dev, dctf_stream stream)
+{
+    if (!supported_n(N))
+        return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
+    if (img_dev == nullptr || coeffs_dev == nullptr || h < 1 || w < 1 || pitch < w || !aligned16(coeffs_dev))
+        return DCTF_EINVAL;
+    return hip_status(launch_forward_dct_u8(img_dev, h, w, pitch, N, coeffs_dev,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+extern "C" dctf_status dctf_idct_u8_verify(int N, const float *coeffs_dev, int64_t B, uint8_t *pix_dev,
+                                           const uint8_t *expected_dev, unsigned long long *counters_dev,
+                                           dctf_stream stream)
+{
+    if (!supported_n(N))
+        return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
+    if (B < 0)
+        return DCTF_EINVAL;
+    if (B == 0)
+        return DCTF_OK;
+    if (coeffs_dev == nullptr || pix_dev == nullptr || !aligned16(coeffs_dev))
+        return DCTF_EINVAL;
+    if (counters_dev != nullptr && ((uintptr_t)counters_dev & 7u))
+        return DCTF_EINVAL;
+    return hip_status(launch_idct_u8_verify(N, coeffs_dev, B, pix_dev, expected_dev, counters_dev,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+// =================================================================== tuning
+
+extern "C" int dctf_variant_count(int N, int prec)
+{
+    if (!supported_n(N) || (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16))
+        return 0;
+    return variant_count(N, prec);
+}
+
+extern "C" const char *dctf_variant_name(int N, int prec, int v)
+{
+    if (dctf_variant_count(N, prec) <= v || v < 0)
+        return nullptr;
+    return variant_name(N, prec, v);
+}
+
+extern "C" dctf_status dctf_get_variant(int N, int prec, int *variant)
+{
+    if (variant == nullptr || dctf_variant_count(N, prec) == 0)
+        return DCTF_EINVAL;
+    *variant = current_variant(N, prec);
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_set_variant(int N, int prec, int variant)
+{
+    if (variant < 0 || variant >= dctf_variant_count(N, prec))
+        return DCTF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_variant_mu);
+    g_variant[N][prec] = variant;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float *out_dev,
+                                     int64_t B, int iters, dctf_stream stream, int *best_variant,
+                                     float *best_ms)
+{
+    if (op == nullptr || iters < 1 || B <= 0)
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
+        return DCTF_EINVAL;
+    dctf_status st = validate_io(op->N, in_dev, out_dev, B);
+    if (st != DCTF_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const FilterArgs a = filter_args(op, in_dev, out_dev, B);
+    const int nv = variant_count(op->N, prec);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            hipEventDestroy(e0);
+        return DCTF_EHIP;
+    }
+    int best = -1;
+    float best_t = 0.0f;
+    for (int v = 0; v < nv && st == DCTF_OK; ++v) {
+        for (int w = 0; w < 2 && st == DCTF_OK; ++w)
+            st = hip_status(launch_filter(op->N, prec, v, a, s));
+        if (st == DCTF_OK)
+            st = hip_status(hipEventRecord(e0, s));
+        for (int i = 0; i < iters && st == DCTF_OK; ++i)
+            st = hip_status(launch_filter(op->N, prec, v, a, s));
+        if (st == DCTF_OK)
+            st = hip_status(hipEventRecord(e1, s));
+        if (st == DCTF_OK)
+            st = hip_status(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        if (st == DCTF_OK)
+            st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+        ms /= iters;
+        if (st == DCTF_OK && (best < 0 || ms < best_t)) {
+            best = v;
+            best_t = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != DCTF_OK)
+        return st;
+    dctf_set_variant(op->N, prec, best);
+    if (best_variant)
+        *best_variant = best;
+    if (best_ms)
+        *best_ms = best_t;
+    return DCTF_OK;
+}
+
+// ===================================================================== misc
+
+extern "C" const char *dctf_status_string(dctf_status s)
+{
+    switch (s) {
+    case DCTF_OK: return "ok";
+    case DCTF_EINVAL: return "invalid argument";
+    case DCTF_EUNSUPPORTED: return "unsupported block size or precision";
+    case DCTF_ENOMEM: return "out of memory";
+    case DCTF_EHIP: return "HIP runtime error";
+    case DCTF_EBUSY: return "resource budget exhausted";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *dctf_version(void) { return "dctf 0.1.0 (gfx950)"; }
+
+extern "C" dctf_status dctf_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.on = on != 0;
+    g_timing.used = 0;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_timing_read(double *avg_ms, int *count)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double total = 0.0;
+    int n = 0;
+    for (int i = 0; i < g_timing.used; ++i) {
+        hipEvent_t a = g_timing.ev[2 * i], b = g_timing.ev[2 * i + 1];
+        if (!a || !b)
+            continue;
+        if (hipEventSynchronize(b) != hipSuccess)
+            return DCTF_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess)
+            return DCTF_EHIP;
+        total += ms;
+        ++n;
+    }
+    g_timing.used = 0;
+    if (avg_ms)
+        *avg_ms = n ? total / n : 0.0;
+    if (count)
+        *count = n;
+    return DCTF_OK;
+}

@@ -1,0 +1,225 @@
+// FP64 operator builder (gfx950).
+//
+// For a kh x kw mask W, block size N and border mode, forms
+//
+//   H[(u,v),(k,l)] = sum_p sum_q W[p][q] T_{p-a_h}[u][k] T_{q-a_w}[v][l],
+//   T_d = C S_d C^t,  T_d[u][k] = sum_i C[u][i] C[k][s_d(i)],
+//
+// where C is the orthonormal DCT-II matrix (Sec. II.A, eq. 1-2) and s_d(i)
+// the source row of output row i under a shift by d: i + d with zero fill
+// outside the block (zero padding, Sec. II.B) or clamp(i + d, 0, N-1) (border
+// replication, Sec. II.C / Fig. 1).  This is the Kronecker form of the
+// paper's DCT-domain products A.BLOCK.B (eq. 6-8): a row selector a = S_d
+// becomes A = C a C^t (eq. 7), and a horizontal band of mask row p becomes
+// B_p = sum_q W[p][q] T_q^t.  Summing over every mask row reproduces eq. 11
+// (zero padding) and, with the clamped selectors, the corner / lateral terms
+// of eq. 13-19 that eq. 20 adds.
+//
+// The sum over q is taken first: G_p[j][l] = sum_q W[p][q] C[l][s_q(j)],
+// B_p = C G_p (so B_p[v][l] = sum_q W[p][q] T_q[v][l]); then
+// H += T_p (x) B_p for each mask row p.  Everything is FP64.  One workgroup
+// owns 16 rows of H (all N^2 columns) for one operator and writes every image
+// of those rows: FP64, FP32, the MFMA fragments and the DC column.
+//
+// Fragment layouts (lane = 16 g + m of a 64-lane wave, M-tile t = row / 16,
+// m = row % 16):
+//   frag32  FP32 A operand of v_mfma_f32_16x16x4_f32, DC column zeroed
+//   frag_hi / frag_lo  BF16 A operands of v_mfma_f32_16x16x32_bf16, with the
+//           low-frequency columns zeroed
+//   frag_lf FP32 A operand for the 16 low-frequency columns: slot q = 4 g + j
+//           of lf_slot() at ((t * 64 + lane) * 4 + j)
+#include "dctf_internal.h"
+
+#include <math.h>
+
+namespace dctf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRowsPerGroup = 16;
+constexpr int kMaxN = 16;
+constexpr int kMaxK = 2 * kMaxN + 1;
+
+__device__ inline int src_index(int i, int d, int N, int border, bool *valid)
+{
+    int m = i + d;
+    if (border == DCTF_BORDER_ZERO) {
+        *valid = (m >= 0 && m < N);
+        return m;
+    }
+    *valid = true;
+    return m < 0 ? 0 : (m >= N ? N - 1 : m);
+}
+
+// Round an FP32 value to BF16, round-to-nearest-even (finite inputs).
+__device__ inline uint16_t bf16_rne(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Position of H[r][c] in the FP32 MFMA fragment layout.
+//   N = 8  (v_mfma_f32_16x16x4_f32, whole operator per wave): lane = 16g + m,
+//          r = 16t + m, c = 16i + 4g + j -> ((t*4 + i)*64 + lane)*4 + j.
+//   N = 16 (weight-stationary, 16 M-tiles over 8 waves): r = 16T + m,
+//          c = 16i + 4g + j -> ((T*16 + i)*64 + lane)*4 + j.
+__device__ inline int frag32_index(int N, int r, int c)
+{
+    int t = r >> 4, m = r & 15;
+    int i = c >> 4, g = (c >> 2) & 3, j = c & 3;
+    int lane = 16 * g + m;
+    int ni = (N == 8) ? 4 : 16;
+    return ((t * ni + i) * 64 + lane) * 4 + j;
+}
+
+// Position of H[r][c] in the BF16 MFMA fragment layout
+// (v_mfma_f32_16x16x32_bf16, 8 BF16 per lane per k-step).
+//   N = 8:  c = 16(2s + e) + 4g + j, element 4e + j   -> ((t*2 + s)*64 + lane)*8 + 4e + j.
+//   N = 16: c = 32s + 8g + e8, element e8             -> ((T*8 + s)*64 + lane)*8 + e8.
+__device__ inline int frag16_index(int N, int r, int c)
+{
+    int t = r >> 4, m = r & 15;
+    if (N == 8) {
+        int ii = c >> 4, s = ii >> 1, e = ii & 1, g = (c >> 2) & 3, j = c & 3;
+        return ((t * 2 + s) * 64 + 16 * g + m) * 8 + 4 * e + j;
+    }
+    int s = c >> 5, g = (c >> 3) & 3, e8 = c & 7;
+    return ((t * 8 + s) * 64 + 16 * g + m) * 8 + e8;
+}
+
+__global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
+{
+    const int op = blockIdx.y;
+    if (op >= args.n)
+        return;
+    const BuildDesc &d = args.d[op];
+    const int N = d.N, NN = N * N, kh = d.kh, kw = d.kw, border = d.border;
+    const int rows_per_group = NN < kRowsPerGroup ? NN : kRowsPerGroup;
+    const int r0 = blockIdx.x * rows_per_group;
+    if (r0 >= NN)
+        return;
+
+    __shared__ double sC[kMaxN * kMaxN];
+    __shared__ double sT[kMaxN * kMaxN];   // T_p for the current mask row
+    __shared__ double sG[kMaxN * kMaxN];   // G_p
+    __shared__ double sB[kMaxN * kMaxN];   // B_p = C G_p
+    __shared__ double sW[kMaxK * kMaxK];
+
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NN; e += kThreads) {
+        int k = e / N, n = e % N;
+        double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
+        sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N));
+    }
+    for (int e = tid; e < kh * kw; e += kThreads)
+        sW[e] = d.img.mask[e];
+
+    // Entries of H owned by this thread: rows [r0, r0 + rows), all columns.
+    const int owned = rows_per_group * NN;       // <= 16 * 256
+    constexpr int kMaxOwned = kRowsPerGroup * kMaxN * kMaxN / kThreads;  // 16
+    double acc[kMaxOwned];
+#pragma unroll
+    for (int o = 0; o < kMaxOwned; ++o)
+        acc[o] = 0.0;
+
+    const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+    __syncthreads();
+
+    for (int p = 0; p < kh; ++p) {
+        const int dp = p - ah;
+        for (int e = tid; e < NN; e += kThreads) {
+            // T_p[u][k] = sum_i C[u][i] C[k][s_dp(i)]
+            int u = e / N, k = e % N;
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) {
+                bool ok;
+                int m = src_index(i, dp, N, border, &ok);
+                if (ok)
+                    s += sC[u * N + i] * sC[k * N + m];
+            }
+            sT[e] = s;
+            // G_p[j][l] = sum_q W[p][q] C[l][s_dq(j)]
+            int j = e / N, l = e % N;
+            double g = 0.0;
+            for (int q = 0; q < kw; ++q) {
+                bool ok;
+                int m = src_index(j, q - aw, N, border, &ok);
+                if (ok)
+                    g += sW[p * kw + q] * sC[l * N + m];
+            }
+            sG[e] = g;
+        }
+        __syncthreads();
+        for (int e = tid; e < NN; e += kThreads) {
+            int v = e / N, l = e % N;
+            double s = 0.0;
+            for (int j = 0; j < N; ++j)
+                s += sC[v * N + j] * sG[j * N + l];
+            sB[e] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < kMaxOwned; ++o) {
+            int e = tid + o * kThreads;
+            if (e < owned) {
+                int r = r0 + e / NN, c = e % NN;
+                int u = r / N, v = r % N, k = c / N, l = c % N;
+                acc[o] += sT[u * N + k] * sB[v * N + l];
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int o = 0; o < kMaxOwned; ++o) {
+        int e = tid + o * kThreads;
+        if (e >= owned)
+            continue;
+        int r = r0 + e / NN, c = e % NN;
+        double h = acc[o];
+        float h32 = __double2float_rn(h);
+        d.img.H64[(size_t)r * NN + c] = h;
+        d.img.H32[(size_t)r * NN + c] = h32;
+        if (c == 0)
+            d.img.h0[r] = h32;
+        if (N >= 8) {
+            // FP32 MFMA image: the operator without its DC column, which the
+            // FP32 filter applies separately in VALU arithmetic.
+            d.img.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
+            // Split path: low-frequency columns (DC included) go to the FP32
+            // MFMA image frag_lf; every other column is split into BF16
+            // hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
+            const int q = lf_slot(N, c);
+            uint16_t hi = 0, lo = 0;
+            if (q >= 0) {
+                const int t = r >> 4, m = r & 15, lane = 16 * (q >> 2) + m;
+                d.img.frag_lf[(t * 64 + lane) * 4 + (q & 3)] = h32;
+            } else {
+                hi = bf16_rne(h32);
+                lo = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(hi)));
+            }
+            const int fi = frag16_index(N, r, c);
+            d.img.frag_hi[fi] = hi;
+            d.img.frag_lo[fi] = lo;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
+{
+    if (args.n <= 0)
+        return hipSuccess;
+    int maxN = 0;
+    for (int i = 0; i < args.n; ++i)
+        maxN = args.d[i].N > maxN ? args.d[i].N : maxN;
+    int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
+    hipLaunchKernelGGL(k_build, dim3(groups, args.n), dim3(kThreads), 0, stream, args);
+    return hipGetLastError();
+}
+
+}  // namespace dctf

@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP sources of libdctf (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dctf.h"
+
+namespace dctf {
+
+// ---------------------------------------------------------------- operator
+
+// Device image of one operator, all in a single allocation.
+struct OpImages {
+    double *mask;        // kh*kw, row-major (device copy of the caller's mask)
+    double *H64;         // N^2 x N^2 row-major, FP64
+    float *H32;          // N^2 x N^2 row-major, FP32 (RNE of H64)
+    float *frag32;       // FP32 MFMA A-operand fragments (N = 8, 16), DC column zeroed
+    uint16_t *frag_hi;   // BF16 hi fragments (N = 8, 16), DC column zeroed
+    uint16_t *frag_lo;   // BF16 lo fragments
+    float *frag_lf;      // FP32 A fragments of the low-frequency columns (split path)
+    float *h0;           // DC column H[:, 0] in FP32 (N^2 floats)
+};
+
+// Low-frequency input coefficients that the split-BF16 path multiplies in
+// FP32 MFMA instead of BF16 (they carry the largest magnitudes of natural
+// images, where a two-term BF16 split loses the most absolute precision).
+//   N = 8 : the 16 coefficients of rows u = 0, 1 (k < 16);
+//   N = 16: the first 16 in zigzag order: u + v <= 4, then (0, 5).
+// Returns the slot 0..15 of coefficient k, or -1.
+__host__ __device__ inline int lf_slot(int N, int k)
+{
+    if (N == 8)
+        return k < 16 ? k : -1;
+    const int u = k / N, v = k % N, d = u + v;
+    if (d <= 4)
+        return d * (d + 1) / 2 + u;
+    return (u == 0 && v == 5) ? 15 : -1;
+}
+constexpr int kLfCount = 16;
+
+}  // namespace dctf
+
+struct dctf_operator_s {
+    int N, kh, kw, border;
+    int device;
+    void *base;   // owning device allocation
+    size_t bytes;
+    dctf::OpImages img;
+};
+
+namespace dctf {
+
+constexpr int kMaxBuildPerLaunch = 16;
+
+struct BuildDesc {
+    OpImages img;
+    int N, kh, kw, border;
+};
+
+struct BuildArgs {
+    BuildDesc d[kMaxBuildPerLaunch];
+    int n;
+};
+
+// Fragment sizes (elements) per operator.
+inline size_t frag_elems(int N) { return (N >= 8) ? (size_t)N * N * N * N : 0; }
+inline size_t frag_lf_elems(int N) { return (N >= 8) ? (size_t)N * N * kLfCount : 0; }
+
+// builder.hip
+hipError_t launch_build(const BuildArgs &args, hipStream_t stream);
+
+// filter.hip — single-operator filter of B blocks.
+struct FilterArgs {
+    const float *in;
+    float *out;
+    int64_t B;
+    const float *frag32;
+    const uint16_t *frag_hi;
+    const uint16_t *frag_lo;
+    const float *frag_lf;
+    const float *h0;
+    const float *H32;
+};
+hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipStream_t stream);
+int variant_count(int N, int prec);
+const char *variant_name(int N, int prec, int v);
+int default_variant(int N, int prec);
+
+// batch.hip — persistent launch over a device work table.
+struct JobDesc {
+    const float *in;
+    float *out;
+    int64_t B;
+    int64_t unit_begin;   // first work unit of this job within its N class
+    int op;               // index into the op table
+    int N;
+};
+
+struct OpDesc {
+    const float *frag32;
+    const uint16_t *frag_hi;
+    const uint16_t *frag_lo;
+    const float *frag_lf;
+    const float *h0;
+};
+
+struct BatchArgs {
+    const JobDesc *jobs8;    // N = 8 jobs, units of kUnitBlocks8 blocks
+    int njobs8;
+    int64_t units8;
+    const JobDesc *jobs16;   // N = 16 jobs, units of 16 blocks
+    int njobs16;
+    int64_t units16;
+    const OpDesc *ops;
+    int groups8;             // workgroups [0, groups8) take N = 8 work
+    int groups16;            // workgroups [groups8, groups8 + groups16) take N = 16 work
+    int prec;
+};
+
+constexpr int kBatchThreads = 512;
+constexpr int kUnitBlocks8 = 32;    // blocks per N = 8 work unit (two 16-block MFMA tiles)
+constexpr int kUnitBlocks16 = 16;   // blocks per N = 16 work unit
+
+hipError_t launch_batch(const BatchArgs &a, hipStream_t stream);
+
+// verify.hip
+hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
+                                 const uint8_t *expected, unsigned long long *counters,
+                                 hipStream_t stream);
+hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
+                                 float *coeffs, hipStream_t stream);
+
+// Device properties cached per device.
+int cu_count();
+
+}  // namespace dctf

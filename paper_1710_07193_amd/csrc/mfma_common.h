@@ -1,0 +1,383 @@
+// Device helpers shared by the filter kernels: MFMA operand types, the
+// FP32 -> BF16 hi/lo split and the per-tile compute of the N = 8 and N = 16
+// paths.  Everything here targets gfx950 (64-lane waves, 16x16 MFMA tiles).
+#pragma once
+
+#include "dctf_internal.h"
+
+namespace dctf {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values -> packed BF16 pair (low half = a), round-to-nearest-even.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
+{
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// x = hi + lo + r with hi = bf16(x), lo = bf16(x - hi); x - hi is exact in FP32.
+__device__ __forceinline__ void split_bf16(float4 x, uint32_t &h01, uint32_t &h23, uint32_t &l01,
+                                           uint32_t &l23)
+{
+    h01 = pack_bf16x2(x.x, x.y);
+    h23 = pack_bf16x2(x.z, x.w);
+    float hx = __uint_as_float(h01 << 16), hy = __uint_as_float(h01 & 0xffff0000u);
+    float hz = __uint_as_float(h23 << 16), hw = __uint_as_float(h23 & 0xffff0000u);
+    l01 = pack_bf16x2(x.x - hx, x.y - hy);
+    l23 = pack_bf16x2(x.z - hz, x.w - hw);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(u32x4 a, u32x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Value of `v` held by lane `src` (within the wave).
+__device__ __forceinline__ float lane_read(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ float4 ld4(const float *p)
+{
+    return *reinterpret_cast<const float4 *>(p);
+}
+
+__device__ __forceinline__ float4 ld4_nt(const float *p)
+{
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ void st4(float *p, f32x4 v)
+{
+    *reinterpret_cast<f32x4 *>(p) = v;
+}
+
+__device__ __forceinline__ void st4_nt(float *p, f32x4 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(p));
+}
+
+// ------------------------------------------------------------------ N = 8
+//
+// One wave holds the whole 64 x 64 operator in VGPRs as MFMA A fragments and
+// computes Y^t = H . X^t for 16 blocks per MFMA tile: M = 64 output
+// coefficients (4 M-tiles of 16), N = 16 blocks, K = 64 input coefficients.
+// Lane (n, g) = (lane % 16, lane / 16) loads X[n][16i + 4g + j] (i, j in
+// 0..3) with four 16-byte loads, so each load instruction covers 64
+// contiguous bytes of 16 blocks.  The MFMA contraction index is permuted to
+// match (the builder wrote H's columns in the same permutation).  Lane (n, g)
+// receives Y[n][16t + 4g + r], r = 0..3, and stores it as one 16-byte store
+// per M-tile.
+
+struct OpRegs8F32 {
+    float A[4][4][4];   // [t][i][j]
+    float h0[4][4];     // [t][r] = H[16t + 4g + r][0]
+};
+
+struct OpRegs8BF16 {
+    u32x4 hi[4][2];     // [t][s]
+    u32x4 lo[4][2];
+    float lf[4][4];     // [t][j]: FP32 A operand of the low-frequency k-steps
+};
+
+__device__ __forceinline__ void load_op8(OpRegs8F32 &R, const float *frag32, const float *h0, int lane)
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float4 v = ld4(frag32 + ((t * 4 + i) * 64 + lane) * 4);
+            R.A[t][i][0] = v.x;
+            R.A[t][i][1] = v.y;
+            R.A[t][i][2] = v.z;
+            R.A[t][i][3] = v.w;
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float4 v = ld4(h0 + 16 * t + 4 * g);
+        R.h0[t][0] = v.x;
+        R.h0[t][1] = v.y;
+        R.h0[t][2] = v.z;
+        R.h0[t][3] = v.w;
+    }
+}
+
+__device__ __forceinline__ void load_op8(OpRegs8BF16 &R, const uint16_t *fhi, const uint16_t *flo,
+                                         const float *flf, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            R.hi[t][s] = *reinterpret_cast<const u32x4 *>(fhi + ((t * 2 + s) * 64 + lane) * 8);
+            R.lo[t][s] = *reinterpret_cast<const u32x4 *>(flo + ((t * 2 + s) * 64 + lane) * 8);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float4 v = ld4(flf + (t * 64 + lane) * 4);
+        R.lf[t][0] = v.x;
+        R.lf[t][1] = v.y;
+        R.lf[t][2] = v.z;
+        R.lf[t][3] = v.w;
+    }
+}
+
+// Y for one 16-block tile held in x[4] (lane layout above); DC in FP32.
+__device__ __forceinline__ void tile8(const OpRegs8F32 &R, float4 x[4], int lane, f32x4 acc[4])
+{
+    const int n = lane & 15;
+    const float x0 = lane_read(x[0].x, n);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float xv[4] = {x[i].x, x[i].y, x[i].z, x[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[t][r] = fmaf(R.h0[t][r], x0, acc[t][r]);
+}
+
+// Split path.  The 16 coefficients of load 0 (rows u = 0, 1, DC included)
+// are multiplied in FP32 MFMA; the other 48 are split into BF16 hi + lo and
+// multiplied as hi.hi + hi.lo + lo.hi (the low-frequency columns of the BF16
+// fragments are zero, so load 0 enters the BF16 products as zeros).
+__device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lane, f32x4 acc[4])
+{
+    (void)lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float x0[4] = {x[0].x, x[0].y, x[0].z, x[0].w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_f32(R.lf[t][j], x0[j], acc[t]);
+    u32x4 bh[2], bl[2];
+    {
+        uint32_t h2, h3, l2, l3;
+        split_bf16(x[1], h2, h3, l2, l3);
+        bh[0] = u32x4{0u, 0u, h2, h3};
+        bl[0] = u32x4{0u, 0u, l2, l3};
+        uint32_t h0, h1, l0, l1;
+        split_bf16(x[2], h0, h1, l0, l1);
+        split_bf16(x[3], h2, h3, l2, l3);
+        bh[1] = u32x4{h0, h1, h2, h3};
+        bl[1] = u32x4{l0, l1, l2, l3};
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.lo[t][s], bh[s], acc[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bl[s], acc[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bh[s], acc[t]);
+    }
+}
+
+// ----------------------------------------------------------------- N = 16
+//
+// Weight-stationary: a workgroup of 8 waves holds the 256 x 256 operator in
+// VGPRs, wave w owning output rows [32w, 32w + 32) (two M-tiles).  A tile of
+// 16 blocks is staged in LDS once and read by all 8 waves.
+//   FP32: LDS tile [16][260] floats (row padded by 16 B: conflict-free
+//         16-byte reads); lane (n, g) reads X[n][16i + 4g .. +3], i = 0..15.
+//   BF16: LDS tiles hi / lo [16][264] BF16, split once when written; lane
+//         (n, g) reads 8 BF16 at X[n][32s + 8g], s = 0..7.  The 16
+//         low-frequency coefficients (lf_slot) go to an FP32 LDS array
+//         [16][20] instead and are multiplied in FP32 MFMA.
+
+constexpr int kLd16F32 = 260;    // floats per LDS row (FP32 path)
+constexpr int kLd16BF16 = 264;   // BF16 per LDS row (split path)
+constexpr int kLd16Lf = 20;      // floats per LDS row of the low-frequency FP32 part
+
+// LDS bytes of one 16-block tile buffer.
+constexpr int kTile16BytesF32 = 16 * kLd16F32 * 4;
+constexpr int kTile16BytesSplit = 2 * 16 * kLd16BF16 * 2 + 16 * kLd16Lf * 4;
+
+struct OpRegs16F32 {
+    float A[2][16][4];
+    float h0[2][4];
+};
+
+struct OpRegs16BF16 {
+    u32x4 hi[2][8];
+    u32x4 lo[2][8];
+    float lf[2][4];     // [t][j]: FP32 A operand of the low-frequency k-steps
+};
+
+__device__ __forceinline__ void load_op16(OpRegs16F32 &R, const float *frag32, const float *h0,
+                                          int wave, int lane)
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int T = 2 * wave + t;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            float4 v = ld4(frag32 + ((T * 16 + i) * 64 + lane) * 4);
+            R.A[t][i][0] = v.x;
+            R.A[t][i][1] = v.y;
+            R.A[t][i][2] = v.z;
+            R.A[t][i][3] = v.w;
+        }
+        float4 v = ld4(h0 + 16 * T + 4 * g);
+        R.h0[t][0] = v.x;
+        R.h0[t][1] = v.y;
+        R.h0[t][2] = v.z;
+        R.h0[t][3] = v.w;
+    }
+}
+
+__device__ __forceinline__ void load_op16(OpRegs16BF16 &R, const uint16_t *fhi, const uint16_t *flo,
+                                          const float *flf, int wave, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int T = 2 * wave + t;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            R.hi[t][s] = *reinterpret_cast<const u32x4 *>(fhi + ((T * 8 + s) * 64 + lane) * 8);
+            R.lo[t][s] = *reinterpret_cast<const u32x4 *>(flo + ((T * 8 + s) * 64 + lane) * 8);
+        }
+        float4 v = ld4(flf + (T * 64 + lane) * 4);
+        R.lf[t][0] = v.x;
+        R.lf[t][1] = v.y;
+        R.lf[t][2] = v.z;
+        R.lf[t][3] = v.w;
+    }
+}
+
+// LDS staging of one 16-block tile: thread q of the workgroup holds the
+// 16-byte chunk (block q / 64, coefficients 4(q % 64) .. +3) and the chunk
+// q + 512.
+struct Stage16 {
+    float4 v[2];
+};
+
+__device__ __forceinline__ void stage16_load(Stage16 &S, const float *in, int64_t B, int64_t tile,
+                                             int tid)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h;
+        int64_t blk = tile * 16 + (q >> 6);
+        blk = blk < B ? blk : B - 1;
+        S.v[h] = ld4(in + blk * 256 + 4 * (q & 63));
+    }
+}
+
+__device__ __forceinline__ void stage16_store(const Stage16 &S, float *lds, int tid)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h;
+        *reinterpret_cast<float4 *>(lds + (q >> 6) * kLd16F32 + 4 * (q & 63)) = S.v[h];
+    }
+}
+
+// Split path: the low-frequency coefficients go to the FP32 array llf (slot
+// order of lf_slot) and enter the BF16 arrays as zeros.
+__device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, uint16_t *llo,
+                                              float *llf, int tid)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h;
+        const int b = q >> 6, c = q & 63;
+        float xv[4] = {S.v[h].x, S.v[h].y, S.v[h].z, S.v[h].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int slot = lf_slot(16, 4 * c + e);
+            if (slot >= 0) {
+                llf[b * kLd16Lf + slot] = xv[e];
+                xv[e] = 0.0f;
+            }
+        }
+        uint32_t h01, h23, l01, l23;
+        split_bf16(make_float4(xv[0], xv[1], xv[2], xv[3]), h01, h23, l01, l23);
+        *reinterpret_cast<uint2 *>(lhi + b * kLd16BF16 + 4 * c) = make_uint2(h01, h23);
+        *reinterpret_cast<uint2 *>(llo + b * kLd16BF16 + 4 * c) = make_uint2(l01, l23);
+    }
+}
+
+__device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, int lane, f32x4 acc[2])
+{
+    const int n = lane & 15, g = lane >> 4;
+    acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc[1] = acc[0];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const float4 xv4 = *reinterpret_cast<const float4 *>(lds + n * kLd16F32 + 16 * i + 4 * g);
+        const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
+    }
+    const float x0 = lds[n * kLd16F32];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[t][r] = fmaf(R.h0[t][r], x0, acc[t][r]);
+}
+
+__device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lhi, const uint16_t *llo,
+                                       const float *llf, int lane, f32x4 acc[2])
+{
+    const int n = lane & 15, g = lane >> 4;
+    acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc[1] = acc[0];
+    const float4 lv = *reinterpret_cast<const float4 *>(llf + n * kLd16Lf + 4 * g);
+    const float lfv[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + n * kLd16BF16 + 32 * s + 8 * g);
+        const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + n * kLd16BF16 + 32 * s + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.lo[t][s], bh, acc[t]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bl, acc[t]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
+    }
+}
+
+}  // namespace dctf

@@ -1,0 +1,146 @@
+// Kernels around the filter path:
+//   k_forward_dct_u8   uint8 image -> FP32 coefficient blocks (eq. 1, FP64 arithmetic)
+//   k_idct_u8_verify   FP32 coefficients -> uint8 pixels (eq. 3 in FP32, then the
+//                      Sec. III uint8 conversion) with mismatch / near-1/2 counters
+// One workgroup of 256 threads handles 256 / (N*N) blocks (N <= 16), one
+// thread per pixel or coefficient.  The N x N DCT matrix is formed in LDS
+// from its closed form.
+#include "dctf_internal.h"
+
+#include <math.h>
+
+namespace dctf {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ inline void fill_dct(T *sC, int N)
+{
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        int k = e / N, n = e % N;
+        double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
+        sC[e] = (T)(alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N)));
+    }
+}
+
+// X[u][v] = sum_i C[u][i] (sum_j x[i][j] C[v][j]) in FP64, rounded once to FP32.
+__global__ __launch_bounds__(kThreads) void k_forward_dct_u8(const uint8_t *img, int h, int w,
+                                                             int64_t pitch, int N, float *coeffs,
+                                                             int64_t nblocks)
+{
+    __shared__ double sC[256];
+    __shared__ double sx[256];
+    __shared__ double st[256];
+    fill_dct(sC, N);
+    const int NN = N * N;
+    const int per = kThreads / NN;
+    const int local = threadIdx.x / NN, e = threadIdx.x % NN;
+    const int i = e / N, j = e % N;
+    const int64_t blk = (int64_t)blockIdx.x * per + local;
+    const bool active = local < per && blk < nblocks;
+    const int bw = (w + N - 1) / N;
+    if (active) {
+        const int64_t by = blk / bw, bx = blk % bw;
+        int64_t y = by * N + i, x = bx * N + j;
+        y = y < h ? y : h - 1;
+        x = x < w ? x : w - 1;
+        sx[threadIdx.x] = (double)img[y * pitch + x];
+    }
+    __syncthreads();
+    const int base = local * NN;
+    if (active) {
+        // t[i][v] with (i, v) = (i, j) of this thread
+        double s = 0.0;
+        for (int jj = 0; jj < N; ++jj)
+            s += sx[base + i * N + jj] * sC[j * N + jj];
+        st[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (active) {
+        // X[u][v] with (u, v) = (i, j) of this thread
+        double s = 0.0;
+        for (int ii = 0; ii < N; ++ii)
+            s += sC[i * N + ii] * st[base + ii * N + j];
+        coeffs[blk * NN + e] = __double2float_rn(s);
+    }
+}
+
+// pix[i][j] = sum_u C[u][i] (sum_v Y[u][v] C[v][j]) in FP32.
+__global__ __launch_bounds__(kThreads) void k_idct_u8_verify(int N, const float *Y, int64_t B,
+                                                             uint8_t *pix, const uint8_t *expected,
+                                                             unsigned long long *counters)
+{
+    __shared__ float sC[256];
+    __shared__ float sy[256];
+    __shared__ float st[256];
+    fill_dct(sC, N);
+    const int NN = N * N;
+    const int per = kThreads / NN;
+    const int local = threadIdx.x / NN, e = threadIdx.x % NN;
+    const int i = e / N, j = e % N;
+    const int64_t blk = (int64_t)blockIdx.x * per + local;
+    const bool active = local < per && blk < B;
+    if (active)
+        sy[threadIdx.x] = Y[blk * NN + e];
+    __syncthreads();
+    const int base = local * NN;
+    if (active) {
+        // t[u][j] with u = i of this thread
+        float s = 0.0f;
+        for (int v = 0; v < N; ++v)
+            s = fmaf(sy[base + i * N + v], sC[v * N + j], s);
+        st[threadIdx.x] = s;
+    }
+    __syncthreads();
+    unsigned long long bad = 0, near = 0;
+    if (active) {
+        float p = 0.0f;
+        for (int u = 0; u < N; ++u)
+            p = fmaf(sC[u * N + i], st[base + u * N + j], p);
+        const float r = floorf(p + 0.5f);
+        const uint8_t q = (uint8_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
+        pix[blk * NN + e] = q;
+        const bool nh = fabsf(p - floorf(p) - 0.5f) < 1e-3f;
+        near = nh ? 1 : 0;
+        if (expected != nullptr && !nh && q != expected[blk * NN + e])
+            bad = 1;
+    }
+    if (counters != nullptr) {
+        // one atomic per wave and counter
+        const unsigned long long nb = __popcll(__ballot(bad != 0));
+        const unsigned long long nn = __popcll(__ballot(near != 0));
+        if ((threadIdx.x & 63) == 0) {
+            if (nb)
+                atomicAdd(&counters[0], nb);
+            if (nn)
+                atomicAdd(&counters[1], nn);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
+                                 float *coeffs, hipStream_t stream)
+{
+    const int64_t nblocks = (int64_t)((h + N - 1) / N) * ((w + N - 1) / N);
+    const int per = kThreads / (N * N);
+    const int64_t groups = (nblocks + per - 1) / per;
+    hipLaunchKernelGGL(k_forward_dct_u8, dim3((unsigned)groups), dim3(kThreads), 0, stream, img, h, w,
+                       pitch, N, coeffs, nblocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
+                                 const uint8_t *expected, unsigned long long *counters,
+                                 hipStream_t stream)
+{
+    const int per = kThreads / (N * N);
+    const int64_t groups = (B + per - 1) / per;
+    hipLaunchKernelGGL(k_idct_u8_verify, dim3((unsigned)groups), dim3(kThreads), 0, stream, N, Y, B,
+                       pix, expected, counters);
+    return hipGetLastError();
+}
+
+}  // namespace dctf

@@ -1,0 +1,114 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments on the host before any device
+work (no compute call is made here)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "dctf.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dctf_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1710_07193_amd as dctf
+    return dctf.raw_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("dctf_build_operator", "dctf_filter_blocks", "dctf_filter_batch",
+                     "dctf_batch_create", "dctf_batch_capture", "dctf_idct_u8_verify",
+                     "dctf_autotune", "dctf_operator_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_library_is_in_tree_and_gfx950():
+    import paper_1710_07193_amd as dctf
+    assert os.path.dirname(dctf.LIB_PATH) == os.path.join(ROOT, "paper_1710_07193_amd")
+    assert "gfx950" in dctf.dctf_version()
+
+
+def test_status_strings(lib):
+    import paper_1710_07193_amd as dctf
+    for s in (0, -1, -2, -3, -4, -5):
+        assert dctf.dctf_status_string(s)
+    assert dctf.dctf_status_string(-99) == "unknown status"
+
+
+def _mask(vals):
+    arr = (ctypes.c_double * len(vals))(*vals)
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+def test_build_operator_validation(lib):
+    out = ctypes.c_void_p()
+    m, keep = _mask([1.0 / 9] * 9)
+    assert lib.dctf_build_operator(m, 3, 3, 3, 0, None, ctypes.byref(out)) == -2   # N = 3
+    assert lib.dctf_build_operator(m, 3, 3, 32, 0, None, ctypes.byref(out)) == -2  # N = 32
+    assert lib.dctf_build_operator(m, 3, 3, 0, 0, None, ctypes.byref(out)) == -1
+    assert lib.dctf_build_operator(None, 3, 3, 8, 0, None, ctypes.byref(out)) == -1
+    assert lib.dctf_build_operator(m, 0, 3, 8, 0, None, ctypes.byref(out)) == -1
+    assert lib.dctf_build_operator(m, 3, 18, 8, 0, None, ctypes.byref(out)) == -1  # > 2N+1
+    assert lib.dctf_build_operator(m, 3, 3, 8, 2, None, ctypes.byref(out)) == -1   # border
+    assert lib.dctf_build_operator(m, 3, 3, 8, 0, None, None) == -1
+    bad, keep2 = _mask([1.0, math.nan, 0.0])
+    assert lib.dctf_build_operator(bad, 1, 3, 8, 0, None, ctypes.byref(out)) == -1
+    inf, keep3 = _mask([1.0, math.inf, 0.0])
+    assert lib.dctf_build_operator(inf, 1, 3, 8, 0, None, ctypes.byref(out)) == -1
+
+
+def test_filter_and_batch_validation(lib):
+    assert lib.dctf_filter_blocks(None, 0, None, None, 10, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.dctf_batch_create(None, -1, 0, ctypes.byref(out)) == -1
+    assert lib.dctf_batch_create(None, 0, 7, ctypes.byref(out)) == -1
+    assert lib.dctf_batch_create(None, 0, 0, None) == -1
+    assert lib.dctf_batch_run(None, 0, None) == -1
+    assert lib.dctf_batch_capture(None, 0, None) == -1
+    assert lib.dctf_batch_launch_graph(None, None) == -1
+    assert lib.dctf_rebuild_operators(None, -1, None) == -1
+    assert lib.dctf_operator_fp64(None, None) == -1
+    assert lib.dctf_autotune(None, 0, None, None, 1, 1, None, None, None) == -1
+
+
+def test_verify_and_forward_dct_validation(lib):
+    assert lib.dctf_idct_u8_verify(3, None, 1, None, None, None, None) == -2
+    assert lib.dctf_idct_u8_verify(8, None, -1, None, None, None, None) == -1
+    assert lib.dctf_idct_u8_verify(8, None, 0, None, None, None, None) == 0     # B = 0: no-op
+    assert lib.dctf_idct_u8_verify(8, None, 5, None, None, None, None) == -1
+    assert lib.dctf_forward_dct_u8(None, 8, 8, 8, 6, None, None) == -2
+    assert lib.dctf_forward_dct_u8(None, 8, 8, 8, 8, None, None) == -1
+
+
+def test_variant_table(lib):
+    import paper_1710_07193_amd as dctf
+    for N in (2, 4, 8, 16):
+        for prec in (0, 1):
+            n = dctf.dctf_variant_count(N, prec)
+            assert n >= 1
+            names = [dctf.dctf_variant_name(N, prec, v) for v in range(n)]
+            assert all(names) and len(set(names)) == n
+            assert dctf.dctf_variant_name(N, prec, n) is None
+    assert dctf.dctf_variant_count(3, 0) == 0
+    assert lib.dctf_set_variant(8, 0, 999) == -1
+    n8 = dctf.dctf_variant_count(8, 1)
+    dctf.dctf_set_variant(8, 1, n8 - 1)
+    assert dctf.dctf_get_variant(8, 1) == n8 - 1
+    dctf.dctf_set_variant(8, 1, 0)
+    assert dctf.dctf_get_variant(8, 1) == 0
