@@ -126,8 +126,11 @@ void dctf_operator_destroy(dctf_operator op);
  * Y[b] = H_dct . X[b] for b = 0..B-1 (eq. 11 / eq. 20 for every block at
  * once).  in_dev, out_dev: device, B * N*N floats each, block-contiguous,
  * 16-byte aligned, non-overlapping (in-place is not supported).
- * prec: dctf_precision.  The DC column H[:,0] is always applied in FP32
- * VALU arithmetic; the MFMA sums over the other columns.
+ * prec: dctf_precision.  FP32: the MFMA sums over every column but the DC
+ * column H[:,0], which is applied in FP32 VALU arithmetic.  Split-BF16: the
+ * 16 low-frequency input coefficients (N = 8: rows u = 0, 1; N = 16: the
+ * first 16 in zigzag order) are multiplied in FP32 MFMA, the others as
+ * BF16 hi.hi + hi.lo + lo.hi; both accumulate in FP32.
  * For N <= 4 both precisions run one FP32 kernel (the operator is at most
  * 16 x 16).  B = 0 is a no-op.  Each block's result depends only on that
  * block and the operator: it is bit-identical whatever B, the tuning variant
@@ -173,7 +176,8 @@ dctf_status dctf_batch_capture(dctf_batch batch, unsigned flags, dctf_stream str
 dctf_status dctf_batch_launch_graph(dctf_batch batch, dctf_stream stream);
 
 /* Grid shape of the plan's persistent launch (workgroups for N = 8 work,
- * workgroups for N = 16 work, threads per workgroup).  Any pointer may be NULL. */
+ * workgroups for N = 16 work, threads per workgroup: 256 when the plan holds
+ * only N = 8 jobs, else 512).  Any pointer may be NULL. */
 dctf_status dctf_batch_info(dctf_batch batch, int *groups_n8, int *groups_n16, int *threads);
 
 void dctf_batch_destroy(dctf_batch batch);
@@ -208,6 +212,14 @@ dctf_status dctf_idct_u8_verify(int N, const float *coeffs_dev, int64_t B, uint8
                                 const uint8_t *expected_dev, unsigned long long *counters_dev,
                                 dctf_stream stream);
 
+/*
+ * Measurement aid, not part of the method: a plain streaming copy of n floats
+ * (n a multiple of 4, 16-byte aligned, non-overlapping).  Its bandwidth is the
+ * achievable-HBM reference for the filter kernels, and its FETCH_SIZE /
+ * WRITE_SIZE counter readings calibrate the traffic figures of the others.
+ */
+dctf_status dctf_stream_copy(const float *in_dev, float *out_dev, int64_t n, dctf_stream stream);
+
 /* ----------------------------------------------------------------- tuning */
 
 /*
@@ -222,6 +234,18 @@ int dctf_variant_count(int N, int prec);
 const char *dctf_variant_name(int N, int prec, int variant);
 dctf_status dctf_get_variant(int N, int prec, int *variant);
 dctf_status dctf_set_variant(int N, int prec, int variant);
+/*
+ * Sweep fronts of a batch plan's N = 8 work (read when a plan is created;
+ * results are bit-identical for every setting).  The operator-sorted work
+ * units are cut at operator boundaries into `fronts` runs of about equal
+ * size; the waves of a run stride over it together and reload their operator
+ * when they reach the next operator's units.  1 = one front over all units;
+ * 0 = one front per operator (each wave loads one operator); default 2.
+ * Errors: DCTF_EINVAL outside [0, 4096].
+ */
+dctf_status dctf_set_batch_fronts(int fronts);
+int dctf_get_batch_fronts(void);
+
 dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float *out_dev,
                           int64_t B, int iters, dctf_stream stream, int *best_variant,
                           float *best_ms);

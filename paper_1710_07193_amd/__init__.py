@@ -57,11 +57,14 @@ _SIGS = {
     "dctf_filter_batch": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
     "dctf_forward_dct_u8": ([_P, _I, _I, _I64, _I, _P, _P], _I),
     "dctf_idct_u8_verify": ([_I, _P, _I64, _P, _P, _P, _P], _I),
+    "dctf_stream_copy": ([_P, _P, _I64, _P], _I),
     "dctf_variant_count": ([_I, _I], _I),
     "dctf_variant_name": ([_I, _I, _I], ctypes.c_char_p),
     "dctf_get_variant": ([_I, _I, _P], _I),
     "dctf_set_variant": ([_I, _I, _I], _I),
     "dctf_autotune": ([_P, _I, _P, _P, _I64, _I, _P, _P, _P], _I),
+    "dctf_set_batch_fronts": ([_I], _I),
+    "dctf_get_batch_fronts": ([], _I),
     "dctf_status_string": ([_I], ctypes.c_char_p),
     "dctf_version": ([], ctypes.c_char_p),
     "dctf_timing_enable": ([_I], _I),
@@ -289,6 +292,14 @@ def dctf_idct_u8_verify(N: int, Y: torch.Tensor, pix: torch.Tensor, expected=Non
            "dctf_idct_u8_verify")
 
 
+def dctf_stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Plain device copy (measurement aid: the achievable-HBM reference)."""
+    if src.numel() != dst.numel():
+        raise ValueError("sizes differ")
+    _check(_lib.dctf_stream_copy(_dptr(src, torch.float32, "src"), _dptr(dst, torch.float32, "dst"),
+                                 src.numel(), _stream(stream)), "dctf_stream_copy")
+
+
 def dctf_variant_count(N: int, prec: int) -> int:
     return int(_lib.dctf_variant_count(N, prec))
 
@@ -317,6 +328,14 @@ def dctf_autotune(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor, ite
                               X.numel() // nn, iters, _stream(stream), ctypes.byref(v),
                               ctypes.byref(ms)), "dctf_autotune")
     return v.value, ms.value
+
+
+def dctf_set_batch_fronts(fronts: int):
+    _check(_lib.dctf_set_batch_fronts(fronts), "dctf_set_batch_fronts")
+
+
+def dctf_get_batch_fronts() -> int:
+    return int(_lib.dctf_get_batch_fronts())
 
 
 def dctf_status_string(s: int) -> str:

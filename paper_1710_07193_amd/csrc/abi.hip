@@ -14,7 +14,6 @@
 
 namespace dctf {
 
-int batch_occupancy(int prec);   // batch.hip
 
 namespace {
 
@@ -23,6 +22,7 @@ std::atomic<int> g_cu[kMaxDevices];
 
 std::mutex g_variant_mu;
 int g_variant[17][2];   // [N][prec]; zero-initialised = default variant 0
+std::atomic<int> g_batch_fronts{2};
 
 bool supported_n(int N) { return N == 2 || N == 4 || N == 8 || N == 16; }
 
@@ -100,6 +100,9 @@ int cu_count()
     }
     return v;
 }
+
+int batch_fronts() { return g_batch_fronts.load(); }
+void set_batch_fronts(int fronts) { g_batch_fronts.store(fronts); }
 
 }  // namespace dctf
 
@@ -435,41 +438,21 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
         }
     }
 
-    const size_t bytes = sizeof(JobDesc) * (j8.size() + j16.size()) + sizeof(OpDesc) * od.size();
-    if (bytes > 0) {
-        hipError_t e = hipMalloc(&b->dev, bytes);
-        if (e != hipSuccess) {
-            delete b;
-            return hip_status(e);
-        }
-        std::vector<char> host(bytes);
-        char *p = host.data();
-        memcpy(p, j8.data(), sizeof(JobDesc) * j8.size());
-        memcpy(p + sizeof(JobDesc) * j8.size(), j16.data(), sizeof(JobDesc) * j16.size());
-        memcpy(p + sizeof(JobDesc) * (j8.size() + j16.size()), od.data(), sizeof(OpDesc) * od.size());
-        e = hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            hipFree(b->dev);
-            delete b;
-            return hip_status(e);
-        }
-    }
-    char *dp = static_cast<char *>(b->dev);
     BatchArgs &a = b->args;
-    a.jobs8 = reinterpret_cast<const JobDesc *>(dp);
-    a.njobs8 = (int)j8.size();
-    a.units8 = u8;
-    a.jobs16 = reinterpret_cast<const JobDesc *>(dp + sizeof(JobDesc) * j8.size());
-    a.njobs16 = (int)j16.size();
-    a.units16 = u16;
-    a.ops = reinterpret_cast<const OpDesc *>(dp + sizeof(JobDesc) * (j8.size() + j16.size()));
     a.prec = prec;
+    variant_io(8, prec, current_variant(8, prec), &a.io, &a.nt);
 
     // Split the persistent grid between the two block sizes in proportion to
     // their estimated time (bytes for the HBM-bound cases, MFMA work for
     // N = 16 in FP32).
-    const int occ = std::max(1, batch_occupancy(prec));
+    // One block size: a kernel holding only that worker, one persistent
+    // grid.  Both: the combined kernel, its grid split in proportion to the
+    // estimated time (bytes for the HBM-bound cases, MFMA work for N = 16 in
+    // FP32).
+    const int kind = (u16 == 0) ? 8 : (u8 == 0 ? 16 : 0);
+    const int occ = std::max(1, batch_occupancy(prec, a.io, a.nt, kind));
     const int G = std::max(1, cu_count() * occ);
+    const int wpg8 = (kind == 8 ? kBatch8Threads : kBatchThreads) / 64;   // waves per N = 8 workgroup
     const double c16 = (prec == DCTF_PREC_FP32) ? 16.0 : 4.0;
     const double w8 = (double)blocks8, w16 = c16 * (double)blocks16;
     int g16 = 0;
@@ -479,12 +462,99 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
         g16 = 1;
     if (u8 > 0 && g16 > G - 1)
         g16 = G - 1;
-    int g8 = (u8 > 0) ? G - g16 : 0;
-    const int64_t waves8 = kBatchThreads / 64;
-    g8 = (int)std::min<int64_t>(g8, (u8 + waves8 - 1) / waves8);
-    g16 = (int)std::min<int64_t>(g16, u16);
-    a.groups8 = g8;
-    a.groups16 = g16;
+    const int g8 = (u8 > 0) ? G - g16 : 0;
+
+    // Fronts: runs of consecutive jobs (N = 8: `fronts` runs cut at operator
+    // boundaries with about equal units; N = 16: one run per operator), with
+    // workers in proportion to their units.
+    auto cut = [](const std::vector<JobDesc> &jobs, int64_t units, int64_t workers, int fronts) {
+        std::vector<size_t> starts;   // first job of each operator segment
+        for (size_t i = 0; i < jobs.size(); ++i)
+            if (i == 0 || jobs[i].op != jobs[i - 1].op)
+                starts.push_back(i);
+        std::vector<size_t> cuts{0};
+        if (fronts > 0) {
+            for (int f = 1; f < fronts; ++f) {
+                const int64_t target = units * f / fronts;
+                size_t best = cuts.back();
+                for (size_t st : starts)
+                    if (st > cuts.back() && jobs[st].unit_begin <= target)
+                        best = st;
+                if (best > cuts.back())
+                    cuts.push_back(best);
+            }
+        } else {
+            cuts = starts;
+        }
+        std::vector<SegDesc> segs;
+        int64_t next_worker = 0;
+        for (size_t c = 0; c < cuts.size(); ++c) {
+            const size_t i = cuts[c], e = (c + 1 < cuts.size()) ? cuts[c + 1] : jobs.size();
+            SegDesc sd;
+            sd.unit_begin = jobs[i].unit_begin;
+            sd.unit_end = (e < jobs.size()) ? jobs[e].unit_begin : units;
+            const int64_t su = sd.unit_end - sd.unit_begin;
+            int64_t w = (int64_t)std::llround((double)workers * (double)su / (double)units);
+            w = std::max<int64_t>(1, std::min(w, su));
+            sd.worker_begin = next_worker;
+            sd.nworkers = w;
+            next_worker += w;
+            sd.job_begin = (int)i;
+            sd.job_end = (int)e;
+            sd.op = jobs[i].op;
+            segs.push_back(sd);
+        }
+        return segs;
+    };
+    const std::vector<SegDesc> s8 = j8.empty() ? std::vector<SegDesc>()
+                                               : cut(j8, u8, (int64_t)g8 * wpg8, batch_fronts());
+    const std::vector<SegDesc> s16 = j16.empty() ? std::vector<SegDesc>() : cut(j16, u16, g16, 0);
+    const int64_t workers8 = s8.empty() ? 0 : s8.back().worker_begin + s8.back().nworkers;
+    const int64_t workers16 = s16.empty() ? 0 : s16.back().worker_begin + s16.back().nworkers;
+
+    const size_t bytes = sizeof(JobDesc) * (j8.size() + j16.size()) + sizeof(SegDesc) * (s8.size() + s16.size()) +
+                         sizeof(OpDesc) * od.size();
+    if (bytes > 0) {
+        hipError_t e = hipMalloc(&b->dev, bytes);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_status(e);
+        }
+        std::vector<char> host(bytes);
+        char *p = host.data();
+        auto put = [&](const void *src, size_t n) {
+            if (n)
+                memcpy(p, src, n);
+            p += n;
+        };
+        put(j8.data(), sizeof(JobDesc) * j8.size());
+        put(j16.data(), sizeof(JobDesc) * j16.size());
+        put(s8.data(), sizeof(SegDesc) * s8.size());
+        put(s16.data(), sizeof(SegDesc) * s16.size());
+        put(od.data(), sizeof(OpDesc) * od.size());
+        e = hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(b->dev);
+            delete b;
+            return hip_status(e);
+        }
+    }
+    char *dp = static_cast<char *>(b->dev);
+    a.jobs8 = reinterpret_cast<const JobDesc *>(dp);
+    dp += sizeof(JobDesc) * j8.size();
+    a.jobs16 = reinterpret_cast<const JobDesc *>(dp);
+    dp += sizeof(JobDesc) * j16.size();
+    a.segs8 = reinterpret_cast<const SegDesc *>(dp);
+    a.nsegs8 = (int)s8.size();
+    dp += sizeof(SegDesc) * s8.size();
+    a.segs16 = reinterpret_cast<const SegDesc *>(dp);
+    a.nsegs16 = (int)s16.size();
+    dp += sizeof(SegDesc) * s16.size();
+    a.ops = reinterpret_cast<const OpDesc *>(dp);
+    a.workers8 = workers8;
+    a.workers16 = workers16;
+    a.groups8 = (int)((workers8 + wpg8 - 1) / wpg8);
+    a.groups16 = (int)workers16;
     *out = b;
     return DCTF_OK;
 }
@@ -561,7 +631,7 @@ extern "C" dctf_status dctf_batch_info(dctf_batch b, int *groups_n8, int *groups
     if (groups_n16)
         *groups_n16 = b->args.groups16;
     if (threads)
-        *threads = kBatchThreads;
+        *threads = (b->args.groups16 == 0) ? kBatch8Threads : kBatchThreads;
     return DCTF_OK;
 }
 
@@ -621,6 +691,19 @@ extern "C" dctf_status dctf_idct_u8_verify(int N, const float *coeffs_dev, int64
                                             static_cast<hipStream_t>(stream)));
 }
 
+extern "C" dctf_status dctf_stream_copy(const float *in_dev, float *out_dev, int64_t n, dctf_stream stream)
+{
+    if (n < 0 || (n & 3))
+        return DCTF_EINVAL;
+    if (n == 0)
+        return DCTF_OK;
+    if (in_dev == nullptr || out_dev == nullptr || !aligned16(in_dev) || !aligned16(out_dev))
+        return DCTF_EINVAL;
+    if (ranges_overlap(in_dev, (size_t)n * 4, out_dev, (size_t)n * 4))
+        return DCTF_EINVAL;
+    return hip_status(launch_stream_copy(in_dev, out_dev, n, static_cast<hipStream_t>(stream)));
+}
+
 // =================================================================== tuning
 
 extern "C" int dctf_variant_count(int N, int prec)
@@ -653,6 +736,16 @@ extern "C" dctf_status dctf_set_variant(int N, int prec, int variant)
     g_variant[N][prec] = variant;
     return DCTF_OK;
 }
+
+extern "C" dctf_status dctf_set_batch_fronts(int fronts)
+{
+    if (fronts < 0 || fronts > 4096)
+        return DCTF_EINVAL;
+    set_batch_fronts(fronts);
+    return DCTF_OK;
+}
+
+extern "C" int dctf_get_batch_fronts(void) { return batch_fronts(); }
 
 extern "C" dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float *out_dev,
                                      int64_t B, int iters, dctf_stream stream, int *best_variant,

@@ -3,20 +3,21 @@
 //
 // The host groups jobs by N and, within N, by operator, and numbers work
 // units consecutively across the jobs of each class (JobDesc::unit_begin):
-//   N = 8 : a unit is 32 blocks (two 16-block MFMA tiles), done by one wave;
-//   N = 16: a unit is 16 blocks, done by one 8-wave workgroup.
+//   N = 8 : a unit is one 16-block MFMA tile, done by one wave;
+//   N = 16: a unit is one 16-block tile, done by one 8-wave workgroup.
 // Workgroups [0, groups8) take the N = 8 units, the rest the N = 16 units.
-// Each wave (N = 8) or workgroup (N = 16) takes one contiguous range of
-// units, so it crosses few job and operator boundaries; its operator
-// fragments are reloaded only when the operator changes.  The per-block
-// arithmetic is the one of the single-operator kernels, so every block's
-// result is bit-identical to filtering its job alone.
+// The units of a class are cut into "fronts": N = 8 work into a few runs of
+// operator segments (one sweep front each: fewer fronts stream HBM better,
+// more fronts mean fewer operator reloads per wave), N = 16 work into one
+// front per operator.  Each front owns a contiguous range of workers (waves
+// for N = 8, workgroups for N = 16) in proportion to its units, and they
+// stride over its units front to back.  The per-block arithmetic is the one
+// of the single-operator kernels, so every block's result is bit-identical
+// to filtering its job alone.
 #include "mfma_common.h"
 
 namespace dctf {
 namespace {
-
-constexpr int kU8 = kUnitBlocks8 / 16;   // MFMA tiles per N = 8 unit
 
 struct UnitRef {
     const float *in;
@@ -26,12 +27,13 @@ struct UnitRef {
     int op;
 };
 
-__device__ __forceinline__ int find_job(const JobDesc *jobs, int njobs, int64_t unit)
+// Segment of worker w: the last segment whose worker_begin <= w.
+__device__ __forceinline__ int find_segment(const SegDesc *segs, int nsegs, int64_t w)
 {
-    int lo = 0, hi = njobs - 1;
+    int lo = 0, hi = nsegs - 1;
     while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].unit_begin <= unit)
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].worker_begin <= w)
             lo = mid;
         else
             hi = mid - 1;
@@ -39,169 +41,228 @@ __device__ __forceinline__ int find_job(const JobDesc *jobs, int njobs, int64_t 
     return lo;
 }
 
-__device__ __forceinline__ UnitRef resolve(const JobDesc *jobs, int njobs, int &j, int64_t unit,
-                                           int blocks_per_unit)
-{
-    while (j + 1 < njobs && jobs[j + 1].unit_begin <= unit)
-        ++j;
-    const JobDesc &d = jobs[j];
-    UnitRef r;
-    r.in = d.in;
-    r.out = d.out;
-    r.B = d.B;
-    r.blk0 = (unit - d.unit_begin) * blocks_per_unit;
-    r.op = d.op;
-    return r;
-}
+// Walks the job table forward as the unit index grows.  The descriptor of
+// the job after the current one is fetched one step early, so crossing one
+// job boundary per step does not wait on a scalar load.
+struct JobCursor {
+    const JobDesc *jobs;
+    int end, j;
+    JobDesc cur, next;
+    int64_t next_begin;
 
-template <int PREC>
-__device__ void worker8(const BatchArgs &a, int64_t gw, int64_t nwaves, int lane)
+    __device__ __forceinline__ void start(const JobDesc *t, int job_begin, int job_end, int64_t unit)
+    {
+        jobs = t;
+        end = job_end;
+        j = job_begin;
+        cur = t[j];
+        fetch_next();
+        while (unit >= next_begin)
+            advance();
+    }
+    __device__ __forceinline__ void fetch_next()
+    {
+        if (j + 1 < end) {
+            next = jobs[j + 1];
+            next_begin = next.unit_begin;
+        } else {
+            next_begin = INT64_MAX;
+        }
+    }
+    __device__ __forceinline__ void advance()
+    {
+        ++j;
+        cur = next;
+        fetch_next();
+    }
+    __device__ __forceinline__ UnitRef at(int64_t unit, int blocks_per_unit)
+    {
+        while (unit >= next_begin)
+            advance();
+        UnitRef r;
+        r.in = cur.in;
+        r.out = cur.out;
+        r.B = cur.B;
+        r.blk0 = (unit - cur.unit_begin) * blocks_per_unit;
+        r.op = cur.op;
+        return r;
+    }
+};
+
+// The waves of a front (a run of consecutive segments) stride over its
+// units together; a wave reloads its operator fragments when the unit it
+// reaches belongs to another operator.
+template <int PREC, int IO, bool NT>
+__device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
 {
-    const int64_t u_begin = gw * a.units8 / nwaves;
-    const int64_t u_end = (gw + 1) * a.units8 / nwaves;
-    if (u_begin >= u_end)
+    if (gw >= a.workers8)
         return;
+    const SegDesc &sg = a.segs8[find_segment(a.segs8, a.nsegs8, gw)];
+    const int64_t first = sg.unit_begin + (gw - sg.worker_begin);
+    const int64_t stride = sg.nworkers, end = sg.unit_end;
+    const int job_begin = sg.job_begin, job_end = sg.job_end;
+    if (first >= end)
+        return;
+    const int64_t my_units = (end - first + stride - 1) / stride;
     const int n = lane & 15, g = lane >> 4;
+
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8BF16>::type Regs;
     Regs R;
     int loaded_op = -1;
+    auto op_load = [&](int op) {
+        const OpDesc &o = a.ops[op];
+        if constexpr (PREC == DCTF_PREC_FP32)
+            load_op8(R, o.frag32, o.h0, lane);
+        else
+            load_op8(R, o.frag_hi, o.frag_lo, o.frag_lf, lane);
+        loaded_op = op;
+    };
 
-    auto load_unit = [&](float4 (&x)[kU8][4], const UnitRef &r) {
-#pragma unroll
-        for (int u = 0; u < kU8; ++u) {
-            int64_t blk = r.blk0 + 16 * u + n;
+    auto load_unit = [&](float4 (&x)[4], const UnitRef &r) {
+        if constexpr (IO == 1) {
+            load_tile_coalesced<NT>(x, r.in + r.blk0 * 64, r.B - r.blk0, lane);
+        } else {
+            int64_t blk = r.blk0 + n;
             blk = blk < r.B ? blk : r.B - 1;
             const float *src = r.in + blk * 64 + 4 * g;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                x[u][i] = ld4(src + 16 * i);
+                x[i] = NT ? ld4_nt(src + 16 * i) : ld4(src + 16 * i);
         }
     };
-    auto compute_store = [&](float4 (&x)[kU8][4], const UnitRef &r) {
-        if (r.op != loaded_op) {
-            const OpDesc &o = a.ops[r.op];
-            if constexpr (PREC == DCTF_PREC_FP32)
-                load_op8(R, o.frag32, o.h0, lane);
-            else
-                load_op8(R, o.frag_hi, o.frag_lo, o.frag_lf, lane);
-            loaded_op = r.op;
-        }
-#pragma unroll
-        for (int u = 0; u < kU8; ++u) {
+    auto compute_store = [&](float4 (&x)[4], const UnitRef &r) {
+        if (r.op != loaded_op)
+            op_load(r.op);
+        if constexpr (IO == 1) {
+            tile8_coalesced<NT>(R, x, lds, r.out + r.blk0 * 64, r.B - r.blk0, lane);
+        } else {
             f32x4 acc[4];
-            tile8(R, x[u], lane, acc);
-            const int64_t blk = r.blk0 + 16 * u + n;
+            tile8(R, x, lane, acc);
+            const int64_t blk = r.blk0 + n;
             if (blk < r.B) {
                 float *dst = r.out + blk * 64 + 4 * g;
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    st4(dst + 16 * t, acc[t]);
+                for (int t = 0; t < 4; ++t) {
+                    if (NT)
+                        st4_nt(dst + 16 * t, acc[t]);
+                    else
+                        st4(dst + 16 * t, acc[t]);
+                }
             }
         }
     };
 
-    int j = find_job(a.jobs8, a.njobs8, u_begin);
-    UnitRef rc = resolve(a.jobs8, a.njobs8, j, u_begin, kUnitBlocks8);
-    float4 cur[kU8][4], nxt[kU8][4];
+    JobCursor jc;
+    int64_t unit = first;
+    jc.start(a.jobs8, job_begin, job_end, unit);
+    UnitRef rc = jc.at(unit, kUnitBlocks8);
+    float4 cur[4], nxt[4];
     load_unit(cur, rc);
-    for (int64_t u = u_begin + 1; u < u_end; ++u) {
-        const UnitRef rn = resolve(a.jobs8, a.njobs8, j, u, kUnitBlocks8);
+    for (int64_t k = 1; k < my_units; ++k) {
+        unit += stride;
+        const UnitRef rn = jc.at(unit, kUnitBlocks8);
         load_unit(nxt, rn);
         compute_store(cur, rc);
 #pragma unroll
-        for (int q = 0; q < kU8; ++q)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                cur[q][i] = nxt[q][i];
+        for (int i = 0; i < 4; ++i)
+            cur[i] = nxt[i];
         rc = rn;
     }
     compute_store(cur, rc);
 }
 
-template <int PREC>
-__device__ void worker16(const BatchArgs &a, int64_t wg, int64_t ngroups, char *smem)
+template <int PREC, int D>
+__device__ void worker16(const BatchArgs &a, int64_t wg, char *smem)
 {
-    const int64_t t_begin = wg * a.units16 / ngroups;
-    const int64_t t_end = (wg + 1) * a.units16 / ngroups;
-    if (t_begin >= t_end)
+    if (wg >= a.workers16)
         return;   // uniform over the workgroup
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = lane & 15, g = lane >> 4;
+    const SegDesc &sg = a.segs16[find_segment(a.segs16, a.nsegs16, wg)];
+    const int64_t first = sg.unit_begin + (wg - sg.worker_begin);
+    if (first >= sg.unit_end)
+        return;
+    const int64_t stride = sg.nworkers;
+    const int64_t count = (sg.unit_end - first + stride - 1) / stride;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
     Regs R;
-    int loaded_op = -1;
-
-    constexpr int kF32 = 16 * kLd16F32;
-    constexpr int kB16 = 16 * kLd16BF16;
-    float *lf = reinterpret_cast<float *>(smem);
-    uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
-    uint16_t *llo = lhi + 2 * kB16;
-    float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
-
-    auto stage = [&](Stage16 &S, const UnitRef &r) {
-        stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid);
-    };
-    auto put = [&](const Stage16 &S, int buf) {
+    JobCursor jc;
+    jc.start(a.jobs16, sg.job_begin, sg.job_end, first);
+    auto ref = [&](int64_t t) { return jc.at(first + t * stride, kUnitBlocks16); };
+    auto op_load = [&](int op) {
+        const OpDesc &o = a.ops[op];
         if constexpr (PREC == DCTF_PREC_FP32)
-            stage16_store(S, lf + buf * kF32, tid);
+            load_op16(R, o.frag32, o.h0, wave, lane);
         else
-            stage16_store(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, tid);
+            load_op16(R, o.frag_hi, o.frag_lo, o.frag_lf, wave, lane);
     };
-
-    int j = find_job(a.jobs16, a.njobs16, t_begin);
-    UnitRef rc = resolve(a.jobs16, a.njobs16, j, t_begin, kUnitBlocks16);
-    Stage16 S;
-    stage(S, rc);
-    put(S, 0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t t = t_begin;; ++t) {
-        const bool more = t + 1 < t_end;
-        UnitRef rn = rc;
-        if (more) {
-            rn = resolve(a.jobs16, a.njobs16, j, t + 1, kUnitBlocks16);
-            stage(S, rn);
-        }
-        if (rc.op != loaded_op) {
-            const OpDesc &o = a.ops[rc.op];
-            if constexpr (PREC == DCTF_PREC_FP32)
-                load_op16(R, o.frag32, o.h0, wave, lane);
-            else
-                load_op16(R, o.frag_hi, o.frag_lo, o.frag_lf, wave, lane);
-            loaded_op = rc.op;
-        }
-        f32x4 acc[2];
-        if constexpr (PREC == DCTF_PREC_FP32)
-            tile16(R, lf + buf * kF32, lane, acc);
-        else
-            tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
-        const int64_t blk = rc.blk0 + n;
-        if (blk < rc.B) {
-            float *dst = rc.out + blk * 256 + 32 * wave + 4 * g;
-            st4(dst, acc[0]);
-            st4(dst + 16, acc[1]);
-        }
-        if (!more)
-            break;
-        put(S, buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-        rc = rn;
-    }
+    run_tiles16<PREC, D, UnitRef>(count, ref, op_load, R, smem);
 }
 
-template <int PREC>
+template <int PREC, int IO, bool NT>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
 {
-    constexpr int kBytes = PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32 : 2 * kTile16BytesSplit;
+    // N = 16 workgroups use the LDS for their double-buffered tiles, N = 8
+    // workgroups for the per-wave staging of the coalesced I/O.
+    constexpr int k16 = PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32 : 2 * kTile16BytesSplit;
+    constexpr int k8 = IO ? (kBatchThreads / 64) * 256 * 16 : 0;
+    constexpr int kBytes = k16 > k8 ? k16 : k8;
     __shared__ __attribute__((aligned(16))) char smem[kBytes];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if ((int)blockIdx.x < a.groups8) {
-        const int64_t nw = (int64_t)a.groups8 * (kBatchThreads / 64);
-        worker8<PREC>(a, (int64_t)blockIdx.x * (kBatchThreads / 64) + wave, nw, lane);
+        float4 *lds = reinterpret_cast<float4 *>(smem) + (IO ? wave * 256 : 0);
+        worker8<PREC, IO, NT>(a, (int64_t)blockIdx.x * (kBatchThreads / 64) + wave, lane, lds);
     } else {
-        worker16<PREC>(a, (int64_t)blockIdx.x - a.groups8, a.groups16, smem);
+        worker16<PREC, kBatchDepth16>(a, (int64_t)blockIdx.x - a.groups8, smem);
     }
+}
+
+// Batches of one block size run a kernel holding only that worker, so the
+// register allocation and schedule are those of the worker alone.
+template <int PREC, int IO, bool NT>
+__global__ __launch_bounds__(kBatch8Threads) void k_batch8(BatchArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float4 lds_all[IO ? (kBatch8Threads / 64) * 256 : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    worker8<PREC, IO, NT>(a, (int64_t)blockIdx.x * (kBatch8Threads / 64) + wave, lane, lds_all + (IO ? wave * 256 : 0));
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBatchThreads) void k_batch16(BatchArgs a)
+{
+    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32
+                                                                             : 2 * kTile16BytesSplit];
+    worker16<PREC, kBatchDepth16>(a, blockIdx.x, smem);
+}
+
+template <int PREC, int IO, bool NT>
+hipError_t launch_batch_t(const BatchArgs &a, hipStream_t stream)
+{
+    if (a.groups16 == 0)
+        hipLaunchKernelGGL((k_batch8<PREC, IO, NT>), dim3(a.groups8), dim3(kBatch8Threads), 0, stream, a);
+    else if (a.groups8 == 0)
+        hipLaunchKernelGGL((k_batch16<PREC>), dim3(a.groups16), dim3(kBatchThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_batch<PREC, IO, NT>), dim3(a.groups8 + a.groups16), dim3(kBatchThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename K>
+int occ(K kernel, int threads)
+{
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+template <int PREC, int IO, bool NT>
+int occupancy_t(int kind)
+{
+    if (kind == 8)
+        return occ(k_batch8<PREC, IO, NT>, kBatch8Threads);
+    if (kind == 16)
+        return occ(k_batch16<PREC>, kBatchThreads);
+    return occ(k_batch<PREC, IO, NT>, kBatchThreads);
 }
 
 }  // namespace
@@ -211,24 +272,24 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t stream)
     const int groups = a.groups8 + a.groups16;
     if (groups <= 0)
         return hipSuccess;
-    if (a.prec == DCTF_PREC_FP32)
-        hipLaunchKernelGGL(k_batch<DCTF_PREC_FP32>, dim3(groups), dim3(kBatchThreads), 0, stream, a);
-    else
-        hipLaunchKernelGGL(k_batch<DCTF_PREC_SPLIT_BF16>, dim3(groups), dim3(kBatchThreads), 0, stream, a);
-    return hipGetLastError();
+    const bool f32 = a.prec == DCTF_PREC_FP32;
+    switch (a.io * 2 + (a.nt ? 1 : 0)) {
+    case 0: return f32 ? launch_batch_t<DCTF_PREC_FP32, 0, false>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 0, false>(a, stream);
+    case 1: return f32 ? launch_batch_t<DCTF_PREC_FP32, 0, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 0, true>(a, stream);
+    case 2: return f32 ? launch_batch_t<DCTF_PREC_FP32, 1, false>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 1, false>(a, stream);
+    default: return f32 ? launch_batch_t<DCTF_PREC_FP32, 1, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 1, true>(a, stream);
+    }
 }
 
-}  // namespace dctf
-
-namespace dctf {
-
-int batch_occupancy(int prec)
+int batch_occupancy(int prec, int io, bool nt, int kind)
 {
-    int nb = 0;
-    hipError_t e = (prec == DCTF_PREC_FP32)
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<DCTF_PREC_FP32>, kBatchThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<DCTF_PREC_SPLIT_BF16>, kBatchThreads, 0);
-    return (e == hipSuccess && nb > 0) ? nb : 1;
+    const bool f32 = prec == DCTF_PREC_FP32;
+    switch (io * 2 + (nt ? 1 : 0)) {
+    case 0: return f32 ? occupancy_t<DCTF_PREC_FP32, 0, false>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 0, false>(kind);
+    case 1: return f32 ? occupancy_t<DCTF_PREC_FP32, 0, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 0, true>(kind);
+    case 2: return f32 ? occupancy_t<DCTF_PREC_FP32, 1, false>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 1, false>(kind);
+    default: return f32 ? occupancy_t<DCTF_PREC_FP32, 1, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 1, true>(kind);
+    }
 }
 
 }  // namespace dctf

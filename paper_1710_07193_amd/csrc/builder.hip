@@ -17,9 +17,11 @@
 //
 // The sum over q is taken first: G_p[j][l] = sum_q W[p][q] C[l][s_q(j)],
 // B_p = C G_p (so B_p[v][l] = sum_q W[p][q] T_q[v][l]); then
-// H += T_p (x) B_p for each mask row p.  Everything is FP64.  One workgroup
-// owns 16 rows of H (all N^2 columns) for one operator and writes every image
-// of those rows: FP64, FP32, the MFMA fragments and the DC column.
+// H += T_p (x) B_p for each mask row p.  Mask rows are processed in chunks
+// that fit in LDS (all rows at once for the usual mask sizes), three barriers
+// per chunk.  Everything is FP64.  One workgroup owns 16 rows of H (all N^2
+// columns) for one operator and writes every image of those rows: FP64,
+// FP32, the MFMA fragments and the DC column.
 //
 // Fragment layouts (lane = 16 g + m of a 64-lane wave, M-tile t = row / 16,
 // m = row % 16):
@@ -40,14 +42,13 @@ constexpr int kRowsPerGroup = 16;
 constexpr int kMaxN = 16;
 constexpr int kMaxK = 2 * kMaxN + 1;
 
+// Source index of row (or column) i under a shift by d.  The returned index
+// is always inside the block (clamped); in zero mode *valid tells whether the
+// unclamped index was inside (otherwise the term is zero).
 __device__ inline int src_index(int i, int d, int N, int border, bool *valid)
 {
-    int m = i + d;
-    if (border == DCTF_BORDER_ZERO) {
-        *valid = (m >= 0 && m < N);
-        return m;
-    }
-    *valid = true;
+    const int m = i + d;
+    *valid = (border != DCTF_BORDER_ZERO) || (m >= 0 && m < N);
     return m < 0 ? 0 : (m >= N ? N - 1 : m);
 }
 
@@ -90,102 +91,110 @@ __device__ inline int frag16_index(int N, int r, int c)
     return ((t * 8 + s) * 64 + 16 * g + m) * 8 + e8;
 }
 
-__global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
-{
-    const int op = blockIdx.y;
-    if (op >= args.n)
-        return;
-    const BuildDesc &d = args.d[op];
-    const int N = d.N, NN = N * N, kh = d.kh, kw = d.kw, border = d.border;
-    const int rows_per_group = NN < kRowsPerGroup ? NN : kRowsPerGroup;
-    const int r0 = blockIdx.x * rows_per_group;
-    if (r0 >= NN)
-        return;
+// LDS budget for the per-chunk matrices: T_p, G_p and B_p (3 N x N FP64
+// each) for up to kChunk(N) mask rows at once.
+template <int N>
+constexpr int chunk_rows() { return N >= 16 ? 8 : (N == 8 ? 17 : 33); }
 
-    __shared__ double sC[kMaxN * kMaxN];
-    __shared__ double sT[kMaxN * kMaxN];   // T_p for the current mask row
-    __shared__ double sG[kMaxN * kMaxN];   // G_p
-    __shared__ double sB[kMaxN * kMaxN];   // B_p = C G_p
-    __shared__ double sW[kMaxK * kMaxK];
+template <int N>
+__device__ void build_op(const BuildDesc &d, int r0, double *lds)
+{
+    constexpr int NN = N * N;
+    constexpr int P = chunk_rows<N>();
+    constexpr int rows = NN < kRowsPerGroup ? NN : kRowsPerGroup;   // H rows of this group
+    constexpr int owned = rows * NN;                                 // H entries of this group
+    constexpr int per_thread = (owned + kThreads - 1) / kThreads;
+    const int kh = d.kh, kw = d.kw, border = d.border;
+    const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+
+    double *sC = lds;                 // NN
+    double *sW = sC + NN;             // kh * kw (<= 33 * 33)
+    double *sT = sW + kMaxK * kMaxK;  // P * NN
+    double *sG = sT + P * NN;         // P * NN
+    double *sB = sG + P * NN;         // P * NN
 
     const int tid = threadIdx.x;
     for (int e = tid; e < NN; e += kThreads) {
-        int k = e / N, n = e % N;
-        double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
+        const int k = e / N, n = e % N;
+        const double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
         sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N));
     }
     for (int e = tid; e < kh * kw; e += kThreads)
         sW[e] = d.img.mask[e];
 
-    // Entries of H owned by this thread: rows [r0, r0 + rows), all columns.
-    const int owned = rows_per_group * NN;       // <= 16 * 256
-    constexpr int kMaxOwned = kRowsPerGroup * kMaxN * kMaxN / kThreads;  // 16
-    double acc[kMaxOwned];
+    double acc[per_thread];
 #pragma unroll
-    for (int o = 0; o < kMaxOwned; ++o)
+    for (int o = 0; o < per_thread; ++o)
         acc[o] = 0.0;
-
-    const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
     __syncthreads();
 
-    for (int p = 0; p < kh; ++p) {
-        const int dp = p - ah;
-        for (int e = tid; e < NN; e += kThreads) {
-            // T_p[u][k] = sum_i C[u][i] C[k][s_dp(i)]
-            int u = e / N, k = e % N;
+    for (int p0 = 0; p0 < kh; p0 += P) {
+        const int np = kh - p0 < P ? kh - p0 : P;
+        // T_p[u][k] = sum_i C[u][i] C[k][s_{p-ah}(i)];  G_p[j][l] = sum_q W[p][q] C[l][s_{q-aw}(j)]
+        for (int e = tid; e < 2 * np * NN; e += kThreads) {
+            const int which = e / (np * NN), rest = e % (np * NN);
+            const int pp = rest / NN, idx = rest % NN;
+            const int a = idx / N, b = idx % N;
             double s = 0.0;
-            for (int i = 0; i < N; ++i) {
-                bool ok;
-                int m = src_index(i, dp, N, border, &ok);
-                if (ok)
-                    s += sC[u * N + i] * sC[k * N + m];
+            if (which == 0) {
+                const int dp = p0 + pp - ah;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    bool ok;
+                    const int m = src_index(i, dp, N, border, &ok);
+                    s += ok ? sC[a * N + i] * sC[b * N + m] : 0.0;
+                }
+                sT[pp * NN + idx] = s;
+            } else {
+                const double *w = sW + (p0 + pp) * kw;
+                for (int q = 0; q < kw; ++q) {
+                    bool ok;
+                    const int m = src_index(a, q - aw, N, border, &ok);
+                    s += ok ? w[q] * sC[b * N + m] : 0.0;
+                }
+                sG[pp * NN + idx] = s;
             }
-            sT[e] = s;
-            // G_p[j][l] = sum_q W[p][q] C[l][s_dq(j)]
-            int j = e / N, l = e % N;
-            double g = 0.0;
-            for (int q = 0; q < kw; ++q) {
-                bool ok;
-                int m = src_index(j, q - aw, N, border, &ok);
-                if (ok)
-                    g += sW[p * kw + q] * sC[l * N + m];
-            }
-            sG[e] = g;
         }
         __syncthreads();
-        for (int e = tid; e < NN; e += kThreads) {
-            int v = e / N, l = e % N;
+        // B_p[v][l] = sum_j C[v][j] G_p[j][l]
+        for (int e = tid; e < np * NN; e += kThreads) {
+            const int pp = e / NN, idx = e % NN, v = idx / N, l = idx % N;
             double s = 0.0;
+#pragma unroll
             for (int j = 0; j < N; ++j)
-                s += sC[v * N + j] * sG[j * N + l];
+                s += sC[v * N + j] * sG[pp * NN + j * N + l];
             sB[e] = s;
         }
         __syncthreads();
+        // H[(u,v),(k,l)] += sum_p T_p[u][k] B_p[v][l]
 #pragma unroll
-        for (int o = 0; o < kMaxOwned; ++o) {
-            int e = tid + o * kThreads;
+        for (int o = 0; o < per_thread; ++o) {
+            const int e = tid + o * kThreads;
             if (e < owned) {
-                int r = r0 + e / NN, c = e % NN;
-                int u = r / N, v = r % N, k = c / N, l = c % N;
-                acc[o] += sT[u * N + k] * sB[v * N + l];
+                const int r = r0 + e / NN, c = e % NN;
+                const int u = r / N, v = r % N, k = c / N, l = c % N;
+                double s = acc[o];
+                for (int pp = 0; pp < np; ++pp)
+                    s += sT[pp * NN + u * N + k] * sB[pp * NN + v * N + l];
+                acc[o] = s;
             }
         }
         __syncthreads();
     }
 
 #pragma unroll
-    for (int o = 0; o < kMaxOwned; ++o) {
-        int e = tid + o * kThreads;
+    for (int o = 0; o < per_thread; ++o) {
+        const int e = tid + o * kThreads;
         if (e >= owned)
             continue;
-        int r = r0 + e / NN, c = e % NN;
-        double h = acc[o];
-        float h32 = __double2float_rn(h);
+        const int r = r0 + e / NN, c = e % NN;
+        const double h = acc[o];
+        const float h32 = __double2float_rn(h);
         d.img.H64[(size_t)r * NN + c] = h;
         d.img.H32[(size_t)r * NN + c] = h32;
         if (c == 0)
             d.img.h0[r] = h32;
-        if (N >= 8) {
+        if constexpr (N >= 8) {
             // FP32 MFMA image: the operator without its DC column, which the
             // FP32 filter applies separately in VALU arithmetic.
             d.img.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
@@ -205,6 +214,29 @@ __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
             d.img.frag_hi[fi] = hi;
             d.img.frag_lo[fi] = lo;
         }
+    }
+}
+
+constexpr int lds_doubles(int N) { return N * N + kMaxK * kMaxK + 3 * (N >= 16 ? 8 : (N == 8 ? 17 : 33)) * N * N; }
+constexpr int kLdsDoubles = lds_doubles(16) > lds_doubles(8) ? lds_doubles(16) : lds_doubles(8);
+
+__global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
+{
+    const int op = blockIdx.y;
+    if (op >= args.n)
+        return;
+    const BuildDesc &d = args.d[op];
+    const int NN = d.N * d.N;
+    const int rows_per_group = NN < kRowsPerGroup ? NN : kRowsPerGroup;
+    const int r0 = blockIdx.x * rows_per_group;
+    if (r0 >= NN)
+        return;
+    __shared__ double lds[kLdsDoubles];
+    switch (d.N) {
+    case 2: build_op<2>(d, r0, lds); break;
+    case 4: build_op<4>(d, r0, lds); break;
+    case 8: build_op<8>(d, r0, lds); break;
+    default: build_op<16>(d, r0, lds); break;
     }
 }
 

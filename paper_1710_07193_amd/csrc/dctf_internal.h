@@ -105,24 +105,48 @@ struct OpDesc {
     const float *h0;
 };
 
+// A front: a run of consecutive jobs of one class and the workers that share
+// its units: workers [worker_begin, worker_begin + nworkers).
+struct SegDesc {
+    int64_t unit_begin, unit_end;
+    int64_t worker_begin, nworkers;
+    int job_begin, job_end;   // [job_begin, job_end) in the class's job table
+    int op;                   // operator of the first job
+};
+
 struct BatchArgs {
     const JobDesc *jobs8;    // N = 8 jobs, units of kUnitBlocks8 blocks
-    int njobs8;
-    int64_t units8;
+    const SegDesc *segs8;
+    int nsegs8;
+    int64_t workers8;        // waves with N = 8 work (<= 8 * groups8)
     const JobDesc *jobs16;   // N = 16 jobs, units of 16 blocks
-    int njobs16;
-    int64_t units16;
+    const SegDesc *segs16;
+    int nsegs16;
+    int64_t workers16;       // workgroups with N = 16 work (<= groups16)
     const OpDesc *ops;
     int groups8;             // workgroups [0, groups8) take N = 8 work
     int groups16;            // workgroups [groups8, groups8 + groups16) take N = 16 work
     int prec;
+    int io;                  // N = 8 I/O: 0 registers, 1 coalesced through LDS
+    bool nt;                 // N = 8: nontemporal global accesses
 };
 
-constexpr int kBatchThreads = 512;
-constexpr int kUnitBlocks8 = 32;    // blocks per N = 8 work unit (two 16-block MFMA tiles)
+// Sweep fronts for N = 8 batch work (process-wide setting, read at plan creation).
+int batch_fronts();
+void set_batch_fronts(int fronts);
+
+constexpr int kBatchThreads = 512;    // mixed and N = 16 batch workgroups
+constexpr int kBatch8Threads = 256;   // N = 8-only batch workgroups
+constexpr int kUnitBlocks8 = 16;    // blocks per N = 8 work unit (one MFMA tile)
 constexpr int kUnitBlocks16 = 16;   // blocks per N = 16 work unit
+constexpr int kBatchDepth16 = 3;    // N = 16 tiles of loads in flight
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t stream);
+// Workgroups per CU of the batch kernel for kind 8 (N = 8 only), 16 (N = 16
+// only) or 0 (mixed).
+int batch_occupancy(int prec, int io, bool nt, int kind);
+// I/O mode of the current N = 8 variant (used by the batch kernel's N = 8 work).
+void variant_io(int N, int prec, int variant, int *io, bool *nt);
 
 // verify.hip
 hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
@@ -130,6 +154,7 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
                                  hipStream_t stream);
 hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
                                  float *coeffs, hipStream_t stream);
+hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_t stream);
 
 // Device properties cached per device.
 int cu_count();

@@ -16,14 +16,19 @@ namespace {
 
 // ---------------------------------------------------------------- N = 8
 
-template <int U, int PREC, bool NT>
+// IO = 0: registers in MFMA layout (each load / store instruction covers 64
+//         contiguous bytes of 16 blocks);
+// IO = 1: coalesced 1 KiB accesses staged through a wave-private LDS region.
+template <int U, int PREC, bool NT, int IO>
 __global__ __launch_bounds__(256) void k_filter_n8(FilterArgs a, int64_t units, int64_t waves)
 {
+    __shared__ __attribute__((aligned(16))) float4 lds_all[IO ? 4 * U * 256 : 1];
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, g = lane >> 4;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= waves)   // waves <= units
         return;
+    float4 *lds = lds_all + (IO ? (threadIdx.x >> 6) * U * 256 : 0);
 
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8BF16>::type Regs;
     Regs R;
@@ -39,28 +44,40 @@ __global__ __launch_bounds__(256) void k_filter_n8(FilterArgs a, int64_t units, 
     auto load_unit = [&](float4 (&x)[U][4], int64_t unit) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            int64_t blk = unit * (16 * U) + 16 * u + n;
-            blk = blk < B ? blk : B - 1;   // clamped: the store below is masked
-            const float *src = a.in + blk * 64 + 4 * g;
+            const int64_t blk0 = unit * (16 * U) + 16 * u;
+            if constexpr (IO == 1) {
+                const int64_t nv = B - blk0;   // >= 1 for u = 0; clamp for empty tiles
+                load_tile_coalesced<NT>(x[u], a.in + (nv > 0 ? blk0 : B - 1) * 64, nv > 0 ? nv : 1, lane);
+            } else {
+                int64_t blk = blk0 + n;
+                blk = blk < B ? blk : B - 1;   // clamped: the store below is masked
+                const float *src = a.in + blk * 64 + 4 * g;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                x[u][i] = NT ? ld4_nt(src + 16 * i) : ld4(src + 16 * i);
+                for (int i = 0; i < 4; ++i)
+                    x[u][i] = NT ? ld4_nt(src + 16 * i) : ld4(src + 16 * i);
+            }
         }
     };
     auto compute_store = [&](float4 (&x)[U][4], int64_t unit) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            f32x4 acc[4];
-            tile8(R, x[u], lane, acc);
-            const int64_t blk = unit * (16 * U) + 16 * u + n;
-            if (blk < B) {
-                float *dst = a.out + blk * 64 + 4 * g;
+            const int64_t blk0 = unit * (16 * U) + 16 * u;
+            if constexpr (IO == 1) {
+                if (blk0 < B)
+                    tile8_coalesced<NT>(R, x[u], lds + u * 256, a.out + blk0 * 64, B - blk0, lane);
+            } else {
+                f32x4 acc[4];
+                tile8(R, x[u], lane, acc);
+                const int64_t blk = blk0 + n;
+                if (blk < B) {
+                    float *dst = a.out + blk * 64 + 4 * g;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (NT)
-                        st4_nt(dst + 16 * t, acc[t]);
-                    else
-                        st4(dst + 16 * t, acc[t]);
+                    for (int t = 0; t < 4; ++t) {
+                        if (NT)
+                            st4_nt(dst + 16 * t, acc[t]);
+                        else
+                            st4(dst + 16 * t, acc[t]);
+                    }
                 }
             }
         }
@@ -84,69 +101,45 @@ __global__ __launch_bounds__(256) void k_filter_n8(FilterArgs a, int64_t units, 
 
 // ---------------------------------------------------------------- N = 16
 
-template <int PREC>
+struct Ref16 {
+    const float *in;
+    float *out;
+    int64_t B;
+    int64_t blk0;
+    int op;
+};
+
+// Workgroup w takes tiles w, w + G, w + 2G, ... (G = grid size); loads run D
+// tiles ahead.
+template <int PREC, int D>
 __global__ __launch_bounds__(512) void k_filter_n16(FilterArgs a, int64_t tiles)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int n = lane & 15, g = lane >> 4;
-    const int64_t B = a.B;
-    if ((int64_t)blockIdx.x >= tiles)
+    const int64_t wg = blockIdx.x, G = gridDim.x;
+    if (wg >= tiles)
         return;
-
-    typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
-    Regs R;
-    if constexpr (PREC == DCTF_PREC_FP32)
-        load_op16(R, a.frag32, a.h0, wave, lane);
-    else
-        load_op16(R, a.frag_hi, a.frag_lo, a.frag_lf, wave, lane);
-
-    constexpr int kF32 = 16 * kLd16F32;           // floats per FP32 buffer
-    constexpr int kB16 = 16 * kLd16BF16;          // BF16 per hi (or lo) buffer
     __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32
                                                                              : 2 * kTile16BytesSplit];
-    float *lf = reinterpret_cast<float *>(smem);
-    uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
-    uint16_t *llo = lhi + 2 * kB16;
-    float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
-
-    const int64_t step = gridDim.x;
-    int64_t tile = blockIdx.x;
-    Stage16 S;
-    stage16_load(S, a.in, B, tile, tid);
-    if constexpr (PREC == DCTF_PREC_FP32)
-        stage16_store(S, lf, tid);
-    else
-        stage16_store(S, lhi, llo, llf, tid);
-    __syncthreads();
-
-    int buf = 0;
-    for (;;) {
-        const int64_t next = tile + step;
-        const bool more = next < tiles;
-        if (more)
-            stage16_load(S, a.in, B, next, tid);
-        f32x4 acc[2];
+    typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
+    Regs R;
+    const int64_t count = (tiles - wg + G - 1) / G;
+    auto ref = [&](int64_t t) {
+        Ref16 r;
+        r.in = a.in;
+        r.out = a.out;
+        r.B = a.B;
+        r.blk0 = (wg + t * G) * 16;
+        r.op = 0;
+        return r;
+    };
+    auto op_load = [&](int) {
         if constexpr (PREC == DCTF_PREC_FP32)
-            tile16(R, lf + buf * kF32, lane, acc);
+            load_op16(R, a.frag32, a.h0, wave, lane);
         else
-            tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
-        const int64_t blk = tile * 16 + n;
-        if (blk < B) {
-            float *dst = a.out + blk * 256 + 32 * wave + 4 * g;
-            st4(dst, acc[0]);
-            st4(dst + 16, acc[1]);
-        }
-        if (!more)
-            break;
-        if constexpr (PREC == DCTF_PREC_FP32)
-            stage16_store(S, lf + (buf ^ 1) * kF32, tid);
-        else
-            stage16_store(S, lhi + (buf ^ 1) * kB16, llo + (buf ^ 1) * kB16, llf + (buf ^ 1) * 16 * kLd16Lf, tid);
-        __syncthreads();
-        buf ^= 1;
-        tile = next;
-    }
+            load_op16(R, a.frag_hi, a.frag_lo, a.frag_lf, wave, lane);
+    };
+    run_tiles16<PREC, D, Ref16>(count, ref, op_load, R, smem);
 }
 
 // ---------------------------------------------------------------- N <= 4
@@ -186,51 +179,81 @@ __global__ __launch_bounds__(256) void k_filter_small(FilterArgs a, int N)
 struct Variant8 {
     int U;
     bool nt;
+    int io;             // 0: registers, 1: coalesced through LDS
     int waves_per_cu;   // persistent grid: CUs * waves_per_cu waves
     const char *name;
 };
 
 const Variant8 kVariants8[] = {
-    {2, false, 8, "u2_w8"},
-    {1, false, 8, "u1_w8"},
-    {4, false, 4, "u4_w4"},
-    {2, true, 8, "u2_w8_nt"},
-    {1, false, 16, "u1_w16"},
-    {2, false, 16, "u2_w16"},
-    {4, true, 4, "u4_w4_nt"},
+    {1, true, 1, 8, "lds_u1_w8_nt"},
+    {2, true, 1, 8, "lds_u2_w8_nt"},
+    {2, false, 0, 8, "u2_w8"},
+    {1, false, 0, 8, "u1_w8"},
+    {2, false, 0, 16, "u2_w16"},
+    {1, false, 0, 16, "u1_w16"},
+    {4, false, 0, 4, "u4_w4"},
+    {2, false, 1, 8, "lds_u2_w8"},
+    {1, true, 1, 12, "lds_u1_w12_nt"},
+    {2, true, 1, 16, "lds_u2_w16_nt"},
+    {4, true, 1, 8, "lds_u4_w8_nt"},
 };
 constexpr int kNumVariants8 = sizeof(kVariants8) / sizeof(kVariants8[0]);
 
-template <int U, int PREC, bool NT>
+template <int U, int PREC, bool NT, int IO>
 hipError_t run8(const FilterArgs &a, int waves_per_cu, hipStream_t stream)
 {
     const int64_t units = (a.B + 16 * U - 1) / (16 * U);
     int64_t waves = (int64_t)cu_count() * waves_per_cu;
     waves = waves < units ? waves : units;
     const int64_t groups = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_filter_n8<U, PREC, NT>), dim3((unsigned)groups), dim3(256), 0, stream, a,
+    hipLaunchKernelGGL((k_filter_n8<U, PREC, NT, IO>), dim3((unsigned)groups), dim3(256), 0, stream, a,
                        units, waves);
     return hipGetLastError();
+}
+
+template <int U, int PREC>
+hipError_t dispatch8u(const Variant8 &v, const FilterArgs &a, hipStream_t stream)
+{
+    if (v.io)
+        return v.nt ? run8<U, PREC, true, 1>(a, v.waves_per_cu, stream) : run8<U, PREC, false, 1>(a, v.waves_per_cu, stream);
+    return v.nt ? run8<U, PREC, true, 0>(a, v.waves_per_cu, stream) : run8<U, PREC, false, 0>(a, v.waves_per_cu, stream);
 }
 
 template <int PREC>
 hipError_t dispatch8(const Variant8 &v, const FilterArgs &a, hipStream_t stream)
 {
     if (v.U == 1)
-        return v.nt ? run8<1, PREC, true>(a, v.waves_per_cu, stream) : run8<1, PREC, false>(a, v.waves_per_cu, stream);
+        return dispatch8u<1, PREC>(v, a, stream);
     if (v.U == 2)
-        return v.nt ? run8<2, PREC, true>(a, v.waves_per_cu, stream) : run8<2, PREC, false>(a, v.waves_per_cu, stream);
-    return v.nt ? run8<4, PREC, true>(a, v.waves_per_cu, stream) : run8<4, PREC, false>(a, v.waves_per_cu, stream);
+        return dispatch8u<2, PREC>(v, a, stream);
+    return dispatch8u<4, PREC>(v, a, stream);
 }
 
-template <int PREC>
-hipError_t run16(const FilterArgs &a, int groups_per_cu, hipStream_t stream)
+template <int PREC, int D>
+hipError_t run16(const FilterArgs &a, hipStream_t stream)
 {
     const int64_t tiles = (a.B + 15) / 16;
-    int64_t groups = (int64_t)cu_count() * groups_per_cu;
+    int64_t groups = (int64_t)cu_count();
     groups = groups < tiles ? groups : tiles;
-    hipLaunchKernelGGL((k_filter_n16<PREC>), dim3((unsigned)groups), dim3(512), 0, stream, a, tiles);
+    hipLaunchKernelGGL((k_filter_n16<PREC, D>), dim3((unsigned)groups), dim3(512), 0, stream, a, tiles);
     return hipGetLastError();
+}
+
+struct Variant16 {
+    int depth;   // tiles of global loads in flight ahead of the MFMA work
+    const char *name;
+};
+const Variant16 kVariants16[] = {{3, "wg8_ahead3"}, {2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
+constexpr int kNumVariants16 = sizeof(kVariants16) / sizeof(kVariants16[0]);
+
+template <int PREC>
+hipError_t dispatch16(int variant, const FilterArgs &a, hipStream_t stream)
+{
+    switch (kVariants16[(variant >= 0 && variant < kNumVariants16) ? variant : 0].depth) {
+    case 1: return run16<PREC, 1>(a, stream);
+    case 2: return run16<PREC, 2>(a, stream);
+    default: return run16<PREC, 3>(a, stream);
+    }
 }
 
 }  // namespace
@@ -240,6 +263,8 @@ int variant_count(int N, int prec)
     (void)prec;
     if (N == 8)
         return kNumVariants8;
+    if (N == 16)
+        return kNumVariants16;
     return 1;
 }
 
@@ -248,11 +273,27 @@ const char *variant_name(int N, int prec, int v)
     (void)prec;
     if (N == 8 && v >= 0 && v < kNumVariants8)
         return kVariants8[v].name;
-    if (N == 16 && v == 0)
-        return "wg8_lds2";
+    if (N == 16 && v >= 0 && v < kNumVariants16)
+        return kVariants16[v].name;
     if (N <= 4 && v == 0)
         return "valu";
     return nullptr;
+}
+
+void variant_io(int N, int prec, int variant, int *io, bool *nt)
+{
+    (void)prec;
+    *io = 0;
+    *nt = false;
+    if (N == 8 && variant >= 0 && variant < kNumVariants8) {
+        *io = kVariants8[variant].io;
+        *nt = kVariants8[variant].nt;
+    }
+}
+
+int variant_depth16(int variant)
+{
+    return kVariants16[(variant >= 0 && variant < kNumVariants16) ? variant : 0].depth;
 }
 
 int default_variant(int N, int prec)
@@ -276,8 +317,8 @@ hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipS
         return prec == DCTF_PREC_FP32 ? dispatch8<DCTF_PREC_FP32>(v, a, stream)
                                       : dispatch8<DCTF_PREC_SPLIT_BF16>(v, a, stream);
     }
-    return prec == DCTF_PREC_FP32 ? run16<DCTF_PREC_FP32>(a, 1, stream)
-                                  : run16<DCTF_PREC_SPLIT_BF16>(a, 1, stream);
+    return prec == DCTF_PREC_FP32 ? dispatch16<DCTF_PREC_FP32>(variant, a, stream)
+                                  : dispatch16<DCTF_PREC_SPLIT_BF16>(variant, a, stream);
 }
 
 }  // namespace dctf

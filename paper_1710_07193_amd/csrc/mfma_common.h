@@ -202,6 +202,101 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
     }
 }
 
+// ------------------------------------------------- N = 8, coalesced I/O
+//
+// Optional staging of a 16-block tile (4 KiB) through a wave-private LDS
+// region so that every global load and store instruction of the wave covers
+// 1 KiB of contiguous memory (four whole blocks).  Chunk c (16 bytes,
+// coefficients 4c..4c+3) of block b lives in LDS slot b*16 + (c ^ b):
+//   - global side: instruction i, lane l handles block b = 4i + l/16, chunk
+//     (l % 16) ^ b, i.e. LDS slot i*64 + l (a permutation inside the same
+//     1 KiB, so the access stays fully coalesced);
+//   - MFMA side: lane (n, g) reads chunk 4j + g of block n (the register
+//     layout of tile8), slot n*16 + ((4j + g) ^ n): the 16 lanes of a phase
+//     hit 16 different bank groups.
+// LDS accesses of one wave execute in order; wave_lds_sync() only keeps the
+// compiler from moving them across each other.
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool NT>
+__device__ __forceinline__ void load_tile_coalesced(float4 x[4], const float *tile, int64_t nvalid, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int b = 4 * i + (lane >> 4);
+        const int c = (lane & 15) ^ b;
+        const int64_t bb = b < nvalid ? b : nvalid - 1;   // clamped: its result is never stored
+        const float *p = tile + bb * 64 + 4 * c;
+        x[i] = NT ? ld4_nt(p) : ld4(p);
+    }
+}
+
+__device__ __forceinline__ void stage_in(float4 *lds, const float4 x[4], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        lds[i * 64 + lane] = x[i];
+}
+
+__device__ __forceinline__ void read_mfma(const float4 *lds, float4 x[4], int lane)
+{
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        x[j] = lds[n * 16 + ((4 * j + g) ^ n)];
+}
+
+__device__ __forceinline__ void stage_out(float4 *lds, const f32x4 acc[4], int lane)
+{
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        lds[n * 16 + ((4 * t + g) ^ n)] = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+}
+
+template <bool NT>
+__device__ __forceinline__ void store_tile_coalesced(float *tile, int64_t nvalid, const float4 *lds, int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int b = 4 * i + (lane >> 4);
+        const int c = (lane & 15) ^ b;
+        const float4 v = lds[i * 64 + lane];
+        if (b < nvalid) {
+            const f32x4 w = {v.x, v.y, v.z, v.w};
+            if (NT)
+                st4_nt(tile + (int64_t)b * 64 + 4 * c, w);
+            else
+                st4(tile + (int64_t)b * 64 + 4 * c, w);
+        }
+    }
+}
+
+// One 16-block tile through the coalesced path: registers x (coalesced
+// layout) -> LDS -> MFMA -> LDS -> global.
+template <bool NT, typename Regs>
+__device__ __forceinline__ void tile8_coalesced(const Regs &R, const float4 xin[4], float4 *lds, float *tile,
+                                                int64_t nvalid, int lane)
+{
+    stage_in(lds, xin, lane);
+    wave_lds_sync();
+    float4 xm[4];
+    read_mfma(lds, xm, lane);
+    f32x4 acc[4];
+    tile8(R, xm, lane, acc);
+    wave_lds_sync();
+    stage_out(lds, acc, lane);
+    wave_lds_sync();
+    store_tile_coalesced<NT>(tile, nvalid, lds, lane);
+    wave_lds_sync();
+}
+
 // ----------------------------------------------------------------- N = 16
 //
 // Weight-stationary: a workgroup of 8 waves holds the 256 x 256 operator in
@@ -377,6 +472,76 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 #pragma unroll
         for (int t = 0; t < 2; ++t)
             acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
+    }
+}
+
+// ----------------------------------------------- N = 16 tile loop (shared)
+//
+// Runs `count` tiles of one workgroup through the weight-stationary path.
+// Global loads run D tiles ahead of the MFMA work (a ring of D register
+// stages); LDS tiles are double-buffered with one barrier per tile.
+// ref(t) returns the UnitRef-like descriptor of the t-th tile (called in
+// increasing t); op_load(op) loads the operator fragments into R.
+template <int PREC, int D, typename Ref, typename RefFn, typename OpFn, typename Regs>
+__device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    constexpr int kF32 = 16 * kLd16F32;
+    constexpr int kB16 = 16 * kLd16BF16;
+    float *lf = reinterpret_cast<float *>(smem);
+    uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
+    uint16_t *llo = lhi + 2 * kB16;
+    float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
+    auto put = [&](const Stage16 &S, int buf) {
+        if constexpr (PREC == DCTF_PREC_FP32)
+            stage16_store(S, lf + buf * kF32, tid);
+        else
+            stage16_store(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, tid);
+    };
+    auto stage = [&](Stage16 &S, const Ref &r) { stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid); };
+
+    Stage16 S[D];
+    Ref Rf[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (d < count) {
+            Rf[d] = ref(d);
+            stage(S[d], Rf[d]);
+        }
+    put(S[0], 0);
+    __syncthreads();
+    int loaded_op = -1;
+    for (int64_t t0 = 0;; t0 += D) {
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+            const int64_t t = t0 + p;
+            const Ref rc = Rf[p];
+            if (t + D < count) {          // S[p] is free: its tile is in LDS
+                Rf[p] = ref(t + D);
+                stage(S[p], Rf[p]);
+            }
+            if (rc.op != loaded_op) {
+                op_load(rc.op);
+                loaded_op = rc.op;
+            }
+            const int buf = (int)(t & 1);
+            f32x4 acc[2];
+            if constexpr (PREC == DCTF_PREC_FP32)
+                tile16(R, lf + buf * kF32, lane, acc);
+            else
+                tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
+            const int64_t blk = rc.blk0 + n;
+            if (blk < rc.B) {
+                float *dst = rc.out + blk * 256 + 32 * wave + 4 * g;
+                st4(dst, acc[0]);
+                st4(dst + 16, acc[1]);
+            }
+            if (t + 1 >= count)
+                return;
+            put(S[(p + 1) % D], buf ^ 1);
+            __syncthreads();
+        }
     }
 }
 

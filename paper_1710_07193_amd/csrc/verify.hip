@@ -119,7 +119,37 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(int N, const float 
     }
 }
 
+// Plain streaming copy, 4 independent 16-byte loads in flight per thread.
+__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ in, float4 *__restrict__ out,
+                                                     int64_t n4)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = in[i], b = in[i + stride], c = in[i + 2 * stride], d = in[i + 3 * stride];
+        out[i] = a;
+        out[i + stride] = b;
+        out[i + 2 * stride] = c;
+        out[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride)
+        out[i] = in[i];
+}
+
 }  // namespace
+
+hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_t stream)
+{
+    const int64_t n4 = n / 4;
+    int64_t groups = (int64_t)cu_count() * 8;
+    const int64_t need = (n4 + 255) / 256;
+    groups = groups < need ? groups : need;
+    if (groups <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)groups), dim3(256), 0, stream,
+                       reinterpret_cast<const float4 *>(in), reinterpret_cast<float4 *>(out), n4);
+    return hipGetLastError();
+}
 
 hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
                                  float *coeffs, hipStream_t stream)

@@ -114,6 +114,41 @@ def test_batch_only_one_block_size(dctf):
         assert np.array_equal(j["Y"].cpu().numpy(), alone(dctf, j, SPLIT))
 
 
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_batch_many_small_jobs(dctf, prec):
+    """Hundreds of tiny jobs over 24 operators (more segments than usual,
+    ragged tiles everywhere), for every N = 8 I/O variant the batch can use."""
+    rng = np.random.default_rng(77)
+    specs = [(syn.random_mask(rng, k, k), N, b) for N in (8, 16) for k in (3, 5, 7) for b in (Z, R)
+             for _ in range(2)]
+    ops = dctf.dctf_build_operators(specs)
+    jobs = []
+    for i in range(300):
+        op = ops[int(rng.integers(0, len(ops)))]
+        B = int(rng.integers(1, 60))
+        X = torch.randn(B * op.N * op.N, device="cuda") * 100
+        jobs.append((op, X, torch.empty_like(X)))
+    want = []
+    for op, X, _ in jobs:
+        Y = torch.empty_like(X)
+        dctf.dctf_filter_blocks(op, prec, X, Y)
+        want.append(Y)
+    fronts0 = dctf.dctf_get_batch_fronts()
+    for order in (0, 1, 3):
+        dctf.dctf_set_batch_fronts(order)
+        for v in range(dctf.dctf_variant_count(8, prec)):
+            dctf.dctf_set_variant(8, prec, v)
+            try:
+                for _, _, Y in jobs:
+                    Y.fill_(float("nan"))
+                dctf.dctf_filter_batch(jobs, prec)
+                for (op, X, Y), w in zip(jobs, want):
+                    assert torch.equal(Y, w), (order, dctf.dctf_variant_name(8, prec, v))
+            finally:
+                dctf.dctf_set_variant(8, prec, 0)
+                dctf.dctf_set_batch_fronts(fronts0)
+
+
 def test_batch_rejections(dctf):
     jobs = make_jobs(dctf, seed=4)
     a, b = jobs[0], jobs[1]

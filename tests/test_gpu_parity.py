@@ -175,14 +175,13 @@ def test_ragged_counts_are_prefix_identical(dctf, N, prec):
     assert np.abs(full - Yref).max() <= TOL[prec]
     for B in (1, 15, 16, 17, 31, 32, 33, 63, 100, 255):
         assert np.array_equal(gpu_filter(dctf, op, X[:B], prec), full[:B]), B
-    if N == 8:
-        for v in range(dctf.dctf_variant_count(8, prec)):
-            dctf.dctf_set_variant(8, prec, v)
-            try:
-                assert np.array_equal(gpu_filter(dctf, op, X, prec), full), dctf.dctf_variant_name(8, prec, v)
-                assert np.array_equal(gpu_filter(dctf, op, X[:33], prec), full[:33])
-            finally:
-                dctf.dctf_set_variant(8, prec, 0)
+    for v in range(dctf.dctf_variant_count(N, prec)):
+        dctf.dctf_set_variant(N, prec, v)
+        try:
+            assert np.array_equal(gpu_filter(dctf, op, X, prec), full), dctf.dctf_variant_name(N, prec, v)
+            assert np.array_equal(gpu_filter(dctf, op, X[:33], prec), full[:33])
+        finally:
+            dctf.dctf_set_variant(N, prec, 0)
 
 
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
