@@ -250,6 +250,62 @@ dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float
                           int64_t B, int iters, dctf_stream stream, int *best_variant,
                           float *best_ms);
 
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching server (not part of the paper's method: the serving
+ * layer around it).  dctf_server_run replays requests in real time on the
+ * calling thread: a request is admitted, in arrival order, once its output
+ * fits in the server's device arena (the HBM budget) and a launch slot is
+ * free; the requests admitted together form one batch (one persistent launch,
+ * operators from a device cache keyed by mask bytes, kh, kw, N and border,
+ * LRU eviction); up to max_inflight batches run at once on their own streams,
+ * so requests that arrive while others are on the GPU overlap with them.
+ * Each request's result equals, bit for bit, a dctf_filter_blocks call with
+ * the same operator and precision.
+ */
+typedef struct dctf_server_s *dctf_server;
+
+typedef struct {
+    int64_t arena_bytes;   /* device memory for request outputs (>= 256) */
+    int max_inflight;      /* batches in flight at once, 1..16 (one stream each) */
+    int max_batch_jobs;    /* requests per batch, 1..4096 */
+    int max_cached_ops;    /* operator cache entries, >= 1 */
+    int prec;              /* dctf_precision */
+} dctf_server_config;
+
+typedef struct {
+    /* set by the caller */
+    double arrival_s;          /* seconds after the start of the run; non-decreasing */
+    const double *mask_host;   /* kh*kw doubles (host) */
+    int kh, kw, N, border;     /* N = 8 or 16 */
+    const float *in_dev;       /* B*N*N coefficients, device-resident, 16-byte aligned */
+    int64_t B;                 /* >= 1 */
+    float *out_dev;            /* NULL: the output is written to the arena and dropped at
+                                  completion; else also copied here (device, 16-byte aligned)
+                                  before the request completes */
+    /* set by dctf_server_run (seconds after the start; -1 if never reached) */
+    double admit_s, launch_s, done_s;
+    int status;                /* DCTF_OK, or DCTF_EBUSY: the output alone exceeds the arena */
+    int batch;                 /* index of the launch that carried it */
+} dctf_request;
+
+typedef struct {
+    int64_t batches, cache_hits, cache_misses, cache_evictions;
+    int64_t peak_arena_bytes, peak_inflight_batches, rejected;
+    double busy_s;             /* wall time spent in dctf_server_run */
+} dctf_server_stats;
+
+/* Errors: DCTF_EINVAL (bad config), DCTF_ENOMEM (arena), DCTF_EHIP. */
+dctf_status dctf_server_create(const dctf_server_config *cfg, dctf_server *out);
+/* Runs until every request has completed or been rejected.  Returns
+ * DCTF_EINVAL for a malformed request list (nothing runs), DCTF_EHIP on a
+ * device error (in-flight work is drained first). */
+dctf_status dctf_server_run(dctf_server s, dctf_request *reqs, int n);
+dctf_status dctf_server_stats_get(dctf_server s, dctf_server_stats *out);
+/* Waits for the server's streams, then frees everything it owns. */
+void dctf_server_destroy(dctf_server s);
+
 /* ------------------------------------------------------------------ misc */
 
 const char *dctf_status_string(dctf_status s);

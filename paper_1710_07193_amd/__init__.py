@@ -40,6 +40,23 @@ class _Job(ctypes.Structure):
     _fields_ = [("op", _P), ("in_", _P), ("out", _P), ("B", _I64)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("arena_bytes", _I64), ("max_inflight", _I), ("max_batch_jobs", _I),
+                ("max_cached_ops", _I), ("prec", _I)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("mask_host", _P), ("kh", _I), ("kw", _I), ("N", _I),
+                ("border", _I), ("in_dev", _P), ("B", _I64), ("out_dev", _P), ("admit_s", ctypes.c_double),
+                ("launch_s", ctypes.c_double), ("done_s", ctypes.c_double), ("status", _I), ("batch", _I)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("batches", _I64), ("cache_hits", _I64), ("cache_misses", _I64), ("cache_evictions", _I64),
+                ("peak_arena_bytes", _I64), ("peak_inflight_batches", _I64), ("rejected", _I64),
+                ("busy_s", ctypes.c_double)]
+
+
 _SIGS = {
     "dctf_build_operator": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
     "dctf_build_operators": ([ctypes.POINTER(_MaskDesc), _I, _P, ctypes.POINTER(_P)], _I),
@@ -65,6 +82,10 @@ _SIGS = {
     "dctf_autotune": ([_P, _I, _P, _P, _I64, _I, _P, _P, _P], _I),
     "dctf_set_batch_fronts": ([_I], _I),
     "dctf_get_batch_fronts": ([], _I),
+    "dctf_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(_P)], _I),
+    "dctf_server_run": ([_P, ctypes.POINTER(_Request), _I], _I),
+    "dctf_server_stats_get": ([_P, ctypes.POINTER(_ServerStats)], _I),
+    "dctf_server_destroy": ([_P], None),
     "dctf_status_string": ([_I], ctypes.c_char_p),
     "dctf_version": ([], ctypes.c_char_p),
     "dctf_timing_enable": ([_I], _I),
@@ -336,6 +357,67 @@ def dctf_set_batch_fronts(fronts: int):
 
 def dctf_get_batch_fronts() -> int:
     return int(_lib.dctf_get_batch_fronts())
+
+
+class Server:
+    """Owning handle of a continuous-batching server."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def _as_parameter_(self):
+        return _P(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            _lib.dctf_server_destroy(_P(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def dctf_server_create(arena_bytes: int, max_inflight: int = 4, max_batch_jobs: int = 64,
+                       max_cached_ops: int = 64, prec: int = DCTF_PREC_SPLIT_BF16) -> Server:
+    cfg = _ServerConfig(arena_bytes, max_inflight, max_batch_jobs, max_cached_ops, prec)
+    h = _P()
+    _check(_lib.dctf_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dctf_server_create")
+    return Server(h.value)
+
+
+def dctf_server_run(server: Server, requests):
+    """``requests``: list of dicts with arrival_s, mask, N, border, X (device
+    float32 tensor, B*N*N elements) and optionally Y (device tensor receiving
+    the output).  Returns a list of dicts with admit_s, launch_s, done_s,
+    status and batch for each request."""
+    arr = (_Request * max(len(requests), 1))()
+    keep = []
+    for i, r in enumerate(requests):
+        m = _mask_array(r["mask"])
+        keep.append(m)
+        N = r["N"]
+        X = r["X"]
+        Y = r.get("Y")
+        if X.numel() % (N * N) or X.numel() == 0:
+            raise ValueError("request %d: X must hold a whole, positive number of N*N blocks" % i)
+        if Y is not None and Y.numel() != X.numel():
+            raise ValueError("request %d: Y has the wrong size" % i)
+        arr[i] = _Request(r["arrival_s"], m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, r["border"],
+                          _dptr(X, torch.float32, "X"), X.numel() // (N * N), _dptr(Y, torch.float32, "Y"),
+                          -1.0, -1.0, -1.0, 0, -1)
+    _check(_lib.dctf_server_run(server, arr, len(requests)), "dctf_server_run")
+    return [dict(admit_s=arr[i].admit_s, launch_s=arr[i].launch_s, done_s=arr[i].done_s,
+                 status=arr[i].status, batch=arr[i].batch) for i in range(len(requests))]
+
+
+def dctf_server_stats(server: Server) -> dict:
+    st = _ServerStats()
+    _check(_lib.dctf_server_stats_get(server, ctypes.byref(st)), "dctf_server_stats_get")
+    return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
 
 
 def dctf_status_string(s: int) -> str:

@@ -370,9 +370,12 @@ bool jobs_conflict(const dctf_job *jobs, int n)
 
 }  // namespace
 
-extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out)
+namespace dctf {
+
+dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<char> &table, BatchArgs &a,
+                       std::vector<dctf_operator> &ops)
 {
-    if (out == nullptr || njobs < 0 || (njobs > 0 && jobs == nullptr))
+    if (njobs < 0 || (njobs > 0 && jobs == nullptr))
         return DCTF_EINVAL;
     if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
         return DCTF_EINVAL;
@@ -389,11 +392,6 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
     if (jobs_conflict(jobs, njobs))
         return DCTF_EINVAL;
 
-    dctf_batch b = new (std::nothrow) dctf_batch_s();
-    if (!b)
-        return DCTF_ENOMEM;
-    b->prec = prec;
-
     // Group by N, then operator (stable in the caller's order otherwise).
     std::vector<int> order;
     for (int i = 0; i < njobs; ++i)
@@ -404,18 +402,18 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
             return jobs[x].op->N < jobs[y].op->N;
         return jobs[x].op < jobs[y].op;
     });
+    ops.clear();
     std::vector<JobDesc> j8, j16;
     std::vector<OpDesc> od;
     int64_t u8 = 0, u16 = 0, blocks8 = 0, blocks16 = 0;
     for (int idx : order) {
         const dctf_job &j = jobs[idx];
         int opi = -1;
-        for (size_t k = 0; k < b->ops.size(); ++k)
-            if (b->ops[k] == j.op)
-                opi = (int)k;
+        if (!ops.empty() && ops.back() == j.op)   // jobs are grouped by operator
+            opi = (int)ops.size() - 1;
         if (opi < 0) {
-            opi = (int)b->ops.size();
-            b->ops.push_back(j.op);
+            opi = (int)ops.size();
+            ops.push_back(j.op);
             od.push_back({j.op->img.frag32, j.op->img.frag_hi, j.op->img.frag_lo, j.op->img.frag_lf,
                           j.op->img.h0});
         }
@@ -438,13 +436,10 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
         }
     }
 
-    BatchArgs &a = b->args;
+    a = BatchArgs{};
     a.prec = prec;
     variant_io(8, prec, current_variant(8, prec), &a.io, &a.nt);
 
-    // Split the persistent grid between the two block sizes in proportion to
-    // their estimated time (bytes for the HBM-bound cases, MFMA work for
-    // N = 16 in FP32).
     // One block size: a kernel holding only that worker, one persistent
     // grid.  Both: the combined kernel, its grid split in proportion to the
     // estimated time (bytes for the HBM-bound cases, MFMA work for N = 16 in
@@ -467,10 +462,10 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
     // Fronts: runs of consecutive jobs (N = 8: `fronts` runs cut at operator
     // boundaries with about equal units; N = 16: one run per operator), with
     // workers in proportion to their units.
-    auto cut = [](const std::vector<JobDesc> &jobs, int64_t units, int64_t workers, int fronts) {
+    auto cut = [](const std::vector<JobDesc> &js, int64_t units, int64_t workers, int fronts) {
         std::vector<size_t> starts;   // first job of each operator segment
-        for (size_t i = 0; i < jobs.size(); ++i)
-            if (i == 0 || jobs[i].op != jobs[i - 1].op)
+        for (size_t i = 0; i < js.size(); ++i)
+            if (i == 0 || js[i].op != js[i - 1].op)
                 starts.push_back(i);
         std::vector<size_t> cuts{0};
         if (fronts > 0) {
@@ -478,7 +473,7 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
                 const int64_t target = units * f / fronts;
                 size_t best = cuts.back();
                 for (size_t st : starts)
-                    if (st > cuts.back() && jobs[st].unit_begin <= target)
+                    if (st > cuts.back() && js[st].unit_begin <= target)
                         best = st;
                 if (best > cuts.back())
                     cuts.push_back(best);
@@ -489,10 +484,10 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
         std::vector<SegDesc> segs;
         int64_t next_worker = 0;
         for (size_t c = 0; c < cuts.size(); ++c) {
-            const size_t i = cuts[c], e = (c + 1 < cuts.size()) ? cuts[c + 1] : jobs.size();
+            const size_t i = cuts[c], e = (c + 1 < cuts.size()) ? cuts[c + 1] : js.size();
             SegDesc sd;
-            sd.unit_begin = jobs[i].unit_begin;
-            sd.unit_end = (e < jobs.size()) ? jobs[e].unit_begin : units;
+            sd.unit_begin = js[i].unit_begin;
+            sd.unit_end = (e < js.size()) ? js[e].unit_begin : units;
             const int64_t su = sd.unit_end - sd.unit_begin;
             int64_t w = (int64_t)std::llround((double)workers * (double)su / (double)units);
             w = std::max<int64_t>(1, std::min(w, su));
@@ -501,7 +496,7 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
             next_worker += w;
             sd.job_begin = (int)i;
             sd.job_end = (int)e;
-            sd.op = jobs[i].op;
+            sd.op = js[i].op;
             segs.push_back(sd);
         }
         return segs;
@@ -512,49 +507,69 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
     const int64_t workers8 = s8.empty() ? 0 : s8.back().worker_begin + s8.back().nworkers;
     const int64_t workers16 = s16.empty() ? 0 : s16.back().worker_begin + s16.back().nworkers;
 
-    const size_t bytes = sizeof(JobDesc) * (j8.size() + j16.size()) + sizeof(SegDesc) * (s8.size() + s16.size()) +
-                         sizeof(OpDesc) * od.size();
-    if (bytes > 0) {
-        hipError_t e = hipMalloc(&b->dev, bytes);
-        if (e != hipSuccess) {
-            delete b;
-            return hip_status(e);
-        }
-        std::vector<char> host(bytes);
-        char *p = host.data();
-        auto put = [&](const void *src, size_t n) {
-            if (n)
-                memcpy(p, src, n);
-            p += n;
-        };
-        put(j8.data(), sizeof(JobDesc) * j8.size());
-        put(j16.data(), sizeof(JobDesc) * j16.size());
-        put(s8.data(), sizeof(SegDesc) * s8.size());
-        put(s16.data(), sizeof(SegDesc) * s16.size());
-        put(od.data(), sizeof(OpDesc) * od.size());
-        e = hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(b->dev);
-            delete b;
-            return hip_status(e);
-        }
-    }
-    char *dp = static_cast<char *>(b->dev);
-    a.jobs8 = reinterpret_cast<const JobDesc *>(dp);
-    dp += sizeof(JobDesc) * j8.size();
-    a.jobs16 = reinterpret_cast<const JobDesc *>(dp);
-    dp += sizeof(JobDesc) * j16.size();
-    a.segs8 = reinterpret_cast<const SegDesc *>(dp);
+    // Table layout: JobDesc[j8] | JobDesc[j16] | SegDesc[s8] | SegDesc[s16] | OpDesc[ops].
+    table.clear();
+    auto put = [&](const void *src, size_t n) -> uintptr_t {
+        const uintptr_t off = table.size();
+        table.resize(off + n);
+        if (n)
+            memcpy(table.data() + off, src, n);
+        return off;
+    };
+    a.jobs8 = reinterpret_cast<const JobDesc *>(put(j8.data(), sizeof(JobDesc) * j8.size()));
+    a.jobs16 = reinterpret_cast<const JobDesc *>(put(j16.data(), sizeof(JobDesc) * j16.size()));
+    a.segs8 = reinterpret_cast<const SegDesc *>(put(s8.data(), sizeof(SegDesc) * s8.size()));
+    a.segs16 = reinterpret_cast<const SegDesc *>(put(s16.data(), sizeof(SegDesc) * s16.size()));
+    a.ops = reinterpret_cast<const OpDesc *>(put(od.data(), sizeof(OpDesc) * od.size()));
     a.nsegs8 = (int)s8.size();
-    dp += sizeof(SegDesc) * s8.size();
-    a.segs16 = reinterpret_cast<const SegDesc *>(dp);
     a.nsegs16 = (int)s16.size();
-    dp += sizeof(SegDesc) * s16.size();
-    a.ops = reinterpret_cast<const OpDesc *>(dp);
     a.workers8 = workers8;
     a.workers16 = workers16;
     a.groups8 = (int)((workers8 + wpg8 - 1) / wpg8);
     a.groups16 = (int)workers16;
+    return DCTF_OK;
+}
+
+void rebase_batch(BatchArgs &a, const void *dev)
+{
+    const uintptr_t base = (uintptr_t)dev;
+    a.jobs8 = reinterpret_cast<const JobDesc *>(base + (uintptr_t)a.jobs8);
+    a.jobs16 = reinterpret_cast<const JobDesc *>(base + (uintptr_t)a.jobs16);
+    a.segs8 = reinterpret_cast<const SegDesc *>(base + (uintptr_t)a.segs8);
+    a.segs16 = reinterpret_cast<const SegDesc *>(base + (uintptr_t)a.segs16);
+    a.ops = reinterpret_cast<const OpDesc *>(base + (uintptr_t)a.ops);
+}
+
+}  // namespace dctf
+
+extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out)
+{
+    if (out == nullptr)
+        return DCTF_EINVAL;
+    std::vector<char> table;
+    BatchArgs a;
+    std::vector<dctf_operator> ops;
+    dctf_status st = plan_batch(jobs, njobs, prec, table, a, ops);
+    if (st != DCTF_OK)
+        return st;
+    dctf_batch b = new (std::nothrow) dctf_batch_s();
+    if (!b)
+        return DCTF_ENOMEM;
+    b->prec = prec;
+    b->ops = ops;
+    if (!table.empty()) {
+        hipError_t e = hipMalloc(&b->dev, table.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(b->dev, table.data(), table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (b->dev)
+                (void)hipFree(b->dev);
+            delete b;
+            return hip_status(e);
+        }
+    }
+    rebase_batch(a, b->dev);
+    b->args = a;
     *out = b;
     return DCTF_OK;
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dctf.h"
 
 namespace dctf {
@@ -145,6 +147,13 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t stream);
 // Workgroups per CU of the batch kernel for kind 8 (N = 8 only), 16 (N = 16
 // only) or 0 (mixed).
 int batch_occupancy(int prec, int io, bool nt, int kind);
+// Batch planning: validates the jobs, groups them, cuts fronts and sizes the
+// grid.  The work table is written to `table`; the pointers in `a` hold
+// offsets into it until rebase_batch() adds the table's device address.
+dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<char> &table, BatchArgs &a,
+                       std::vector<dctf_operator> &ops);
+void rebase_batch(BatchArgs &a, const void *dev);
+
 // I/O mode of the current N = 8 variant (used by the batch kernel's N = 8 work).
 void variant_io(int N, int prec, int variant, int *io, bool *nt);
 

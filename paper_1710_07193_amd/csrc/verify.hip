@@ -119,20 +119,28 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(int N, const float 
     }
 }
 
-// Plain streaming copy, 4 independent 16-byte loads in flight per thread.
-__global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ in, float4 *__restrict__ out,
+// Plain streaming copy: each wave moves 4 KiB per step (4 x 1 KiB contiguous
+// 16-byte-per-lane accesses, nontemporal), waves stride over the buffer.
+typedef float f32x4c __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const f32x4c *__restrict__ in, f32x4c *__restrict__ out,
                                                      int64_t n4)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        const float4 a = in[i], b = in[i + stride], c = in[i + 2 * stride], d = in[i + 3 * stride];
-        out[i] = a;
-        out[i + stride] = b;
-        out[i + 2 * stride] = c;
-        out[i + 3 * stride] = d;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t base = wave * 256;
+    for (; base + 256 <= n4; base += nw * 256) {
+        f32x4c v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = __builtin_nontemporal_load(&in[base + 64 * k + lane]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            __builtin_nontemporal_store(v[k], &out[base + 64 * k + lane]);
     }
-    for (; i < n4; i += stride)
+    // tail (fewer than 256 float4 left for this wave)
+    for (int64_t i = base + lane; i < n4 && i < base + 256; i += 64)
         out[i] = in[i];
 }
 
@@ -141,13 +149,13 @@ __global__ __launch_bounds__(256) void k_stream_copy(const float4 *__restrict__ 
 hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_t stream)
 {
     const int64_t n4 = n / 4;
-    int64_t groups = (int64_t)cu_count() * 8;
-    const int64_t need = (n4 + 255) / 256;
+    int64_t groups = (int64_t)cu_count() * 16;
+    const int64_t need = (n4 + 1023) / 1024;   // 4 waves x 256 float4 per group and step
     groups = groups < need ? groups : need;
     if (groups <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)groups), dim3(256), 0, stream,
-                       reinterpret_cast<const float4 *>(in), reinterpret_cast<float4 *>(out), n4);
+                       reinterpret_cast<const f32x4c *>(in), reinterpret_cast<f32x4c *>(out), n4);
     return hipGetLastError();
 }
 

@@ -112,3 +112,15 @@ def test_variant_table(lib):
     assert dctf.dctf_get_variant(8, 1) == n8 - 1
     dctf.dctf_set_variant(8, 1, 0)
     assert dctf.dctf_get_variant(8, 1) == 0
+
+
+def test_server_config_validation(lib):
+    import paper_1710_07193_amd as dctf
+    out = ctypes.c_void_p()
+    for cfg in [(100, 4, 8, 8, 1), (1 << 20, 0, 8, 8, 1), (1 << 20, 17, 8, 8, 1), (1 << 20, 4, 0, 8, 1),
+                (1 << 20, 4, 8, 0, 1), (1 << 20, 4, 8, 8, 3)]:
+        c = dctf._ServerConfig(*cfg)
+        assert lib.dctf_server_create(ctypes.byref(c), ctypes.byref(out)) == -1, cfg
+    assert lib.dctf_server_create(None, ctypes.byref(out)) == -1
+    assert lib.dctf_server_run(None, None, 0) == -1
+    assert lib.dctf_server_stats_get(None, None) == -1

@@ -1,0 +1,139 @@
+"""GPU tests of the continuous-batching server.
+
+Requests of different sizes, block sizes and masks arrive while others are on
+the GPU; each result must be bit-identical to the same request served alone
+(and to a direct dctf_filter_blocks call), admission must respect the device
+arena, and the operator cache must evict and rebuild correctly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+SPLIT, FP32 = 1, 0
+
+
+@pytest.fixture(scope="module")
+def dctf():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1710_07193_amd as m
+    return m
+
+
+def make_requests(n, seed, rate_hz, masks):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    t = 0.0
+    for i in range(n):
+        N = 16 if rng.random() < 0.25 else 8
+        B = int(rng.integers(1, 3000))
+        spec = masks[int(rng.integers(0, len(masks)))]
+        X = torch.randn(B * N * N, device="cuda") * 60
+        reqs.append(dict(arrival_s=t, mask=spec.mask, N=N, border=spec.border, X=X,
+                         Y=torch.full_like(X, float("nan"))))
+        t += float(rng.exponential(1.0 / rate_hz))
+    return reqs
+
+
+@pytest.mark.parametrize("prec", [SPLIT, FP32])
+def test_same_result_alone_and_in_the_mix(dctf, prec):
+    masks = syn.mask_set_32()[:12]
+    reqs = make_requests(48, 5, 200000.0, masks)        # arrivals ~5 us apart: they overlap
+    server = dctf.dctf_server_create(arena_bytes=1 << 28, max_inflight=4, max_batch_jobs=8, prec=prec)
+    res = dctf.dctf_server_run(server, reqs)
+    torch.cuda.synchronize()
+    assert all(r["status"] == 0 for r in res)
+    stats = dctf.dctf_server_stats(server)
+    assert stats["batches"] >= 2
+    mixed = [r["Y"].clone() for r in reqs]
+    # alone: one request per run
+    for i, r in enumerate(reqs):
+        r["Y"].fill_(float("nan"))
+        one = dict(r, arrival_s=0.0)
+        res1 = dctf.dctf_server_run(server, [one])
+        assert res1[0]["status"] == 0
+        torch.cuda.synchronize()
+        assert torch.equal(r["Y"], mixed[i]), i
+    # and the direct single-operator call
+    for i, r in enumerate(reqs[:10]):
+        op = dctf.dctf_build_operator(r["mask"], r["N"], r["border"])
+        Y = torch.empty_like(r["X"])
+        dctf.dctf_filter_blocks(op, prec, r["X"], Y)
+        torch.cuda.synchronize()
+        assert torch.equal(Y, mixed[i]), i
+    for r in res:
+        assert 0 <= r["admit_s"] <= r["launch_s"] <= r["done_s"]
+
+
+def test_work_overlaps_on_the_device(dctf):
+    masks = syn.mask_set_32()[:4]
+    rng = np.random.default_rng(1)
+    reqs = []
+    for i in range(24):
+        X = torch.randn(40000 * 64, device="cuda")       # 40k blocks: long enough to overlap
+        reqs.append(dict(arrival_s=i * 2e-6, mask=masks[i % 4].mask, N=8, border=masks[i % 4].border, X=X))
+    server = dctf.dctf_server_create(arena_bytes=1 << 30, max_inflight=4, max_batch_jobs=2)
+    res = dctf.dctf_server_run(server, reqs)
+    stats = dctf.dctf_server_stats(server)
+    assert all(r["status"] == 0 for r in res)
+    assert stats["peak_inflight_batches"] >= 2
+    assert stats["batches"] >= 12
+
+
+def test_admission_by_arena_bytes(dctf):
+    masks = syn.mask_set_32()[:2]
+    small = torch.randn(100 * 64, device="cuda")
+    big = torch.randn(5000 * 64, device="cuda")
+    arena = 3000 * 64 * 4                                 # smaller than `big`, room for ~2 smalls at once
+    reqs = [dict(arrival_s=0.0, mask=masks[0].mask, N=8, border=0, X=small, Y=torch.empty_like(small)),
+            dict(arrival_s=0.0, mask=masks[1].mask, N=8, border=1, X=big),
+            dict(arrival_s=0.0, mask=masks[0].mask, N=8, border=0, X=small, Y=torch.empty_like(small))]
+    server = dctf.dctf_server_create(arena_bytes=arena, max_inflight=2, max_batch_jobs=4)
+    res = dctf.dctf_server_run(server, reqs)
+    assert [r["status"] for r in res] == [0, dctf.DCTF_EBUSY, 0]
+    stats = dctf.dctf_server_stats(server)
+    assert stats["rejected"] == 1 and stats["peak_arena_bytes"] <= arena
+    assert torch.equal(reqs[0]["Y"], reqs[2]["Y"])
+
+
+def test_arena_limits_requests_in_flight(dctf):
+    masks = syn.mask_set_32()[:1]
+    X = torch.randn(2000 * 64, device="cuda")
+    reqs = [dict(arrival_s=0.0, mask=masks[0].mask, N=8, border=0, X=X) for _ in range(6)]
+    one = 2000 * 64 * 4
+    server = dctf.dctf_server_create(arena_bytes=one + one // 2, max_inflight=4, max_batch_jobs=4)
+    res = dctf.dctf_server_run(server, reqs)
+    assert all(r["status"] == 0 for r in res)
+    assert dctf.dctf_server_stats(server)["peak_arena_bytes"] <= one + one // 2
+    # only one request fits at a time: every launch carries exactly one
+    assert len({r["batch"] for r in res}) == 6
+
+
+def test_operator_cache_evicts_and_rebuilds(dctf):
+    masks = syn.mask_set_32()[8:12]
+    X = torch.randn(300 * 64, device="cuda")
+    reqs = []
+    for i in range(16):
+        m = masks[i % 4]
+        reqs.append(dict(arrival_s=i * 1e-3, mask=m.mask, N=8, border=m.border, X=X, Y=torch.empty_like(X)))
+    server = dctf.dctf_server_create(arena_bytes=1 << 26, max_inflight=1, max_batch_jobs=1, max_cached_ops=2)
+    res = dctf.dctf_server_run(server, reqs)
+    assert all(r["status"] == 0 for r in res)
+    stats = dctf.dctf_server_stats(server)
+    assert stats["cache_evictions"] > 0 and stats["cache_misses"] > 4
+    for i in range(4, 16):
+        assert torch.equal(reqs[i]["Y"], reqs[i - 4]["Y"])
+
+
+def test_malformed_request_lists(dctf):
+    masks = syn.mask_set_32()[:1]
+    X = torch.randn(64, device="cuda")
+    server = dctf.dctf_server_create(arena_bytes=1 << 20)
+    bad_order = [dict(arrival_s=1.0, mask=masks[0].mask, N=8, border=0, X=X),
+                 dict(arrival_s=0.5, mask=masks[0].mask, N=8, border=0, X=X)]
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_server_run(server, bad_order)
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_server_run(server, [dict(arrival_s=0.0, mask=masks[0].mask, N=4, border=0, X=X)])
