@@ -41,44 +41,66 @@ __device__ __forceinline__ int find_segment(const SegDesc *segs, int nsegs, int6
     return lo;
 }
 
-// Walks the job table forward as the unit index grows.  The descriptor of
-// the job after the current one is fetched one step early, so crossing one
-// job boundary per step does not wait on a scalar load.
+// Walks the job table forward as the unit index grows.  The end of the
+// current job follows from its own descriptor.  The next job's descriptor is
+// requested by refill() with a vector load (lane k loads dword k) issued just
+// before a step's data loads: a scalar load would share its wait counter with
+// the LDS accesses of the tile pipeline and stall them, while the vector load
+// completes in order ahead of the data it precedes.  At the crossing the
+// fields are read back from the lanes.
+template <int BPU>   // blocks per work unit
 struct JobCursor {
+    static_assert(sizeof(JobDesc) == 40, "JobDesc is 10 dwords");
+    static constexpr int blocks_per_unit = BPU;
     const JobDesc *jobs;
     int end, j;
-    JobDesc cur, next;
-    int64_t next_begin;
+    JobDesc cur;
+    int64_t cur_end;   // first unit after the current job
+    uint32_t nextv;    // lane k < 10: dword k of jobs[j + 1]
+    bool have_next;
 
+    __device__ __forceinline__ int64_t units_of(const JobDesc &d) const
+    {
+        return (d.B + blocks_per_unit - 1) / blocks_per_unit;
+    }
     __device__ __forceinline__ void start(const JobDesc *t, int job_begin, int job_end, int64_t unit)
     {
         jobs = t;
         end = job_end;
         j = job_begin;
         cur = t[j];
-        fetch_next();
-        while (unit >= next_begin)
-            advance();
+        cur_end = cur.unit_begin + units_of(cur);
+        have_next = false;
+        at(unit);
     }
-    __device__ __forceinline__ void fetch_next()
+    __device__ __forceinline__ void refill()
     {
-        if (j + 1 < end) {
-            next = jobs[j + 1];
-            next_begin = next.unit_begin;
-        } else {
-            next_begin = INT64_MAX;
+        if (!have_next && j + 1 < end) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(jobs + j + 1);
+            const int lane = __lane_id();
+            nextv = p[lane < 10 ? lane : 0];
+            have_next = true;
         }
     }
-    __device__ __forceinline__ void advance()
+    __device__ __forceinline__ JobDesc unpack() const
     {
-        ++j;
-        cur = next;
-        fetch_next();
+        uint32_t w[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            w[k] = (uint32_t)__builtin_amdgcn_readlane((int)nextv, k);
+        JobDesc d;
+        __builtin_memcpy(&d, w, sizeof(d));
+        return d;
     }
-    __device__ __forceinline__ UnitRef at(int64_t unit, int blocks_per_unit)
+    __device__ __forceinline__ UnitRef at(int64_t unit)
     {
-        while (unit >= next_begin)
-            advance();
+        while (unit >= cur_end && j + 1 < end) {
+            refill();   // no-op when the descriptor was requested earlier
+            cur = unpack();
+            ++j;
+            have_next = false;
+            cur_end = cur.unit_begin + units_of(cur);
+        }
         UnitRef r;
         r.in = cur.in;
         r.out = cur.out;
@@ -152,15 +174,16 @@ __device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
         }
     };
 
-    JobCursor jc;
+    JobCursor<kUnitBlocks8> jc;
     int64_t unit = first;
     jc.start(a.jobs8, job_begin, job_end, unit);
-    UnitRef rc = jc.at(unit, kUnitBlocks8);
+    UnitRef rc = jc.at(unit);
     float4 cur[4], nxt[4];
     load_unit(cur, rc);
     for (int64_t k = 1; k < my_units; ++k) {
         unit += stride;
-        const UnitRef rn = jc.at(unit, kUnitBlocks8);
+        const UnitRef rn = jc.at(unit);
+        jc.refill();
         load_unit(nxt, rn);
         compute_store(cur, rc);
 #pragma unroll
@@ -186,9 +209,13 @@ __device__ void worker16(const BatchArgs &a, int64_t wg, char *smem)
 
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
     Regs R;
-    JobCursor jc;
+    JobCursor<kUnitBlocks16> jc;
     jc.start(a.jobs16, sg.job_begin, sg.job_end, first);
-    auto ref = [&](int64_t t) { return jc.at(first + t * stride, kUnitBlocks16); };
+    auto ref = [&](int64_t t) {
+        const UnitRef r = jc.at(first + t * stride);
+        jc.refill();   // ahead of the tile's data loads
+        return r;
+    };
     auto op_load = [&](int op) {
         const OpDesc &o = a.ops[op];
         if constexpr (PREC == DCTF_PREC_FP32)

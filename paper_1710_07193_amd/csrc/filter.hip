@@ -243,16 +243,34 @@ struct Variant16 {
     int depth;   // tiles of global loads in flight ahead of the MFMA work
     const char *name;
 };
-const Variant16 kVariants16[] = {{3, "wg8_ahead3"}, {2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
-constexpr int kNumVariants16 = sizeof(kVariants16) / sizeof(kVariants16[0]);
+// The FP32 kernel keeps the whole FP32 operator slice in registers; three
+// tiles in flight push it past the register file, so its table stops at two.
+const Variant16 kVariants16Split[] = {{3, "wg8_ahead3"}, {2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
+const Variant16 kVariants16F32[] = {{2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
+constexpr int kNumVariants16Split = sizeof(kVariants16Split) / sizeof(kVariants16Split[0]);
+constexpr int kNumVariants16F32 = sizeof(kVariants16F32) / sizeof(kVariants16F32[0]);
 
-template <int PREC>
-hipError_t dispatch16(int variant, const FilterArgs &a, hipStream_t stream)
+const Variant16 &variant16(int prec, int variant)
 {
-    switch (kVariants16[(variant >= 0 && variant < kNumVariants16) ? variant : 0].depth) {
-    case 1: return run16<PREC, 1>(a, stream);
-    case 2: return run16<PREC, 2>(a, stream);
-    default: return run16<PREC, 3>(a, stream);
+    if (prec == DCTF_PREC_FP32)
+        return kVariants16F32[(variant >= 0 && variant < kNumVariants16F32) ? variant : 0];
+    return kVariants16Split[(variant >= 0 && variant < kNumVariants16Split) ? variant : 0];
+}
+
+hipError_t dispatch16_f32(int variant, const FilterArgs &a, hipStream_t stream)
+{
+    switch (variant16(DCTF_PREC_FP32, variant).depth) {
+    case 1: return run16<DCTF_PREC_FP32, 1>(a, stream);
+    default: return run16<DCTF_PREC_FP32, 2>(a, stream);
+    }
+}
+
+hipError_t dispatch16_split(int variant, const FilterArgs &a, hipStream_t stream)
+{
+    switch (variant16(DCTF_PREC_SPLIT_BF16, variant).depth) {
+    case 1: return run16<DCTF_PREC_SPLIT_BF16, 1>(a, stream);
+    case 2: return run16<DCTF_PREC_SPLIT_BF16, 2>(a, stream);
+    default: return run16<DCTF_PREC_SPLIT_BF16, 3>(a, stream);
     }
 }
 
@@ -260,21 +278,19 @@ hipError_t dispatch16(int variant, const FilterArgs &a, hipStream_t stream)
 
 int variant_count(int N, int prec)
 {
-    (void)prec;
     if (N == 8)
         return kNumVariants8;
     if (N == 16)
-        return kNumVariants16;
+        return prec == DCTF_PREC_FP32 ? kNumVariants16F32 : kNumVariants16Split;
     return 1;
 }
 
 const char *variant_name(int N, int prec, int v)
 {
-    (void)prec;
     if (N == 8 && v >= 0 && v < kNumVariants8)
         return kVariants8[v].name;
-    if (N == 16 && v >= 0 && v < kNumVariants16)
-        return kVariants16[v].name;
+    if (N == 16 && v >= 0 && v < variant_count(16, prec))
+        return variant16(prec, v).name;
     if (N <= 4 && v == 0)
         return "valu";
     return nullptr;
@@ -289,11 +305,6 @@ void variant_io(int N, int prec, int variant, int *io, bool *nt)
         *io = kVariants8[variant].io;
         *nt = kVariants8[variant].nt;
     }
-}
-
-int variant_depth16(int variant)
-{
-    return kVariants16[(variant >= 0 && variant < kNumVariants16) ? variant : 0].depth;
 }
 
 int default_variant(int N, int prec)
@@ -317,8 +328,7 @@ hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipS
         return prec == DCTF_PREC_FP32 ? dispatch8<DCTF_PREC_FP32>(v, a, stream)
                                       : dispatch8<DCTF_PREC_SPLIT_BF16>(v, a, stream);
     }
-    return prec == DCTF_PREC_FP32 ? dispatch16<DCTF_PREC_FP32>(variant, a, stream)
-                                  : dispatch16<DCTF_PREC_SPLIT_BF16>(variant, a, stream);
+    return prec == DCTF_PREC_FP32 ? dispatch16_f32(variant, a, stream) : dispatch16_split(variant, a, stream);
 }
 
 }  // namespace dctf

@@ -301,21 +301,27 @@ __device__ __forceinline__ void tile8_coalesced(const Regs &R, const float4 xin[
 //
 // Weight-stationary: a workgroup of 8 waves holds the 256 x 256 operator in
 // VGPRs, wave w owning output rows [32w, 32w + 32) (two M-tiles).  A tile of
-// 16 blocks is staged in LDS once and read by all 8 waves.
-//   FP32: LDS tile [16][260] floats (row padded by 16 B: conflict-free
-//         16-byte reads); lane (n, g) reads X[n][16i + 4g .. +3], i = 0..15.
-//   BF16: LDS tiles hi / lo [16][264] BF16, split once when written; lane
-//         (n, g) reads 8 BF16 at X[n][32s + 8g], s = 0..7.  The 16
-//         low-frequency coefficients (lf_slot) go to an FP32 LDS array
-//         [16][20] instead and are multiplied in FP32 MFMA.
+// 16 blocks is staged in LDS once and read by all 8 waves.  Rows (one block
+// each) are split into 16-byte chunks stored XOR-swizzled by the row index,
+// chunk c of row b at position c ^ b, which keeps the 16-byte MFMA-layout
+// reads of a wave free of bank conflicts (padded rows are not, on gfx950):
+//   FP32: [16][256] floats; lane (n, g) reads chunk 4i + g of row n, i = 0..15.
+//   BF16: hi / lo [16][256] BF16, split once when written; lane (n, g) reads
+//         chunk 4s + g (8 BF16), s = 0..7.  The 16 low-frequency coefficients
+//         (lf_slot) go to an FP32 array [4][16][4] instead (chunk g of row n
+//         at g*16 + n) and are multiplied in FP32 MFMA.
 
-constexpr int kLd16F32 = 260;    // floats per LDS row (FP32 path)
-constexpr int kLd16BF16 = 264;   // BF16 per LDS row (split path)
-constexpr int kLd16Lf = 20;      // floats per LDS row of the low-frequency FP32 part
+constexpr int kLd16F32 = 256;    // floats per LDS row (FP32 path)
+constexpr int kLd16BF16 = 256;   // BF16 per LDS row (split path)
+constexpr int kLd16Lf = 16;      // floats per block of the low-frequency FP32 part
 
 // LDS bytes of one 16-block tile buffer.
 constexpr int kTile16BytesF32 = 16 * kLd16F32 * 4;
 constexpr int kTile16BytesSplit = 2 * 16 * kLd16BF16 * 2 + 16 * kLd16Lf * 4;
+
+// Element offsets of 16-byte chunk c of row b.
+__device__ __forceinline__ int f32_chunk(int b, int c) { return b * kLd16F32 + 4 * (c ^ b); }
+__device__ __forceinline__ int bf16_chunk(int b, int c) { return b * kLd16BF16 + 8 * (c ^ b); }
 
 struct OpRegs16F32 {
     float A[2][16][4];
@@ -394,7 +400,7 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, float *lds, int 
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int q = tid + 512 * h;
-        *reinterpret_cast<float4 *>(lds + (q >> 6) * kLd16F32 + 4 * (q & 63)) = S.v[h];
+        *reinterpret_cast<float4 *>(lds + f32_chunk(q >> 6, q & 63)) = S.v[h];
     }
 }
 
@@ -412,14 +418,15 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, u
         for (int e = 0; e < 4; ++e) {
             const int slot = lf_slot(16, 4 * c + e);
             if (slot >= 0) {
-                llf[b * kLd16Lf + slot] = xv[e];
+                llf[((slot >> 2) * 16 + b) * 4 + (slot & 3)] = xv[e];
                 xv[e] = 0.0f;
             }
         }
         uint32_t h01, h23, l01, l23;
         split_bf16(make_float4(xv[0], xv[1], xv[2], xv[3]), h01, h23, l01, l23);
-        *reinterpret_cast<uint2 *>(lhi + b * kLd16BF16 + 4 * c) = make_uint2(h01, h23);
-        *reinterpret_cast<uint2 *>(llo + b * kLd16BF16 + 4 * c) = make_uint2(l01, l23);
+        const int off = bf16_chunk(b, c >> 1) + 4 * (c & 1);
+        *reinterpret_cast<uint2 *>(lhi + off) = make_uint2(h01, h23);
+        *reinterpret_cast<uint2 *>(llo + off) = make_uint2(l01, l23);
     }
 }
 
@@ -430,7 +437,7 @@ __device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, i
     acc[1] = acc[0];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const float4 xv4 = *reinterpret_cast<const float4 *>(lds + n * kLd16F32 + 16 * i + 4 * g);
+        const float4 xv4 = *reinterpret_cast<const float4 *>(lds + f32_chunk(n, 4 * i + g));
         const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -438,7 +445,7 @@ __device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, i
             for (int t = 0; t < 2; ++t)
                 acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
     }
-    const float x0 = lds[n * kLd16F32];
+    const float x0 = lds[f32_chunk(n, 0)];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -452,7 +459,7 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
     acc[1] = acc[0];
-    const float4 lv = *reinterpret_cast<const float4 *>(llf + n * kLd16Lf + 4 * g);
+    const float4 lv = *reinterpret_cast<const float4 *>(llf + (g * 16 + n) * 4);
     const float lfv[4] = {lv.x, lv.y, lv.z, lv.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -461,8 +468,8 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
             acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + n * kLd16BF16 + 32 * s + 8 * g);
-        const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + n * kLd16BF16 + 32 * s + 8 * g);
+        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + bf16_chunk(n, 4 * s + g));
+        const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + bf16_chunk(n, 4 * s + g));
 #pragma unroll
         for (int t = 0; t < 2; ++t)
             acc[t] = mfma_bf16(R.lo[t][s], bh, acc[t]);
