@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=60)
     ap.add_argument("--images", type=int, default=64)
     ap.add_argument("--side", type=int, default=2048)
     ap.add_argument("--prec", choices=["split", "fp32"], default="split")
@@ -89,6 +89,132 @@ def timed_steps(torch, fn, steps, warmup, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def replay_times(torch, fn, steps, warmup, stream):
+    """Per-call times (ms) of `steps` calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+
+
+def small_workloads(dctf, torch, stream):
+    """Latency of the two small configurations: a 64x64 image with the 3x3
+    box mask (zero border, 64 blocks), and a 512x512 image under the 3x3
+    Gaussian and the 5x5 asymmetric mask with both borders (4 operators of
+    4096 blocks each, alone and as one batch)."""
+    import numpy as np
+
+    import synthetic as syn
+    res = {}
+    X1 = torch.empty(64 * 64, dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8(torch.from_numpy(syn.image_u8(1, 64, 64)).cuda(), 8, X1)
+    Y1 = torch.empty_like(X1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        opb = dctf.dctf_build_operator(syn.box_mask(3), 8, dctf.DCTF_BORDER_ZERO)
+    torch.cuda.synchronize()
+    res["build_operator_us_host"] = (time.perf_counter() - t0) / 20 * 1e6
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        t = replay_times(torch, lambda: dctf.dctf_filter_blocks(opb, p, X1, Y1, stream), 200, 20, stream)
+        res["img64_box3_zero_%s_us_median" % pname] = float(np.median(t)) * 1e3
+    X2 = torch.empty(512 * 512, dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8(torch.from_numpy(syn.image_u8(2, 512, 512)).cuda(), 8, X2)
+    specs = [(m, 8, b) for m in (syn.gaussian_mask(3), syn.asym_mask_5x5())
+             for b in (dctf.DCTF_BORDER_ZERO, dctf.DCTF_BORDER_REPLICATE)]
+    ops = dctf.dctf_build_operators(specs)
+    Ys = [torch.empty_like(X2) for _ in ops]
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        def four():
+            for op, Yk in zip(ops, Ys):
+                dctf.dctf_filter_blocks(op, p, X2, Yk, stream)
+        t = replay_times(torch, four, 100, 10, stream)
+        res["img512_4ops_%s_us_median_4_launches" % pname] = float(np.median(t)) * 1e3
+        bt = dctf.dctf_batch_create([(op, X2, Yk) for op, Yk in zip(ops, Ys)], p)
+        t = replay_times(torch, lambda: dctf.dctf_batch_run(bt, 0, stream), 100, 10, stream)
+        res["img512_4ops_%s_us_median_one_batch" % pname] = float(np.median(t)) * 1e3
+    return res
+
+
+def n16_frames(dctf, torch, stream, steps, warmup):
+    """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
+    one 7x7 asymmetric mask with zero border, in both precisions."""
+    import numpy as np
+
+    import synthetic as syn
+    N, frames, h, w = 16, 32, 2160, 3840
+    nb = (h // N) * (w // N)
+    X = torch.empty(frames * nb * N * N, dtype=torch.float32, device="cuda")
+    for f in range(frames):
+        img = torch.from_numpy(syn.image_u8(3000 + f, h, w)).cuda()
+        dctf.dctf_forward_dct_u8(img, N, X[f * nb * N * N:(f + 1) * nb * N * N])
+    Y = torch.empty_like(X)
+    op = dctf.dctf_build_operator(syn.random_mask(np.random.default_rng(7), 7, 7), N, dctf.DCTF_BORDER_ZERO)
+    B = frames * nb
+    res = {"blocks": B, "alg_bytes_per_launch": B * N * N * 8}
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, p, X, Y, stream), steps, warmup, stream)
+        res[pname] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
+                      "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9,
+                      "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
+    res["split_over_fp32_speedup"] = res["fp32"]["ms_per_launch"] / res["split"]["ms_per_launch"]
+    res["fp32_mfma_TFLOPs"] = B * 2.0 * (N * N) ** 2 / (res["fp32"]["ms_per_launch"] * 1e-3) / 1e12
+    del X, Y
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_context(torch, images, side, pool, draws, N=8, seconds=5.0):
+    """Two more CPU figures beside the baseline: the oracle on one thread,
+    and the method itself on the CPU (Y = X . H^T in FP32 with torch's CPU
+    GEMM on all its threads, H from the oracle's operator probe)."""
+    import numpy as np
+
+    import oracle
+    import synthetic as syn
+    out = {}
+    oracle.set_num_threads(1)
+    try:
+        done, spent = 0, 0.0
+        for i in range(images):
+            X = oracle.dct_pixels(oracle.tile_u8(syn.image_u8(1000 + i, side, side), N))
+            spec = pool[draws[i]]
+            t0 = time.perf_counter()
+            oracle.filter_coeffs(X, spec.mask, spec.border)
+            spent += time.perf_counter() - t0
+            done += len(X)
+            if spent >= seconds:
+                break
+        out["oracle_1thread"] = {"value": done / spent, "unit": "blocks/s", "cores": 1,
+                                 "sample": "%d blocks, %.1f s" % (done, spent)}
+    finally:
+        oracle.set_num_threads(0)
+    Hs = {}
+    done, spent = 0, 0.0
+    for i in range(images):
+        spec = pool[draws[i]]
+        key = int(draws[i])
+        if key not in Hs:
+            Hs[key] = torch.from_numpy(oracle.operator_probe(N, spec.mask, spec.border).astype(np.float32))
+        X = torch.from_numpy(oracle.dct_pixels(oracle.tile_u8(syn.image_u8(1000 + i, side, side), N))
+                             .reshape(-1, N * N).astype(np.float32))
+        t0 = time.perf_counter()
+        torch.mm(X, Hs[key].t())
+        spent += time.perf_counter() - t0
+        done += X.shape[0]
+        if spent >= seconds:
+            break
+    out["method_fp32_gemm"] = {"value": done / spent, "unit": "blocks/s", "cores": torch.get_num_threads(),
+                               "sample": "%d blocks, %.2f s" % (done, spent)}
+    return out
 
 
 def cpu_baseline(images, side, pool, draws, seconds, N=8):
@@ -252,14 +378,16 @@ def main():
 
     if not args.no_extras:
         extras = {}
-        # the same step replayed from a captured HIP graph
+        # the same step replayed from a captured HIP graph, one event pair per replay
         side_stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         with torch.cuda.stream(side_stream):
             dctf.dctf_batch_capture(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, side_stream)
-            gms = timed_steps(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
-                              args.steps, args.warmup, side_stream)
-        extras["graph_replay"] = {"ms_per_step": gms, "blocks_per_s": B / (gms * 1e-3)}
+            per_replay = replay_times(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
+                                      args.steps, args.warmup, side_stream)
+        extras["graph_replay"] = {"replays": len(per_replay), "ms_median": float(np.median(per_replay)),
+                                  "ms_p99": float(np.percentile(per_replay, 99)),
+                                  "blocks_per_s_median": B / (float(np.median(per_replay)) * 1e-3)}
         # the other precision on the same jobs (split-BF16 vs FP32 speedup)
         other = dctf.DCTF_PREC_FP32 if prec == dctf.DCTF_PREC_SPLIT_BF16 else dctf.DCTF_PREC_SPLIT_BF16
         ob = dctf.dctf_batch_create(jobs, other)
@@ -269,19 +397,25 @@ def main():
             "ms_per_step": oms, "blocks_per_s": B / (oms * 1e-3),
             "split_over_fp32_speedup": (oms / ms) if other == dctf.DCTF_PREC_FP32 else (ms / oms)}
         del ob
-        # all blocks through the single 5x5 asymmetric inseparable mask (one operator)
-        op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, dctf.DCTF_BORDER_REPLICATE)
-        for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
-            sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
-                              args.steps, args.warmup, stream)
-            extras["mask5x5_single_op_" + pname] = {
-                "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
-                "GBps": alg_bytes / (sms * 1e-3) / 1e9, "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
+        # all blocks through the single 5x5 asymmetric inseparable mask (one operator),
+        # once per border mode and precision
+        for bname, border in (("zero", dctf.DCTF_BORDER_ZERO), ("replicate", dctf.DCTF_BORDER_REPLICATE)):
+            op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, border)
+            for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+                sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
+                                  args.steps, args.warmup, stream)
+                extras["mask5x5_%s_single_op_%s" % (bname, pname)] = {
+                    "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
+                    "GBps": alg_bytes / (sms * 1e-3) / 1e9,
+                    "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
+        extras["small_workloads"] = small_workloads(dctf, torch, stream)
         # optional verify kernel: inverse DCT + uint8 of every output block
         pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
         vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)
         extras["verify_kernel_ms"] = vms
         out["extras"] = extras
+        del pix
+        extras["n16_frames"] = n16_frames(dctf, torch, stream, max(10, args.steps // 5), max(5, args.warmup // 6))
 
     if args.serve_seconds > 0:
         del X, Y
@@ -300,6 +434,7 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.images, args.side, pool, draws, args.cpu_seconds, N)
+        out["cpu_context"] = cpu_context(torch, args.images, args.side, pool, draws, N)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -58,6 +58,7 @@ def _load():
             i32, i64 = ctypes.c_int, ctypes.c_int64
             sig = {
                 "or_num_threads": ([], i32),
+                "or_set_num_threads": ([i32], None),
                 "or_dct_matrix": ([i32, P], None),
                 "or_dct2": ([i32, i64, P, P], i32),
                 "or_idct2": ([i32, i64, P, P], i32),
@@ -97,6 +98,11 @@ def _mask(W):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the loops over blocks; n < 1 restores the default."""
+    _load().or_set_num_threads(int(n))
 
 
 def dct_matrix(N: int) -> np.ndarray:

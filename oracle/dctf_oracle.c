@@ -42,6 +42,19 @@
 #define OR_BORDER_ZERO 0
 #define OR_BORDER_REPLICATE 1
 
+/* Threads used by the loops over blocks (n < 1 restores the default). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    static int deflt = 0;
+    if (deflt == 0)
+        deflt = omp_get_max_threads();
+    omp_set_num_threads(n >= 1 ? n : deflt);
+#else
+    (void)n;
+#endif
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -152,9 +152,13 @@ __device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
                 x[i] = NT ? ld4_nt(src + 16 * i) : ld4(src + 16 * i);
         }
     };
+    // Operator fragments are requested before the data loads of the unit
+    // after, so the wait for them does not also drain that unit's loads.
+    auto ensure_op = [&](int op) {
+        if (op != loaded_op)
+            op_load(op);
+    };
     auto compute_store = [&](float4 (&x)[4], const UnitRef &r) {
-        if (r.op != loaded_op)
-            op_load(r.op);
         if constexpr (IO == 1) {
             tile8_coalesced<NT>(R, x, lds, r.out + r.blk0 * 64, r.B - r.blk0, lane);
         } else {
@@ -179,11 +183,13 @@ __device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
     jc.start(a.jobs8, job_begin, job_end, unit);
     UnitRef rc = jc.at(unit);
     float4 cur[4], nxt[4];
+    ensure_op(rc.op);
     load_unit(cur, rc);
     for (int64_t k = 1; k < my_units; ++k) {
         unit += stride;
         const UnitRef rn = jc.at(unit);
         jc.refill();
+        ensure_op(rc.op);
         load_unit(nxt, rn);
         compute_store(cur, rc);
 #pragma unroll
@@ -191,6 +197,7 @@ __device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
             cur[i] = nxt[i];
         rc = rn;
     }
+    ensure_op(rc.op);
     compute_store(cur, rc);
 }
 

@@ -524,13 +524,13 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
         for (int p = 0; p < D; ++p) {
             const int64_t t = t0 + p;
             const Ref rc = Rf[p];
+            if (rc.op != loaded_op) {     // requested ahead of the newest tile's loads
+                op_load(rc.op);
+                loaded_op = rc.op;
+            }
             if (t + D < count) {          // S[p] is free: its tile is in LDS
                 Rf[p] = ref(t + D);
                 stage(S[p], Rf[p]);
-            }
-            if (rc.op != loaded_op) {
-                op_load(rc.op);
-                loaded_op = rc.op;
             }
             const int buf = (int)(t & 1);
             f32x4 acc[2];

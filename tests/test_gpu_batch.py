@@ -149,6 +149,36 @@ def test_batch_many_small_jobs(dctf, prec):
                 dctf.dctf_set_batch_fronts(fronts0)
 
 
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_batch_operator_changes_within_a_wave(dctf, prec):
+    """Enough units that every wave walks through several jobs and operators
+    (including a change right at its last unit), for each front setting."""
+    rng = np.random.default_rng(91)
+    ops = dctf.dctf_build_operators([(syn.random_mask(rng, k, k), 8, b) for k in (3, 5, 7) for b in (Z, R)
+                                     for _ in range(4)])
+    jobs = []
+    for i in range(96):
+        B = int(rng.integers(1, 12000))
+        X = torch.randn(B * 64, device="cuda") * 100
+        jobs.append((ops[int(rng.integers(0, len(ops)))], X, torch.empty_like(X)))
+    want = []
+    for op, X, _ in jobs:
+        Y = torch.empty_like(X)
+        dctf.dctf_filter_blocks(op, prec, X, Y)
+        want.append(Y)
+    fronts0 = dctf.dctf_get_batch_fronts()
+    try:
+        for fronts in (0, 1, 2, 5):
+            dctf.dctf_set_batch_fronts(fronts)
+            for _, _, Y in jobs:
+                Y.fill_(float("nan"))
+            dctf.dctf_filter_batch(jobs, prec)
+            for k, ((op, X, Y), w) in enumerate(zip(jobs, want)):
+                assert torch.equal(Y, w), (fronts, k)
+    finally:
+        dctf.dctf_set_batch_fronts(fronts0)
+
+
 def test_batch_rejections(dctf):
     jobs = make_jobs(dctf, seed=4)
     a, b = jobs[0], jobs[1]
