@@ -214,7 +214,19 @@ def cpu_context(torch, images, side, pool, draws, N=8, seconds=5.0):
             break
     out["method_fp32_gemm"] = {"value": done / spent, "unit": "blocks/s", "cores": torch.get_num_threads(),
                                "sample": "%d blocks, %.2f s" % (done, spent)}
+    out["host"] = {"cpu": cpu_model(), "nproc": os.cpu_count(), "oracle_threads": oracle.num_threads()}
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(images, side, pool, draws, seconds, N=8):
