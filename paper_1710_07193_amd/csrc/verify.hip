@@ -2,9 +2,9 @@
 //   k_forward_dct_u8   uint8 image -> FP32 coefficient blocks (eq. 1, FP64 arithmetic)
 //   k_idct_u8_verify   FP32 coefficients -> uint8 pixels (eq. 3 in FP32, then the
 //                      Sec. III uint8 conversion) with mismatch / near-1/2 counters
-// One workgroup of 256 threads handles 256 / (N*N) blocks (N <= 16), one
-// thread per pixel or coefficient.  The N x N DCT matrix is formed in LDS
-// from its closed form.
+// The forward transform runs one thread per pixel; the verify kernel one
+// thread per row segment of up to four coefficients.  The N x N DCT matrix
+// is formed in LDS from its closed form.
 #include "dctf_internal.h"
 
 #include <math.h>
@@ -66,55 +66,132 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_u8(const uint8_t *img,
     }
 }
 
-// pix[i][j] = sum_u C[u][i] (sum_v Y[u][v] C[v][j]) in FP32.
-__global__ __launch_bounds__(kThreads) void k_idct_u8_verify(int N, const float *Y, int64_t B,
-                                                             uint8_t *pix, const uint8_t *expected,
-                                                             unsigned long long *counters)
+// pix[i][j] = sum_u C[u][i] (sum_v Y[u][v] C[v][j]) in FP32.  Each thread
+// owns V consecutive coefficients of one block row (V = min(N, 4)); a
+// workgroup step covers G blocks and the workgroups stride over the steps,
+// so the DCT matrix is formed once per workgroup and the counters are
+// reduced once per wave at the end.
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int64_t B, uint8_t *pix,
+                                                             const uint8_t *expected,
+                                                             unsigned long long *counters, int vec_bytes)
 {
-    __shared__ float sC[256];
-    __shared__ float sy[256];
-    __shared__ float st[256];
+    constexpr int NN = N * N, V = N < 4 ? N : 4, TPB = NN / V, G = kThreads / TPB;
+    __shared__ __attribute__((aligned(16))) float sC[NN];
+    __shared__ __attribute__((aligned(16))) float sy[G * NN];
+    __shared__ __attribute__((aligned(16))) float st[G * NN];
     fill_dct(sC, N);
-    const int NN = N * N;
-    const int per = kThreads / NN;
-    const int local = threadIdx.x / NN, e = threadIdx.x % NN;
-    const int i = e / N, j = e % N;
-    const int64_t blk = (int64_t)blockIdx.x * per + local;
-    const bool active = local < per && blk < B;
-    if (active)
-        sy[threadIdx.x] = Y[blk * NN + e];
     __syncthreads();
-    const int base = local * NN;
-    if (active) {
-        // t[u][j] with u = i of this thread
-        float s = 0.0f;
-        for (int v = 0; v < N; ++v)
-            s = fmaf(sy[base + i * N + v], sC[v * N + j], s);
-        st[threadIdx.x] = s;
-    }
-    __syncthreads();
+    const int local = threadIdx.x / TPB, e0 = (threadIdx.x % TPB) * V;
+    const int i = e0 / N, j0 = e0 % N, base = local * NN;
     unsigned long long bad = 0, near = 0;
-    if (active) {
-        float p = 0.0f;
-        for (int u = 0; u < N; ++u)
-            p = fmaf(sC[u * N + i], st[base + u * N + j], p);
-        const float r = floorf(p + 0.5f);
-        const uint8_t q = (uint8_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
-        pix[blk * NN + e] = q;
-        const bool nh = fabsf(p - floorf(p) - 0.5f) < 1e-3f;
-        near = nh ? 1 : 0;
-        if (expected != nullptr && !nh && q != expected[blk * NN + e])
-            bad = 1;
+    const int64_t steps = (B + G - 1) / G;
+    for (int64_t step = blockIdx.x; step < steps; step += gridDim.x) {
+        const int64_t blk = step * G + local;
+        const bool active = blk < B;
+        const int64_t off = blk * NN + e0;
+        if (active) {
+            if constexpr (V == 4) {
+                *reinterpret_cast<float4 *>(sy + base + e0) = *reinterpret_cast<const float4 *>(Y + off);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    sy[base + e0 + q] = Y[off + q];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            float t[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                t[q] = 0.0f;
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                const float yv = sy[base + i * N + v];
+                if constexpr (V == 4) {
+                    const float4 c = *reinterpret_cast<const float4 *>(sC + v * N + j0);
+                    t[0] = fmaf(yv, c.x, t[0]);
+                    t[1] = fmaf(yv, c.y, t[1]);
+                    t[2] = fmaf(yv, c.z, t[2]);
+                    t[3] = fmaf(yv, c.w, t[3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        t[q] = fmaf(yv, sC[v * N + j0 + q], t[q]);
+                }
+            }
+            if constexpr (V == 4) {
+                *reinterpret_cast<float4 *>(st + base + e0) = make_float4(t[0], t[1], t[2], t[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    st[base + e0 + q] = t[q];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            uint8_t qv[V];
+            bool nh[V];
+            float pv[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                pv[q] = 0.0f;
+#pragma unroll
+            for (int u = 0; u < N; ++u) {
+                const float c = sC[u * N + i];
+                if constexpr (V == 4) {
+                    const float4 t4 = *reinterpret_cast<const float4 *>(st + base + u * N + j0);
+                    pv[0] = fmaf(c, t4.x, pv[0]);
+                    pv[1] = fmaf(c, t4.y, pv[1]);
+                    pv[2] = fmaf(c, t4.z, pv[2]);
+                    pv[3] = fmaf(c, t4.w, pv[3]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        pv[q] = fmaf(c, st[base + u * N + j0 + q], pv[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const float p = pv[q];
+                const float r = floorf(p + 0.5f);
+                qv[q] = (uint8_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
+                nh[q] = fabsf(p - floorf(p) - 0.5f) < 1e-3f;
+                near += nh[q] ? 1 : 0;
+            }
+            if (V == 4 && vec_bytes) {
+                const uint32_t packed = (uint32_t)qv[0] | ((uint32_t)qv[1] << 8) | ((uint32_t)qv[2] << 16) |
+                                        ((uint32_t)qv[3] << 24);
+                *reinterpret_cast<uint32_t *>(pix + off) = packed;
+                if (expected != nullptr) {
+                    const uint32_t ex = *reinterpret_cast<const uint32_t *>(expected + off);
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        bad += (!nh[q] && (uint8_t)(ex >> (8 * q)) != qv[q]) ? 1 : 0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    pix[off + q] = qv[q];
+                    if (expected != nullptr)
+                        bad += (!nh[q] && expected[off + q] != qv[q]) ? 1 : 0;
+                }
+            }
+        }
+        // the next step writes sy before its first barrier: every read of
+        // sy in this step happened before this step's second barrier
     }
     if (counters != nullptr) {
-        // one atomic per wave and counter
-        const unsigned long long nb = __popcll(__ballot(bad != 0));
-        const unsigned long long nn = __popcll(__ballot(near != 0));
+        // per-wave sums, one atomic per wave and counter
+        for (int d = 32; d >= 1; d >>= 1) {
+            bad += __shfl_xor(bad, d);
+            near += __shfl_xor(near, d);
+        }
         if ((threadIdx.x & 63) == 0) {
-            if (nb)
-                atomicAdd(&counters[0], nb);
-            if (nn)
-                atomicAdd(&counters[1], nn);
+            if (bad)
+                atomicAdd(&counters[0], bad);
+            if (near)
+                atomicAdd(&counters[1], near);
         }
     }
 }
@@ -174,10 +251,18 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
                                  const uint8_t *expected, unsigned long long *counters,
                                  hipStream_t stream)
 {
-    const int per = kThreads / (N * N);
-    const int64_t groups = (B + per - 1) / per;
-    hipLaunchKernelGGL(k_idct_u8_verify, dim3((unsigned)groups), dim3(kThreads), 0, stream, N, Y, B,
-                       pix, expected, counters);
+    const int V = N < 4 ? N : 4;
+    const int64_t G = kThreads / (N * N / V);
+    const int64_t steps = (B + G - 1) / G;
+    int64_t groups = (int64_t)cu_count() * 8;
+    groups = groups < steps ? groups : steps;
+    const int vec = ((uintptr_t)pix & 3u) == 0 && ((uintptr_t)expected & 3u) == 0;
+    switch (N) {
+    case 2: hipLaunchKernelGGL(k_idct_u8_verify<2>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    case 4: hipLaunchKernelGGL(k_idct_u8_verify<4>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    case 8: hipLaunchKernelGGL(k_idct_u8_verify<8>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    default: hipLaunchKernelGGL(k_idct_u8_verify<16>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    }
     return hipGetLastError();
 }
 

@@ -237,6 +237,37 @@ def test_forward_dct_matches_oracle(dctf, N):
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
 
 
+@pytest.mark.parametrize("N", [2, 4, 8, 16])
+def test_verify_kernel_all_sizes_strided(dctf, N):
+    """Every block size, with enough blocks that each workgroup walks several
+    steps and a ragged last one, through byte buffers at odd and at aligned
+    addresses (both must give the same pixels)."""
+    per_step = 256 // (N * N // min(N, 4))
+    B = 3 * 2048 * per_step + per_step // 2 + 1
+    rng = np.random.default_rng(100 + N)
+    Y = (rng.standard_normal((B, N, N)) * 40).astype(np.float32)
+    Y[:, 0, 0] += np.float32(128 * N)          # pixel values around mid-grey, some clipped
+    u8ref, nh = oracle.idct_u8(Y)
+    Yd = dev(Y.reshape(-1))
+    outs = []
+    for shift in (1, 0):
+        raw = torch.zeros(Y.size + 4, dtype=torch.uint8, device="cuda")
+        pix = raw[shift:shift + Y.size]
+        eraw = torch.zeros(Y.size + 4, dtype=torch.uint8, device="cuda")
+        exp = eraw[shift:shift + Y.size]
+        exp.copy_(torch.from_numpy(u8ref.reshape(-1)).cuda())
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        dctf.dctf_idct_u8_verify(N, Yd, pix, exp, cnt)
+        torch.cuda.synchronize()
+        got = pix.cpu().numpy().reshape(Y.shape)
+        assert np.array_equal(got[~nh], u8ref[~nh]), (N, shift)
+        assert int(cnt[0]) == 0
+        assert abs(int(cnt[1]) - int(nh.sum())) <= max(3, int(nh.sum()) // 50)
+        assert int(raw[shift + Y.size:].sum()) == 0 and int(raw[:shift].sum()) == 0   # nothing past the ends
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_verify_kernel_counts(dctf):
     N = 8
     px = oracle.tile_u8(syn.image_u8(9, 256, 256), N)
