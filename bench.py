@@ -146,7 +146,8 @@ def small_workloads(dctf, torch, stream):
 
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
-    one 7x7 asymmetric mask with zero border, in both precisions."""
+    one 7x7 asymmetric mask with zero border, in both precisions, and the
+    factored FP32 path for that mask and for a separable 7x7 Gaussian."""
     import numpy as np
 
     import synthetic as syn
@@ -167,6 +168,18 @@ def n16_frames(dctf, torch, stream, steps, warmup):
                       "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
     res["split_over_fp32_speedup"] = res["fp32"]["ms_per_launch"] / res["split"]["ms_per_launch"]
     res["fp32_mfma_TFLOPs"] = B * 2.0 * (N * N) ** 2 / (res["fp32"]["ms_per_launch"] * 1e-3) / 1e12
+    # the factored (paper-form) FP32 path: this mask (rank 7) and a separable 7x7 Gaussian (rank 1)
+    gop = dctf.dctf_build_operator(syn.gaussian_mask(7), N, dctf.DCTF_BORDER_ZERO)
+    for tag, o in (("mask7x7", op), ("gauss7x7", gop)):
+        rank = dctf.dctf_operator_rank(o)
+        fms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_factored(o, X, Y, stream), steps, warmup, stream)
+        ent = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
+               "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
+        if tag == "gauss7x7":
+            for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+                ent["dense_%s_ms" % pname] = timed_steps(
+                    torch, lambda: dctf.dctf_filter_blocks(o, p, X, Y, stream), steps, warmup, stream)
+        res["factored_" + tag] = ent
     del X, Y
     torch.cuda.empty_cache()
     return res

@@ -120,6 +120,28 @@ dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *
 /* Free an operator.  The caller must ensure no queued work still uses it. */
 void dctf_operator_destroy(dctf_operator op);
 
+/*
+ * Factored (paper-form) operator, Sec. II.B-C, eq. 8-12 and eq. 20: the
+ * paper applies a mask to a block as a sum of products A . BLOCK . B of N x N
+ * DCT-domain matrices.  At build time the mask is decomposed on the host into
+ * rank-one terms, W = sum_r a_r b_r^t (complete-pivoting elimination in FP64,
+ * terms stop when the remainder is below 1e-14 of the largest entry), and the
+ * GPU builder forms, in FP64,
+ *   P_r = C (sum_p a_r[p] S_{p-a_h}) C^t,   Q_r = C (sum_q b_r[q] S_{q-a_w}) C^t,
+ * with the same shift matrices S_d (zero fill or clamp) as the dense
+ * operator, so that H_dct = sum_r P_r (x) Q_r and Y = sum_r P_r X Q_r^t for
+ * each N x N coefficient block X.  Separable masks (and 1-D masks) have rank
+ * 1; mirror-symmetric masks have rank at most ceil(K/2) (the symmetric
+ * shortcut of eq. 12 is this reduction).
+ *
+ * dctf_operator_rank: the number of terms R (1 <= R <= min(kh, kw)).
+ * dctf_operator_factors_fp64: copies P (R x N x N) and Q (R x N x N), each
+ *   row-major FP64, to host memory (caller-owned, R*N*N doubles each).
+ *   Synchronous.
+ */
+dctf_status dctf_operator_rank(dctf_operator op, int *rank);
+dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double *Q_host);
+
 /* ------------------------------------------------------------------- filter */
 
 /*
@@ -139,6 +161,20 @@ void dctf_operator_destroy(dctf_operator op);
  */
 dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, float *out_dev,
                                int64_t B, dctf_stream stream);
+
+/*
+ * Y[b] = sum_r P_r X[b] Q_r^t for b = 0..B-1: the factored form above,
+ * FP32 MFMA (v_mfma_f32_16x16x4_f32, two chained products per rank term,
+ * FP32 accumulation).  It does 2 R N^3 multiply-adds per block against the
+ * dense path's N^4, so at N = 16 it does less MFMA work for R < 8 and keeps
+ * low-rank masks (separable, 1-D, symmetric 3 x 3) at the HBM bound.
+ * Results match dctf_filter_blocks(FP32) within FP32 rounding, not bit for
+ * bit (different summation order).  Buffers as for dctf_filter_blocks.
+ * Errors: DCTF_EINVAL (arguments), DCTF_EUNSUPPORTED (N != 16 or R > 8),
+ * DCTF_EHIP.
+ */
+dctf_status dctf_filter_blocks_factored(dctf_operator op, const float *in_dev, float *out_dev, int64_t B,
+                                        dctf_stream stream);
 
 /* ---------------------------------------------------------- batched launch */
 

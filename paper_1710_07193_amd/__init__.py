@@ -6,7 +6,7 @@ device memory and streams.  The functions carry the C names; tensors stand in
 for device pointers and ``stream`` defaults to torch's current stream.
 
 Importing this module fails loudly when the library has not been built
-(``python -m paper_1710_07193_amd.build`` or ``__graft_entry__.build()``).
+(``python paper_1710_07193_amd/build.py`` or ``__graft_entry__.build()``).
 """
 from __future__ import annotations
 
@@ -65,6 +65,9 @@ _SIGS = {
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
     "dctf_filter_blocks": ([_P, _I, _P, _P, _I64, _P], _I),
+    "dctf_operator_rank": ([_P, _P], _I),
+    "dctf_operator_factors_fp64": ([_P, _P, _P], _I),
+    "dctf_filter_blocks_factored": ([_P, _P, _P, _I64, _P], _I),
     "dctf_batch_create": ([ctypes.POINTER(_Job), _I, _I, ctypes.POINTER(_P)], _I),
     "dctf_batch_run": ([_P, ctypes.c_uint, _P], _I),
     "dctf_batch_capture": ([_P, ctypes.c_uint, _P], _I),
@@ -209,6 +212,32 @@ def dctf_filter_blocks(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor
     _check(_lib.dctf_filter_blocks(op, prec, _dptr(X, torch.float32, "X"),
                                    _dptr(Y, torch.float32, "Y"), X.numel() // nn, _stream(stream)),
            "dctf_filter_blocks")
+
+
+def dctf_operator_rank(op: Operator) -> int:
+    r = ctypes.c_int()
+    _check(_lib.dctf_operator_rank(op, ctypes.byref(r)), "dctf_operator_rank")
+    return r.value
+
+
+def dctf_operator_factors_fp64(op: Operator):
+    """(P, Q): two [R, N, N] FP64 arrays with H_dct = sum_r kron(P[r], Q[r])."""
+    R = dctf_operator_rank(op)
+    P = np.empty((R, op.N, op.N), np.float64)
+    Q = np.empty((R, op.N, op.N), np.float64)
+    _check(_lib.dctf_operator_factors_fp64(op, P.ctypes.data_as(_P), Q.ctypes.data_as(_P)),
+           "dctf_operator_factors_fp64")
+    return P, Q
+
+
+def dctf_filter_blocks_factored(op: Operator, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    """Y[b] = sum_r P_r X[b] Q_r^t (factored form, FP32 MFMA, N = 16)."""
+    nn = op.N * op.N
+    if X.numel() % nn or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold the same whole number of N*N blocks")
+    _check(_lib.dctf_filter_blocks_factored(op, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
+                                            X.numel() // nn, _stream(stream)),
+           "dctf_filter_blocks_factored")
 
 
 def filter_blocks(op: Operator, X: torch.Tensor, prec: int = DCTF_PREC_SPLIT_BF16, stream=None):

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <mutex>
 #include <new>
@@ -126,7 +127,59 @@ static dctf_status validate_mask(const double *mask, int kh, int kw, int N, int 
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static dctf_status alloc_operator(int N, int kh, int kw, int border, dctf_operator *out)
+// Complete-pivoting elimination of the mask: each step takes the largest
+// remaining entry as pivot and removes the rank-one term through it (column
+// times row / pivot), until the remainder is below 1e-14 of the largest mask
+// entry.  The two vectors of a term are scaled to equal largest magnitude.
+int dctf::mask_rank_factors(const double *W, int kh, int kw, std::vector<double> &a, std::vector<double> &b)
+{
+    std::vector<double> E(W, W + (size_t)kh * kw);
+    double wmax = 0.0;
+    for (double v : E)
+        wmax = std::max(wmax, std::fabs(v));
+    int rank = 0;
+    while (wmax > 0.0 && rank < std::min(kh, kw)) {
+        int pi = 0, pj = 0;
+        double best = -1.0;
+        for (int i = 0; i < kh; ++i)
+            for (int j = 0; j < kw; ++j)
+                if (std::fabs(E[(size_t)i * kw + j]) > best) {
+                    best = std::fabs(E[(size_t)i * kw + j]);
+                    pi = i;
+                    pj = j;
+                }
+        if (best <= 1e-14 * wmax)
+            break;
+        const double piv = E[(size_t)pi * kw + pj];
+        std::vector<double> col(kh), row(kw);
+        for (int i = 0; i < kh; ++i)
+            col[i] = E[(size_t)i * kw + pj];
+        for (int j = 0; j < kw; ++j)
+            row[j] = E[(size_t)pi * kw + j] / piv;
+        for (int i = 0; i < kh; ++i)
+            for (int j = 0; j < kw; ++j)
+                E[(size_t)i * kw + j] -= col[i] * row[j];
+        double ca = 0.0, rb = 0.0;
+        for (double v : col)
+            ca = std::max(ca, std::fabs(v));
+        for (double v : row)
+            rb = std::max(rb, std::fabs(v));
+        const double f = std::sqrt(rb / ca);   // ca, rb > 0: both contain the pivot
+        for (double v : col)
+            a.push_back(v * f);
+        for (double v : row)
+            b.push_back(v / f);
+        ++rank;
+    }
+    if (rank == 0) {
+        a.insert(a.end(), kh, 0.0);
+        b.insert(b.end(), kw, 0.0);
+        rank = 1;
+    }
+    return rank;
+}
+
+static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, dctf_operator *out)
 {
     const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
     size_t off = 0;
@@ -138,6 +191,12 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, dctf_operat
     const size_t o_flo = off;  off = align_up(off + sizeof(uint16_t) * F);
     const size_t o_flf = off;  off = align_up(off + sizeof(float) * frag_lf_elems(N));
     const size_t o_h0 = off;   off = align_up(off + sizeof(float) * NN);
+    const size_t o_fa = off;   off = align_up(off + sizeof(double) * rank * kh);
+    const size_t o_fb = off;   off = align_up(off + sizeof(double) * rank * kw);
+    const size_t o_p64 = off;  off = align_up(off + sizeof(double) * rank * NN);
+    const size_t o_q64 = off;  off = align_up(off + sizeof(double) * rank * NN);
+    const size_t o_p32 = off;  off = align_up(off + sizeof(float) * rank * NN);
+    const size_t o_q32 = off;  off = align_up(off + sizeof(float) * rank * NN);
 
     dctf_operator op = new (std::nothrow) dctf_operator_s();
     if (!op)
@@ -164,6 +223,13 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, dctf_operat
     op->img.frag_lo = F ? reinterpret_cast<uint16_t *>(b + o_flo) : nullptr;
     op->img.frag_lf = F ? reinterpret_cast<float *>(b + o_flf) : nullptr;
     op->img.h0 = reinterpret_cast<float *>(b + o_h0);
+    op->rank = rank;
+    op->img.fac_a = reinterpret_cast<double *>(b + o_fa);
+    op->img.fac_b = reinterpret_cast<double *>(b + o_fb);
+    op->img.P64 = reinterpret_cast<double *>(b + o_p64);
+    op->img.Q64 = reinterpret_cast<double *>(b + o_q64);
+    op->img.P32 = reinterpret_cast<float *>(b + o_p32);
+    op->img.Q32 = reinterpret_cast<float *>(b + o_q32);
     *out = op;
     return DCTF_OK;
 }
@@ -181,6 +247,7 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
             args.d[i].kh = op->kh;
             args.d[i].kw = op->kw;
             args.d[i].border = op->border;
+            args.d[i].rank = op->rank;
         }
         dctf_status st = hip_status(launch_build(args, s));
         if (st != DCTF_OK)
@@ -202,18 +269,27 @@ extern "C" dctf_status dctf_build_operators(const dctf_mask_desc *masks, int n, 
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<dctf_operator> ops(n, nullptr);
+    // host-side rank factors, kept alive until the stream has consumed them
+    std::vector<std::vector<double>> fa(n), fb(n);
     dctf_status st = DCTF_OK;
     for (int i = 0; i < n && st == DCTF_OK; ++i) {
-        st = alloc_operator(masks[i].N, masks[i].kh, masks[i].kw, masks[i].border, &ops[i]);
+        const int kh = masks[i].kh, kw = masks[i].kw;
+        const int rank = mask_rank_factors(masks[i].mask_host, kh, kw, fa[i], fb[i]);
+        st = alloc_operator(masks[i].N, kh, kw, masks[i].border, rank, &ops[i]);
         if (st == DCTF_OK)
-            st = hip_status(hipMemcpyAsync(ops[i]->img.mask, masks[i].mask_host,
-                                           sizeof(double) * masks[i].kh * masks[i].kw,
+            st = hip_status(hipMemcpyAsync(ops[i]->img.mask, masks[i].mask_host, sizeof(double) * kh * kw,
+                                           hipMemcpyHostToDevice, s));
+        if (st == DCTF_OK)
+            st = hip_status(hipMemcpyAsync(ops[i]->img.fac_a, fa[i].data(), sizeof(double) * rank * kh,
+                                           hipMemcpyHostToDevice, s));
+        if (st == DCTF_OK)
+            st = hip_status(hipMemcpyAsync(ops[i]->img.fac_b, fb[i].data(), sizeof(double) * rank * kw,
                                            hipMemcpyHostToDevice, s));
     }
     if (st == DCTF_OK)
         st = launch_rebuild(ops.data(), n, s);
-    // The mask copies are from pageable memory: make them complete before the
-    // caller may free its masks.
+    // The mask and factor copies are from pageable memory: make them complete
+    // before the caller may free its masks.
     if (st == DCTF_OK)
         st = hip_status(hipStreamSynchronize(s));
     if (st != DCTF_OK) {
@@ -323,6 +399,43 @@ extern "C" dctf_status dctf_filter_blocks(dctf_operator op, int prec, const floa
     int slot;
     timing_begin(s, &slot);
     st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
+    timing_end(s, slot);
+    return st;
+}
+
+extern "C" dctf_status dctf_operator_rank(dctf_operator op, int *rank)
+{
+    if (op == nullptr || rank == nullptr)
+        return DCTF_EINVAL;
+    *rank = op->rank;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double *Q_host)
+{
+    if (op == nullptr || P_host == nullptr || Q_host == nullptr)
+        return DCTF_EINVAL;
+    const size_t bytes = sizeof(double) * op->rank * op->N * op->N;
+    dctf_status st = hip_status(hipMemcpy(P_host, op->img.P64, bytes, hipMemcpyDeviceToHost));
+    if (st == DCTF_OK)
+        st = hip_status(hipMemcpy(Q_host, op->img.Q64, bytes, hipMemcpyDeviceToHost));
+    return st;
+}
+
+extern "C" dctf_status dctf_filter_blocks_factored(dctf_operator op, const float *in_dev, float *out_dev,
+                                                   int64_t B, dctf_stream stream)
+{
+    if (op == nullptr)
+        return DCTF_EINVAL;
+    if (op->N != 16 || op->rank > kFactoredMaxRank)
+        return DCTF_EUNSUPPORTED;
+    dctf_status st = validate_io(op->N, in_dev, out_dev, B);
+    if (st != DCTF_OK || B == 0)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    st = hip_status(launch_filter_factored(op->N, op->rank, op->img.P32, op->img.Q32, in_dev, out_dev, B, s));
     timing_end(s, slot);
     return st;
 }

@@ -240,17 +240,77 @@ __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
     }
 }
 
+// Factored (paper-form) operator: for rank term r and axis x (0: block rows
+// with fac_a and the kh anchor, 1: block columns with fac_b and kw),
+//   F = C M C^t,  M[i][m] = sum_p coef[p] [s_{p-a}(i) = m]  (valid shifts only),
+// i.e. F = sum_p coef[p] T_{p-a}: the DCT-domain matrices A (eq. 7) of the
+// mask's rank-one terms, so that H = sum_r P_r (x) Q_r and every block
+// becomes Y = sum_r P_r X Q_r^t (eq. 8, 11, 20 with the mask rows merged
+// into rank terms).  FP64 throughout; one workgroup per (operator, r, axis).
+__global__ __launch_bounds__(kThreads) void k_build_factors(BuildArgs args)
+{
+    const int op = blockIdx.y;
+    if (op >= args.n)
+        return;
+    const BuildDesc &d = args.d[op];
+    const int r = blockIdx.x >> 1, axis = blockIdx.x & 1;
+    if (r >= d.rank)
+        return;
+    const int N = d.N, NN = N * N, tid = threadIdx.x;
+    const int K = axis ? d.kw : d.kh, anchor = (K - 1) / 2;
+    const double *coef = axis ? d.img.fac_b + (size_t)r * d.kw : d.img.fac_a + (size_t)r * d.kh;
+    __shared__ double sC[kMaxN * kMaxN], sM[kMaxN * kMaxN], sT[kMaxN * kMaxN];
+    for (int e = tid; e < NN; e += kThreads) {
+        const int k = e / N, n = e % N;
+        const double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
+        sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N));
+        const int i = e / N, m = e % N;
+        double acc = 0.0;
+        for (int p = 0; p < K; ++p) {
+            bool ok;
+            const int src = src_index(i, p - anchor, N, d.border, &ok);
+            acc += (ok && src == m) ? coef[p] : 0.0;
+        }
+        sM[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < NN; e += kThreads) {   // T = C M
+        const int u = e / N, m = e % N;
+        double acc = 0.0;
+        for (int i = 0; i < N; ++i)
+            acc += sC[u * N + i] * sM[i * N + m];
+        sT[e] = acc;
+    }
+    __syncthreads();
+    double *F64 = (axis ? d.img.Q64 : d.img.P64) + (size_t)r * NN;
+    float *F32 = (axis ? d.img.Q32 : d.img.P32) + (size_t)r * NN;
+    for (int e = tid; e < NN; e += kThreads) {   // F = T C^t
+        const int u = e / N, k = e % N;
+        double acc = 0.0;
+        for (int m = 0; m < N; ++m)
+            acc += sT[u * N + m] * sC[k * N + m];
+        F64[e] = acc;
+        F32[e] = __double2float_rn(acc);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
 {
     if (args.n <= 0)
         return hipSuccess;
-    int maxN = 0;
-    for (int i = 0; i < args.n; ++i)
+    int maxN = 0, maxRank = 0;
+    for (int i = 0; i < args.n; ++i) {
         maxN = args.d[i].N > maxN ? args.d[i].N : maxN;
+        maxRank = args.d[i].rank > maxRank ? args.d[i].rank : maxRank;
+    }
     int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
     hipLaunchKernelGGL(k_build, dim3(groups, args.n), dim3(kThreads), 0, stream, args);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || maxRank <= 0)
+        return e;
+    hipLaunchKernelGGL(k_build_factors, dim3(2 * maxRank, args.n), dim3(kThreads), 0, stream, args);
     return hipGetLastError();
 }
 

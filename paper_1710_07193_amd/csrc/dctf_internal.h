@@ -22,6 +22,14 @@ struct OpImages {
     uint16_t *frag_lo;   // BF16 lo fragments
     float *frag_lf;      // FP32 A fragments of the low-frequency columns (split path)
     float *h0;           // DC column H[:, 0] in FP32 (N^2 floats)
+    // Rank factors of the mask, W = sum_r fac_a[r] (outer) fac_b[r], and the
+    // matching DCT-domain factors H = sum_r P_r (x) Q_r (paper form F =
+    // sum A . BLOCK . B^t): P_r = C (sum_p fac_a[r][p] S_{p-a_h}) C^t over
+    // block rows, Q_r likewise over block columns with fac_b[r].
+    double *fac_a;       // rank x kh
+    double *fac_b;       // rank x kw
+    double *P64, *Q64;   // rank x N x N each, row-major, FP64
+    float *P32, *Q32;    // FP32 (RNE) copies
 };
 
 // Low-frequency input coefficients that the split-BF16 path multiplies in
@@ -45,6 +53,7 @@ constexpr int kLfCount = 16;
 
 struct dctf_operator_s {
     int N, kh, kw, border;
+    int rank;     // terms of the rank factorisation of the mask (>= 1)
     int device;
     void *base;   // owning device allocation
     size_t bytes;
@@ -58,6 +67,7 @@ constexpr int kMaxBuildPerLaunch = 16;
 struct BuildDesc {
     OpImages img;
     int N, kh, kw, border;
+    int rank;
 };
 
 struct BuildArgs {
@@ -71,6 +81,17 @@ inline size_t frag_lf_elems(int N) { return (N >= 8) ? (size_t)N * N * kLfCount 
 
 // builder.hip
 hipError_t launch_build(const BuildArgs &args, hipStream_t stream);
+
+// Rank factorisation of a kh x kw mask (host, FP64): W = sum_r a_r b_r^t with
+// a_r (kh values) and b_r (kw values) appended to a and b.  Returns the rank
+// (at least 1: a zero mask gives one zero term).
+int mask_rank_factors(const double *W, int kh, int kw, std::vector<double> &a, std::vector<double> &b);
+
+// filter.hip — the factored (paper-form) path Y = sum_r P_r X Q_r^t, N = 16,
+// FP32, rank <= kFactoredMaxRank.
+constexpr int kFactoredMaxRank = 8;
+hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *in,
+                                  float *out, int64_t B, hipStream_t stream);
 
 // filter.hip — single-operator filter of B blocks.
 struct FilterArgs {

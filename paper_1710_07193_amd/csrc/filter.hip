@@ -274,7 +274,123 @@ hipError_t dispatch16_split(int variant, const FilterArgs &a, hipStream_t stream
     }
 }
 
+// ------------------------------------------------- N = 16, factored form
+//
+// Y = sum_r P_r X Q_r^t per block (the paper's A . BLOCK . B products with
+// the mask rows merged into rank terms), FP32 MFMA v_mfma_f32_16x16x4_f32.
+// Lane (n, g) of a wave loads X[n][4g..4g+3] (one 16-byte load per lane
+// covers the 1 KiB block) and the same slices of P_r and Q_r.  With the
+// contraction index of k-step s taken as 4g + s on both operands:
+//   stage 1: Z_r = X Q_r^t   (A = X, B = Q_r^t), D: lane (j, g) holds Z_r[4g + i][j];
+//   stage 2: Y^t += Z_r^t P_r^t (A = Z_r^t read straight from stage 1's D
+//            registers, B = P_r^t), D: lane (u, g) holds Y[u][4g + i],
+// which is the load layout again, so the store is one 16-byte access per
+// lane.  Each wave carries U blocks per iteration (independent MFMA chains)
+// and has the next U blocks' loads in flight.
+template <int R, int U>
+__global__ __launch_bounds__(256) void k_filter_factored16(const float *in, float *out, int64_t B,
+                                                           const float *P32, const float *Q32, int64_t waves)
+{
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= waves)
+        return;
+    const int off = n * 16 + 4 * g;
+    float4 P[R], Q[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        P[r] = ld4(P32 + r * 256 + off);
+        Q[r] = ld4(Q32 + r * 256 + off);
+    }
+    const int64_t units = (B + U - 1) / U;
+    const int64_t my_units = (units - wave + waves - 1) / waves;
+    auto load = [&](float4 (&x)[U], int64_t unit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t b = unit * U + u;
+            b = b < B ? b : B - 1;   // clamped: the store is skipped
+            x[u] = ld4_nt(in + b * 256 + off);
+        }
+    };
+    auto compute_store = [&](const float4 (&x)[U], int64_t unit) {
+        f32x4 y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            y[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float q[4] = {Q[r].x, Q[r].y, Q[r].z, Q[r].w};
+            const float p[4] = {P[r].x, P[r].y, P[r].z, P[r].w};
+            f32x4 z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+                z[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    z[u] = mfma_f32(xv[k], q[k], z[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    y[u] = mfma_f32(z[u][k], p[k], y[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t b = unit * U + u;
+            if (b < B)
+                st4_nt(out + b * 256 + off, y[u]);
+        }
+    };
+    float4 cur[U], nxt[U];
+    int64_t unit = wave;
+    load(cur, unit);
+    for (int64_t k = 1; k < my_units; ++k) {
+        load(nxt, unit + waves);
+        compute_store(cur, unit);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            cur[u] = nxt[u];
+        unit += waves;
+    }
+    compute_store(cur, unit);
+}
+
+template <int R>
+hipError_t run_factored16(const float *P32, const float *Q32, const float *in, float *out, int64_t B,
+                          hipStream_t stream)
+{
+    constexpr int U = 4;
+    const int64_t units = (B + U - 1) / U;
+    int64_t waves = (int64_t)cu_count() * 16;
+    waves = waves < units ? waves : units;
+    const int64_t groups = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_filter_factored16<R, U>), dim3((unsigned)groups), dim3(256), 0, stream, in, out, B,
+                       P32, Q32, waves);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *in,
+                                  float *out, int64_t B, hipStream_t stream)
+{
+    if (B <= 0)
+        return hipSuccess;
+    if (N != 16 || rank < 1 || rank > kFactoredMaxRank)
+        return hipErrorInvalidValue;
+    switch (rank) {
+    case 1: return run_factored16<1>(P32, Q32, in, out, B, stream);
+    case 2: return run_factored16<2>(P32, Q32, in, out, B, stream);
+    case 3: return run_factored16<3>(P32, Q32, in, out, B, stream);
+    case 4: return run_factored16<4>(P32, Q32, in, out, B, stream);
+    case 5: return run_factored16<5>(P32, Q32, in, out, B, stream);
+    case 6: return run_factored16<6>(P32, Q32, in, out, B, stream);
+    case 7: return run_factored16<7>(P32, Q32, in, out, B, stream);
+    default: return run_factored16<8>(P32, Q32, in, out, B, stream);
+    }
+}
 
 int variant_count(int N, int prec)
 {

@@ -85,6 +85,9 @@ def test_filter_and_batch_validation(lib):
     assert lib.dctf_rebuild_operators(None, -1, None) == -1
     assert lib.dctf_operator_fp64(None, None) == -1
     assert lib.dctf_autotune(None, 0, None, None, 1, 1, None, None, None) == -1
+    assert lib.dctf_operator_rank(None, None) == -1
+    assert lib.dctf_operator_factors_fp64(None, None, None) == -1
+    assert lib.dctf_filter_blocks_factored(None, None, None, 1, None) == -1
 
 
 def test_verify_and_forward_dct_validation(lib):
