@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
 {
     // N = 16 workgroups use the LDS for their double-buffered tiles, N = 8
     // workgroups for the per-wave staging of the coalesced I/O.
-    constexpr int k16 = PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32 : 2 * kTile16BytesSplit;
+    constexpr int k16 = PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split;
     constexpr int k8 = IO ? (kBatchThreads / 64) * 256 * 16 : 0;
     constexpr int kBytes = k16 > k8 ? k16 : k8;
     __shared__ __attribute__((aligned(16))) char smem[kBytes];
@@ -264,8 +264,7 @@ __global__ __launch_bounds__(kBatch8Threads) void k_batch8(BatchArgs a)
 template <int PREC>
 __global__ __launch_bounds__(kBatchThreads) void k_batch16(BatchArgs a)
 {
-    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32
-                                                                             : 2 * kTile16BytesSplit];
+    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split];
     worker16<PREC, kBatchDepth16>(a, blockIdx.x, smem);
 }
 

@@ -162,7 +162,7 @@ constexpr int kBatchThreads = 512;    // mixed and N = 16 batch workgroups
 constexpr int kBatch8Threads = 256;   // N = 8-only batch workgroups
 constexpr int kUnitBlocks8 = 16;    // blocks per N = 8 work unit (one MFMA tile)
 constexpr int kUnitBlocks16 = 16;   // blocks per N = 16 work unit
-constexpr int kBatchDepth16 = 3;    // N = 16 tiles of loads in flight
+constexpr int kBatchDepth16 = 2;    // N = 16 tiles of loads in flight
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t stream);
 // Workgroups per CU of the batch kernel for kind 8 (N = 8 only), 16 (N = 16

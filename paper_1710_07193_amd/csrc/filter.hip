@@ -119,8 +119,7 @@ __global__ __launch_bounds__(512) void k_filter_n16(FilterArgs a, int64_t tiles)
     const int64_t wg = blockIdx.x, G = gridDim.x;
     if (wg >= tiles)
         return;
-    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? 2 * kTile16BytesF32
-                                                                             : 2 * kTile16BytesSplit];
+    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split];
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
     Regs R;
     const int64_t count = (tiles - wg + G - 1) / G;
@@ -245,7 +244,7 @@ struct Variant16 {
 };
 // The FP32 kernel keeps the whole FP32 operator slice in registers; three
 // tiles in flight push it past the register file, so its table stops at two.
-const Variant16 kVariants16Split[] = {{3, "wg8_ahead3"}, {2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
+const Variant16 kVariants16Split[] = {{2, "wg8_ahead2"}, {3, "wg8_ahead3"}, {1, "wg8_ahead1"}};
 const Variant16 kVariants16F32[] = {{2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
 constexpr int kNumVariants16Split = sizeof(kVariants16Split) / sizeof(kVariants16Split[0]);
 constexpr int kNumVariants16F32 = sizeof(kVariants16F32) / sizeof(kVariants16F32[0]);

@@ -318,6 +318,11 @@ constexpr int kLd16Lf = 16;      // floats per block of the low-frequency FP32 p
 // LDS bytes of one 16-block tile buffer.
 constexpr int kTile16BytesF32 = 16 * kLd16F32 * 4;
 constexpr int kTile16BytesSplit = 2 * 16 * kLd16BF16 * 2 + 16 * kLd16Lf * 4;
+// LDS of the tile loop: two tiles, plus (split path) 64 floats that the
+// loader's lanes without a low-frequency coefficient write instead, so that
+// the extraction has no branches.
+constexpr int kSmem16F32 = 2 * kTile16BytesF32;
+constexpr int kSmem16Split = 2 * kTile16BytesSplit + 64 * 4;
 
 // Element offsets of 16-byte chunk c of row b.
 __device__ __forceinline__ int f32_chunk(int b, int c) { return b * kLd16F32 + 4 * (c ^ b); }
@@ -405,9 +410,11 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, float *lds, int 
 }
 
 // Split path: the low-frequency coefficients go to the FP32 array llf (slot
-// order of lf_slot) and enter the BF16 arrays as zeros.
+// order of lf_slot) and enter the BF16 arrays as zeros.  Every element is
+// written somewhere (other lanes' values to their word of `trash`), so the
+// extraction is branch-free.
 __device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, uint16_t *llo,
-                                              float *llf, int tid)
+                                              float *llf, float *trash, int tid)
 {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -417,10 +424,10 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, u
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int slot = lf_slot(16, 4 * c + e);
-            if (slot >= 0) {
-                llf[((slot >> 2) * 16 + b) * 4 + (slot & 3)] = xv[e];
-                xv[e] = 0.0f;
-            }
+            const bool lf = slot >= 0;
+            float *dst = lf ? llf + ((slot >> 2) * 16 + b) * 4 + (slot & 3) : trash + (tid & 63);
+            *dst = xv[e];
+            xv[e] = lf ? 0.0f : xv[e];
         }
         uint32_t h01, h23, l01, l23;
         split_bf16(make_float4(xv[0], xv[1], xv[2], xv[3]), h01, h23, l01, l23);
@@ -500,11 +507,12 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
     uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
     uint16_t *llo = lhi + 2 * kB16;
     float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
+    float *trash = llf + 2 * 16 * kLd16Lf;   // split path only: 64 floats past the two tiles
     auto put = [&](const Stage16 &S, int buf) {
         if constexpr (PREC == DCTF_PREC_FP32)
             stage16_store(S, lf + buf * kF32, tid);
         else
-            stage16_store(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, tid);
+            stage16_store(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, trash, tid);
     };
     auto stage = [&](Stage16 &S, const Ref &r) { stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid); };
 
