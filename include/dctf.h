@@ -150,9 +150,12 @@ dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double 
  * 16-byte aligned, non-overlapping (in-place is not supported).
  * prec: dctf_precision.  FP32: the MFMA sums over every column but the DC
  * column H[:,0], which is applied in FP32 VALU arithmetic.  Split-BF16: the
- * 16 low-frequency input coefficients (N = 8: rows u = 0, 1; N = 16: the
- * first 16 in zigzag order) are multiplied in FP32 MFMA, the others as
- * BF16 hi.hi + hi.lo + lo.hi; both accumulate in FP32.
+ * low-frequency input coefficients (N = 8: the 16 of rows u = 0, 1; N = 16:
+ * the first 8 in zigzag order) are multiplied in FP32 MFMA, the others as
+ * BF16 hi.hi + hi.lo + lo.hi; both accumulate in FP32.  The split keeps about
+ * 16 bits of each operand, so its error grows with the magnitude of the
+ * mid- and high-frequency coefficients: the 5e-3 bound holds for natural-image
+ * content, not for arbitrary inputs (binary stripe patterns reach ~2e-2).
  * For N <= 4 both precisions run one FP32 kernel (the operator is at most
  * 16 x 16).  B = 0 is a no-op.  Each block's result depends only on that
  * block and the operator: it is bit-identical whatever B, the tuning variant

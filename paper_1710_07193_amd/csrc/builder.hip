@@ -28,8 +28,9 @@
 //   frag32  FP32 A operand of v_mfma_f32_16x16x4_f32, DC column zeroed
 //   frag_hi / frag_lo  BF16 A operands of v_mfma_f32_16x16x32_bf16, with the
 //           low-frequency columns zeroed
-//   frag_lf FP32 A operand for the 16 low-frequency columns: slot q = 4 g + j
-//           of lf_slot() at ((t * 64 + lane) * 4 + j)
+//   frag_lf FP32 A operand for the low-frequency columns (lf_slot()): N = 8
+//           slot q = 4 g + j at ((t * 64 + lane) * 4 + j), N = 16 slot q = 2 g + j
+//           at ((t * 64 + lane) * 2 + j), j the k-step
 #include "dctf_internal.h"
 
 #include <math.h>
@@ -204,8 +205,10 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
             const int q = lf_slot(N, c);
             uint16_t hi = 0, lo = 0;
             if (q >= 0) {
-                const int t = r >> 4, m = r & 15, lane = 16 * (q >> 2) + m;
-                d.img.frag_lf[(t * 64 + lane) * 4 + (q & 3)] = h32;
+                // N = 8: slot 4g + j of k-step j (4 steps); N = 16: slot 2g + j (2 steps)
+                const int t = r >> 4, m = r & 15;
+                const int steps = lf_count(N) / 4, lane = 16 * (q / steps) + m;
+                d.img.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;
             } else {
                 hi = bf16_rne(h32);
                 lo = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(hi)));

@@ -36,18 +36,20 @@ struct OpImages {
 // FP32 MFMA instead of BF16 (they carry the largest magnitudes of natural
 // images, where a two-term BF16 split loses the most absolute precision).
 //   N = 8 : the 16 coefficients of rows u = 0, 1 (k < 16);
-//   N = 16: the first 16 in zigzag order: u + v <= 4, then (0, 5).
-// Returns the slot 0..15 of coefficient k, or -1.
+//   N = 16: the first 8 in zigzag order: u + v <= 2, then (0, 3), (1, 2).
+// Returns the slot of coefficient k (0 .. lf_count(N) - 1), or -1.
 __host__ __device__ inline int lf_slot(int N, int k)
 {
     if (N == 8)
         return k < 16 ? k : -1;
     const int u = k / N, v = k % N, d = u + v;
-    if (d <= 4)
+    if (d <= 2)
         return d * (d + 1) / 2 + u;
-    return (u == 0 && v == 5) ? 15 : -1;
+    if (d == 3 && u <= 1)
+        return 6 + u;
+    return -1;
 }
-constexpr int kLfCount = 16;
+__host__ __device__ constexpr int lf_count(int N) { return N == 16 ? 8 : 16; }
 
 }  // namespace dctf
 
@@ -77,7 +79,7 @@ struct BuildArgs {
 
 // Fragment sizes (elements) per operator.
 inline size_t frag_elems(int N) { return (N >= 8) ? (size_t)N * N * N * N : 0; }
-inline size_t frag_lf_elems(int N) { return (N >= 8) ? (size_t)N * N * kLfCount : 0; }
+inline size_t frag_lf_elems(int N) { return (N >= 8) ? (size_t)N * N * lf_count(N) : 0; }
 
 // builder.hip
 hipError_t launch_build(const BuildArgs &args, hipStream_t stream);

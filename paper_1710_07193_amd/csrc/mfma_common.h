@@ -313,7 +313,7 @@ __device__ __forceinline__ void tile8_coalesced(const Regs &R, const float4 xin[
 
 constexpr int kLd16F32 = 256;    // floats per LDS row (FP32 path)
 constexpr int kLd16BF16 = 256;   // BF16 per LDS row (split path)
-constexpr int kLd16Lf = 16;      // floats per block of the low-frequency FP32 part
+constexpr int kLd16Lf = 8;       // floats per block of the low-frequency FP32 part
 
 // LDS bytes of one 16-block tile buffer.
 constexpr int kTile16BytesF32 = 16 * kLd16F32 * 4;
@@ -336,7 +336,7 @@ struct OpRegs16F32 {
 struct OpRegs16BF16 {
     u32x4 hi[2][8];
     u32x4 lo[2][8];
-    float lf[2][4];     // [t][j]: FP32 A operand of the low-frequency k-steps
+    float lf[2][2];     // [t][j]: FP32 A operand of the two low-frequency k-steps
 };
 
 __device__ __forceinline__ void load_op16(OpRegs16F32 &R, const float *frag32, const float *h0,
@@ -373,11 +373,9 @@ __device__ __forceinline__ void load_op16(OpRegs16BF16 &R, const uint16_t *fhi, 
             R.hi[t][s] = *reinterpret_cast<const u32x4 *>(fhi + ((T * 8 + s) * 64 + lane) * 8);
             R.lo[t][s] = *reinterpret_cast<const u32x4 *>(flo + ((T * 8 + s) * 64 + lane) * 8);
         }
-        float4 v = ld4(flf + (T * 64 + lane) * 4);
+        const float2 v = *reinterpret_cast<const float2 *>(flf + (T * 64 + lane) * 2);
         R.lf[t][0] = v.x;
         R.lf[t][1] = v.y;
-        R.lf[t][2] = v.z;
-        R.lf[t][3] = v.w;
     }
 }
 
@@ -425,7 +423,7 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, u
         for (int e = 0; e < 4; ++e) {
             const int slot = lf_slot(16, 4 * c + e);
             const bool lf = slot >= 0;
-            float *dst = lf ? llf + ((slot >> 2) * 16 + b) * 4 + (slot & 3) : trash + (tid & 63);
+            float *dst = lf ? llf + ((slot >> 1) * 16 + b) * 2 + (slot & 1) : trash + (tid & 63);
             *dst = xv[e];
             xv[e] = lf ? 0.0f : xv[e];
         }
@@ -466,10 +464,11 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
     acc[1] = acc[0];
-    const float4 lv = *reinterpret_cast<const float4 *>(llf + (g * 16 + n) * 4);
-    const float lfv[4] = {lv.x, lv.y, lv.z, lv.w};
+    // low-frequency slots 2g + j of block n, FP32
+    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
+    const float lfv[2] = {lv.x, lv.y};
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int t = 0; t < 2; ++t)
             acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
