@@ -68,6 +68,8 @@ def _load():
                 "or_filter_pixels": ([i32, P, i32, i32, i32, i64, P, P, P, P], i32),
                 "or_idct_u8": ([i32, i64, P, P, P], i32),
                 "or_operator_probe": ([i32, P, i32, i32, i32, P], i32),
+                "or_filter_coeffs_to_pixels": ([i32, P, i32, i32, i32, i64, P, P, P, P], i32),
+                "or_pixel_operator_probe": ([i32, P, i32, i32, i32, P], i32),
                 "or_tile_u8": ([P, i32, i32, i32, P], i32),
             }
             for name, (args, res) in sig.items():
@@ -208,6 +210,46 @@ def operator_probe(N: int, W, border: int) -> np.ndarray:
     _check(_load().or_operator_probe(N, _ptr(W), W.shape[0], W.shape[1], border, _ptr(H)),
            "operator_probe")
     return H
+
+
+def filter_coeffs_to_pixels(X, W, border: int):
+    """From coefficient blocks ``[B, N, N]``: (f = filter(IDCT(X)) FP64,
+    uint8 pixels of f, near-1/2 flags)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    W = _mask(W)
+    N = X.shape[-1]
+    f = np.empty(X.shape, np.float64)
+    u8 = np.empty(X.shape, np.uint8)
+    nh = np.empty(X.shape, np.uint8)
+    _check(_load().or_filter_coeffs_to_pixels(N, _ptr(W), W.shape[0], W.shape[1], border,
+                                              X.size // (N * N), _ptr(X), _ptr(f), _ptr(u8), _ptr(nh)),
+           "filter_coeffs_to_pixels")
+    return f, u8, nh.astype(bool)
+
+
+def pixel_operator_probe(N: int, W, border: int) -> np.ndarray:
+    """G[:, k] = filter(IDCT(e_k)): the N^2 x N^2 map from coefficients to
+    filtered pixels, row = output pixel i*N+j, column = input coefficient."""
+    W = _mask(W)
+    G = np.empty((N * N, N * N), np.float64)
+    _check(_load().or_pixel_operator_probe(N, _ptr(W), W.shape[0], W.shape[1], border, _ptr(G)),
+           "pixel_operator_probe")
+    return G
+
+
+def dequantize(qcoef, qtable, dc_offset: float = 0.0) -> np.ndarray:
+    """JPEG-style dequantisation of integer coefficient blocks ``[B, N, N]``:
+    X[u][v] = qtable[u][v] * qcoef[u][v], plus ``dc_offset`` on X[0][0] (the
+    DC term of a level shift: a codec that subtracted 128 from every pixel
+    before its orthonormal DCT passes 128 * N here).  FP64."""
+    qc = np.asarray(qcoef, dtype=np.float64)
+    q = np.asarray(qtable, dtype=np.float64)
+    N = qc.shape[-1]
+    if q.shape != (N, N):
+        raise ValueError("qtable must be N x N")
+    X = qc * q
+    X[..., 0, 0] += dc_offset
+    return X
 
 
 def tile_u8(img, N: int) -> np.ndarray:

@@ -22,6 +22,9 @@
  *     method must reproduce (eq. 11 for zero padding, eq. 20 for
  *     replication), and the operator obtained by probing that map with unit
  *     coefficient vectors.
+ *   - the filtered pixels filter(IDCT(X)) of coefficient blocks and the
+ *     pixel-output operator probed the same way (the filtered result taken
+ *     back to the spatial domain, Sec. III);
  *   - the uint8 conversion of a filtered pixel (Sec. III): saturate to
  *     [0, 255] after rounding half up, the decision taken in FP32 (the
  *     precision the GPU verify kernel decides in); pixels whose FP64 value
@@ -289,6 +292,60 @@ int or_idct_u8(int N, int64_t B, const double *Y, uint8_t *u8, uint8_t *nearhalf
             if (nearhalf)
                 nearhalf[b * nn + k] = (uint8_t)near_half(x[k]);
         }
+    }
+    return 0;
+}
+
+/* Filtered pixels from coefficients, f = filter(IDCT(X)): the inverse DCT of
+ * eq. 3 followed by the block-local filter of eq. 5 / Fig. 1.  This is what
+ * the DCT-domain result becomes once it is taken back to the spatial domain
+ * and converted to uint8 (Sec. III), and, by the similarity of eq. 7-8,
+ * equals IDCT(F) for the filtered coefficients F of eq. 11 / eq. 20.
+ * f, u8 and nearhalf may each be NULL. */
+int or_filter_coeffs_to_pixels(int N, const double *W, int kh, int kw, int border, int64_t B,
+                               const double *X, double *f, uint8_t *u8, uint8_t *nearhalf)
+{
+    if (check_args(N, kh, kw, border) || B < 0)
+        return -1;
+    double C[OR_MAXN * OR_MAXN];
+    or_dct_matrix(N, C);
+    int64_t nn = (int64_t)N * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < B; ++b) {
+        double x[OR_MAXN * OR_MAXN], fb[OR_MAXN * OR_MAXN];
+        idct2_block(N, C, X + b * nn, x);
+        filter_block(N, x, W, kh, kw, border, fb);
+        for (int64_t k = 0; k < nn; ++k) {
+            if (f)
+                f[b * nn + k] = fb[k];
+            if (u8)
+                u8[b * nn + k] = to_u8(fb[k]);
+            if (nearhalf)
+                nearhalf[b * nn + k] = (uint8_t)near_half(fb[k]);
+        }
+    }
+    return 0;
+}
+
+/* The pixel-output operator probed column by column:
+ * G[:, k] = filter(IDCT(e_k)), row index = output pixel i*N+j, column index =
+ * input coefficient.  No Kronecker product is formed. */
+int or_pixel_operator_probe(int N, const double *W, int kh, int kw, int border, double *G)
+{
+    if (check_args(N, kh, kw, border))
+        return -1;
+    double C[OR_MAXN * OR_MAXN];
+    or_dct_matrix(N, C);
+    int nn = N * N;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nn; ++k) {
+        double e[OR_MAXN * OR_MAXN], x[OR_MAXN * OR_MAXN], f[OR_MAXN * OR_MAXN];
+        memset(e, 0, sizeof(double) * nn);
+        e[k] = 1.0;
+        idct2_block(N, C, e, x);
+        filter_block(N, x, W, kh, kw, border, f);
+        for (int r = 0; r < nn; ++r)
+            G[(int64_t)r * nn + k] = f[r];
     }
     return 0;
 }

@@ -10,6 +10,12 @@ publishes no data set and its test block's values are not available):
     img[y][x] = clamp(floor(128 + 60 sin(x/7) cos(y/5) + n + 1/2), 0, 255),
     n ~ N(0, 10^2), x the column and y the row, both 0-based.
 
+Quantised-coefficient recipe (stands in for the entropy-decoded blocks of a
+JPEG-style codec; no standard table is reproduced): a table
+    q[u][v] = round(q0 * (1 + slope * (u + v))),  q0 = 4, slope = 0.75,
+growing with frequency like a codec's luminance table, and integer
+coefficients round((X - dc_offset e_0) / q) of given coefficient blocks X.
+
 Mask recipes:
   * box K x K (1/K^2 each);
   * sampled Gaussian, g(u, v) ~ exp(-(u^2+v^2) / (2 sigma^2)) on the K x K
@@ -149,6 +155,22 @@ def coeff_like_fp32(seed: int, nblocks: int, N: int) -> np.ndarray:
     X = rng.standard_normal((nblocks, N, N)) * scale
     X[:, 0, 0] = rng.uniform(40.0 * N, 220.0 * N, size=nblocks)
     return X.astype(np.float32)
+
+
+def quant_table(N: int, q0: float = 4.0, slope: float = 0.75) -> np.ndarray:
+    """N x N quantisation table q[u][v] = round(q0 (1 + slope (u + v))), >= 1."""
+    u = np.arange(N, dtype=np.float64)[:, None]
+    v = np.arange(N, dtype=np.float64)[None, :]
+    return np.maximum(np.round(q0 * (1.0 + slope * (u + v))), 1.0)
+
+
+def quantize(X, qtable, dc_offset: float = 0.0) -> np.ndarray:
+    """int16 coefficients round((X - dc_offset e_0) / q) of blocks ``[B, N, N]``
+    (round half to even; the offset is taken off the DC term first)."""
+    Xs = np.array(X, dtype=np.float64)
+    Xs[..., 0, 0] -= dc_offset
+    c = np.rint(Xs / np.asarray(qtable, dtype=np.float64))
+    return np.clip(c, -32768, 32767).astype(np.int16)
 
 
 @dataclass
