@@ -114,6 +114,12 @@ dctf_status dctf_rebuild_operators(const dctf_operator *ops, int n, dctf_stream 
  * u*N+v, column = input coefficient) to host memory.  Synchronous. */
 dctf_status dctf_operator_fp64(dctf_operator op, double *host_out);
 
+/* Copy the FP64 pixel-domain operator G = (C (x) C)^t . H_dct (N^2 x N^2,
+ * row-major, row = output pixel i*N+j, column = input coefficient) to host
+ * memory: the filter of eq. 11 / eq. 20 followed by the inverse DCT of
+ * eq. 3.  The builder forms it in FP64 with H_dct.  Synchronous. */
+dctf_status dctf_operator_pixel_fp64(dctf_operator op, double *host_out);
+
 /* Block size, mask size and border of an operator (any pointer may be NULL). */
 dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *border);
 
@@ -178,6 +184,43 @@ dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, 
  */
 dctf_status dctf_filter_blocks_factored(dctf_operator op, const float *in_dev, float *out_dev, int64_t B,
                                         dctf_stream stream);
+
+/* ------------------------------------------------- filtered pixels (uint8) */
+
+/*
+ * Filter, inverse DCT and uint8 conversion in one pass: for every block,
+ * P[b] = u8(G . X[b]) with G the pixel-domain operator above, i.e. the
+ * filtered coefficients of eq. 11 / eq. 20 taken back to the spatial domain
+ * (eq. 3) and converted to uint8 as in Sec. III (round half up, saturate to
+ * [0, 255], decided in FP32).  The filtered coefficients are not written.
+ *   in_dev   B * N*N FP32 coefficients (device, block-contiguous, 16-byte aligned).
+ *   pix_dev  B * N*N bytes out (device, 16-byte aligned; block b at b*N*N,
+ *            row-major i*N+j inside the block), not overlapping in_dev.
+ *   prec     as for dctf_filter_blocks, applied to G (same low-frequency
+ *            FP32 columns in the split path).
+ * B = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned, overlapping,
+ * B < 0, bad prec), DCTF_EHIP (launch failure).
+ */
+dctf_status dctf_filter_blocks_u8(dctf_operator op, int prec, const float *in_dev, uint8_t *pix_dev,
+                                  int64_t B, dctf_stream stream);
+
+/*
+ * The same from quantised coefficients, as an entropy-decoded JPEG-style
+ * stream holds them (the setting of the paper's introduction: filtering
+ * compressed images in the DCT domain).  Each block is dequantised in
+ * registers, X[k] = qtable[k] * qcoef[k] (FP32), plus dc_offset on the DC
+ * coefficient X[0] (a codec that subtracted 128 from every pixel before its
+ * orthonormal DCT passes 128 * N), then filtered, inverse transformed and
+ * converted as above.
+ *   qcoef_dev   B * N*N int16 coefficients (device, 16-byte aligned).
+ *   qtable_dev  N*N FP32 dequantisation factors, row-major (device,
+ *               16-byte aligned).
+ *   dc_offset   finite.
+ * Errors as for dctf_filter_blocks_u8 (qtable_dev must not overlap pix_dev).
+ */
+dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *qcoef_dev,
+                                     const float *qtable_dev, float dc_offset, uint8_t *pix_dev,
+                                     int64_t B, dctf_stream stream);
 
 /* ---------------------------------------------------------- batched launch */
 

@@ -62,6 +62,9 @@ _SIGS = {
     "dctf_build_operators": ([ctypes.POINTER(_MaskDesc), _I, _P, ctypes.POINTER(_P)], _I),
     "dctf_rebuild_operators": ([ctypes.POINTER(_P), _I, _P], _I),
     "dctf_operator_fp64": ([_P, _P], _I),
+    "dctf_operator_pixel_fp64": ([_P, _P], _I),
+    "dctf_filter_blocks_u8": ([_P, _I, _P, _P, _I64, _P], _I),
+    "dctf_filter_quantized_u8": ([_P, _I, _P, _P, ctypes.c_float, _P, _I64, _P], _I),
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
     "dctf_filter_blocks": ([_P, _I, _P, _P, _I64, _P], _I),
@@ -198,6 +201,13 @@ def dctf_operator_fp64(op: Operator) -> np.ndarray:
     return H
 
 
+def dctf_operator_pixel_fp64(op: Operator) -> np.ndarray:
+    nn = op.N * op.N
+    G = np.empty((nn, nn), np.float64)
+    _check(_lib.dctf_operator_pixel_fp64(op, G.ctypes.data_as(_P)), "dctf_operator_pixel_fp64")
+    return G
+
+
 def dctf_operator_info(op: Operator):
     vals = [ctypes.c_int() for _ in range(4)]
     _check(_lib.dctf_operator_info(op, *[ctypes.byref(v) for v in vals]), "dctf_operator_info")
@@ -238,6 +248,31 @@ def dctf_filter_blocks_factored(op: Operator, X: torch.Tensor, Y: torch.Tensor, 
     _check(_lib.dctf_filter_blocks_factored(op, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
                                             X.numel() // nn, _stream(stream)),
            "dctf_filter_blocks_factored")
+
+
+def dctf_filter_blocks_u8(op: Operator, prec: int, X: torch.Tensor, pix: torch.Tensor, stream=None):
+    """pix[b] = u8(IDCT(H_dct . X[b])); X float32, pix uint8, B*N*N elements each."""
+    nn = op.N * op.N
+    if X.numel() % nn or pix.numel() != X.numel():
+        raise ValueError("X and pix must hold the same whole number of N*N blocks")
+    _check(_lib.dctf_filter_blocks_u8(op, prec, _dptr(X, torch.float32, "X"), _dptr(pix, torch.uint8, "pix"),
+                                      X.numel() // nn, _stream(stream)),
+           "dctf_filter_blocks_u8")
+
+
+def dctf_filter_quantized_u8(op: Operator, prec: int, qcoef: torch.Tensor, qtable: torch.Tensor,
+                             dc_offset: float, pix: torch.Tensor, stream=None):
+    """pix[b] = u8(IDCT(H_dct . (qtable * qcoef[b] + dc_offset e_0))); qcoef int16,
+    qtable float32 (N*N), pix uint8."""
+    nn = op.N * op.N
+    if qcoef.numel() % nn or pix.numel() != qcoef.numel():
+        raise ValueError("qcoef and pix must hold the same whole number of N*N blocks")
+    if qtable.numel() != nn:
+        raise ValueError("qtable must hold N*N factors")
+    _check(_lib.dctf_filter_quantized_u8(op, prec, _dptr(qcoef, torch.int16, "qcoef"),
+                                         _dptr(qtable, torch.float32, "qtable"), float(dc_offset),
+                                         _dptr(pix, torch.uint8, "pix"), qcoef.numel() // nn, _stream(stream)),
+           "dctf_filter_quantized_u8")
 
 
 def filter_blocks(op: Operator, X: torch.Tensor, prec: int = DCTF_PREC_SPLIT_BF16, stream=None):

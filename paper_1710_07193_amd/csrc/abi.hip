@@ -184,13 +184,17 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
     size_t off = 0;
     const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
-    const size_t o_h64 = off;  off = align_up(off + sizeof(double) * N4);
-    const size_t o_h32 = off;  off = align_up(off + sizeof(float) * N4);
-    const size_t o_f32 = off;  off = align_up(off + sizeof(float) * F);
-    const size_t o_fhi = off;  off = align_up(off + sizeof(uint16_t) * F);
-    const size_t o_flo = off;  off = align_up(off + sizeof(uint16_t) * F);
-    const size_t o_flf = off;  off = align_up(off + sizeof(float) * frag_lf_elems(N));
-    const size_t o_h0 = off;   off = align_up(off + sizeof(float) * NN);
+    // one dense image set per domain (DCT-domain H, pixel-domain G)
+    size_t o_h64[2], o_h32[2], o_f32[2], o_fhi[2], o_flo[2], o_flf[2], o_h0[2];
+    for (int d = 0; d < 2; ++d) {
+        o_h64[d] = off; off = align_up(off + sizeof(double) * N4);
+        o_h32[d] = off; off = align_up(off + sizeof(float) * N4);
+        o_f32[d] = off; off = align_up(off + sizeof(float) * F);
+        o_fhi[d] = off; off = align_up(off + sizeof(uint16_t) * F);
+        o_flo[d] = off; off = align_up(off + sizeof(uint16_t) * F);
+        o_flf[d] = off; off = align_up(off + sizeof(float) * frag_lf_elems(N));
+        o_h0[d] = off;  off = align_up(off + sizeof(float) * NN);
+    }
     const size_t o_fa = off;   off = align_up(off + sizeof(double) * rank * kh);
     const size_t o_fb = off;   off = align_up(off + sizeof(double) * rank * kw);
     const size_t o_p64 = off;  off = align_up(off + sizeof(double) * rank * NN);
@@ -216,13 +220,16 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     op->base = base;
     op->bytes = off;
     op->img.mask = reinterpret_cast<double *>(b + o_mask);
-    op->img.H64 = reinterpret_cast<double *>(b + o_h64);
-    op->img.H32 = reinterpret_cast<float *>(b + o_h32);
-    op->img.frag32 = F ? reinterpret_cast<float *>(b + o_f32) : nullptr;
-    op->img.frag_hi = F ? reinterpret_cast<uint16_t *>(b + o_fhi) : nullptr;
-    op->img.frag_lo = F ? reinterpret_cast<uint16_t *>(b + o_flo) : nullptr;
-    op->img.frag_lf = F ? reinterpret_cast<float *>(b + o_flf) : nullptr;
-    op->img.h0 = reinterpret_cast<float *>(b + o_h0);
+    for (int d = 0; d < 2; ++d) {
+        DenseImages &D = d == 0 ? op->img.dct : op->img.pix;
+        D.H64 = reinterpret_cast<double *>(b + o_h64[d]);
+        D.H32 = reinterpret_cast<float *>(b + o_h32[d]);
+        D.frag32 = F ? reinterpret_cast<float *>(b + o_f32[d]) : nullptr;
+        D.frag_hi = F ? reinterpret_cast<uint16_t *>(b + o_fhi[d]) : nullptr;
+        D.frag_lo = F ? reinterpret_cast<uint16_t *>(b + o_flo[d]) : nullptr;
+        D.frag_lf = F ? reinterpret_cast<float *>(b + o_flf[d]) : nullptr;
+        D.h0 = reinterpret_cast<float *>(b + o_h0[d]);
+    }
     op->rank = rank;
     op->img.fac_a = reinterpret_cast<double *>(b + o_fa);
     op->img.fac_b = reinterpret_cast<double *>(b + o_fb);
@@ -234,12 +241,13 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     return DCTF_OK;
 }
 
-static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s)
+static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s, unsigned parts)
 {
     for (int first = 0; first < n; first += kMaxBuildPerLaunch) {
         BuildArgs args;
         memset(&args, 0, sizeof(args));
         args.n = std::min(kMaxBuildPerLaunch, n - first);
+        args.parts = parts;
         for (int i = 0; i < args.n; ++i) {
             const dctf_operator op = ops[first + i];
             args.d[i].img = op->img;
@@ -287,7 +295,7 @@ extern "C" dctf_status dctf_build_operators(const dctf_mask_desc *masks, int n, 
                                            hipMemcpyHostToDevice, s));
     }
     if (st == DCTF_OK)
-        st = launch_rebuild(ops.data(), n, s);
+        st = launch_rebuild(ops.data(), n, s, kBuildAll);
     // The mask and factor copies are from pageable memory: make them complete
     // before the caller may free its masks.
     if (st == DCTF_OK)
@@ -318,7 +326,7 @@ extern "C" dctf_status dctf_rebuild_operators(const dctf_operator *ops, int n, d
     for (int i = 0; i < n; ++i)
         if (ops[i] == nullptr)
             return DCTF_EINVAL;
-    return launch_rebuild(ops, n, static_cast<hipStream_t>(stream));
+    return launch_rebuild(ops, n, static_cast<hipStream_t>(stream), kBuildAll);
 }
 
 extern "C" dctf_status dctf_operator_fp64(dctf_operator op, double *host_out)
@@ -326,7 +334,15 @@ extern "C" dctf_status dctf_operator_fp64(dctf_operator op, double *host_out)
     if (op == nullptr || host_out == nullptr)
         return DCTF_EINVAL;
     const size_t NN = (size_t)op->N * op->N;
-    return hip_status(hipMemcpy(host_out, op->img.H64, sizeof(double) * NN * NN, hipMemcpyDeviceToHost));
+    return hip_status(hipMemcpy(host_out, op->img.dct.H64, sizeof(double) * NN * NN, hipMemcpyDeviceToHost));
+}
+
+extern "C" dctf_status dctf_operator_pixel_fp64(dctf_operator op, double *host_out)
+{
+    if (op == nullptr || host_out == nullptr)
+        return DCTF_EINVAL;
+    const size_t NN = (size_t)op->N * op->N;
+    return hip_status(hipMemcpy(host_out, op->img.pix.H64, sizeof(double) * NN * NN, hipMemcpyDeviceToHost));
 }
 
 extern "C" dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *border)
@@ -375,12 +391,12 @@ static FilterArgs filter_args(dctf_operator op, const float *in, float *out, int
     a.in = in;
     a.out = out;
     a.B = B;
-    a.frag32 = op->img.frag32;
-    a.frag_hi = op->img.frag_hi;
-    a.frag_lo = op->img.frag_lo;
-    a.frag_lf = op->img.frag_lf;
-    a.h0 = op->img.h0;
-    a.H32 = op->img.H32;
+    a.frag32 = op->img.dct.frag32;
+    a.frag_hi = op->img.dct.frag_hi;
+    a.frag_lo = op->img.dct.frag_lo;
+    a.frag_lf = op->img.dct.frag_lf;
+    a.h0 = op->img.dct.h0;
+    a.H32 = op->img.dct.H32;
     return a;
 }
 
@@ -438,6 +454,56 @@ extern "C" dctf_status dctf_filter_blocks_factored(dctf_operator op, const float
     st = hip_status(launch_filter_factored(op->N, op->rank, op->img.P32, op->img.Q32, in_dev, out_dev, B, s));
     timing_end(s, slot);
     return st;
+}
+
+// ============================================================ pixel output
+
+static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void *in, const float *qtab,
+                             float dc_offset, uint8_t *pix, int64_t B, dctf_stream stream)
+{
+    if (op == nullptr)
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
+        return DCTF_EINVAL;
+    if (B < 0 || !std::isfinite(dc_offset))
+        return DCTF_EINVAL;
+    if (B == 0)
+        return DCTF_OK;
+    const size_t nn = (size_t)op->N * op->N;
+    const size_t in_bytes = (size_t)B * nn * (in_kind ? sizeof(int16_t) : sizeof(float));
+    if (in == nullptr || pix == nullptr || !aligned16(in) || !aligned16(pix))
+        return DCTF_EINVAL;
+    if (in_kind && (qtab == nullptr || !aligned16(qtab) || ranges_overlap(qtab, nn * sizeof(float), pix, (size_t)B * nn)))
+        return DCTF_EINVAL;
+    if (ranges_overlap(in, in_bytes, pix, (size_t)B * nn))
+        return DCTF_EINVAL;
+    PxArgs a;
+    a.in = in_kind ? nullptr : static_cast<const float *>(in);
+    a.qin = in_kind ? static_cast<const int16_t *>(in) : nullptr;
+    a.qtab = qtab;
+    a.dc_offset = dc_offset;
+    a.pix = pix;
+    a.B = B;
+    a.G = op->img.pix;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    dctf_status st = hip_status(launch_filter_px(op->N, prec, in_kind, a, s));
+    timing_end(s, slot);
+    return st;
+}
+
+extern "C" dctf_status dctf_filter_blocks_u8(dctf_operator op, int prec, const float *in_dev, uint8_t *pix_dev,
+                                             int64_t B, dctf_stream stream)
+{
+    return filter_px(op, prec, 0, in_dev, nullptr, 0.0f, pix_dev, B, stream);
+}
+
+extern "C" dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *qcoef_dev,
+                                                const float *qtable_dev, float dc_offset, uint8_t *pix_dev,
+                                                int64_t B, dctf_stream stream)
+{
+    return filter_px(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, pix_dev, B, stream);
 }
 
 // ==================================================================== batch
@@ -527,8 +593,8 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<ch
         if (opi < 0) {
             opi = (int)ops.size();
             ops.push_back(j.op);
-            od.push_back({j.op->img.frag32, j.op->img.frag_hi, j.op->img.frag_lo, j.op->img.frag_lf,
-                          j.op->img.h0});
+            const DenseImages &D = j.op->img.dct;
+            od.push_back({D.frag32, D.frag_hi, D.frag_lo, D.frag_lf, D.h0});
         }
         JobDesc d;
         d.in = j.in;
@@ -690,7 +756,7 @@ extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int pr
 static dctf_status batch_enqueue(dctf_batch b, unsigned flags, hipStream_t s)
 {
     if (flags & DCTF_RUN_REBUILD_OPERATORS) {
-        dctf_status st = launch_rebuild(b->ops.data(), (int)b->ops.size(), s);
+        dctf_status st = launch_rebuild(b->ops.data(), (int)b->ops.size(), s, kBuildDct);
         if (st != DCTF_OK)
             return st;
     }

@@ -17,7 +17,14 @@
 //
 // The sum over q is taken first: G_p[j][l] = sum_q W[p][q] C[l][s_q(j)],
 // B_p = C G_p (so B_p[v][l] = sum_q W[p][q] T_q[v][l]); then
-// H += T_p (x) B_p for each mask row p.  Mask rows are processed in chunks
+// H += T_p (x) B_p for each mask row p.
+//
+// The same launch also forms the pixel-domain operator G = (C (x) C)^t H,
+// the map from coefficients to filtered pixels (the filtered block taken
+// back to the spatial domain, eq. 3).  Because C^t C = I, its factors are
+// C^t T_p = S_p C^t and C^t B_p = G_p, so
+//   G[(i,j),(k,l)] = sum_p [s_{p-a_h}(i) valid] C[k][s_{p-a_h}(i)] G_p[j][l],
+// built in the same loop with T_p replaced by S_p C^t and B_p by G_p.  Mask rows are processed in chunks
 // that fit in LDS (all rows at once for the usual mask sizes), three barriers
 // per chunk.  Everything is FP64.  One workgroup owns 16 rows of H (all N^2
 // columns) for one operator and writes every image of those rows: FP64,
@@ -98,7 +105,7 @@ template <int N>
 constexpr int chunk_rows() { return N >= 16 ? 8 : (N == 8 ? 17 : 33); }
 
 template <int N>
-__device__ void build_op(const BuildDesc &d, int r0, double *lds)
+__device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
 {
     constexpr int NN = N * N;
     constexpr int P = chunk_rows<N>();
@@ -107,6 +114,8 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
     constexpr int per_thread = (owned + kThreads - 1) / kThreads;
     const int kh = d.kh, kw = d.kw, border = d.border;
     const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+    const bool pix = domain == 1;   // pixel-domain operator G instead of H_dct
+    const DenseImages &out = pix ? d.img.pix : d.img.dct;
 
     double *sC = lds;                 // NN
     double *sW = sC + NN;             // kh * kw (<= 33 * 33)
@@ -139,11 +148,18 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
             double s = 0.0;
             if (which == 0) {
                 const int dp = p0 + pp - ah;
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
+                if (pix) {
+                    // (S_p C^t)[i][k] with (i, k) = (a, b)
                     bool ok;
-                    const int m = src_index(i, dp, N, border, &ok);
-                    s += ok ? sC[a * N + i] * sC[b * N + m] : 0.0;
+                    const int m = src_index(a, dp, N, border, &ok);
+                    s = ok ? sC[b * N + m] : 0.0;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        bool ok;
+                        const int m = src_index(i, dp, N, border, &ok);
+                        s += ok ? sC[a * N + i] * sC[b * N + m] : 0.0;
+                    }
                 }
                 sT[pp * NN + idx] = s;
             } else {
@@ -157,17 +173,20 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
             }
         }
         __syncthreads();
-        // B_p[v][l] = sum_j C[v][j] G_p[j][l]
-        for (int e = tid; e < np * NN; e += kThreads) {
-            const int pp = e / NN, idx = e % NN, v = idx / N, l = idx % N;
-            double s = 0.0;
+        // B_p[v][l] = sum_j C[v][j] G_p[j][l] (the pixel domain uses G_p itself)
+        if (!pix) {
+            for (int e = tid; e < np * NN; e += kThreads) {
+                const int pp = e / NN, idx = e % NN, v = idx / N, l = idx % N;
+                double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < N; ++j)
-                s += sC[v * N + j] * sG[pp * NN + j * N + l];
-            sB[e] = s;
+                for (int j = 0; j < N; ++j)
+                    s += sC[v * N + j] * sG[pp * NN + j * N + l];
+                sB[e] = s;
+            }
         }
         __syncthreads();
-        // H[(u,v),(k,l)] += sum_p T_p[u][k] B_p[v][l]
+        // H[(u,v),(k,l)] += sum_p T_p[u][k] B_p[v][l]  (pixel domain: (S_p C^t)[i][k] G_p[j][l])
+        const double *sR = pix ? sG : sB;
 #pragma unroll
         for (int o = 0; o < per_thread; ++o) {
             const int e = tid + o * kThreads;
@@ -176,7 +195,7 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
                 const int u = r / N, v = r % N, k = c / N, l = c % N;
                 double s = acc[o];
                 for (int pp = 0; pp < np; ++pp)
-                    s += sT[pp * NN + u * N + k] * sB[pp * NN + v * N + l];
+                    s += sT[pp * NN + u * N + k] * sR[pp * NN + v * N + l];
                 acc[o] = s;
             }
         }
@@ -191,14 +210,14 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
         const int r = r0 + e / NN, c = e % NN;
         const double h = acc[o];
         const float h32 = __double2float_rn(h);
-        d.img.H64[(size_t)r * NN + c] = h;
-        d.img.H32[(size_t)r * NN + c] = h32;
+        out.H64[(size_t)r * NN + c] = h;
+        out.H32[(size_t)r * NN + c] = h32;
         if (c == 0)
-            d.img.h0[r] = h32;
+            out.h0[r] = h32;
         if constexpr (N >= 8) {
             // FP32 MFMA image: the operator without its DC column, which the
             // FP32 filter applies separately in VALU arithmetic.
-            d.img.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
+            out.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
             // Split path: low-frequency columns (DC included) go to the FP32
             // MFMA image frag_lf; every other column is split into BF16
             // hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
@@ -208,14 +227,14 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds)
                 // N = 8: slot 4g + j of k-step j (4 steps); N = 16: slot 2g + j (2 steps)
                 const int t = r >> 4, m = r & 15;
                 const int steps = lf_count(N) / 4, lane = 16 * (q / steps) + m;
-                d.img.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;
+                out.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;
             } else {
                 hi = bf16_rne(h32);
                 lo = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(hi)));
             }
             const int fi = frag16_index(N, r, c);
-            d.img.frag_hi[fi] = hi;
-            d.img.frag_lo[fi] = lo;
+            out.frag_hi[fi] = hi;
+            out.frag_lo[fi] = lo;
         }
     }
 }
@@ -235,11 +254,13 @@ __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
     if (r0 >= NN)
         return;
     __shared__ double lds[kLdsDoubles];
+    // z = 0: H_dct, z = 1: pixel-domain G (only the parts requested are in the grid)
+    const int domain = (args.parts & kBuildDct) ? (int)blockIdx.z : 1;
     switch (d.N) {
-    case 2: build_op<2>(d, r0, lds); break;
-    case 4: build_op<4>(d, r0, lds); break;
-    case 8: build_op<8>(d, r0, lds); break;
-    default: build_op<16>(d, r0, lds); break;
+    case 2: build_op<2>(d, r0, lds, domain); break;
+    case 4: build_op<4>(d, r0, lds, domain); break;
+    case 8: build_op<8>(d, r0, lds, domain); break;
+    default: build_op<16>(d, r0, lds, domain); break;
     }
 }
 
@@ -308,11 +329,16 @@ hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
         maxN = args.d[i].N > maxN ? args.d[i].N : maxN;
         maxRank = args.d[i].rank > maxRank ? args.d[i].rank : maxRank;
     }
-    int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
-    hipLaunchKernelGGL(k_build, dim3(groups, args.n), dim3(kThreads), 0, stream, args);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || maxRank <= 0)
-        return e;
+    const int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
+    const int domains = ((args.parts & kBuildDct) ? 1 : 0) + ((args.parts & kBuildPix) ? 1 : 0);
+    if (domains > 0) {
+        hipLaunchKernelGGL(k_build, dim3(groups, args.n, domains), dim3(kThreads), 0, stream, args);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (!(args.parts & kBuildFactors) || maxRank <= 0)
+        return hipSuccess;
     hipLaunchKernelGGL(k_build_factors, dim3(2 * maxRank, args.n), dim3(kThreads), 0, stream, args);
     return hipGetLastError();
 }

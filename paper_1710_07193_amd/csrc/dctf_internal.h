@@ -12,16 +12,24 @@ namespace dctf {
 
 // ---------------------------------------------------------------- operator
 
-// Device image of one operator, all in a single allocation.
-struct OpImages {
-    double *mask;        // kh*kw, row-major (device copy of the caller's mask)
+// One dense N^2 x N^2 operator (columns = input coefficients) in every form
+// the kernels read.
+struct DenseImages {
     double *H64;         // N^2 x N^2 row-major, FP64
     float *H32;          // N^2 x N^2 row-major, FP32 (RNE of H64)
     float *frag32;       // FP32 MFMA A-operand fragments (N = 8, 16), DC column zeroed
-    uint16_t *frag_hi;   // BF16 hi fragments (N = 8, 16), DC column zeroed
+    uint16_t *frag_hi;   // BF16 hi fragments (N = 8, 16), low-frequency columns zeroed
     uint16_t *frag_lo;   // BF16 lo fragments
     float *frag_lf;      // FP32 A fragments of the low-frequency columns (split path)
     float *h0;           // DC column H[:, 0] in FP32 (N^2 floats)
+};
+
+// Device image of one operator, all in a single allocation.
+struct OpImages {
+    double *mask;        // kh*kw, row-major (device copy of the caller's mask)
+    DenseImages dct;     // H_dct: coefficients -> filtered coefficients (row u*N+v)
+    DenseImages pix;     // G = (C (x) C)^t H_dct: coefficients -> filtered pixels
+                         // (row i*N+j), the filter followed by the inverse DCT
     // Rank factors of the mask, W = sum_r fac_a[r] (outer) fac_b[r], and the
     // matching DCT-domain factors H = sum_r P_r (x) Q_r (paper form F =
     // sum A . BLOCK . B^t): P_r = C (sum_p fac_a[r][p] S_{p-a_h}) C^t over
@@ -72,9 +80,16 @@ struct BuildDesc {
     int rank;
 };
 
+// Parts of an operator a builder call forms.
+constexpr unsigned kBuildDct = 1u;       // H_dct images (dense filter, batches, server)
+constexpr unsigned kBuildPix = 2u;       // pixel-domain images (filter + inverse DCT)
+constexpr unsigned kBuildFactors = 4u;   // rank factors P_r, Q_r (factored filter)
+constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors;
+
 struct BuildArgs {
     BuildDesc d[kMaxBuildPerLaunch];
     int n;
+    unsigned parts;   // kBuild* bits
 };
 
 // Fragment sizes (elements) per operator.
@@ -94,6 +109,20 @@ int mask_rank_factors(const double *W, int kh, int kw, std::vector<double> &a, s
 constexpr int kFactoredMaxRank = 8;
 hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *in,
                                   float *out, int64_t B, hipStream_t stream);
+
+// pixels.hip — filter + inverse DCT + uint8 in one pass (pixel-domain images),
+// from FP32 coefficients (IN = 0) or from quantised int16 coefficients that
+// are dequantised in registers (IN = 1).
+struct PxArgs {
+    const float *in;        // IN = 0: B * N*N FP32 coefficients
+    const int16_t *qin;     // IN = 1: B * N*N quantised coefficients
+    const float *qtab;      // IN = 1: N*N dequantisation factors (device)
+    float dc_offset;        // IN = 1: added to every dequantised DC coefficient
+    uint8_t *pix;           // B * N*N filtered pixels
+    int64_t B;
+    DenseImages G;          // the pixel-domain images of the operator
+};
+hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
 
 // filter.hip — single-operator filter of B blocks.
 struct FilterArgs {

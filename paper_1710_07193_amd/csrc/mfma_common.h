@@ -70,6 +70,35 @@ __device__ __forceinline__ void st4_nt(float *p, f32x4 v)
     __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(p));
 }
 
+// uint8 conversion of a filtered pixel (Sec. III): round half up, saturate
+// to [0, 255], decided in FP32 (NaN gives 0).
+__device__ __forceinline__ uint32_t pixel_u8(float p)
+{
+    const float r = floorf(p + 0.5f);
+    return (uint32_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
+}
+
+// Four pixels -> one little-endian word (first pixel in the low byte).
+__device__ __forceinline__ uint32_t pack_u8x4(float a, float b, float c, float d)
+{
+    return pixel_u8(a) | (pixel_u8(b) << 8) | (pixel_u8(c) << 16) | (pixel_u8(d) << 24);
+}
+
+// Eight quantised coefficients (one 16-byte load, little-endian int16) times
+// their dequantisation factors q[0..7]; `dc` is added to the first one.
+__device__ __forceinline__ void dequant8(u32x4 raw, const float q[8], float dc, float4 &lo, float4 &hi)
+{
+    float x[8];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        x[2 * w] = (float)(int16_t)(raw[w] & 0xffffu) * q[2 * w];
+        x[2 * w + 1] = (float)((int32_t)raw[w] >> 16) * q[2 * w + 1];
+    }
+    x[0] += dc;
+    lo = make_float4(x[0], x[1], x[2], x[3]);
+    hi = make_float4(x[4], x[5], x[6], x[7]);
+}
+
 // ------------------------------------------------------------------ N = 8
 //
 // One wave holds the whole 64 x 64 operator in VGPRs as MFMA A fragments and
@@ -379,14 +408,60 @@ __device__ __forceinline__ void load_op16(OpRegs16BF16 &R, const uint16_t *fhi, 
     }
 }
 
-// LDS staging of one 16-block tile: thread q of the workgroup holds the
-// 16-byte chunk (block q / 64, coefficients 4(q % 64) .. +3) and the chunk
-// q + 512.
-struct Stage16 {
+// LDS staging of one 16-block tile.  Each thread holds two 16-byte FP32
+// chunks of the tile (stage16_pos): from FP32 coefficients (IN = 0) thread q
+// of the workgroup holds chunk (block q / 64, coefficients 4(q % 64) .. +3)
+// and the chunk q + 512; from quantised int16 coefficients (IN = 1) its one
+// 16-byte load is coefficients 8(q % 32) .. +7 of block q / 32, kept raw in
+// registers and dequantised into the two chunks 2(q % 32), 2(q % 32) + 1
+// when the tile is written to LDS.
+template <int IN>
+struct Stage16;
+
+template <>
+struct Stage16<0> {
     float4 v[2];
 };
 
-__device__ __forceinline__ void stage16_load(Stage16 &S, const float *in, int64_t B, int64_t tile,
+template <>
+struct Stage16<1> {
+    u32x4 raw;
+};
+
+__device__ __forceinline__ void stage16_chunks(const Stage16<0> &S, const float *, float, float4 v[2])
+{
+    v[0] = S.v[0];
+    v[1] = S.v[1];
+}
+
+// qv: the thread's eight dequantisation factors; dc: the offset of the DC
+// coefficient (non-zero only in the thread holding it).
+__device__ __forceinline__ void stage16_chunks(const Stage16<1> &S, const float *qv, float dc, float4 v[2])
+{
+    dequant8(S.raw, qv, dc, v[0], v[1]);
+}
+
+template <int IN>
+__device__ __forceinline__ void stage16_pos(int tid, int h, int &b, int &c)
+{
+    if constexpr (IN == 0) {
+        const int q = tid + 512 * h;
+        b = q >> 6;
+        c = q & 63;
+    } else {
+        b = tid >> 5;
+        c = 2 * (tid & 31) + h;
+    }
+}
+
+__device__ __forceinline__ void stage16_load_q(Stage16<1> &S, const int16_t *qin, int64_t B, int tid)
+{
+    int64_t blk = tid >> 5;
+    blk = blk < B ? blk : B - 1;
+    S.raw = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(qin + blk * 256 + 8 * (tid & 31)));
+}
+
+__device__ __forceinline__ void stage16_load(Stage16<0> &S, const float *in, int64_t B, int64_t tile,
                                              int tid)
 {
 #pragma unroll
@@ -398,12 +473,16 @@ __device__ __forceinline__ void stage16_load(Stage16 &S, const float *in, int64_
     }
 }
 
-__device__ __forceinline__ void stage16_store(const Stage16 &S, float *lds, int tid)
+template <int IN>
+__device__ __forceinline__ void stage16_store(const Stage16<IN> &S, float *lds, int tid, const float *qv, float dc)
 {
+    float4 v[2];
+    stage16_chunks(S, qv, dc, v);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int q = tid + 512 * h;
-        *reinterpret_cast<float4 *>(lds + f32_chunk(q >> 6, q & 63)) = S.v[h];
+        int b, c;
+        stage16_pos<IN>(tid, h, b, c);
+        *reinterpret_cast<float4 *>(lds + f32_chunk(b, c)) = v[h];
     }
 }
 
@@ -411,14 +490,17 @@ __device__ __forceinline__ void stage16_store(const Stage16 &S, float *lds, int 
 // order of lf_slot) and enter the BF16 arrays as zeros.  Every element is
 // written somewhere (other lanes' values to their word of `trash`), so the
 // extraction is branch-free.
-__device__ __forceinline__ void stage16_store(const Stage16 &S, uint16_t *lhi, uint16_t *llo,
-                                              float *llf, float *trash, int tid)
+template <int IN>
+__device__ __forceinline__ void stage16_store(const Stage16<IN> &S, uint16_t *lhi, uint16_t *llo,
+                                              float *llf, float *trash, int tid, const float *qv, float dc)
 {
+    float4 v[2];
+    stage16_chunks(S, qv, dc, v);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int q = tid + 512 * h;
-        const int b = q >> 6, c = q & 63;
-        float xv[4] = {S.v[h].x, S.v[h].y, S.v[h].z, S.v[h].w};
+        int b, c;
+        stage16_pos<IN>(tid, h, b, c);
+        float xv[4] = {v[h].x, v[h].y, v[h].z, v[h].w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int slot = lf_slot(16, 4 * c + e);
@@ -495,11 +577,24 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // stages); LDS tiles are double-buffered with one barrier per tile.
 // ref(t) returns the UnitRef-like descriptor of the t-th tile (called in
 // increasing t); op_load(op) loads the operator fragments into R.
-template <int PREC, int D, typename Ref, typename RefFn, typename OpFn, typename Regs>
-__device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem)
+// IN = 0: FP32 coefficients from r.in; IN = 1: int16 coefficients from
+// r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term.
+// OUT = 0: FP32 results to r.out; OUT = 1: uint8 pixels to r.pix (the
+// operator is then the pixel-domain one).
+template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, typename RefFn, typename OpFn, typename Regs>
+__device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
+                                            const float *qtab = nullptr, float dc_offset = 0.0f)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
+    float qv[8];
+    float dc = 0.0f;
+    if constexpr (IN == 1) {
+        const float4 q0 = ld4(qtab + 8 * (tid & 31)), q1 = ld4(qtab + 8 * (tid & 31) + 4);
+        qv[0] = q0.x; qv[1] = q0.y; qv[2] = q0.z; qv[3] = q0.w;
+        qv[4] = q1.x; qv[5] = q1.y; qv[6] = q1.z; qv[7] = q1.w;
+        dc = (tid & 31) == 0 ? dc_offset : 0.0f;
+    }
     constexpr int kF32 = 16 * kLd16F32;
     constexpr int kB16 = 16 * kLd16BF16;
     float *lf = reinterpret_cast<float *>(smem);
@@ -507,15 +602,21 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
     uint16_t *llo = lhi + 2 * kB16;
     float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
     float *trash = llf + 2 * 16 * kLd16Lf;   // split path only: 64 floats past the two tiles
-    auto put = [&](const Stage16 &S, int buf) {
+    auto put = [&](const Stage16<IN> &S, int buf) {
         if constexpr (PREC == DCTF_PREC_FP32)
-            stage16_store(S, lf + buf * kF32, tid);
+            stage16_store<IN>(S, lf + buf * kF32, tid, qv, dc);
         else
-            stage16_store(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, trash, tid);
+            stage16_store<IN>(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, trash, tid, qv,
+                              dc);
     };
-    auto stage = [&](Stage16 &S, const Ref &r) { stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid); };
+    auto stage = [&](Stage16<IN> &S, const Ref &r) {
+        if constexpr (IN == 0)
+            stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid);
+        else
+            stage16_load_q(S, r.qin + r.blk0 * 256, r.B - r.blk0, tid);
+    };
 
-    Stage16 S[D];
+    Stage16<IN> S[D];
     Ref Rf[D];
 #pragma unroll
     for (int d = 0; d < D; ++d)
@@ -547,9 +648,15 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
                 tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
             const int64_t blk = rc.blk0 + n;
             if (blk < rc.B) {
-                float *dst = rc.out + blk * 256 + 32 * wave + 4 * g;
-                st4(dst, acc[0]);
-                st4(dst + 16, acc[1]);
+                if constexpr (OUT == 0) {
+                    float *dst = rc.out + blk * 256 + 32 * wave + 4 * g;
+                    st4(dst, acc[0]);
+                    st4(dst + 16, acc[1]);
+                } else {
+                    uint32_t *dst = reinterpret_cast<uint32_t *>(rc.pix + blk * 256 + 32 * wave + 4 * g);
+                    dst[0] = pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
+                    dst[4] = pack_u8x4(acc[1][0], acc[1][1], acc[1][2], acc[1][3]);
+                }
             }
             if (t + 1 >= count)
                 return;

@@ -88,6 +88,9 @@ def test_filter_and_batch_validation(lib):
     assert lib.dctf_operator_rank(None, None) == -1
     assert lib.dctf_operator_factors_fp64(None, None, None) == -1
     assert lib.dctf_filter_blocks_factored(None, None, None, 1, None) == -1
+    assert lib.dctf_operator_pixel_fp64(None, None) == -1
+    assert lib.dctf_filter_blocks_u8(None, 0, None, None, 1, None) == -1
+    assert lib.dctf_filter_quantized_u8(None, 0, None, None, ctypes.c_float(0.0), None, 1, None) == -1
 
 
 def test_verify_and_forward_dct_validation(lib):
