@@ -144,6 +144,41 @@ def small_workloads(dctf, torch, stream):
     return res
 
 
+def pixel_outputs(dctf, torch, stream, X, N, steps, warmup):
+    """Filter + inverse DCT + uint8 in one pass over the same blocks, with the
+    5x5 asymmetric mask and border replication: from the FP32 coefficients
+    (4 B in, 1 B out per coefficient) and from JPEG-style quantised int16
+    coefficients (2 B in, 1 B out; the quantised input is made from the same
+    coefficients with the seeded table q[u][v] = round(4 (1 + 0.75 (u + v)))
+    and a 128 N level shift, outside the timed region)."""
+    import numpy as np
+
+    import synthetic as syn
+    nn = N * N
+    B = X.numel() // nn
+    op = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, dctf.DCTF_BORDER_REPLICATE)
+    qt = torch.from_numpy(syn.quant_table(N).astype(np.float32).reshape(-1)).cuda()
+    dc = 128.0 * N
+    Xs = X.view(-1, nn).clone()
+    Xs[:, 0] -= dc
+    Q = torch.round(Xs / qt).clamp_(-32768, 32767).to(torch.int16).view(-1)
+    del Xs
+    pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
+    res = {"blocks": B, "mask": "5x5 asymmetric, replicate"}
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        for src, fn, per_coef in (
+                ("coeffs_f32", lambda: dctf.dctf_filter_blocks_u8(op, p, X, pix, stream), 5),
+                ("quantized_s16", lambda: dctf.dctf_filter_quantized_u8(op, p, Q, qt, dc, pix, stream), 3)):
+            ms = timed_steps(torch, fn, steps, warmup, stream)
+            gbs = B * nn * per_coef / (ms * 1e-3) / 1e9
+            res["%s_to_u8_%s" % (src, pname)] = {
+                "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "alg_bytes_per_block": nn * per_coef,
+                "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+    del Q, pix
+    torch.cuda.empty_cache()
+    return res
+
+
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
     one 7x7 asymmetric mask with zero border, in both precisions, and the
@@ -434,6 +469,7 @@ def main():
                     "GBps": alg_bytes / (sms * 1e-3) / 1e9,
                     "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
         extras["small_workloads"] = small_workloads(dctf, torch, stream)
+        extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup)
         # optional verify kernel: inverse DCT + uint8 of every output block
         pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
         vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)

@@ -78,10 +78,18 @@ __device__ __forceinline__ uint32_t pixel_u8(float p)
     return (uint32_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
 }
 
-// Four pixels -> one little-endian word (first pixel in the low byte).
+// Four pixels -> one little-endian word (first pixel in the low byte), the
+// rule of pixel_u8 for finite values: floor(p + 1/2) clamped to [0, 255] by
+// v_med3_f32 is an exact integer in range, which v_cvt_pk_u8_f32 converts
+// exactly and packs into its byte.
 __device__ __forceinline__ uint32_t pack_u8x4(float a, float b, float c, float d)
 {
-    return pixel_u8(a) | (pixel_u8(b) << 8) | (pixel_u8(c) << 16) | (pixel_u8(d) << 24);
+    const float v[4] = {a, b, c, d};
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(floorf(v[k] + 0.5f), 0.0f, 255.0f), k, w);
+    return w;
 }
 
 // Eight quantised coefficients (one 16-byte load, little-endian int16) times

@@ -24,28 +24,51 @@ namespace dctf {
 namespace {
 
 // ---------------------------------------------------------------- N = 8
+//
+// Loads (LI): 1 = coalesced through the wave's LDS region (every load
+// instruction covers contiguous memory, the tile is then re-read in MFMA
+// layout); 0 = straight into the MFMA layout (lane (n, g) loads coefficients
+// 16i + 4g .. +3 of block n).  Stores (SO): 1 = through LDS, one 16-byte
+// store per lane covering the tile's 1 KiB; 0 = straight from the MFMA
+// result layout (lane (n, g) stores pixels 16t + 4g .. +3 of block n, four
+// bytes).  U tiles per iteration; the next iteration's loads are in flight
+// while the current one is multiplied.
 
 // Tile input held in registers while the previous tile is multiplied.
-template <int IN>
+template <int IN, int LI>
 struct In8;
 
-template <>
-struct In8<0> {
-    float4 x[4];   // the coalesced layout of load_tile_coalesced
+template <int LI>
+struct In8<0, LI> {
+    float4 x[4];   // LI = 1: the layout of load_tile_coalesced; LI = 0: MFMA layout
 };
 
 template <>
-struct In8<1> {
+struct In8<1, 1> {
     u32x4 raw[2];  // 2 KiB tile: lane l, load i holds coefficients 8(l % 8) .. +7 of block 8i + l / 8
 };
 
-__device__ __forceinline__ void load8(In8<0> &t, const PxArgs &a, int64_t blk0, int lane)
+template <>
+struct In8<1, 0> {
+    uint2 raw[4];  // lane (n, g), load i: coefficients 16i + 4g .. +3 of block n
+};
+
+template <int LI>
+__device__ __forceinline__ void load8(In8<0, LI> &t, const PxArgs &a, int64_t blk0, int lane)
 {
     const int64_t nv = a.B - blk0;
-    load_tile_coalesced<true>(t.x, a.in + blk0 * 64, nv, lane);
+    if constexpr (LI == 1) {
+        load_tile_coalesced<true>(t.x, a.in + blk0 * 64, nv, lane);
+    } else {
+        const int64_t n = lane & 15;
+        const float *src = a.in + (blk0 + (n < nv ? n : nv - 1)) * 64 + 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            t.x[i] = ld4_nt(src + 16 * i);
+    }
 }
 
-__device__ __forceinline__ void load8(In8<1> &t, const PxArgs &a, int64_t blk0, int lane)
+__device__ __forceinline__ void load8(In8<1, 1> &t, const PxArgs &a, int64_t blk0, int lane)
 {
     const int64_t nv = a.B - blk0;
 #pragma unroll
@@ -57,30 +80,69 @@ __device__ __forceinline__ void load8(In8<1> &t, const PxArgs &a, int64_t blk0, 
     }
 }
 
-// Write the tile to the wave's LDS region in the swizzled layout read_mfma
-// expects (chunk c of block b at slot 16 b + (c ^ b)).
-__device__ __forceinline__ void stage8(const In8<0> &t, float4 *lds, int lane, const float *, float)
+__device__ __forceinline__ void load8(In8<1, 0> &t, const PxArgs &a, int64_t blk0, int lane)
 {
-    stage_in(lds, t.x, lane);
+    const int64_t nv = a.B - blk0;
+    const int64_t n = lane & 15;
+    const int16_t *src = a.qin + (blk0 + (n < nv ? n : nv - 1)) * 64 + 4 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        t.raw[i] = *reinterpret_cast<const uint2 *>(src + 16 * i);
 }
 
-__device__ __forceinline__ void stage8(const In8<1> &t, float4 *lds, int lane, const float *qv, float dc)
+// The tile in MFMA layout (xm), through the wave's LDS region where the
+// loads were coalesced (chunk c of block b at slot 16 b + (c ^ b)).
+// q: the dequantisation factors this lane needs (IN = 1), dc the DC offset.
+template <int LI>
+__device__ __forceinline__ void to_mfma8(const In8<0, LI> &t, float4 *lds, int lane, const float *, float,
+                                         float4 xm[4])
+{
+    if constexpr (LI == 1) {
+        stage_in(lds, t.x, lane);
+        wave_lds_sync();
+        read_mfma(lds, xm, lane);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            xm[i] = t.x[i];
+    }
+}
+
+// LI = 1: q[e] is the factor of coefficient 8(lane % 8) + e.
+__device__ __forceinline__ void to_mfma8(const In8<1, 1> &t, float4 *lds, int lane, const float *q, float dc,
+                                         float4 xm[4])
 {
     const int c8 = lane & 7;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int b = 8 * i + (lane >> 3);
         float4 lo, hi;
-        dequant8(t.raw[i], qv, dc, lo, hi);
+        dequant8(t.raw[i], q, dc, lo, hi);
         lds[b * 16 + ((2 * c8) ^ b)] = lo;
         lds[b * 16 + ((2 * c8 + 1) ^ b)] = hi;
     }
+    wave_lds_sync();
+    read_mfma(lds, xm, lane);
 }
 
-// Pixels of the tile from the LDS staging (floats, swizzled): lane l writes
-// the 16 pixels 16(l % 4) .. +15 of block l / 4, one 16-byte store, so the
-// wave's store covers the tile's 1 KiB contiguously.
-__device__ __forceinline__ void store_px8(uint8_t *pix, int64_t nvalid, const float4 *lds, int lane)
+// LI = 0: q[4i + j] is the factor of coefficient 16i + 4(lane / 16) + j.
+__device__ __forceinline__ void to_mfma8(const In8<1, 0> &t, float4 *, int, const float *q, float dc,
+                                         float4 xm[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint2 r = t.raw[i];
+        xm[i] = make_float4((float)(int16_t)(r.x & 0xffffu) * q[4 * i],
+                            (float)((int32_t)r.x >> 16) * q[4 * i + 1],
+                            (float)(int16_t)(r.y & 0xffffu) * q[4 * i + 2],
+                            (float)((int32_t)r.y >> 16) * q[4 * i + 3]);
+    }
+    xm[0].x += dc;
+}
+
+// SO = 1: lane l writes the 16 pixels 16(l % 4) .. +15 of block l / 4 from
+// the LDS staging (floats, swizzled), one 16-byte store per lane.
+__device__ __forceinline__ void store_px8_lds(uint8_t *pix, int64_t nvalid, const float4 *lds, int lane)
 {
     const int b = lane >> 2, k4 = lane & 3;
     if (b >= nvalid)
@@ -94,17 +156,29 @@ __device__ __forceinline__ void store_px8(uint8_t *pix, int64_t nvalid, const fl
     __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(pix + (int64_t)b * 64 + 16 * k4));
 }
 
-// Wave w takes 16-block tiles w, w + waves, ...; the next tile's loads are in
-// flight while the current one is multiplied.
-template <int PREC, int IN>
+// SO = 0: lane (n, g) holds pixels 16t + 4g + r of block n.
+__device__ __forceinline__ void store_px8_direct(uint8_t *pix, int64_t nvalid, const f32x4 acc[4], int lane)
+{
+    const int n = lane & 15, g = lane >> 4;
+    if (n >= nvalid)
+        return;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(pix + (int64_t)n * 64 + 4 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        dst[4 * t] = pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+}
+
+// Wave w takes units (U tiles of 16 blocks) w, w + waves, ...
+template <int PREC, int IN, int U, int LI, int SO>
 __global__ __launch_bounds__(256) void k_filter_px8(PxArgs a, int64_t units, int64_t waves)
 {
-    __shared__ __attribute__((aligned(16))) float4 lds_all[4 * 256];
+    constexpr bool kLds = LI == 1 || SO == 1;
+    __shared__ __attribute__((aligned(16))) float4 lds_all[kLds ? 4 * U * 256 : 1];
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= waves)   // waves <= units
         return;
-    float4 *lds = lds_all + (threadIdx.x >> 6) * 256;
+    float4 *lds = lds_all + (kLds ? (threadIdx.x >> 6) * U * 256 : 0);
 
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8BF16>::type Regs;
     Regs R;
@@ -113,38 +187,67 @@ __global__ __launch_bounds__(256) void k_filter_px8(PxArgs a, int64_t units, int
     else
         load_op8(R, a.G.frag_hi, a.G.frag_lo, a.G.frag_lf, lane);
 
-    float qv[8];
+    constexpr int kQ = IN == 0 ? 1 : (LI == 1 ? 8 : 16);
+    float q[kQ];
     float dc = 0.0f;
     if constexpr (IN == 1) {
-        const float4 q0 = ld4(a.qtab + 8 * (lane & 7)), q1 = ld4(a.qtab + 8 * (lane & 7) + 4);
-        qv[0] = q0.x; qv[1] = q0.y; qv[2] = q0.z; qv[3] = q0.w;
-        qv[4] = q1.x; qv[5] = q1.y; qv[6] = q1.z; qv[7] = q1.w;
-        dc = (lane & 7) == 0 ? a.dc_offset : 0.0f;
+        if constexpr (LI == 1) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                q[e] = a.qtab[8 * (lane & 7) + e];
+            dc = (lane & 7) == 0 ? a.dc_offset : 0.0f;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    q[4 * i + j] = a.qtab[16 * i + 4 * (lane >> 4) + j];
+            dc = (lane >> 4) == 0 ? a.dc_offset : 0.0f;
+        }
     }
 
+    const int64_t B = a.B;
     const int64_t my_units = (units - wave + waves - 1) / waves;
-    auto compute_store = [&](const In8<IN> &t, int64_t unit) {
-        const int64_t blk0 = unit * 16;
-        stage8(t, lds, lane, qv, dc);
-        wave_lds_sync();
-        float4 xm[4];
-        read_mfma(lds, xm, lane);
-        f32x4 acc[4];
-        tile8(R, xm, lane, acc);
-        wave_lds_sync();
-        stage_out(lds, acc, lane);
-        wave_lds_sync();
-        store_px8(a.pix + blk0 * 64, a.B - blk0, lds, lane);
-        wave_lds_sync();
+    auto load_unit = [&](In8<IN, LI> (&t)[U], int64_t unit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t blk0 = unit * (16 * U) + 16 * u;
+            load8(t[u], a, blk0 < B ? blk0 : B - 1, lane);   // an empty tail tile re-reads the last block
+        }
+    };
+    auto compute_store = [&](const In8<IN, LI> (&t)[U], int64_t unit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t blk0 = unit * (16 * U) + 16 * u;
+            if (blk0 >= B)
+                break;
+            float4 *L = lds + (kLds ? u * 256 : 0);
+            float4 xm[4];
+            to_mfma8(t[u], L, lane, q, dc, xm);
+            f32x4 acc[4];
+            tile8(R, xm, lane, acc);
+            if constexpr (SO == 1) {
+                wave_lds_sync();
+                stage_out(L, acc, lane);
+                wave_lds_sync();
+                store_px8_lds(a.pix + blk0 * 64, B - blk0, L, lane);
+            } else {
+                store_px8_direct(a.pix + blk0 * 64, B - blk0, acc, lane);
+            }
+            if constexpr (kLds)
+                wave_lds_sync();
+        }
     };
 
-    In8<IN> cur, nxt;
+    In8<IN, LI> cur[U], nxt[U];
     int64_t unit = wave;
-    load8(cur, a, unit * 16, lane);
+    load_unit(cur, unit);
     for (int64_t k = 1; k < my_units; ++k) {
-        load8(nxt, a, (unit + waves) * 16, lane);
+        load_unit(nxt, unit + waves);
         compute_store(cur, unit);
-        cur = nxt;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            cur[u] = nxt[u];
         unit += waves;
     }
     compute_store(cur, unit);
@@ -222,17 +325,22 @@ __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
 
 // ------------------------------------------------------------- launches
 
+// N = 8 launch shape: tiles per iteration, load / store paths, waves per CU.
+constexpr int kPx8U = 2;
+constexpr int kPx8Li = 1;
+constexpr int kPx8So = 0;
 constexpr int kPx8WavesPerCu = 8;
 constexpr int kPx16Depth = 2;
 
 template <int PREC, int IN>
 hipError_t run_px8(const PxArgs &a, hipStream_t stream)
 {
-    const int64_t units = (a.B + 15) / 16;
+    const int64_t units = (a.B + 16 * kPx8U - 1) / (16 * kPx8U);
     int64_t waves = (int64_t)cu_count() * kPx8WavesPerCu;
     waves = waves < units ? waves : units;
     const int64_t groups = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_filter_px8<PREC, IN>), dim3((unsigned)groups), dim3(256), 0, stream, a, units, waves);
+    hipLaunchKernelGGL((k_filter_px8<PREC, IN, kPx8U, kPx8Li, kPx8So>), dim3((unsigned)groups), dim3(256), 0,
+                       stream, a, units, waves);
     return hipGetLastError();
 }
 
