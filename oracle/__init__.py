@@ -70,6 +70,7 @@ def _load():
                 "or_operator_probe": ([i32, P, i32, i32, i32, P], i32),
                 "or_filter_coeffs_to_pixels": ([i32, P, i32, i32, i32, i64, P, P, P, P], i32),
                 "or_pixel_operator_probe": ([i32, P, i32, i32, i32, P], i32),
+                "or_filter_image_coeffs": ([i32, P, i32, i32, i32, i32, i32, i32, P, P], i32),
                 "or_tile_u8": ([P, i32, i32, i32, P], i32),
             }
             for name, (args, res) in sig.items():
@@ -235,6 +236,41 @@ def pixel_operator_probe(N: int, W, border: int) -> np.ndarray:
     _check(_load().or_pixel_operator_probe(N, _ptr(W), W.shape[0], W.shape[1], border, _ptr(G)),
            "pixel_operator_probe")
     return G
+
+
+def filter_image_coeffs(X, Bh: int, Bw: int, W, border: int) -> np.ndarray:
+    """Image-level filter of block-DCT images: ``X`` holds nimg images of
+    Bh x Bw coefficient blocks ``[nimg*Bh*Bw, N, N]`` (raster order); each
+    image is inverse transformed, correlated with ``W`` over the whole image
+    (zero or replicated pixels outside the image only), and cut into blocks
+    and transformed again.  FP64."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    W = _mask(W)
+    N = X.shape[-1]
+    nb = X.size // (N * N)
+    if nb % (Bh * Bw):
+        raise ValueError("block count is not a multiple of Bh * Bw")
+    Y = np.empty_like(X)
+    rc = _load().or_filter_image_coeffs(N, _ptr(W), W.shape[0], W.shape[1], border, Bh, Bw,
+                                        nb // (Bh * Bw), _ptr(X), _ptr(Y))
+    _check(rc, "filter_image_coeffs")
+    return Y
+
+
+def image_operator_probe(N: int, W, border: int, Bh: int, Bw: int, R: int, S: int, dr: int, ds: int):
+    """Column k of the result is the filtered block (R, S) of a Bh x Bw image
+    whose only non-zero block is (R + dr, S + ds) = e_k (the operator block
+    that carries neighbour (dr, ds) into (R, S)); zero if that neighbour is
+    outside the image."""
+    nn = N * N
+    H = np.zeros((nn, nn))
+    if not (0 <= R + dr < Bh and 0 <= S + ds < Bw):
+        return H
+    X = np.zeros((nn, Bh * Bw, N, N))
+    for k in range(nn):
+        X[k, (R + dr) * Bw + S + ds].flat[k] = 1.0
+    Y = filter_image_coeffs(X.reshape(-1, N, N), Bh, Bw, W, border).reshape(nn, Bh * Bw, nn)
+    return Y[:, R * Bw + S, :].T.copy()
 
 
 def dequantize(qcoef, qtable, dc_offset: float = 0.0) -> np.ndarray:

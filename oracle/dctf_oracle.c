@@ -25,6 +25,8 @@
  *   - the filtered pixels filter(IDCT(X)) of coefficient blocks and the
  *     pixel-output operator probed the same way (the filtered result taken
  *     back to the spatial domain, Sec. III);
+ *   - the image-level variant: the whole image filtered across block
+ *     boundaries (only the image border padded), then cut into blocks again;
  *   - the uint8 conversion of a filtered pixel (Sec. III): saturate to
  *     [0, 255] after rounding half up, the decision taken in FP32 (the
  *     precision the GPU verify kernel decides in); pixels whose FP64 value
@@ -372,6 +374,78 @@ int or_operator_probe(int N, const double *W, int kh, int kw, int border, double
         for (int r = 0; r < nn; ++r)
             H[(int64_t)r * nn + k] = Y[r];
     }
+    return 0;
+}
+
+/* Image-level filtering of a block-DCT image (the cross-block variant the
+ * paper's replication of Fig. 1 stands in for): the Bh x Bw coefficient
+ * blocks (raster order) are taken back to one Bh*N x Bw*N pixel image
+ * (eq. 3), the mask is correlated over the whole image, reading zeros
+ * outside the image (zero padding) or the nearest image pixel
+ * (replication), and every block of the result is transformed again
+ * (eq. 1).  Blocks now see their neighbours' pixels; only the image border
+ * is padded.  nimg images of the same size are stored one after another. */
+int or_filter_image_coeffs(int N, const double *W, int kh, int kw, int border, int Bh, int Bw,
+                           int nimg, const double *X, double *Y)
+{
+    if (check_args(N, kh, kw, border) || Bh < 1 || Bw < 1 || nimg < 0)
+        return -1;
+    double C[OR_MAXN * OR_MAXN];
+    or_dct_matrix(N, C);
+    const int H = Bh * N, Wd = Bw * N, ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+    const int64_t nn = (int64_t)N * N, per = (int64_t)Bh * Bw * nn;
+    double *img = (double *)malloc(sizeof(double) * H * Wd);
+    double *out = (double *)malloc(sizeof(double) * H * Wd);
+    if (!img || !out) {
+        free(img);
+        free(out);
+        return -2;
+    }
+    for (int im = 0; im < nimg; ++im) {
+        const double *Xi = X + im * per;
+        double *Yi = Y + im * per;
+        /* inverse DCT of every block into the image */
+#pragma omp parallel for schedule(static)
+        for (int64_t b = 0; b < (int64_t)Bh * Bw; ++b) {
+            double x[OR_MAXN * OR_MAXN];
+            idct2_block(N, C, Xi + b * nn, x);
+            const int by = (int)(b / Bw), bx = (int)(b % Bw);
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j)
+                    img[(int64_t)(by * N + i) * Wd + bx * N + j] = x[i * N + j];
+        }
+        /* correlation over the image */
+#pragma omp parallel for schedule(static)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < Wd; ++x) {
+                double s = 0.0;
+                for (int p = 0; p < kh; ++p)
+                    for (int q = 0; q < kw; ++q) {
+                        int r = y + p - ah, c = x + q - aw;
+                        if (border == OR_BORDER_ZERO) {
+                            if (r < 0 || r >= H || c < 0 || c >= Wd)
+                                continue;
+                        } else {
+                            r = clamp_index(r, H);
+                            c = clamp_index(c, Wd);
+                        }
+                        s += W[p * kw + q] * img[(int64_t)r * Wd + c];
+                    }
+                out[(int64_t)y * Wd + x] = s;
+            }
+        /* forward DCT of every block of the result */
+#pragma omp parallel for schedule(static)
+        for (int64_t b = 0; b < (int64_t)Bh * Bw; ++b) {
+            double f[OR_MAXN * OR_MAXN];
+            const int by = (int)(b / Bw), bx = (int)(b % Bw);
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j)
+                    f[i * N + j] = out[(int64_t)(by * N + i) * Wd + bx * N + j];
+            dct2_block(N, C, f, Yi + b * nn);
+        }
+    }
+    free(img);
+    free(out);
     return 0;
 }
 
