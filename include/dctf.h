@@ -66,6 +66,7 @@ typedef enum {
 typedef void *dctf_stream;                 /* hipStream_t */
 typedef struct dctf_operator_s *dctf_operator;
 typedef struct dctf_batch_s *dctf_batch;
+typedef struct dctf_image_operator_s *dctf_image_operator;
 
 /* Supported block sizes N: 2, 4, 8, 16.  Mask sides: 1 <= kh, kw <= 2N + 1. */
 
@@ -221,6 +222,58 @@ dctf_status dctf_filter_blocks_u8(dctf_operator op, int prec, const float *in_de
 dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *qcoef_dev,
                                      const float *qtable_dev, float dc_offset, uint8_t *pix_dev,
                                      int64_t B, dctf_stream stream);
+
+/* ------------------------------------------------- image-level filtering */
+
+/*
+ * Cross-block (image-level) filtering in the DCT domain.  The block-local
+ * filter above pads every block on its own (zeros, or the block's own edge
+ * pixels, Fig. 1), which is what lets the paper write the result as
+ * products of the block with constant matrices (Sec. II.B-C).  Here the
+ * image is filtered across block boundaries: a block's result reads the
+ * pixels of its 8 neighbour blocks, and the border rule (zero or
+ * replication) applies only at the image edge.  The same Kronecker
+ * construction (eq. 6-8) with shift matrices that select rows of a
+ * neighbour gives one N^2 x N^2 operator per neighbour offset (dr, ds):
+ *
+ *   Y[R][S] = sum_{dr, ds in {-1, 0, 1}} H^{rc, cc}_{dr, ds} X[R + dr][S + ds],
+ *
+ * where the row class rc of block row R (and cc of block column S) is
+ * 0 = interior, 1 = first, 2 = last, 3 = both (a one-block image side); the
+ * class decides which neighbours exist and where reads are clamped.  The
+ * builder forms all 16 class pairs x 9 offsets in FP64 on the GPU, with
+ * their FP32 MFMA fragments (N = 8: 4.7 MB FP64 + 2.4 MB FP32); each
+ * operator's DC column is applied in FP32 VALU arithmetic, the rest in
+ * FP32 MFMA.
+ * Masks: 1 <= kh, kw <= 2N + 1 (a mask never reaches past a neighbour).
+ * Errors: as dctf_build_operator; DCTF_EUNSUPPORTED for N != 8.
+ * Synchronises `stream` (the mask copy is from host memory).
+ */
+dctf_status dctf_build_image_operator(const double *mask_host, int kh, int kw, int N, int border,
+                                      dctf_stream stream, dctf_image_operator *out);
+
+/* Copy H^{row_class, col_class}_{dr, ds} (N^2 x N^2 FP64, row-major, row =
+ * output coefficient) to host memory.  Synchronous.  Operators of
+ * neighbours a class does not have are zero. */
+dctf_status dctf_image_operator_fp64(dctf_image_operator op, int row_class, int col_class, int dr, int ds,
+                                     double *host_out);
+
+void dctf_image_operator_destroy(dctf_image_operator op);
+
+/*
+ * Filter nimg images of Bh x Bw blocks each (block-contiguous, raster
+ * order inside an image, images one after another: Bh*Bw*nimg blocks of
+ * N*N floats), FP32 MFMA with FP32 accumulation; each block's sum runs over
+ * the neighbour offsets in a fixed order, so its result does not depend on
+ * nimg or on where the block falls in the work partition.
+ *   in_dev, out_dev  device, 16-byte aligned, non-overlapping.
+ *   prec             DCTF_PREC_FP32 (DCTF_PREC_SPLIT_BF16 returns
+ *                    DCTF_EUNSUPPORTED).
+ * nimg = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned, overlap,
+ * Bh or Bw < 1, nimg < 0), DCTF_EUNSUPPORTED, DCTF_EHIP.
+ */
+dctf_status dctf_filter_image(dctf_image_operator op, int prec, const float *in_dev, float *out_dev, int Bh,
+                              int Bw, int64_t nimg, dctf_stream stream);
 
 /* ---------------------------------------------------------- batched launch */
 

@@ -64,6 +64,10 @@ _SIGS = {
     "dctf_operator_fp64": ([_P, _P], _I),
     "dctf_operator_pixel_fp64": ([_P, _P], _I),
     "dctf_filter_blocks_u8": ([_P, _I, _P, _P, _I64, _P], _I),
+    "dctf_build_image_operator": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
+    "dctf_image_operator_fp64": ([_P, _I, _I, _I, _I, _P], _I),
+    "dctf_image_operator_destroy": ([_P], None),
+    "dctf_filter_image": ([_P, _I, _P, _P, _I, _I, _I64, _P], _I),
     "dctf_filter_quantized_u8": ([_P, _I, _P, _P, ctypes.c_float, _P, _I64, _P], _I),
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
@@ -273,6 +277,56 @@ def dctf_filter_quantized_u8(op: Operator, prec: int, qcoef: torch.Tensor, qtabl
                                          _dptr(qtable, torch.float32, "qtable"), float(dc_offset),
                                          _dptr(pix, torch.uint8, "pix"), qcoef.numel() // nn, _stream(stream)),
            "dctf_filter_quantized_u8")
+
+
+class ImageOperator:
+    """Owning handle of the neighbour operators of image-level filtering."""
+
+    def __init__(self, handle: int, N: int, kh: int, kw: int, border: int):
+        self.handle = handle
+        self.N, self.kh, self.kw, self.border = N, kh, kw, border
+
+    @property
+    def _as_parameter_(self):
+        return _P(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            _lib.dctf_image_operator_destroy(_P(self.handle))
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def dctf_build_image_operator(mask, N: int, border: int, stream=None) -> ImageOperator:
+    m = _mask_array(mask)
+    h = _P()
+    _check(_lib.dctf_build_image_operator(m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, border,
+                                          _stream(stream), ctypes.byref(h)), "dctf_build_image_operator")
+    return ImageOperator(h.value, N, m.shape[0], m.shape[1], border)
+
+
+def dctf_image_operator_fp64(op: ImageOperator, row_class: int, col_class: int, dr: int, ds: int) -> np.ndarray:
+    nn = op.N * op.N
+    H = np.empty((nn, nn), np.float64)
+    _check(_lib.dctf_image_operator_fp64(op, row_class, col_class, dr, ds, H.ctypes.data_as(_P)),
+           "dctf_image_operator_fp64")
+    return H
+
+
+def dctf_filter_image(op: ImageOperator, prec: int, X: torch.Tensor, Y: torch.Tensor, Bh: int, Bw: int,
+                      stream=None):
+    """Image-level filter of X.numel() // (Bh*Bw*N*N) images of Bh x Bw blocks."""
+    per = Bh * Bw * op.N * op.N
+    if X.numel() % per or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold the same whole number of Bh x Bw block images")
+    _check(_lib.dctf_filter_image(op, prec, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"), Bh, Bw,
+                                  X.numel() // per, _stream(stream)),
+           "dctf_filter_image")
 
 
 def filter_blocks(op: Operator, X: torch.Tensor, prec: int = DCTF_PREC_SPLIT_BF16, stream=None):

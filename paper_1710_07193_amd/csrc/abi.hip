@@ -506,6 +506,186 @@ extern "C" dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, cons
     return filter_px(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, pix_dev, B, stream);
 }
 
+// ============================================================ image level
+
+struct dctf_image_operator_s {
+    int N, kh, kw, border;
+    void *base = nullptr;
+    double *mask = nullptr;
+    double *H64 = nullptr;
+    float *frag32 = nullptr;
+    float *h0 = nullptr;
+};
+
+extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh, int kw, int N, int border,
+                                                 dctf_stream stream, dctf_image_operator *out)
+{
+    if (out == nullptr)
+        return DCTF_EINVAL;
+    dctf_status st = validate_mask(mask_host, kh, kw, N, border);
+    if (st != DCTF_OK)
+        return st;
+    if (N != 8)
+        return DCTF_EUNSUPPORTED;
+    const size_t NN = (size_t)N * N, nops = (size_t)kImageClassPairs * kImageOffsets;
+    size_t off = 0;
+    const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
+    const size_t o_h64 = off;  off = align_up(off + sizeof(double) * nops * NN * NN);
+    const size_t o_f32 = off;  off = align_up(off + sizeof(float) * nops * NN * NN);
+    const size_t o_h0 = off;   off = align_up(off + sizeof(float) * nops * NN);
+    dctf_image_operator op = new (std::nothrow) dctf_image_operator_s();
+    if (!op)
+        return DCTF_ENOMEM;
+    hipError_t e = hipMalloc(&op->base, off);
+    if (e != hipSuccess) {
+        delete op;
+        return hip_status(e);
+    }
+    char *b = static_cast<char *>(op->base);
+    op->N = N;
+    op->kh = kh;
+    op->kw = kw;
+    op->border = border;
+    op->mask = reinterpret_cast<double *>(b + o_mask);
+    op->H64 = reinterpret_cast<double *>(b + o_h64);
+    op->frag32 = reinterpret_cast<float *>(b + o_f32);
+    op->h0 = reinterpret_cast<float *>(b + o_h0);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = hip_status(hipMemcpyAsync(op->mask, mask_host, sizeof(double) * kh * kw, hipMemcpyHostToDevice, s));
+    if (st == DCTF_OK) {
+        ImageBuildArgs a;
+        a.mask = op->mask;
+        a.kh = kh;
+        a.kw = kw;
+        a.border = border;
+        a.H64 = op->H64;
+        a.frag32 = op->frag32;
+        a.h0 = op->h0;
+        st = hip_status(launch_build_image(a, s));
+    }
+    // the mask copy is from pageable memory: complete it before returning
+    if (st == DCTF_OK)
+        st = hip_status(hipStreamSynchronize(s));
+    if (st != DCTF_OK) {
+        dctf_image_operator_destroy(op);
+        return st;
+    }
+    *out = op;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_image_operator_fp64(dctf_image_operator op, int row_class, int col_class, int dr,
+                                                int ds, double *host_out)
+{
+    if (op == nullptr || host_out == nullptr || row_class < 0 || row_class > 3 || col_class < 0 ||
+        col_class > 3 || dr < -1 || dr > 1 || ds < -1 || ds > 1)
+        return DCTF_EINVAL;
+    const size_t NN = (size_t)op->N * op->N;
+    const size_t idx = (size_t)(4 * row_class + col_class) * kImageOffsets + 3 * (dr + 1) + (ds + 1);
+    return hip_status(hipMemcpy(host_out, op->H64 + idx * NN * NN, sizeof(double) * NN * NN,
+                                hipMemcpyDeviceToHost));
+}
+
+extern "C" void dctf_image_operator_destroy(dctf_image_operator op)
+{
+    if (op == nullptr)
+        return;
+    if (op->base)
+        hipFree(op->base);
+    delete op;
+}
+
+namespace {
+
+struct Run {
+    int begin, len, cls;
+};
+
+// Runs of equal class along one axis of n blocks (first, interior, last; or
+// one block that is both).
+int class_runs(int n, Run out[3])
+{
+    if (n == 1) {
+        out[0] = {0, 1, 3};
+        return 1;
+    }
+    int k = 0;
+    out[k++] = {0, 1, 1};
+    if (n > 2)
+        out[k++] = {1, n - 2, 0};
+    out[k++] = {n - 1, 1, 2};
+    return k;
+}
+
+// Neighbour offsets a block of classes (cr, cs) reads: the neighbour exists
+// and the mask reaches into it.
+int image_offsets(int cr, int cs, int kh, int kw)
+{
+    const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+    const bool up = !(cr & 1) && ah > 0, down = !(cr & 2) && kh - 1 - ah > 0;
+    const bool left = !(cs & 1) && aw > 0, right = !(cs & 2) && kw - 1 - aw > 0;
+    int mask = 0;
+    for (int o = 0; o < kImageOffsets; ++o) {
+        const int dr = o / 3 - 1, ds = o % 3 - 1;
+        const bool rok = dr == 0 || (dr < 0 ? up : down);
+        const bool cok = ds == 0 || (ds < 0 ? left : right);
+        if (rok && cok)
+            mask |= 1 << o;
+    }
+    return mask;
+}
+
+}  // namespace
+
+extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const float *in_dev, float *out_dev,
+                                         int Bh, int Bw, int64_t nimg, dctf_stream stream)
+{
+    if (op == nullptr || Bh < 1 || Bw < 1 || nimg < 0)
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
+        return DCTF_EINVAL;
+    if (prec != DCTF_PREC_FP32)
+        return DCTF_EUNSUPPORTED;
+    const int64_t B = (int64_t)Bh * Bw * nimg;
+    dctf_status st = validate_io(op->N, in_dev, out_dev, B);
+    if (st != DCTF_OK || B == 0)
+        return st;
+    ImageFilterArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = in_dev;
+    a.out = out_dev;
+    a.Bh = Bh;
+    a.Bw = Bw;
+    a.nimg = nimg;
+    a.frag32 = op->frag32;
+    a.h0 = op->h0;
+    Run rr[3], cr[3];
+    const int nr = class_runs(Bh, rr), nc = class_runs(Bw, cr);
+    const int T = image_tiles_per_unit();
+    int64_t units = 0;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) {
+            ImageRect &r = a.rect[a.nrect++];
+            r.R0 = rr[i].begin;
+            r.nR = rr[i].len;
+            r.S0 = cr[j].begin;
+            r.nS = cr[j].len;
+            r.cp = 4 * rr[i].cls + cr[j].cls;
+            r.dir = (r.nS > 1 || r.nR == 1) ? 0 : 1;
+            r.offsets = image_offsets(rr[i].cls, cr[j].cls, op->kh, op->kw);
+            r.tiles = r.dir == 0 ? (int64_t)r.nR * ((r.nS + 15) / 16) : (int64_t)r.nS * ((r.nR + 15) / 16);
+            r.unit_begin = units;
+            units += (r.tiles + T - 1) / T;
+        }
+    a.units_per_image = units;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    st = hip_status(launch_filter_image(a, s));
+    timing_end(s, slot);
+    return st;
+}
+
 // ==================================================================== batch
 
 struct dctf_batch_s {

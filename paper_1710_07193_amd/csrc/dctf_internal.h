@@ -124,6 +124,46 @@ struct PxArgs {
 };
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
 
+// image.hip — image-level (cross-block) filtering, N = 8.  Operators are
+// indexed [class pair cp = 4 cr + cs][offset o = 3 (dr + 1) + (ds + 1)], each
+// N^2 x N^2; class bit 0 = first block row / column of the image, bit 1 = last.
+constexpr int kImageClassPairs = 16;
+constexpr int kImageOffsets = 9;
+
+struct ImageBuildArgs {
+    const double *mask;   // kh * kw (device)
+    int kh, kw, border;
+    double *H64;          // [cp][o] N^2 x N^2, row-major
+    float *frag32;        // [cp][o] FP32 MFMA A fragments (N = 8 layout), DC column zeroed
+    float *h0;            // [cp][o] DC columns H[:, 0], FP32
+};
+
+// A rectangle of blocks of one class pair, cut into tiles of up to 16 blocks
+// along a block row (dir 0) or, when it is one block wide, a block column
+// (dir 1).  `offsets` has bit o set for every neighbour the blocks read.
+struct ImageRect {
+    int R0, nR, S0, nS;
+    int cp, dir, offsets;
+    int64_t tiles;        // tiles in the rectangle
+    int64_t unit_begin;   // first work unit of the rectangle within its image
+};
+
+struct ImageFilterArgs {
+    const float *in;
+    float *out;
+    int Bh, Bw;
+    int64_t nimg;
+    int nrect;
+    ImageRect rect[9];
+    int64_t units_per_image;
+    const float *frag32;
+    const float *h0;
+};
+
+hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream);
+hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream);
+int image_tiles_per_unit();
+
 // filter.hip — single-operator filter of B blocks.
 struct FilterArgs {
     const float *in;

@@ -1,0 +1,319 @@
+// Image-level filtering in the DCT domain: every output block is a sum over
+// its 3 x 3 block neighbourhood,
+//
+//   Y[R][S] = sum_{dr, ds in {-1, 0, 1}} H^{c(R), c(S)}_{dr, ds} . X[R + dr][S + ds],
+//
+// the image filtered across block boundaries (the variant the paper's
+// block-edge replication of Fig. 1 approximates), with zero padding or
+// replication only at the image border.  H_{dr,ds} is the Kronecker form of
+// the paper's DCT-domain products (eq. 6-8) with shift matrices that may
+// select rows of the neighbour block:
+//
+//   H^{cr,cs}_{dr,ds} = sum_{p,q} W[p][q] A^{cr}_{dr, p-a_h} (x) A^{cs}_{ds, q-a_w},
+//   A^{c}_{d,e} = C S^{c}_{d,e} C^t,
+//
+// where S^{c}_{d,e}[i][m] = 1 if output row i, shifted by e, reads row m of
+// the neighbour at offset d.  The class c of a block row (or column) says
+// which neighbours exist: bit 0 = it is the first one (no neighbour before:
+// reads before it are dropped (zero) or clamped to its row 0 (replication)),
+// bit 1 = it is the last one.  The builder forms all 4 x 4 class pairs x 9
+// offsets in FP64 (N = 8), with their FP32 MFMA fragments; each operator's
+// DC column is kept out of the MFMA image and applied in FP32 VALU after
+// all AC products (the nine DC products are the largest terms of a sum that
+// cancels: in the MFMA chain they would set the rounding step of every
+// later addition).
+//
+// The filter kernel partitions each image into at most 9 rectangles of one
+// class pair (interior, 4 edges, 4 corners) and those into tiles of 16 blocks
+// along a block row (or, for a one-block-wide rectangle, a block column).
+// A wave takes T tiles of one rectangle, loads the fragments of one
+// neighbour operator at a time into VGPRs and accumulates its product over
+// the T tiles before moving to the next neighbour (the operator is read
+// once per T tiles, the neighbour blocks come from L2).
+#include "mfma_common.h"
+
+namespace dctf {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kN = 8;
+constexpr int kNN = kN * kN;
+constexpr int kMaxK = 2 * kN + 1;
+
+// Source of output row i shifted by e in a block of class c: the neighbour
+// offset d (-1, 0, 1) and its row m; false if the source is dropped (zero
+// padding outside the image).
+__device__ inline bool image_source(int i, int e, int c, int border, int *d, int *m)
+{
+    int y = i + e;
+    if (y < 0 && (c & 1)) {
+        if (border == DCTF_BORDER_ZERO)
+            return false;
+        y = 0;
+    }
+    if (y >= kN && (c & 2)) {
+        if (border == DCTF_BORDER_ZERO)
+            return false;
+        y = kN - 1;
+    }
+    *d = y < 0 ? -1 : (y >= kN ? 1 : 0);
+    *m = y - *d * kN;
+    return true;
+}
+
+// Position of H[r][c] in the FP32 fragment layout of the N = 8 kernels
+// (lane = 16 g + m, r = 16 t + m, c = 16 i + 4 g + j).
+__device__ inline int frag32_index8(int r, int c)
+{
+    const int t = r >> 4, m = r & 15, i = c >> 4, g = (c >> 2) & 3, j = c & 3;
+    return ((t * 4 + i) * 64 + 16 * g + m) * 4 + j;
+}
+
+// One workgroup per (operator, class pair, offset, 16 output rows).
+__global__ __launch_bounds__(kThreads) void k_build_image(ImageBuildArgs args)
+{
+    const int cp = blockIdx.y, o = blockIdx.z;
+    const int cr = cp >> 2, cs = cp & 3, dr = o / 3 - 1, ds = o % 3 - 1;
+    const int r0 = blockIdx.x * 16;
+    const ImageBuildArgs &d = args;
+    const int kh = d.kh, kw = d.kw, ah = (kh - 1) / 2, aw = (kw - 1) / 2;
+    __shared__ double sC[kNN];
+    __shared__ double sW[kMaxK * kMaxK];
+    __shared__ double sT[kMaxK * kNN];   // T_p = A^{cr}_{dr, p - ah}
+    __shared__ double sG[kMaxK * kNN];   // G_p[j][l] = sum_q W[p][q] [row j reads m at ds] C[l][m]
+    __shared__ double sB[kMaxK * kNN];   // B_p = C G_p
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kNN; e += kThreads) {
+        const int k = e / kN, n = e % kN;
+        const double alpha = (k == 0) ? sqrt(1.0 / kN) : sqrt(2.0 / kN);
+        sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * kN));
+    }
+    for (int e = tid; e < kh * kw; e += kThreads)
+        sW[e] = d.mask[e];
+    __syncthreads();
+    for (int e = tid; e < 2 * kh * kNN; e += kThreads) {
+        const int which = e / (kh * kNN), rest = e % (kh * kNN);
+        const int p = rest / kNN, idx = rest % kNN, a = idx / kN, b = idx % kN;
+        double s = 0.0;
+        if (which == 0) {
+            // T_p[u][k] = sum_i C[u][i] C[k][m(i)] over rows i that read neighbour dr
+            for (int i = 0; i < kN; ++i) {
+                int dd, m;
+                if (image_source(i, p - ah, cr, d.border, &dd, &m) && dd == dr)
+                    s += sC[a * kN + i] * sC[b * kN + m];
+            }
+            sT[p * kNN + idx] = s;
+        } else {
+            // G_p[j][l] with (j, l) = (a, b)
+            for (int q = 0; q < kw; ++q) {
+                int dd, m;
+                if (image_source(a, q - aw, cs, d.border, &dd, &m) && dd == ds)
+                    s += sW[p * kw + q] * sC[b * kN + m];
+            }
+            sG[p * kNN + idx] = s;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kh * kNN; e += kThreads) {
+        const int p = e / kNN, idx = e % kNN, v = idx / kN, l = idx % kN;
+        double s = 0.0;
+        for (int j = 0; j < kN; ++j)
+            s += sC[v * kN + j] * sG[p * kNN + j * kN + l];
+        sB[e] = s;
+    }
+    __syncthreads();
+    const size_t opi = (size_t)cp * 9 + o;
+    double *H64 = d.H64 + opi * kNN * kNN;
+    float *F32 = d.frag32 + opi * kNN * kNN;
+    for (int e = tid; e < 16 * kNN; e += kThreads) {
+        const int r = r0 + e / kNN, c = e % kNN;
+        const int u = r / kN, v = r % kN, k = c / kN, l = c % kN;
+        double s = 0.0;
+        for (int p = 0; p < kh; ++p)
+            s += sT[p * kNN + u * kN + k] * sB[p * kNN + v * kN + l];
+        H64[(size_t)r * kNN + c] = s;
+        // the DC column goes to h0 (FP32 VALU in the filter), not to the MFMA image
+        F32[frag32_index8(r, c)] = c == 0 ? 0.0f : __double2float_rn(s);
+        if (c == 0)
+            d.h0[opi * kNN + r] = __double2float_rn(s);
+    }
+}
+
+// ------------------------------------------------------------- filter
+
+// Tile t of rectangle `rc` in image `img`: the first block's (R, S), the
+// step between its blocks (1 along a row, Bw along a column) and the count.
+struct TileRef {
+    int64_t blk0;     // raster index of the tile's first block within the image
+    int64_t step;
+    int count;
+};
+
+__device__ inline TileRef tile_ref(const ImageRect &rc, int64_t t, int Bw)
+{
+    TileRef r;
+    if (rc.dir == 0) {
+        const int64_t tps = (rc.nS + 15) / 16;
+        const int64_t row = rc.R0 + t / tps, seg = t % tps;
+        r.blk0 = row * Bw + rc.S0 + 16 * seg;
+        r.step = 1;
+        r.count = (int)min((int64_t)16, (int64_t)rc.nS - 16 * seg);
+    } else {
+        const int64_t tps = (rc.nR + 15) / 16;
+        const int64_t col = rc.S0 + t / tps, seg = t % tps;
+        r.blk0 = (rc.R0 + 16 * seg) * Bw + col;
+        r.step = Bw;
+        r.count = (int)min((int64_t)16, (int64_t)rc.nR - 16 * seg);
+    }
+    return r;
+}
+
+// Wave w takes units w, w + waves, ...; a unit is up to T consecutive tiles
+// of one rectangle of one image.
+template <int T>
+__global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_t units, int64_t waves)
+{
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= waves)
+        return;
+    const int64_t per_img_blocks = (int64_t)a.Bh * a.Bw;
+    for (int64_t unit = wave; unit < units; unit += waves) {
+        const int64_t img = unit / a.units_per_image;
+        const int64_t lu = unit % a.units_per_image;
+        int ri = 0;
+        while (ri + 1 < a.nrect && a.rect[ri + 1].unit_begin <= lu)
+            ++ri;
+        const ImageRect &rc = a.rect[ri];
+        const int64_t t0 = (lu - rc.unit_begin) * T;
+        const int nt = (int)min((int64_t)T, rc.tiles - t0);
+        const float *X = a.in + img * per_img_blocks * kNN;
+        float *Y = a.out + img * per_img_blocks * kNN;
+        // this lane's block of each tile (clamped to the tile's first block past the count)
+        int64_t blk[T];
+        bool valid[T];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            if (tt < nt) {
+                const TileRef r = tile_ref(rc, t0 + tt, a.Bw);
+                valid[tt] = n < r.count;
+                blk[tt] = r.blk0 + (valid[tt] ? n : 0) * r.step;
+            } else {
+                valid[tt] = false;
+                blk[tt] = 0;
+            }
+        }
+        f32x4 acc[T][4];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[tt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const float *ops = a.frag32 + (size_t)rc.cp * 9 * kNN * kNN;
+        float x0s[T][9];
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            if (!((rc.offsets >> o) & 1))
+                continue;
+            const int64_t shift = (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1);
+            float A[4][4][4];
+            const float *F = ops + (size_t)o * kNN * kNN;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float4 v = ld4(F + ((t * 4 + i) * 64 + lane) * 4);
+                    A[t][i][0] = v.x;
+                    A[t][i][1] = v.y;
+                    A[t][i][2] = v.z;
+                    A[t][i][3] = v.w;
+                }
+            float4 cur[4], nxt[4];
+            auto load = [&](float4 (&x)[4], int tt) {
+                const float *src = X + (blk[tt] + shift) * kNN + 4 * g;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    x[i] = ld4(src + 16 * i);
+            };
+            load(cur, 0);
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                if (tt >= nt)
+                    break;
+                if (tt + 1 < nt)
+                    load(nxt, tt + 1);
+                // DC of the neighbour block (lane (n, 0) holds coefficient 0 of block n),
+                // applied after every AC product
+                x0s[tt][o] = lane_read(cur[0].x, n);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float xv[4] = {cur[i].x, cur[i].y, cur[i].z, cur[i].w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            acc[tt][t] = mfma_f32(A[t][i][j], xv[j], acc[tt][t]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    cur[i] = nxt[i];
+            }
+        }
+        // the DC columns, in FP32 VALU, in offset order
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            if (!((rc.offsets >> o) & 1))
+                continue;
+            const float *D = a.h0 + ((size_t)rc.cp * 9 + o) * kNN + 4 * g;
+            float4 h0[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                h0[t] = ld4(D + 16 * t);
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[tt][t][0] = fmaf(h0[t].x, x0s[tt][o], acc[tt][t][0]);
+                    acc[tt][t][1] = fmaf(h0[t].y, x0s[tt][o], acc[tt][t][1]);
+                    acc[tt][t][2] = fmaf(h0[t].z, x0s[tt][o], acc[tt][t][2]);
+                    acc[tt][t][3] = fmaf(h0[t].w, x0s[tt][o], acc[tt][t][3]);
+                }
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            if (tt < nt && valid[tt]) {
+                float *dst = Y + blk[tt] * kNN + 4 * g;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    st4(dst + 16 * t, acc[tt][t]);
+            }
+        }
+    }
+}
+
+constexpr int kImageT = 4;
+constexpr int kImageWavesPerCu = 8;
+
+}  // namespace
+
+hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_build_image, dim3(kNN / 16, 16, 9), dim3(kThreads), 0, stream, args);
+    return hipGetLastError();
+}
+
+int image_tiles_per_unit() { return kImageT; }
+
+hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream)
+{
+    const int64_t units = a.units_per_image * a.nimg;
+    if (units <= 0)
+        return hipSuccess;
+    int64_t waves = (int64_t)cu_count() * kImageWavesPerCu;
+    waves = waves < units ? waves : units;
+    const int64_t groups = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_filter_image8<kImageT>), dim3((unsigned)groups), dim3(256), 0, stream, a, units, waves);
+    return hipGetLastError();
+}
+
+}  // namespace dctf
