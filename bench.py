@@ -179,6 +179,45 @@ def pixel_outputs(dctf, torch, stream, X, N, steps, warmup):
     return res
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def image_level_flops(Bh, Bw, kh, kw, N=8):
+    """Algorithmic FP32 flops of one image-level pass over one Bh x Bw image:
+    2 N^4 per (block, neighbour it reads); a block reads the neighbours that
+    exist and that the mask reaches (its anchor is floor((K-1)/2))."""
+    ah, aw = (kh - 1) // 2, (kw - 1) // 2
+    up, down, left, right = ah > 0, kh - 1 - ah > 0, aw > 0, kw - 1 - aw > 0
+    rows = {}
+    for R in range(Bh):
+        rows[(R > 0 and up) + 1 + (R < Bh - 1 and down)] = rows.get((R > 0 and up) + 1 + (R < Bh - 1 and down), 0) + 1
+    cols = {}
+    for S in range(Bw):
+        k = (S > 0 and left) + 1 + (S < Bw - 1 and right)
+        cols[k] = cols.get(k, 0) + 1
+    reads = sum(nr * cnt_r * nc * cnt_c for nr, cnt_r in rows.items() for nc, cnt_c in cols.items())
+    return reads * 2 * (N * N) ** 2
+
+
+def image_level(dctf, torch, stream, X, Y, images, side, N, steps, warmup):
+    """Image-level (cross-block) filtering of the same 64 images: every block
+    reads its 8 neighbours, the border rule applies at the image edge only.
+    5x5 asymmetric mask, both borders, FP32 MFMA (bound: FP32 MFMA peak)."""
+    import synthetic as syn
+    Bh = Bw = side // N
+    W = syn.asym_mask_5x5()
+    flops = image_level_flops(Bh, Bw, *W.shape, N) * images
+    res = {"blocks": X.numel() // (N * N), "mask": "5x5 asymmetric", "alg_flops_per_launch": flops}
+    for bname, border in (("zero", dctf.DCTF_BORDER_ZERO), ("replicate", dctf.DCTF_BORDER_REPLICATE)):
+        op = dctf.dctf_build_image_operator(W, N, border)
+        ms = timed_steps(torch, lambda: dctf.dctf_filter_image(op, dctf.DCTF_PREC_FP32, X, Y, Bh, Bw, stream),
+                         steps, warmup, stream)
+        tf = flops / (ms * 1e-3) / 1e12
+        res[bname + "_fp32"] = {"ms_per_launch": ms, "blocks_per_s": res["blocks"] / (ms * 1e-3),
+                                "TFLOPs": tf, "frac_of_fp32_mfma_peak": tf / FP32_MFMA_PEAK_TFLOPS}
+    return res
+
+
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
     one 7x7 asymmetric mask with zero border, in both precisions, and the
@@ -470,6 +509,8 @@ def main():
                     "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
         extras["small_workloads"] = small_workloads(dctf, torch, stream)
         extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup)
+        extras["image_level"] = image_level(dctf, torch, stream, X, Y, args.images, args.side, N,
+                                            max(10, args.steps // 5), max(5, args.warmup // 6))
         # optional verify kernel: inverse DCT + uint8 of every output block
         pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
         vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)
