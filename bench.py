@@ -218,6 +218,28 @@ def image_level(dctf, torch, stream, X, Y, images, side, N, steps, warmup):
     return res
 
 
+def fp64_filter(dctf, torch, stream, X, N, steps, warmup):
+    """The same blocks as FP64 coefficients through the FP64 filter (FP64
+    operator, v_mfma_f64_16x16x4_f64), 5x5 asymmetric mask, replication:
+    16 bytes per coefficient, against a copy of the same bytes."""
+    import synthetic as syn
+    nn = N * N
+    B = X.numel() // nn
+    X64 = X.double()
+    Y64 = torch.empty_like(X64)
+    op = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, dctf.DCTF_BORDER_REPLICATE)
+    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream)
+    cms = timed_steps(torch, lambda: dctf.dctf_stream_copy(X64.view(torch.float32), Y64.view(torch.float32), stream),
+                      steps, warmup, stream)
+    bytes_ = B * nn * 16
+    res = {"blocks": B, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": bytes_ / (ms * 1e-3) / 1e9,
+           "frac_of_8TBps": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "copy_GBps": bytes_ / (cms * 1e-3) / 1e9,
+           "fp64_mfma_TFLOPs": B * 2.0 * nn * nn / (ms * 1e-3) / 1e12}
+    del X64, Y64
+    torch.cuda.empty_cache()
+    return res
+
+
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
     one 7x7 asymmetric mask with zero border, in both precisions, and the
@@ -511,6 +533,7 @@ def main():
         extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup)
         extras["image_level"] = image_level(dctf, torch, stream, X, Y, args.images, args.side, N,
                                             max(10, args.steps // 5), max(5, args.warmup // 6))
+        extras["fp64"] = fp64_filter(dctf, torch, stream, X, N, max(10, args.steps // 2), max(5, args.warmup // 3))
         # optional verify kernel: inverse DCT + uint8 of every output block
         pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
         vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)

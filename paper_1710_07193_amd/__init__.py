@@ -64,6 +64,7 @@ _SIGS = {
     "dctf_operator_fp64": ([_P, _P], _I),
     "dctf_operator_pixel_fp64": ([_P, _P], _I),
     "dctf_filter_blocks_u8": ([_P, _I, _P, _P, _I64, _P], _I),
+    "dctf_filter_blocks_f64": ([_P, _P, _P, _I64, _P], _I),
     "dctf_build_image_operator": ([_P, _I, _I, _I, _I, _P, ctypes.POINTER(_P)], _I),
     "dctf_image_operator_fp64": ([_P, _I, _I, _I, _I, _P], _I),
     "dctf_image_operator_destroy": ([_P], None),
@@ -252,6 +253,16 @@ def dctf_filter_blocks_factored(op: Operator, X: torch.Tensor, Y: torch.Tensor, 
     _check(_lib.dctf_filter_blocks_factored(op, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
                                             X.numel() // nn, _stream(stream)),
            "dctf_filter_blocks_factored")
+
+
+def dctf_filter_blocks_f64(op: Operator, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    """Y[b] = H_dct . X[b] in FP64; X, Y: float64 device tensors of B*N*N elements."""
+    nn = op.N * op.N
+    if X.numel() % nn or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold the same whole number of N*N blocks")
+    _check(_lib.dctf_filter_blocks_f64(op, _dptr(X, torch.float64, "X"), _dptr(Y, torch.float64, "Y"),
+                                       X.numel() // nn, _stream(stream)),
+           "dctf_filter_blocks_f64")
 
 
 def dctf_filter_blocks_u8(op: Operator, prec: int, X: torch.Tensor, pix: torch.Tensor, stream=None):

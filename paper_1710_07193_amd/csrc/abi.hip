@@ -456,6 +456,27 @@ extern "C" dctf_status dctf_filter_blocks_factored(dctf_operator op, const float
     return st;
 }
 
+extern "C" dctf_status dctf_filter_blocks_f64(dctf_operator op, const double *in_dev, double *out_dev, int64_t B,
+                                              dctf_stream stream)
+{
+    if (op == nullptr || B < 0)
+        return DCTF_EINVAL;
+    if (op->N > 8)
+        return DCTF_EUNSUPPORTED;
+    if (B == 0)
+        return DCTF_OK;
+    const size_t bytes = (size_t)B * op->N * op->N * sizeof(double);
+    if (in_dev == nullptr || out_dev == nullptr || !aligned16(in_dev) || !aligned16(out_dev) ||
+        ranges_overlap(in_dev, bytes, out_dev, bytes))
+        return DCTF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    dctf_status st = hip_status(launch_filter_f64(op->N, op->img.dct.H64, in_dev, out_dev, B, s));
+    timing_end(s, slot);
+    return st;
+}
+
 // ============================================================ pixel output
 
 static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void *in, const float *qtab,

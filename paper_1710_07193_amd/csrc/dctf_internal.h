@@ -164,6 +164,10 @@ hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream);
 hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream);
 int image_tiles_per_unit();
 
+// fp64.hip — FP64 filter (N = 8 MFMA, N <= 4 VALU) from the FP64 operator.
+hipError_t launch_filter_f64(int N, const double *H64, const double *in, double *out, int64_t B,
+                             hipStream_t stream);
+
 // filter.hip — single-operator filter of B blocks.
 struct FilterArgs {
     const float *in;

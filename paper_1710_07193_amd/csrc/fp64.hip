@@ -1,0 +1,162 @@
+// FP64 filter: Y[b] = H_dct . X[b] with FP64 coefficients and the FP64
+// operator the builder forms (eq. 11 / eq. 20 for every block, no rounding
+// of the operator or the data to a narrower type).
+//
+//   N = 8 : k_filter_n8_f64 — v_mfma_f64_16x16x4_f64, the same tiling as the
+//           FP32 kernel: one wave holds the whole 64 x 64 operator in VGPRs
+//           (64 doubles per lane, read straight from the row-major FP64
+//           operator, rows permuted inside each M-tile to match the FP64
+//           MFMA's result layout) and computes Y^t = H . X^t for 16 blocks
+//           per tile, M = 64 outputs in 4 M-tiles, K = 64 in 16 k-steps; lane
+//           (n, g) supplies coefficients 16i + 4g + j of block n and receives
+//           outputs 16t + 4g + r, both as 32 contiguous bytes.
+//   N <= 4: k_filter_small_f64 — one thread per block, FP64 VALU.
+//
+// With 8 bytes in and 8 out per coefficient the N = 8 kernel is HBM-bound
+// (1 KiB per block against 8192 flop: FP64 MFMA would allow 9.6e9 blocks/s).
+#include "dctf_internal.h"
+
+namespace dctf {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f64x2 ld2_nt(const double *p)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p));
+}
+
+__device__ __forceinline__ void st2_nt(double *p, f64x2 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<f64x2 *>(p));
+}
+
+// Wave w takes tiles (16 blocks) w, w + waves, ...; the next tile's loads are
+// in flight while the current one is multiplied.
+__global__ __launch_bounds__(256) void k_filter_n8_f64(const double *H64, const double *in, double *out,
+                                                       int64_t B, int64_t tiles, int64_t waves)
+{
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= waves)   // waves <= tiles
+        return;
+    // A[t][i][j] = H[16t + s(m)][16i + 4g + j] with m = lane % 16.  The FP64
+    // MFMA returns row g + 4r of its 16 x 16 result in register r of lane
+    // (n, g); taking A's rows in the order s(m) = 4 (m % 4) + m / 4 makes that
+    // row output 16t + 4g + r, so each lane holds four consecutive outputs.
+    const int srow = 4 * (n & 3) + (n >> 2);
+    double A[4][4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const f64x2 v =
+                    *reinterpret_cast<const f64x2 *>(H64 + (16 * t + srow) * 64 + 16 * i + 4 * g + 2 * h);
+                A[t][i][2 * h] = v[0];
+                A[t][i][2 * h + 1] = v[1];
+            }
+    auto load = [&](f64x2 (&x)[4][2], int64_t tile) {
+        int64_t blk = tile * 16 + n;
+        blk = blk < B ? blk : B - 1;   // clamped: the store below is masked
+        const double *src = in + blk * 64 + 4 * g;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                x[i][h] = ld2_nt(src + 16 * i + 2 * h);
+    };
+    auto compute_store = [&](const f64x2 (&x)[4][2], int64_t tile) {
+        f64x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[t] = mfma_f64(A[t][i][j], x[i][j >> 1][j & 1], acc[t]);
+        const int64_t blk = tile * 16 + n;
+        if (blk < B) {
+            double *dst = out + blk * 64 + 4 * g;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                st2_nt(dst + 16 * t, f64x2{acc[t][0], acc[t][1]});
+                st2_nt(dst + 16 * t + 2, f64x2{acc[t][2], acc[t][3]});
+            }
+        }
+    };
+    const int64_t mine = (tiles - wave + waves - 1) / waves;
+    f64x2 cur[4][2], nxt[4][2];
+    int64_t tile = wave;
+    load(cur, tile);
+    for (int64_t k = 1; k < mine; ++k) {
+        load(nxt, tile + waves);
+        compute_store(cur, tile);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            cur[i][0] = nxt[i][0];
+            cur[i][1] = nxt[i][1];
+        }
+        tile += waves;
+    }
+    compute_store(cur, tile);
+}
+
+__global__ __launch_bounds__(256) void k_filter_small_f64(const double *H64, const double *in, double *out,
+                                                          int64_t B, int N)
+{
+    __shared__ double sH[256];
+    const int NN = N * N;
+    for (int e = threadIdx.x; e < NN * NN; e += blockDim.x)
+        sH[e] = H64[e];
+    __syncthreads();
+    const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk >= B)
+        return;
+    double x[16];
+    for (int k = 0; k < NN; ++k)
+        x[k] = in[blk * NN + k];
+    for (int u = 0; u < NN; ++u) {
+        double s = 0.0;
+        for (int k = 0; k < NN; ++k)
+            s = fma(sH[u * NN + k], x[k], s);
+        out[blk * NN + u] = s;
+    }
+}
+
+constexpr int kF64WavesPerCu = 8;
+
+}  // namespace
+
+hipError_t launch_filter_f64(int N, const double *H64, const double *in, double *out, int64_t B,
+                             hipStream_t stream)
+{
+    if (B <= 0)
+        return hipSuccess;
+    if (N <= 4) {
+        const int64_t groups = (B + 255) / 256;
+        hipLaunchKernelGGL(k_filter_small_f64, dim3((unsigned)groups), dim3(256), 0, stream, H64, in, out, B, N);
+        return hipGetLastError();
+    }
+    if (N != 8)
+        return hipErrorInvalidValue;
+    const int64_t tiles = (B + 15) / 16;
+    int64_t waves = (int64_t)cu_count() * kF64WavesPerCu;
+    waves = waves < tiles ? waves : tiles;
+    const int64_t groups = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_filter_n8_f64, dim3((unsigned)groups), dim3(256), 0, stream, H64, in, out, B, tiles,
+                       waves);
+    return hipGetLastError();
+}
+
+}  // namespace dctf

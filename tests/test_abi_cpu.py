@@ -89,6 +89,7 @@ def test_filter_and_batch_validation(lib):
     assert lib.dctf_operator_factors_fp64(None, None, None) == -1
     assert lib.dctf_filter_blocks_factored(None, None, None, 1, None) == -1
     assert lib.dctf_operator_pixel_fp64(None, None) == -1
+    assert lib.dctf_filter_blocks_f64(None, None, None, 1, None) == -1
     assert lib.dctf_filter_image(None, 0, None, None, 1, 1, 1, None) == -1
     assert lib.dctf_image_operator_fp64(None, 0, 0, 0, 0, None) == -1
     assert lib.dctf_build_image_operator(None, 3, 3, 8, 0, None, None) == -1
