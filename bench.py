@@ -545,10 +545,11 @@ def main():
     if args.serve_seconds > 0:
         del X, Y
         torch.cuda.empty_cache()
-        sweep, sstats = serving_sweep(dctf, torch, [1000.0, 10000.0, 50000.0, 100000.0, 200000.0],
+        sweep, sstats = serving_sweep(dctf, torch, [1000.0, 10000.0, 50000.0, 100000.0, 150000.0, 200000.0],
                                       args.serve_seconds)
-        # headline: the highest offered rate the server kept up with (span within 10 % of the offer)
-        kept = [r for r in sweep if r["span_s"] <= 1.1 * r["offered_s"] + 0.005]
+        # headline: the highest offered rate the server kept up with: no queue built up, i.e. the
+        # last request completed within 1 ms of its arrival
+        kept = [r for r in sweep if r["span_s"] - r["offered_s"] <= 1e-3]
         head = kept[-1] if kept else sweep[0]
         out["p99_latency_ms"] = head["p99_ms"]
         out["serving"] = {"at_rate_req_s": head["rate_req_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
