@@ -281,6 +281,34 @@ def n16_frames(dctf, torch, stream, steps, warmup):
     return res
 
 
+def n32_frames(dctf, torch, stream, steps, warmup):
+    """The 32 frames of 3840x2160 in 32x32 blocks (bottom edge padded to 2176:
+    261,120 blocks), one 7x7 asymmetric mask with zero border, through the
+    N = 32 FP32 kernel (1024 x 1024 operator streamed from L2); bound: FP32
+    MFMA (2 * 1024^2 flop per block)."""
+    import numpy as np
+
+    import synthetic as syn
+    N, frames, h, w = 32, 32, 2160, 3840
+    nb = ((h + N - 1) // N) * (w // N)
+    X = torch.empty(frames * nb * N * N, dtype=torch.float32, device="cuda")
+    for f in range(frames):
+        img = torch.from_numpy(syn.image_u8(3000 + f, h, w)).cuda()
+        dctf.dctf_forward_dct_u8(img, N, X[f * nb * N * N:(f + 1) * nb * N * N])
+    Y = torch.empty_like(X)
+    op = dctf.dctf_build_operator(syn.random_mask(np.random.default_rng(7), 7, 7), N, dctf.DCTF_BORDER_ZERO)
+    B = frames * nb
+    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, dctf.DCTF_PREC_FP32, X, Y, stream), steps, warmup,
+                     stream)
+    tf = B * 2.0 * (N * N) ** 2 / (ms * 1e-3) / 1e12
+    res = {"blocks": B, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
+           "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "fp32_mfma_TFLOPs": tf,
+           "frac_of_fp32_mfma_peak": tf / FP32_MFMA_PEAK_TFLOPS}
+    del X, Y
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_context(torch, images, side, pool, draws, N=8, seconds=5.0):
     """Two more CPU figures beside the baseline: the oracle on one thread,
     and the method itself on the CPU (Y = X . H^T in FP32 with torch's CPU
@@ -541,6 +569,7 @@ def main():
         out["extras"] = extras
         del pix
         extras["n16_frames"] = n16_frames(dctf, torch, stream, max(10, args.steps // 5), max(5, args.warmup // 6))
+        extras["n32_frames"] = n32_frames(dctf, torch, stream, max(5, args.steps // 10), 3)
 
     if args.serve_seconds > 0:
         del X, Y

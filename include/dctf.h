@@ -68,7 +68,10 @@ typedef struct dctf_operator_s *dctf_operator;
 typedef struct dctf_batch_s *dctf_batch;
 typedef struct dctf_image_operator_s *dctf_image_operator;
 
-/* Supported block sizes N: 2, 4, 8, 16.  Mask sides: 1 <= kh, kw <= 2N + 1. */
+/* Supported block sizes N: 2, 4, 8, 16, and 32 for the operator build, its
+ * FP64 read-back, dctf_filter_blocks, the forward DCT and the verify kernel
+ * (the other calls return DCTF_EUNSUPPORTED for N = 32).  Mask sides:
+ * 1 <= kh, kw <= 2N + 1. */
 
 /* ------------------------------------------------------------------ operators */
 
@@ -164,7 +167,9 @@ dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double 
  * mid- and high-frequency coefficients: the 5e-3 bound holds for natural-image
  * content, not for arbitrary inputs (binary stripe patterns reach ~2e-2).
  * For N <= 4 both precisions run one FP32 kernel (the operator is at most
- * 16 x 16).  B = 0 is a no-op.  Each block's result depends only on that
+ * 16 x 16); for N = 32 both run the FP32 MFMA kernel that streams the
+ * 1024 x 1024 operator from L2 (its DC column applied in FP32 VALU).
+ * B = 0 is a no-op.  Each block's result depends only on that
  * block and the operator: it is bit-identical whatever B, the tuning variant
  * or the batch the block belongs to.
  * Errors: DCTF_EINVAL, DCTF_EUNSUPPORTED, DCTF_EHIP (launch failure).

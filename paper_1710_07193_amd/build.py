@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdctf.so")
-SOURCES = ["abi.hip", "builder.hip", "filter.hip", "pixels.hip", "image.hip", "fp64.hip", "batch.hip", "verify.hip", "serve.hip"]
+SOURCES = ["abi.hip", "builder.hip", "filter.hip", "pixels.hip", "image.hip", "fp64.hip", "n32.hip", "batch.hip", "verify.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

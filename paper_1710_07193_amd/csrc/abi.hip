@@ -25,7 +25,11 @@ std::mutex g_variant_mu;
 int g_variant[17][2];   // [N][prec]; zero-initialised = default variant 0
 std::atomic<int> g_batch_fronts{2};
 
+// Block sizes of the kernels around the filter (forward DCT, verify,
+// tuning) and of every operator path but the N = 32 dense filter.
 bool supported_n(int N) { return N == 2 || N == 4 || N == 8 || N == 16; }
+// Block sizes an operator can be built for.
+bool supported_op_n(int N) { return supported_n(N) || N == 32; }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -113,7 +117,7 @@ using namespace dctf;
 
 static dctf_status validate_mask(const double *mask, int kh, int kw, int N, int border)
 {
-    if (!supported_n(N))
+    if (!supported_op_n(N))
         return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
     if (mask == nullptr || kh < 1 || kw < 1 || kh > 2 * N + 1 || kw > 2 * N + 1)
         return DCTF_EINVAL;
@@ -182,17 +186,21 @@ int dctf::mask_rank_factors(const double *W, int kh, int kw, std::vector<double>
 static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, dctf_operator *out)
 {
     const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
+    // split-BF16 images exist for N = 8, 16; the pixel-domain set for N <= 16
+    const bool split = N == 8 || N == 16;
+    const size_t FS = split ? F : 0, FL = split ? frag_lf_elems(N) : 0;
+    const int domains = N <= 16 ? 2 : 1;
     size_t off = 0;
     const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
     // one dense image set per domain (DCT-domain H, pixel-domain G)
     size_t o_h64[2], o_h32[2], o_f32[2], o_fhi[2], o_flo[2], o_flf[2], o_h0[2];
-    for (int d = 0; d < 2; ++d) {
+    for (int d = 0; d < domains; ++d) {
         o_h64[d] = off; off = align_up(off + sizeof(double) * N4);
         o_h32[d] = off; off = align_up(off + sizeof(float) * N4);
         o_f32[d] = off; off = align_up(off + sizeof(float) * F);
-        o_fhi[d] = off; off = align_up(off + sizeof(uint16_t) * F);
-        o_flo[d] = off; off = align_up(off + sizeof(uint16_t) * F);
-        o_flf[d] = off; off = align_up(off + sizeof(float) * frag_lf_elems(N));
+        o_fhi[d] = off; off = align_up(off + sizeof(uint16_t) * FS);
+        o_flo[d] = off; off = align_up(off + sizeof(uint16_t) * FS);
+        o_flf[d] = off; off = align_up(off + sizeof(float) * FL);
         o_h0[d] = off;  off = align_up(off + sizeof(float) * NN);
     }
     const size_t o_fa = off;   off = align_up(off + sizeof(double) * rank * kh);
@@ -220,14 +228,15 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     op->base = base;
     op->bytes = off;
     op->img.mask = reinterpret_cast<double *>(b + o_mask);
-    for (int d = 0; d < 2; ++d) {
+    op->img.pix = DenseImages{};
+    for (int d = 0; d < domains; ++d) {
         DenseImages &D = d == 0 ? op->img.dct : op->img.pix;
         D.H64 = reinterpret_cast<double *>(b + o_h64[d]);
         D.H32 = reinterpret_cast<float *>(b + o_h32[d]);
         D.frag32 = F ? reinterpret_cast<float *>(b + o_f32[d]) : nullptr;
-        D.frag_hi = F ? reinterpret_cast<uint16_t *>(b + o_fhi[d]) : nullptr;
-        D.frag_lo = F ? reinterpret_cast<uint16_t *>(b + o_flo[d]) : nullptr;
-        D.frag_lf = F ? reinterpret_cast<float *>(b + o_flf[d]) : nullptr;
+        D.frag_hi = FS ? reinterpret_cast<uint16_t *>(b + o_fhi[d]) : nullptr;
+        D.frag_lo = FS ? reinterpret_cast<uint16_t *>(b + o_flo[d]) : nullptr;
+        D.frag_lf = FL ? reinterpret_cast<float *>(b + o_flf[d]) : nullptr;
         D.h0 = reinterpret_cast<float *>(b + o_h0[d]);
     }
     op->rank = rank;
@@ -341,6 +350,8 @@ extern "C" dctf_status dctf_operator_pixel_fp64(dctf_operator op, double *host_o
 {
     if (op == nullptr || host_out == nullptr)
         return DCTF_EINVAL;
+    if (op->img.pix.H64 == nullptr)
+        return DCTF_EUNSUPPORTED;
     const size_t NN = (size_t)op->N * op->N;
     return hip_status(hipMemcpy(host_out, op->img.pix.H64, sizeof(double) * NN * NN, hipMemcpyDeviceToHost));
 }
@@ -414,7 +425,10 @@ extern "C" dctf_status dctf_filter_blocks(dctf_operator op, int prec, const floa
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);
-    st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
+    if (op->N == 32)
+        st = hip_status(launch_filter_n32(a, s));
+    else
+        st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
     timing_end(s, slot);
     return st;
 }
@@ -431,6 +445,8 @@ extern "C" dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_ho
 {
     if (op == nullptr || P_host == nullptr || Q_host == nullptr)
         return DCTF_EINVAL;
+    if (op->N > 16)
+        return DCTF_EUNSUPPORTED;
     const size_t bytes = sizeof(double) * op->rank * op->N * op->N;
     dctf_status st = hip_status(hipMemcpy(P_host, op->img.P64, bytes, hipMemcpyDeviceToHost));
     if (st == DCTF_OK)
@@ -484,6 +500,8 @@ static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void
 {
     if (op == nullptr)
         return DCTF_EINVAL;
+    if (op->img.pix.H64 == nullptr)
+        return DCTF_EUNSUPPORTED;
     if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
         return DCTF_EINVAL;
     if (B < 0 || !std::isfinite(dc_offset))
@@ -1060,7 +1078,7 @@ extern "C" dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int pr
 extern "C" dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w, int64_t pitch, int N,
                                            float *coeffs_dev, dctf_stream stream)
 {
-    if (!supported_n(N))
+    if (!supported_op_n(N))
         return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
     if (img_dev == nullptr || coeffs_dev == nullptr || h < 1 || w < 1 || pitch < w || !aligned16(coeffs_dev))
         return DCTF_EINVAL;
@@ -1072,7 +1090,7 @@ extern "C" dctf_status dctf_idct_u8_verify(int N, const float *coeffs_dev, int64
                                            const uint8_t *expected_dev, unsigned long long *counters_dev,
                                            dctf_stream stream)
 {
-    if (!supported_n(N))
+    if (!supported_op_n(N))
         return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
     if (B < 0)
         return DCTF_EINVAL;
@@ -1150,6 +1168,8 @@ extern "C" dctf_status dctf_autotune(dctf_operator op, int prec, const float *in
         return DCTF_EINVAL;
     if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
         return DCTF_EINVAL;
+    if (!supported_n(op->N))   // the N = 32 filter has one launch shape
+        return DCTF_EUNSUPPORTED;
     dctf_status st = validate_io(op->N, in_dev, out_dev, B);
     if (st != DCTF_OK)
         return st;

@@ -75,12 +75,14 @@ __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32
 //          r = 16t + m, c = 16i + 4g + j -> ((t*4 + i)*64 + lane)*4 + j.
 //   N = 16 (weight-stationary, 16 M-tiles over 8 waves): r = 16T + m,
 //          c = 16i + 4g + j -> ((T*16 + i)*64 + lane)*4 + j.
+//   N = 32 (operator streamed in 16-column chunks): the same with 64 chunks
+//          per M-tile, ((T*64 + i)*64 + lane)*4 + j.
 __device__ inline int frag32_index(int N, int r, int c)
 {
     int t = r >> 4, m = r & 15;
     int i = c >> 4, g = (c >> 2) & 3, j = c & 3;
     int lane = 16 * g + m;
-    int ni = (N == 8) ? 4 : 16;
+    int ni = N * N / 16;   // k-chunks of 16 per M-tile
     return ((t * ni + i) * 64 + lane) * 4 + j;
 }
 
@@ -102,7 +104,7 @@ __device__ inline int frag16_index(int N, int r, int c)
 // LDS budget for the per-chunk matrices: T_p, G_p and B_p (3 N x N FP64
 // each) for up to kChunk(N) mask rows at once.
 template <int N>
-constexpr int chunk_rows() { return N >= 16 ? 8 : (N == 8 ? 17 : 33); }
+constexpr int chunk_rows() { return N >= 32 ? 1 : (N >= 16 ? 8 : (N == 8 ? 17 : 33)); }
 
 template <int N>
 __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
@@ -117,11 +119,14 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
     const bool pix = domain == 1;   // pixel-domain operator G instead of H_dct
     const DenseImages &out = pix ? d.img.pix : d.img.dct;
 
-    double *sC = lds;                 // NN
-    double *sW = sC + NN;             // kh * kw (<= 33 * 33)
-    double *sT = sW + kMaxK * kMaxK;  // P * NN
-    double *sG = sT + P * NN;         // P * NN
-    double *sB = sG + P * NN;         // P * NN
+    // N = 32 masks (up to 65 x 65) are read from global memory instead of LDS
+    constexpr bool kMaskInLds = N <= 16;
+    double *sC = lds;                                   // NN
+    double *sW = sC + NN;                               // kh * kw (<= 33 * 33), N <= 16
+    double *sT = sW + (kMaskInLds ? kMaxK * kMaxK : 0); // P * NN
+    double *sG = sT + P * NN;                           // P * NN
+    double *sB = sG + P * NN;                           // P * NN
+    const double *Wm = kMaskInLds ? sW : d.img.mask;
 
     const int tid = threadIdx.x;
     for (int e = tid; e < NN; e += kThreads) {
@@ -129,8 +134,9 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
         const double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
         sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N));
     }
-    for (int e = tid; e < kh * kw; e += kThreads)
-        sW[e] = d.img.mask[e];
+    if constexpr (kMaskInLds)
+        for (int e = tid; e < kh * kw; e += kThreads)
+            sW[e] = d.img.mask[e];
 
     double acc[per_thread];
 #pragma unroll
@@ -163,7 +169,7 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
                 }
                 sT[pp * NN + idx] = s;
             } else {
-                const double *w = sW + (p0 + pp) * kw;
+                const double *w = Wm + (p0 + pp) * kw;
                 for (int q = 0; q < kw; ++q) {
                     bool ok;
                     const int m = src_index(a, q - aw, N, border, &ok);
@@ -214,10 +220,11 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
         out.H32[(size_t)r * NN + c] = h32;
         if (c == 0)
             out.h0[r] = h32;
-        if constexpr (N >= 8) {
+        if constexpr (N >= 8)
             // FP32 MFMA image: the operator without its DC column, which the
             // FP32 filter applies separately in VALU arithmetic.
             out.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
+        if constexpr (N == 8 || N == 16) {
             // Split path: low-frequency columns (DC included) go to the FP32
             // MFMA image frag_lf; every other column is split into BF16
             // hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
@@ -239,8 +246,12 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
     }
 }
 
-constexpr int lds_doubles(int N) { return N * N + kMaxK * kMaxK + 3 * (N >= 16 ? 8 : (N == 8 ? 17 : 33)) * N * N; }
-constexpr int kLdsDoubles = lds_doubles(16) > lds_doubles(8) ? lds_doubles(16) : lds_doubles(8);
+constexpr int lds_doubles(int N)
+{
+    return N * N + (N <= 16 ? kMaxK * kMaxK : 0) + 3 * (N >= 32 ? 1 : (N >= 16 ? 8 : (N == 8 ? 17 : 33))) * N * N;
+}
+constexpr int max3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+constexpr int kLdsDoubles = max3(lds_doubles(4), lds_doubles(8), lds_doubles(16));
 
 __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
 {
@@ -260,8 +271,21 @@ __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
     case 2: build_op<2>(d, r0, lds, domain); break;
     case 4: build_op<4>(d, r0, lds, domain); break;
     case 8: build_op<8>(d, r0, lds, domain); break;
-    default: build_op<16>(d, r0, lds, domain); break;
+    case 16: build_op<16>(d, r0, lds, domain); break;
+    default: break;   // N = 32: k_build32
     }
+}
+
+// N = 32 operators (H_dct images only: no split-BF16 or pixel-domain set).
+// A kernel of its own: its 64 FP64 accumulators per thread would otherwise
+// set the register allocation, and so the occupancy, of every block size.
+__global__ __launch_bounds__(kThreads) void k_build32(BuildArgs args)
+{
+    const int op = blockIdx.y;
+    if (op >= args.n || args.d[op].N != 32)
+        return;
+    __shared__ double lds[lds_doubles(32)];
+    build_op<32>(args.d[op], blockIdx.x * kRowsPerGroup, lds, 0);
 }
 
 // Factored (paper-form) operator: for rank term r and axis x (0: block rows
@@ -278,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_build_factors(BuildArgs args)
         return;
     const BuildDesc &d = args.d[op];
     const int r = blockIdx.x >> 1, axis = blockIdx.x & 1;
-    if (r >= d.rank)
+    if (r >= d.rank || d.N > kMaxN)   // the factored form is built for N <= 16
         return;
     const int N = d.N, NN = N * N, tid = threadIdx.x;
     const int K = axis ? d.kw : d.kh, anchor = (K - 1) / 2;
@@ -325,14 +349,24 @@ hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
     if (args.n <= 0)
         return hipSuccess;
     int maxN = 0, maxRank = 0;
+    bool has32 = false;
     for (int i = 0; i < args.n; ++i) {
-        maxN = args.d[i].N > maxN ? args.d[i].N : maxN;
+        if (args.d[i].N == 32)
+            has32 = true;
+        else
+            maxN = args.d[i].N > maxN ? args.d[i].N : maxN;
         maxRank = args.d[i].rank > maxRank ? args.d[i].rank : maxRank;
     }
     const int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
     const int domains = ((args.parts & kBuildDct) ? 1 : 0) + ((args.parts & kBuildPix) ? 1 : 0);
-    if (domains > 0) {
+    if (domains > 0 && maxN > 0) {
         hipLaunchKernelGGL(k_build, dim3(groups, args.n, domains), dim3(kThreads), 0, stream, args);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (has32 && (args.parts & kBuildDct)) {
+        hipLaunchKernelGGL(k_build32, dim3(32 * 32 / kRowsPerGroup, args.n), dim3(kThreads), 0, stream, args);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -181,6 +181,9 @@ struct FilterArgs {
     const float *H32;
 };
 hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipStream_t stream);
+// n32.hip — the N = 32 filter (FP32 MFMA, operator streamed from L2; uses
+// frag32 and h0 of the DCT-domain images).
+hipError_t launch_filter_n32(const FilterArgs &a, hipStream_t stream);
 int variant_count(int N, int prec);
 const char *variant_name(int N, int prec, int v);
 int default_variant(int N, int prec);

@@ -25,16 +25,18 @@ __device__ inline void fill_dct(T *sC, int N)
 }
 
 // X[u][v] = sum_i C[u][i] (sum_j x[i][j] C[v][j]) in FP64, rounded once to FP32.
-__global__ __launch_bounds__(kThreads) void k_forward_dct_u8(const uint8_t *img, int h, int w,
-                                                             int64_t pitch, int N, float *coeffs,
-                                                             int64_t nblocks)
+// One thread per pixel; workgroups of max(256, N*N) threads.
+constexpr int kMaxDctThreads = 1024;
+__global__ __launch_bounds__(kMaxDctThreads) void k_forward_dct_u8(const uint8_t *img, int h, int w,
+                                                                   int64_t pitch, int N, float *coeffs,
+                                                                   int64_t nblocks)
 {
-    __shared__ double sC[256];
-    __shared__ double sx[256];
-    __shared__ double st[256];
+    __shared__ double sC[kMaxDctThreads];
+    __shared__ double sx[kMaxDctThreads];
+    __shared__ double st[kMaxDctThreads];
     fill_dct(sC, N);
     const int NN = N * N;
-    const int per = kThreads / NN;
+    const int per = blockDim.x / NN;
     const int local = threadIdx.x / NN, e = threadIdx.x % NN;
     const int i = e / N, j = e % N;
     const int64_t blk = (int64_t)blockIdx.x * per + local;
@@ -240,9 +242,10 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
                                  float *coeffs, hipStream_t stream)
 {
     const int64_t nblocks = (int64_t)((h + N - 1) / N) * ((w + N - 1) / N);
-    const int per = kThreads / (N * N);
+    const int threads = N * N > kThreads ? N * N : kThreads;   // <= kMaxDctThreads (N <= 32)
+    const int per = threads / (N * N);
     const int64_t groups = (nblocks + per - 1) / per;
-    hipLaunchKernelGGL(k_forward_dct_u8, dim3((unsigned)groups), dim3(kThreads), 0, stream, img, h, w,
+    hipLaunchKernelGGL(k_forward_dct_u8, dim3((unsigned)groups), dim3(threads), 0, stream, img, h, w,
                        pitch, N, coeffs, nblocks);
     return hipGetLastError();
 }
@@ -261,7 +264,8 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
     case 2: hipLaunchKernelGGL(k_idct_u8_verify<2>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
     case 4: hipLaunchKernelGGL(k_idct_u8_verify<4>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
     case 8: hipLaunchKernelGGL(k_idct_u8_verify<8>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
-    default: hipLaunchKernelGGL(k_idct_u8_verify<16>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    case 16: hipLaunchKernelGGL(k_idct_u8_verify<16>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    default: hipLaunchKernelGGL(k_idct_u8_verify<32>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
     }
     return hipGetLastError();
 }

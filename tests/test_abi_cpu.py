@@ -60,7 +60,7 @@ def test_build_operator_validation(lib):
     out = ctypes.c_void_p()
     m, keep = _mask([1.0 / 9] * 9)
     assert lib.dctf_build_operator(m, 3, 3, 3, 0, None, ctypes.byref(out)) == -2   # N = 3
-    assert lib.dctf_build_operator(m, 3, 3, 32, 0, None, ctypes.byref(out)) == -2  # N = 32
+    assert lib.dctf_build_operator(m, 3, 3, 64, 0, None, ctypes.byref(out)) == -2  # N = 64
     assert lib.dctf_build_operator(m, 3, 3, 0, 0, None, ctypes.byref(out)) == -1
     assert lib.dctf_build_operator(None, 3, 3, 8, 0, None, ctypes.byref(out)) == -1
     assert lib.dctf_build_operator(m, 0, 3, 8, 0, None, ctypes.byref(out)) == -1
@@ -103,6 +103,8 @@ def test_filter_and_batch_validation(lib):
 
 def test_verify_and_forward_dct_validation(lib):
     assert lib.dctf_idct_u8_verify(3, None, 1, None, None, None, None) == -2
+    assert lib.dctf_idct_u8_verify(64, None, 1, None, None, None, None) == -2
+    assert lib.dctf_idct_u8_verify(32, None, 5, None, None, None, None) == -1   # N = 32 supported: null
     assert lib.dctf_idct_u8_verify(8, None, -1, None, None, None, None) == -1
     assert lib.dctf_idct_u8_verify(8, None, 0, None, None, None, None) == 0     # B = 0: no-op
     assert lib.dctf_idct_u8_verify(8, None, 5, None, None, None, None) == -1

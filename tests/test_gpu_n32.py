@@ -1,0 +1,127 @@
+"""GPU parity of the N = 32 path (1024 x 1024 operator streamed from L2)
+against the FP64 oracle: the FP64 builder to 1e-12, the FP32 filter to
+2e-3 per coefficient, uint8 exact after the inverse DCT (outside the 1/2
+band), the forward DCT and the verify kernel at N = 32."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+Z, R = 0, 1
+FP32, SPLIT = 0, 1
+N = 32
+
+
+@pytest.fixture(scope="module")
+def dctf():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1710_07193_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("border,kh,kw", [(Z, 7, 7), (R, 5, 5), (R, 1, 9), (Z, 65, 65)])
+def test_n32_builder_matches_oracle_probe(dctf, border, kh, kw):
+    W = np.random.default_rng(kh * 7 + kw).uniform(-1, 1, size=(kh, kw))
+    op = dctf.dctf_build_operator(W, N, border)
+    H = dctf.dctf_operator_fp64(op)
+    assert np.abs(H - oracle.operator_probe(N, W, border)).max() <= 1e-12
+
+
+def gpu_filter(dctf, op, X32, prec=FP32):
+    X = dev(X32.reshape(-1))
+    Y = torch.empty_like(X)
+    dctf.dctf_filter_blocks(op, prec, X, Y)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy().reshape(X32.shape)
+
+
+@pytest.mark.parametrize("border", [Z, R])
+@pytest.mark.parametrize("mask", ["asym7", "gauss5", "box3"])
+def test_n32_filter_matches_oracle(dctf, mask, border):
+    W = {"asym7": syn.random_mask(np.random.default_rng(4), 7, 7), "gauss5": syn.gaussian_mask(5, 1.5),
+         "box3": syn.box_mask(3)}[mask]
+    px = oracle.tile_u8(syn.image_u8(31, 232, 328), N)      # ragged sides, 8 x 11 blocks
+    X = oracle.coeffs_fp32(px)
+    op = dctf.dctf_build_operator(W, N, border)
+    Y = gpu_filter(dctf, op, X)
+    Yref, u8ref, nh = oracle.filter_pixels(px, W, border)
+    err = np.abs(Y.astype(np.float64) - Yref).max()
+    print("N=32 %s border=%d max err %.3e" % (mask, border, err))
+    assert err <= 2e-3, err
+    # the split request runs the same FP32 kernel at N = 32
+    assert np.array_equal(gpu_filter(dctf, op, X, SPLIT), Y)
+    # uint8 after the inverse DCT (verify kernel at N = 32)
+    pix = torch.empty(Y.size, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    dctf.dctf_idct_u8_verify(N, dev(Y.reshape(-1)), pix, dev(u8ref.reshape(-1)), cnt)
+    torch.cuda.synchronize()
+    got = pix.cpu().numpy().reshape(u8ref.shape)
+    assert np.array_equal(got[~nh], u8ref[~nh])
+    assert int(cnt[0]) == 0
+
+
+def test_n32_ragged_counts_are_prefix_identical(dctf):
+    px = oracle.tile_u8(syn.image_u8(32, 6 * N, 13 * N), N)
+    X = oracle.coeffs_fp32(px)[:77]
+    op = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, R)
+    full = gpu_filter(dctf, op, X)
+    for B in (1, 15, 16, 17, 31, 32, 33, 64, 65):
+        assert np.array_equal(gpu_filter(dctf, op, X[:B]), full[:B]), B
+
+
+def test_n32_forward_dct_matches_oracle(dctf):
+    img = syn.image_u8(33, 100, 70)                       # ragged: 4 x 3 blocks
+    X = torch.empty(12 * N * N, dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8(dev(img), N, X)
+    torch.cuda.synchronize()
+    ref = oracle.coeffs_fp32(oracle.tile_u8(img, N))
+    assert np.array_equal(X.cpu().numpy().reshape(ref.shape), ref)
+
+
+def test_n32_full_size_sampled(dctf):
+    """32 frames of 3840 x 2160 (bottom edge padded to 2176: 120 x 68 blocks,
+    261,120 blocks) in one launch; sampled blocks against the oracle."""
+    frames, h, w = 32, 2160, 3840
+    nb = ((h + N - 1) // N) * (w // N)
+    X = torch.empty(frames * nb * N * N, dtype=torch.float32, device="cuda")
+    for f in range(frames):
+        dctf.dctf_forward_dct_u8(dev(syn.image_u8(3000 + f, h, w)), N, X[f * nb * N * N:(f + 1) * nb * N * N])
+    W = syn.random_mask(np.random.default_rng(7), 7, 7)
+    op = dctf.dctf_build_operator(W, N, Z)
+    Y = torch.empty_like(X)
+    dctf.dctf_filter_blocks(op, FP32, X, Y)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    idx = np.concatenate([rng.integers(0, frames * nb, size=150), [0, frames * nb - 1]])
+    ti = torch.from_numpy(idx).cuda()
+    Xs = X.view(-1, N, N)[ti].cpu().numpy().astype(np.float64)
+    Ys = Y.view(-1, N, N)[ti].cpu().numpy().astype(np.float64)
+    err = np.abs(Ys - oracle.filter_coeffs(Xs, W, Z)).max()
+    assert err <= 2e-3, err
+    del X, Y
+    torch.cuda.empty_cache()
+
+
+def test_n32_unsupported_paths(dctf):
+    lib = dctf.raw_library()
+    op = dctf.dctf_build_operator(syn.box_mask(3), N, Z)
+    X = torch.zeros(2 * N * N, dtype=torch.float32, device="cuda")
+    Y = torch.zeros(2 * N * N, dtype=torch.float32, device="cuda")
+    pix = torch.zeros(2 * N * N, dtype=torch.uint8, device="cuda")
+    assert lib.dctf_filter_blocks_u8(op.handle, 0, X.data_ptr(), pix.data_ptr(), 2, None) == -2
+    assert lib.dctf_filter_blocks_factored(op.handle, X.data_ptr(), Y.data_ptr(), 2, None) == -2
+    assert lib.dctf_filter_blocks_f64(op.handle, X.data_ptr(), Y.data_ptr(), 1, None) == -2
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_operator_factors_fp64(op)
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_operator_pixel_fp64(op)
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_batch_create([(op, X, Y)], FP32)
