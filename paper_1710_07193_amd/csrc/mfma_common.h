@@ -181,8 +181,10 @@ __device__ __forceinline__ void tile8(const OpRegs8F32 &R, float4 x[4], int lane
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // rows u = 7, 6 first and u = 1, 0 last: the large low-frequency
+    // products enter the FP32 sum after the many small ones
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 3; i >= 0; --i) {
         const float xv[4] = {x[i].x, x[i].y, x[i].z, x[i].w};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -200,19 +202,15 @@ __device__ __forceinline__ void tile8(const OpRegs8F32 &R, float4 x[4], int lane
 // Split path.  The 16 coefficients of load 0 (rows u = 0, 1, DC included)
 // are multiplied in FP32 MFMA; the other 48 are split into BF16 hi + lo and
 // multiplied as hi.hi + hi.lo + lo.hi (the low-frequency columns of the BF16
-// fragments are zero, so load 0 enters the BF16 products as zeros).
+// fragments are zero, so load 0 enters the BF16 products as zeros).  The
+// BF16 products come first, from the higher-frequency k-step down, and the
+// large low-frequency FP32 products last.
 __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lane, f32x4 acc[4])
 {
     (void)lane;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const float x0[4] = {x[0].x, x[0].y, x[0].z, x[0].w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            acc[t] = mfma_f32(R.lf[t][j], x0[j], acc[t]);
     u32x4 bh[2], bl[2];
     {
         uint32_t h2, h3, l2, l3;
@@ -225,8 +223,9 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
         bh[1] = u32x4{h0, h1, h2, h3};
         bl[1] = u32x4{l0, l1, l2, l3};
     }
+    // higher-frequency k-step first; the FP32 low-frequency part last
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 1; s >= 0; --s) {
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             acc[t] = mfma_bf16(R.lo[t][s], bh[s], acc[t]);
@@ -237,6 +236,12 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
         for (int t = 0; t < 4; ++t)
             acc[t] = mfma_bf16(R.hi[t][s], bh[s], acc[t]);
     }
+    const float x0[4] = {x[0].x, x[0].y, x[0].z, x[0].w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_f32(R.lf[t][j], x0[j], acc[t]);
 }
 
 // ------------------------------------------------- N = 8, coalesced I/O
@@ -530,8 +535,9 @@ __device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, i
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
     acc[1] = acc[0];
+    // highest-frequency rows first, rows u = 0, 1 last (FP32 accuracy)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 15; i >= 0; --i) {
         const float4 xv4 = *reinterpret_cast<const float4 *>(lds + f32_chunk(n, 4 * i + g));
         const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
 #pragma unroll
@@ -554,16 +560,10 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
     acc[1] = acc[0];
-    // low-frequency slots 2g + j of block n, FP32
-    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
-    const float lfv[2] = {lv.x, lv.y};
+    // BF16 products from the highest-frequency k-step down, then the large
+    // low-frequency FP32 products last
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 7; s >= 0; --s) {
         const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + bf16_chunk(n, 4 * s + g));
         const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + bf16_chunk(n, 4 * s + g));
 #pragma unroll
@@ -576,6 +576,14 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
         for (int t = 0; t < 2; ++t)
             acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
     }
+    // low-frequency slots 2g + j of block n, FP32
+    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
+    const float lfv[2] = {lv.x, lv.y};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
 }
 
 // ----------------------------------------------- N = 16 tile loop (shared)
