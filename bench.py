@@ -505,7 +505,7 @@ def main():
                         "rebuild) per step" % (args.images, args.side, args.side, B),
             "images": args.images, "side": args.side, "N": N, "blocks": B, "masks": len(pool),
             "border": "replicate",
-            "precision": "split-bf16: BF16 hi/lo x3 MFMA products, FP32 accumulate, 16 low-frequency "
+            "precision": "split-bf16: BF16 hi/lo x3 MFMA products, FP32 accumulate, 8 low-frequency "
                          "inputs in FP32 MFMA" if prec else "fp32 MFMA, FP32 DC column in VALU",
         },
         "roofline": {

@@ -160,7 +160,8 @@ dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double 
  * 16-byte aligned, non-overlapping (in-place is not supported).
  * prec: dctf_precision.  FP32: the MFMA sums over every column but the DC
  * column H[:,0], which is applied in FP32 VALU arithmetic.  Split-BF16: the
- * low-frequency input coefficients (N = 8: the 16 of rows u = 0, 1; N = 16:
+ * low-frequency input coefficients (N = 8: (0,0) (0,1) (0,4) (0,5) (1,0)
+ * (1,1) (1,4) (1,5), the two FP32 k-steps of the kernel's first load; N = 16:
  * the first 8 in zigzag order) are multiplied in FP32 MFMA, the others as
  * BF16 hi.hi + hi.lo + lo.hi; both accumulate in FP32.  The split keeps about
  * 16 bits of each operand, so its error grows with the magnitude of the

@@ -35,9 +35,9 @@
 //   frag32  FP32 A operand of v_mfma_f32_16x16x4_f32, DC column zeroed
 //   frag_hi / frag_lo  BF16 A operands of v_mfma_f32_16x16x32_bf16, with the
 //           low-frequency columns zeroed
-//   frag_lf FP32 A operand for the low-frequency columns (lf_slot()): N = 8
-//           slot q = 4 g + j at ((t * 64 + lane) * 4 + j), N = 16 slot q = 2 g + j
-//           at ((t * 64 + lane) * 2 + j), j the k-step
+//   frag_lf FP32 A operand for the low-frequency columns (lf_slot()): slot
+//           q = 2 g + j at ((t * 64 + lane) * 2 + j), j the k-step (two k-steps
+//           for N = 8 and N = 16)
 #include "dctf_internal.h"
 
 #include <math.h>
@@ -231,7 +231,7 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
             const int q = lf_slot(N, c);
             uint16_t hi = 0, lo = 0;
             if (q >= 0) {
-                // N = 8: slot 4g + j of k-step j (4 steps); N = 16: slot 2g + j (2 steps)
+                // slot 2g + j of k-step j (2 steps)
                 const int t = r >> 4, m = r & 15;
                 const int steps = lf_count(N) / 4, lane = 16 * (q / steps) + m;
                 out.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;

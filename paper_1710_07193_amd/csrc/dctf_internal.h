@@ -43,13 +43,15 @@ struct OpImages {
 // Low-frequency input coefficients that the split-BF16 path multiplies in
 // FP32 MFMA instead of BF16 (they carry the largest magnitudes of natural
 // images, where a two-term BF16 split loses the most absolute precision).
-//   N = 8 : the 16 coefficients of rows u = 0, 1 (k < 16);
+//   N = 8 : the 8 coefficients of the two FP32 k-steps j = 0, 1 of the first
+//           load (k = 4g + j, g = 0..3): (0,0) (0,1) (0,4) (0,5) (1,0) (1,1)
+//           (1,4) (1,5), slot 2g + j;
 //   N = 16: the first 8 in zigzag order: u + v <= 2, then (0, 3), (1, 2).
 // Returns the slot of coefficient k (0 .. lf_count(N) - 1), or -1.
 __host__ __device__ inline int lf_slot(int N, int k)
 {
     if (N == 8)
-        return k < 16 ? k : -1;
+        return (k < 16 && (k & 3) < 2) ? 2 * (k >> 2) + (k & 3) : -1;
     const int u = k / N, v = k % N, d = u + v;
     if (d <= 2)
         return d * (d + 1) / 2 + u;
@@ -57,7 +59,7 @@ __host__ __device__ inline int lf_slot(int N, int k)
         return 6 + u;
     return -1;
 }
-__host__ __device__ constexpr int lf_count(int N) { return N == 16 ? 8 : 16; }
+__host__ __device__ constexpr int lf_count(int) { return 8; }
 
 }  // namespace dctf
 

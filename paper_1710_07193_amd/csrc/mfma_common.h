@@ -127,7 +127,7 @@ struct OpRegs8F32 {
 struct OpRegs8BF16 {
     u32x4 hi[4][2];     // [t][s]
     u32x4 lo[4][2];
-    float lf[4][4];     // [t][j]: FP32 A operand of the low-frequency k-steps
+    float lf[4][2];     // [t][j]: FP32 A operand of the two low-frequency k-steps
 };
 
 __device__ __forceinline__ void load_op8(OpRegs8F32 &R, const float *frag32, const float *h0, int lane)
@@ -165,11 +165,9 @@ __device__ __forceinline__ void load_op8(OpRegs8BF16 &R, const uint16_t *fhi, co
         }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        float4 v = ld4(flf + (t * 64 + lane) * 4);
+        const float2 v = *reinterpret_cast<const float2 *>(flf + (t * 64 + lane) * 2);
         R.lf[t][0] = v.x;
         R.lf[t][1] = v.y;
-        R.lf[t][2] = v.z;
-        R.lf[t][3] = v.w;
     }
 }
 
@@ -199,12 +197,13 @@ __device__ __forceinline__ void tile8(const OpRegs8F32 &R, float4 x[4], int lane
             acc[t][r] = fmaf(R.h0[t][r], x0, acc[t][r]);
 }
 
-// Split path.  The 16 coefficients of load 0 (rows u = 0, 1, DC included)
-// are multiplied in FP32 MFMA; the other 48 are split into BF16 hi + lo and
-// multiplied as hi.hi + hi.lo + lo.hi (the low-frequency columns of the BF16
-// fragments are zero, so load 0 enters the BF16 products as zeros).  The
-// BF16 products come first, from the higher-frequency k-step down, and the
-// large low-frequency FP32 products last.
+// Split path.  Components x, y of load 0 (k-steps j = 0, 1: coefficients
+// 4g and 4g + 1 of rows u = 0, 1, DC included) are multiplied in FP32 MFMA;
+// the other 56 coefficients are split into BF16 hi + lo and multiplied as
+// hi.hi + hi.lo + lo.hi (the low-frequency columns of the BF16 fragments are
+// zero, and those inputs enter the BF16 products as zeros).  The BF16
+// products come first, from the higher-frequency k-step down, and the large
+// low-frequency FP32 products last.
 __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lane, f32x4 acc[4])
 {
     (void)lane;
@@ -213,11 +212,12 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
         acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     u32x4 bh[2], bl[2];
     {
-        uint32_t h2, h3, l2, l3;
+        // BF16 operand element 4e + j of k-step s is coefficient 16(2s + e) + 4g + j
+        uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+        split_bf16(make_float4(0.0f, 0.0f, x[0].z, x[0].w), h0, h1, l0, l1);
         split_bf16(x[1], h2, h3, l2, l3);
-        bh[0] = u32x4{0u, 0u, h2, h3};
-        bl[0] = u32x4{0u, 0u, l2, l3};
-        uint32_t h0, h1, l0, l1;
+        bh[0] = u32x4{0u, h1, h2, h3};
+        bl[0] = u32x4{0u, l1, l2, l3};
         split_bf16(x[2], h0, h1, l0, l1);
         split_bf16(x[3], h2, h3, l2, l3);
         bh[1] = u32x4{h0, h1, h2, h3};
@@ -236,9 +236,9 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
         for (int t = 0; t < 4; ++t)
             acc[t] = mfma_bf16(R.hi[t][s], bh[s], acc[t]);
     }
-    const float x0[4] = {x[0].x, x[0].y, x[0].z, x[0].w};
+    const float x0[2] = {x[0].x, x[0].y};
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             acc[t] = mfma_f32(R.lf[t][j], x0[j], acc[t]);
@@ -349,9 +349,9 @@ __device__ __forceinline__ void tile8_coalesced(const Regs &R, const float4 xin[
 // reads of a wave free of bank conflicts (padded rows are not, on gfx950):
 //   FP32: [16][256] floats; lane (n, g) reads chunk 4i + g of row n, i = 0..15.
 //   BF16: hi / lo [16][256] BF16, split once when written; lane (n, g) reads
-//         chunk 4s + g (8 BF16), s = 0..7.  The 16 low-frequency coefficients
-//         (lf_slot) go to an FP32 array [4][16][4] instead (chunk g of row n
-//         at g*16 + n) and are multiplied in FP32 MFMA.
+//         chunk 4s + g (8 BF16), s = 0..7.  The 8 low-frequency coefficients
+//         (lf_slot) go to an FP32 array [4][16][2] instead (slots 2g, 2g + 1
+//         of row n at (g*16 + n)*2) and are multiplied in FP32 MFMA.
 
 constexpr int kLd16F32 = 256;    // floats per LDS row (FP32 path)
 constexpr int kLd16BF16 = 256;   // BF16 per LDS row (split path)
