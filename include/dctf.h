@@ -248,9 +248,9 @@ dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *
  * 0 = interior, 1 = first, 2 = last, 3 = both (a one-block image side); the
  * class decides which neighbours exist and where reads are clamped.  The
  * builder forms all 16 class pairs x 9 offsets in FP64 on the GPU, with
- * their FP32 MFMA fragments (N = 8: 4.7 MB FP64 + 2.4 MB FP32); each
- * operator's DC column is applied in FP32 VALU arithmetic, the rest in
- * FP32 MFMA.
+ * their FP32 and split-BF16 MFMA fragments (N = 8: 4.7 MB FP64 + 2.4 MB
+ * FP32 + 2.6 MB split); each operator's DC column is applied in FP32 VALU
+ * arithmetic after all other products.
  * Masks: 1 <= kh, kw <= 2N + 1 (a mask never reaches past a neighbour).
  * Errors: as dctf_build_operator; DCTF_EUNSUPPORTED for N != 8.
  * Synchronises `stream` (the mask copy is from host memory).
@@ -269,12 +269,14 @@ void dctf_image_operator_destroy(dctf_image_operator op);
 /*
  * Filter nimg images of Bh x Bw blocks each (block-contiguous, raster
  * order inside an image, images one after another: Bh*Bw*nimg blocks of
- * N*N floats), FP32 MFMA with FP32 accumulation; each block's sum runs over
+ * N*N floats), MFMA with FP32 accumulation; each block's sum runs over
  * the neighbour offsets in a fixed order, so its result does not depend on
  * nimg or on where the block falls in the work partition.
  *   in_dev, out_dev  device, 16-byte aligned, non-overlapping.
- *   prec             DCTF_PREC_FP32 (DCTF_PREC_SPLIT_BF16 returns
- *                    DCTF_EUNSUPPORTED).
+ *   prec             DCTF_PREC_FP32, or DCTF_PREC_SPLIT_BF16 (per neighbour
+ *                    the split of dctf_filter_blocks at N = 8: 8 low-frequency
+ *                    inputs in FP32 MFMA, the others BF16 hi.hi + hi.lo +
+ *                    lo.hi).
  * nimg = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned, overlap,
  * Bh or Bw < 1, nimg < 0), DCTF_EUNSUPPORTED, DCTF_EHIP.
  */

@@ -554,6 +554,9 @@ struct dctf_image_operator_s {
     double *H64 = nullptr;
     float *frag32 = nullptr;
     float *h0 = nullptr;
+    uint16_t *frag_hi = nullptr;
+    uint16_t *frag_lo = nullptr;
+    float *frag_lf = nullptr;
 };
 
 extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh, int kw, int N, int border,
@@ -572,6 +575,9 @@ extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh
     const size_t o_h64 = off;  off = align_up(off + sizeof(double) * nops * NN * NN);
     const size_t o_f32 = off;  off = align_up(off + sizeof(float) * nops * NN * NN);
     const size_t o_h0 = off;   off = align_up(off + sizeof(float) * nops * NN);
+    const size_t o_fhi = off;  off = align_up(off + sizeof(uint16_t) * nops * NN * NN);
+    const size_t o_flo = off;  off = align_up(off + sizeof(uint16_t) * nops * NN * NN);
+    const size_t o_flf = off;  off = align_up(off + sizeof(float) * nops * NN * lf_count(N));
     dctf_image_operator op = new (std::nothrow) dctf_image_operator_s();
     if (!op)
         return DCTF_ENOMEM;
@@ -589,6 +595,9 @@ extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh
     op->H64 = reinterpret_cast<double *>(b + o_h64);
     op->frag32 = reinterpret_cast<float *>(b + o_f32);
     op->h0 = reinterpret_cast<float *>(b + o_h0);
+    op->frag_hi = reinterpret_cast<uint16_t *>(b + o_fhi);
+    op->frag_lo = reinterpret_cast<uint16_t *>(b + o_flo);
+    op->frag_lf = reinterpret_cast<float *>(b + o_flf);
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = hip_status(hipMemcpyAsync(op->mask, mask_host, sizeof(double) * kh * kw, hipMemcpyHostToDevice, s));
     if (st == DCTF_OK) {
@@ -599,6 +608,9 @@ extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh
         a.border = border;
         a.H64 = op->H64;
         a.frag32 = op->frag32;
+        a.frag_hi = op->frag_hi;
+        a.frag_lo = op->frag_lo;
+        a.frag_lf = op->frag_lf;
         a.h0 = op->h0;
         st = hip_status(launch_build_image(a, s));
     }
@@ -683,8 +695,6 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
         return DCTF_EINVAL;
     if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
         return DCTF_EINVAL;
-    if (prec != DCTF_PREC_FP32)
-        return DCTF_EUNSUPPORTED;
     const int64_t B = (int64_t)Bh * Bw * nimg;
     dctf_status st = validate_io(op->N, in_dev, out_dev, B);
     if (st != DCTF_OK || B == 0)
@@ -697,10 +707,13 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
     a.Bw = Bw;
     a.nimg = nimg;
     a.frag32 = op->frag32;
+    a.frag_hi = op->frag_hi;
+    a.frag_lo = op->frag_lo;
+    a.frag_lf = op->frag_lf;
     a.h0 = op->h0;
     Run rr[3], cr[3];
     const int nr = class_runs(Bh, rr), nc = class_runs(Bw, cr);
-    const int T = image_tiles_per_unit();
+    const int T = image_tiles_per_unit(prec);
     int64_t units = 0;
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < nc; ++j) {
@@ -720,7 +733,7 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);
-    st = hip_status(launch_filter_image(a, s));
+    st = hip_status(launch_filter_image(prec, a, s));
     timing_end(s, slot);
     return st;
 }

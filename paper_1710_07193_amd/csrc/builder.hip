@@ -60,47 +60,6 @@ __device__ inline int src_index(int i, int d, int N, int border, bool *valid)
     return m < 0 ? 0 : (m >= N ? N - 1 : m);
 }
 
-// Round an FP32 value to BF16, round-to-nearest-even (finite inputs).
-__device__ inline uint16_t bf16_rne(float f)
-{
-    uint32_t b = __float_as_uint(f);
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
-
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// Position of H[r][c] in the FP32 MFMA fragment layout.
-//   N = 8  (v_mfma_f32_16x16x4_f32, whole operator per wave): lane = 16g + m,
-//          r = 16t + m, c = 16i + 4g + j -> ((t*4 + i)*64 + lane)*4 + j.
-//   N = 16 (weight-stationary, 16 M-tiles over 8 waves): r = 16T + m,
-//          c = 16i + 4g + j -> ((T*16 + i)*64 + lane)*4 + j.
-//   N = 32 (operator streamed in 16-column chunks): the same with 64 chunks
-//          per M-tile, ((T*64 + i)*64 + lane)*4 + j.
-__device__ inline int frag32_index(int N, int r, int c)
-{
-    int t = r >> 4, m = r & 15;
-    int i = c >> 4, g = (c >> 2) & 3, j = c & 3;
-    int lane = 16 * g + m;
-    int ni = N * N / 16;   // k-chunks of 16 per M-tile
-    return ((t * ni + i) * 64 + lane) * 4 + j;
-}
-
-// Position of H[r][c] in the BF16 MFMA fragment layout
-// (v_mfma_f32_16x16x32_bf16, 8 BF16 per lane per k-step).
-//   N = 8:  c = 16(2s + e) + 4g + j, element 4e + j   -> ((t*2 + s)*64 + lane)*8 + 4e + j.
-//   N = 16: c = 32s + 8g + e8, element e8             -> ((T*8 + s)*64 + lane)*8 + e8.
-__device__ inline int frag16_index(int N, int r, int c)
-{
-    int t = r >> 4, m = r & 15;
-    if (N == 8) {
-        int ii = c >> 4, s = ii >> 1, e = ii & 1, g = (c >> 2) & 3, j = c & 3;
-        return ((t * 2 + s) * 64 + 16 * g + m) * 8 + 4 * e + j;
-    }
-    int s = c >> 5, g = (c >> 3) & 3, e8 = c & 7;
-    return ((t * 8 + s) * 64 + 16 * g + m) * 8 + e8;
-}
-
 // LDS budget for the per-chunk matrices: T_p, G_p and B_p (3 N x N FP64
 // each) for up to kChunk(N) mask rows at once.
 template <int N>

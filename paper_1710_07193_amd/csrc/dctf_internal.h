@@ -61,6 +61,50 @@ __host__ __device__ inline int lf_slot(int N, int k)
 }
 __host__ __device__ constexpr int lf_count(int) { return 8; }
 
+// ------------------------------------------- operator fragment layouts
+// (written by the builders, read by the MFMA kernels)
+
+// Round an FP32 value to BF16, round-to-nearest-even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Position of H[r][c] in the FP32 MFMA fragment layout.
+//   N = 8  (v_mfma_f32_16x16x4_f32, whole operator per wave): lane = 16g + m,
+//          r = 16t + m, c = 16i + 4g + j -> ((t*4 + i)*64 + lane)*4 + j.
+//   N = 16 (weight-stationary, 16 M-tiles over 8 waves): r = 16T + m,
+//          c = 16i + 4g + j -> ((T*16 + i)*64 + lane)*4 + j.
+//   N = 32 (operator streamed in 16-column chunks): the same with 64 chunks
+//          per M-tile, ((T*64 + i)*64 + lane)*4 + j.
+__device__ __forceinline__ int frag32_index(int N, int r, int c)
+{
+    int t = r >> 4, m = r & 15;
+    int i = c >> 4, g = (c >> 2) & 3, j = c & 3;
+    int lane = 16 * g + m;
+    int ni = N * N / 16;   // k-chunks of 16 per M-tile
+    return ((t * ni + i) * 64 + lane) * 4 + j;
+}
+
+// Position of H[r][c] in the BF16 MFMA fragment layout
+// (v_mfma_f32_16x16x32_bf16, 8 BF16 per lane per k-step).
+//   N = 8:  c = 16(2s + e) + 4g + j, element 4e + j   -> ((t*2 + s)*64 + lane)*8 + 4e + j.
+//   N = 16: c = 32s + 8g + e8, element e8             -> ((T*8 + s)*64 + lane)*8 + e8.
+__device__ __forceinline__ int frag16_index(int N, int r, int c)
+{
+    int t = r >> 4, m = r & 15;
+    if (N == 8) {
+        int ii = c >> 4, s = ii >> 1, e = ii & 1, g = (c >> 2) & 3, j = c & 3;
+        return ((t * 2 + s) * 64 + 16 * g + m) * 8 + 4 * e + j;
+    }
+    int s = c >> 5, g = (c >> 3) & 3, e8 = c & 7;
+    return ((t * 8 + s) * 64 + 16 * g + m) * 8 + e8;
+}
+
 }  // namespace dctf
 
 struct dctf_operator_s {
@@ -137,6 +181,9 @@ struct ImageBuildArgs {
     int kh, kw, border;
     double *H64;          // [cp][o] N^2 x N^2, row-major
     float *frag32;        // [cp][o] FP32 MFMA A fragments (N = 8 layout), DC column zeroed
+    uint16_t *frag_hi;    // [cp][o] BF16 hi / lo fragments, low-frequency columns zeroed
+    uint16_t *frag_lo;
+    float *frag_lf;       // [cp][o] FP32 fragments of the low-frequency columns, DC zeroed
     float *h0;            // [cp][o] DC columns H[:, 0], FP32
 };
 
@@ -159,12 +206,15 @@ struct ImageFilterArgs {
     ImageRect rect[9];
     int64_t units_per_image;
     const float *frag32;
+    const uint16_t *frag_hi;
+    const uint16_t *frag_lo;
+    const float *frag_lf;
     const float *h0;
 };
 
 hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream);
-hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream);
-int image_tiles_per_unit();
+hipError_t launch_filter_image(int prec, const ImageFilterArgs &a, hipStream_t stream);
+int image_tiles_per_unit(int prec);
 
 // fp64.hip — FP64 filter (N = 8 MFMA, N <= 4 VALU) from the FP64 operator.
 hipError_t launch_filter_f64(int N, const double *H64, const double *in, double *out, int64_t B,

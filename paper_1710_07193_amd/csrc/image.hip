@@ -17,9 +17,11 @@
 // which neighbours exist: bit 0 = it is the first one (no neighbour before:
 // reads before it are dropped (zero) or clamped to its row 0 (replication)),
 // bit 1 = it is the last one.  The builder forms all 4 x 4 class pairs x 9
-// offsets in FP64 (N = 8), with their FP32 MFMA fragments; each operator's
-// DC column is kept out of the MFMA image and applied in FP32 VALU after
-// all AC products (the nine DC products are the largest terms of a sum that
+// offsets in FP64 (N = 8), with their FP32 and split-BF16 MFMA fragments
+// (the split path of the block-local filter: 8 low-frequency columns in
+// FP32, the others as BF16 hi.hi + hi.lo + lo.hi); each operator's DC
+// column is kept out of the MFMA images and applied in FP32 VALU after all
+// AC products (the nine DC products are the largest terms of a sum that
 // cancels: in the MFMA chain they would set the rounding step of every
 // later addition).
 //
@@ -59,14 +61,6 @@ __device__ inline bool image_source(int i, int e, int c, int border, int *d, int
     *d = y < 0 ? -1 : (y >= kN ? 1 : 0);
     *m = y - *d * kN;
     return true;
-}
-
-// Position of H[r][c] in the FP32 fragment layout of the N = 8 kernels
-// (lane = 16 g + m, r = 16 t + m, c = 16 i + 4 g + j).
-__device__ inline int frag32_index8(int r, int c)
-{
-    const int t = r >> 4, m = r & 15, i = c >> 4, g = (c >> 2) & 3, j = c & 3;
-    return ((t * 4 + i) * 64 + 16 * g + m) * 4 + j;
 }
 
 // One workgroup per (operator, class pair, offset, 16 output rows).
@@ -132,10 +126,25 @@ __global__ __launch_bounds__(kThreads) void k_build_image(ImageBuildArgs args)
         for (int p = 0; p < kh; ++p)
             s += sT[p * kNN + u * kN + k] * sB[p * kNN + v * kN + l];
         H64[(size_t)r * kNN + c] = s;
-        // the DC column goes to h0 (FP32 VALU in the filter), not to the MFMA image
-        F32[frag32_index8(r, c)] = c == 0 ? 0.0f : __double2float_rn(s);
+        // the DC column goes to h0 (FP32 VALU in the filter), not to the MFMA images
+        const float h32 = __double2float_rn(s);
+        F32[frag32_index(kN, r, c)] = c == 0 ? 0.0f : h32;
         if (c == 0)
-            d.h0[opi * kNN + r] = __double2float_rn(s);
+            d.h0[opi * kNN + r] = h32;
+        // split images: low-frequency columns (DC zeroed) in FP32, the rest as
+        // BF16 hi = bf16(fp32(H)), lo = bf16(fp32(H - hi))
+        const int q = lf_slot(kN, c);
+        uint16_t hi = 0, lo = 0;
+        if (q >= 0) {
+            const int t = r >> 4, m = r & 15, lane = 16 * (q >> 1) + m;
+            d.frag_lf[opi * kNN * lf_count(kN) + (t * 64 + lane) * 2 + (q & 1)] = c == 0 ? 0.0f : h32;
+        } else {
+            hi = bf16_rne(h32);
+            lo = bf16_rne(__double2float_rn(s - (double)bf16_to_f32(hi)));
+        }
+        const size_t fi = opi * kNN * kNN + frag16_index(kN, r, c);
+        d.frag_hi[fi] = hi;
+        d.frag_lo[fi] = lo;
     }
 }
 
@@ -170,7 +179,7 @@ __device__ inline TileRef tile_ref(const ImageRect &rc, int64_t t, int Bw)
 
 // Wave w takes units w, w + waves, ...; a unit is up to T consecutive tiles
 // of one rectangle of one image.
-template <int T>
+template <int PREC, int T>
 __global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_t units, int64_t waves)
 {
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
@@ -209,25 +218,31 @@ __global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 acc[tt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const float *ops = a.frag32 + (size_t)rc.cp * 9 * kNN * kNN;
         float x0s[T][9];
 #pragma unroll
         for (int o = 0; o < 9; ++o) {
             if (!((rc.offsets >> o) & 1))
                 continue;
             const int64_t shift = (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1);
+            const size_t opi = (size_t)rc.cp * 9 + o;
             float A[4][4][4];
-            const float *F = ops + (size_t)o * kNN * kNN;
+            OpRegs8BF16 R;
+            if constexpr (PREC == DCTF_PREC_FP32) {
+                const float *F = a.frag32 + opi * kNN * kNN;
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float4 v = ld4(F + ((t * 4 + i) * 64 + lane) * 4);
-                    A[t][i][0] = v.x;
-                    A[t][i][1] = v.y;
-                    A[t][i][2] = v.z;
-                    A[t][i][3] = v.w;
-                }
+                    for (int i = 0; i < 4; ++i) {
+                        const float4 v = ld4(F + ((t * 4 + i) * 64 + lane) * 4);
+                        A[t][i][0] = v.x;
+                        A[t][i][1] = v.y;
+                        A[t][i][2] = v.z;
+                        A[t][i][3] = v.w;
+                    }
+            } else {
+                load_op8(R, a.frag_hi + opi * kNN * kNN, a.frag_lo + opi * kNN * kNN,
+                         a.frag_lf + opi * kNN * lf_count(kN), lane);
+            }
             float4 cur[4], nxt[4];
             auto load = [&](float4 (&x)[4], int tt) {
                 const float *src = X + (blk[tt] + shift) * kNN + 4 * g;
@@ -245,14 +260,19 @@ __global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_
                 // DC of the neighbour block (lane (n, 0) holds coefficient 0 of block n),
                 // applied after every AC product
                 x0s[tt][o] = lane_read(cur[0].x, n);
+                if constexpr (PREC == DCTF_PREC_FP32) {
+                    // rows u = 7, 6 first, u = 1, 0 last (FP32 accuracy)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float xv[4] = {cur[i].x, cur[i].y, cur[i].z, cur[i].w};
+                    for (int i = 3; i >= 0; --i) {
+                        const float xv[4] = {cur[i].x, cur[i].y, cur[i].z, cur[i].w};
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            acc[tt][t] = mfma_f32(A[t][i][j], xv[j], acc[tt][t]);
+                            for (int t = 0; t < 4; ++t)
+                                acc[tt][t] = mfma_f32(A[t][i][j], xv[j], acc[tt][t]);
+                    }
+                } else {
+                    tile8_acc(R, cur, acc[tt]);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -291,7 +311,10 @@ __global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_
     }
 }
 
-constexpr int kImageT = 4;
+// tiles per unit (each neighbour operator is loaded once per unit): 4 for both
+// precisions, the most the register file holds (split: 255 of 256 registers)
+constexpr int kImageT32 = 4;
+constexpr int kImageTSplit = 4;
 constexpr int kImageWavesPerCu = 8;
 
 }  // namespace
@@ -302,9 +325,9 @@ hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream)
     return hipGetLastError();
 }
 
-int image_tiles_per_unit() { return kImageT; }
+int image_tiles_per_unit(int prec) { return prec == DCTF_PREC_FP32 ? kImageT32 : kImageTSplit; }
 
-hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream)
+hipError_t launch_filter_image(int prec, const ImageFilterArgs &a, hipStream_t stream)
 {
     const int64_t units = a.units_per_image * a.nimg;
     if (units <= 0)
@@ -312,7 +335,12 @@ hipError_t launch_filter_image(const ImageFilterArgs &a, hipStream_t stream)
     int64_t waves = (int64_t)cu_count() * kImageWavesPerCu;
     waves = waves < units ? waves : units;
     const int64_t groups = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_filter_image8<kImageT>), dim3((unsigned)groups), dim3(256), 0, stream, a, units, waves);
+    if (prec == DCTF_PREC_FP32)
+        hipLaunchKernelGGL((k_filter_image8<DCTF_PREC_FP32, kImageT32>), dim3((unsigned)groups), dim3(256), 0,
+                           stream, a, units, waves);
+    else
+        hipLaunchKernelGGL((k_filter_image8<DCTF_PREC_SPLIT_BF16, kImageTSplit>), dim3((unsigned)groups),
+                           dim3(256), 0, stream, a, units, waves);
     return hipGetLastError();
 }
 

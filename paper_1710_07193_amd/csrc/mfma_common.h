@@ -204,12 +204,10 @@ __device__ __forceinline__ void tile8(const OpRegs8F32 &R, float4 x[4], int lane
 // zero, and those inputs enter the BF16 products as zeros).  The BF16
 // products come first, from the higher-frequency k-step down, and the large
 // low-frequency FP32 products last.
-__device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lane, f32x4 acc[4])
+// acc += H . x for one tile, split path (the order and operands of tile8
+// below, without clearing acc first).
+__device__ __forceinline__ void tile8_acc(const OpRegs8BF16 &R, const float4 x[4], f32x4 acc[4])
 {
-    (void)lane;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     u32x4 bh[2], bl[2];
     {
         // BF16 operand element 4e + j of k-step s is coefficient 16(2s + e) + 4g + j
@@ -242,6 +240,15 @@ __device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lan
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             acc[t] = mfma_f32(R.lf[t][j], x0[j], acc[t]);
+}
+
+__device__ __forceinline__ void tile8(const OpRegs8BF16 &R, float4 x[4], int lane, f32x4 acc[4])
+{
+    (void)lane;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    tile8_acc(R, x, acc);
 }
 
 // ------------------------------------------------- N = 8, coalesced I/O
