@@ -31,7 +31,9 @@
 // A wave takes T tiles of one rectangle, loads the fragments of one
 // neighbour operator at a time into VGPRs and accumulates its product over
 // the T tiles before moving to the next neighbour (the operator is read
-// once per T tiles, the neighbour blocks come from L2).
+// once per T tiles, the neighbour blocks come from L2).  Units are handed
+// out in XCD order (xcd_wave), so the units that share block rows run on
+// the same XCD and read those rows through one L2.
 #include "mfma_common.h"
 
 namespace dctf {
@@ -183,7 +185,8 @@ template <int PREC, int T>
 __global__ __launch_bounds__(256) void k_filter_image8(ImageFilterArgs a, int64_t units, int64_t waves)
 {
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // consecutive units (the same and adjacent block rows) run on one XCD
+    const int64_t wave = xcd_wave(4);
     if (wave >= waves)
         return;
     const int64_t per_img_blocks = (int64_t)a.Bh * a.Bw;
@@ -334,7 +337,8 @@ hipError_t launch_filter_image(int prec, const ImageFilterArgs &a, hipStream_t s
         return hipSuccess;
     int64_t waves = (int64_t)cu_count() * kImageWavesPerCu;
     waves = waves < units ? waves : units;
-    const int64_t groups = (waves + 3) / 4;
+    const int64_t groups = xcd_groups(waves, 4);
+    waves = groups * 4;   // waves past the last unit find no work
     if (prec == DCTF_PREC_FP32)
         hipLaunchKernelGGL((k_filter_image8<DCTF_PREC_FP32, kImageT32>), dim3((unsigned)groups), dim3(256), 0,
                            stream, a, units, waves);
