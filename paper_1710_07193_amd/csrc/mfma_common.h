@@ -49,29 +49,6 @@ __device__ __forceinline__ float lane_read(float v, int src)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs on
-// XCD g % 8), and each XCD has its own L2.  xcd_wave() renumbers the waves of
-// a grid whose workgroup count is a multiple of 8 so that consecutive
-// numbers run on the same XCD: XCD x holds numbers [x W/8, (x + 1) W/8)
-// (W = all waves).  Kernels whose neighbouring work units share input hand
-// units out in this order, so the sharing happens inside one L2.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int64_t xcd_wave(int waves_per_group)
-{
-    const int64_t per_xcd = gridDim.x / kXcds;
-    return ((int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds) * waves_per_group +
-           (threadIdx.x >> 6);
-}
-
-// Workgroups for `waves` waves of `per` waves each, rounded up to a multiple
-// of the XCD count (as xcd_wave() needs).
-inline int64_t xcd_groups(int64_t waves, int per)
-{
-    const int64_t g = (waves + per - 1) / per;
-    return (g + kXcds - 1) / kXcds * kXcds;
-}
-
 __device__ __forceinline__ float4 ld4(const float *p)
 {
     return *reinterpret_cast<const float4 *>(p);
