@@ -10,11 +10,15 @@
 //           per tile, M = 64 outputs in 4 M-tiles, K = 64 in 16 k-steps; lane
 //           (n, g) supplies coefficients 16i + 4g + j of block n and receives
 //           outputs 16t + 4g + r, both as 32 contiguous bytes.
+//           The blocks move between HBM and the MFMA layout through 8 KiB
+//           of wave-private LDS: every load and store instruction covers 1 KiB
+//           of contiguous memory (two blocks), where the MFMA layout itself
+//           would touch half of every 32-byte span of 16 blocks.
 //   N <= 4: k_filter_small_f64 — one thread per block, FP64 VALU.
 //
 // With 8 bytes in and 8 out per coefficient the N = 8 kernel is HBM-bound
 // (1 KiB per block against 8192 flop: FP64 MFMA would allow 9.6e9 blocks/s).
-#include "dctf_internal.h"
+#include "mfma_common.h"
 
 namespace dctf {
 namespace {
@@ -37,15 +41,31 @@ __device__ __forceinline__ void st2_nt(double *p, f64x2 v)
     __builtin_nontemporal_store(v, reinterpret_cast<f64x2 *>(p));
 }
 
-// Wave w takes tiles (16 blocks) w, w + waves, ...; the next tile's loads are
-// in flight while the current one is multiplied.
-__global__ __launch_bounds__(256) void k_filter_n8_f64(const double *H64, const double *in, double *out,
+// LDS image of one 16-block tile: 16 rows of 32 chunks (2 doubles each),
+// chunk c of block b at b * 32 + (c ^ b).  A coalesced access of instruction
+// k moves blocks 2k and 2k + 1 with lane l at position l of the instruction's
+// 64 chunks (global chunk (l % 32) ^ b); an MFMA-layout access of lane (n, g)
+// takes one chunk of block n, and the XOR spreads the 16 blocks of a lane
+// group over all banks.
+__device__ __forceinline__ int f64_pos(int b, int c) { return b * 32 + (c ^ b); }
+
+// Wave w takes tiles (16 blocks) w, w + waves, ...  Two waves per SIMD
+// (launch bound): one multiplies while the other waits for its tile.  A
+// register double buffer of the next tile would not fit beside the operator
+// at that occupancy, and one wave per SIMD with the buffer is slower
+// (measured: 0.86 against 0.83 ms for 4,194,304 blocks).
+//   IO = 0: blocks loaded and stored in the MFMA layout (0.98 ms);
+//   IO = 1: coalesced through LDS.
+template <int IO>
+__global__ __launch_bounds__(256, 2) void k_filter_n8_f64(const double *H64, const double *in, double *out,
                                                        int64_t B, int64_t tiles, int64_t waves)
 {
+    __shared__ __attribute__((aligned(16))) f64x2 lds_all[IO ? 4 * 16 * 32 : 1];
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= waves)   // waves <= tiles
         return;
+    f64x2 *lds = lds_all + (IO ? (threadIdx.x >> 6) * 16 * 32 : 0);
     // A[t][i][j] = H[16t + s(m)][16i + 4g + j] with m = lane % 16.  The FP64
     // MFMA returns row g + 4r of its 16 x 16 result in register r of lane
     // (n, g); taking A's rows in the order s(m) = 4 (m % 4) + m / 4 makes that
@@ -63,53 +83,87 @@ __global__ __launch_bounds__(256) void k_filter_n8_f64(const double *H64, const 
                 A[t][i][2 * h] = v[0];
                 A[t][i][2 * h + 1] = v[1];
             }
-    auto load = [&](f64x2 (&x)[4][2], int64_t tile) {
-        int64_t blk = tile * 16 + n;
-        blk = blk < B ? blk : B - 1;   // clamped: the store below is masked
-        const double *src = in + blk * 64 + 4 * g;
+    // x[k]: IO = 0, chunk 8 (k / 2) + 2g + k % 2 of block n (coefficients
+    // 16i + 4g + 2h, 16i + 4g + 2h + 1 with i = k / 2, h = k % 2);
+    // IO = 1, position lane of the coalesced instruction k.
+    auto load = [&](f64x2 (&x)[8], int64_t tile) {
+        if constexpr (IO == 1) {
+            const int64_t blk0 = tile * 16;
+            const int64_t nv = B - blk0;   // >= 1
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int k = 0; k < 8; ++k) {
+                const int b = 2 * k + (lane >> 5);
+                const int64_t bb = b < nv ? b : nv - 1;   // clamped: its result is never stored
+                x[k] = ld2_nt(in + (blk0 + bb) * 64 + 2 * ((lane & 31) ^ b));
+            }
+        } else {
+            int64_t blk = tile * 16 + n;
+            blk = blk < B ? blk : B - 1;   // clamped: the store below is masked
+            const double *src = in + blk * 64 + 4 * g;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                x[i][h] = ld2_nt(src + 16 * i + 2 * h);
+            for (int k = 0; k < 8; ++k)
+                x[k] = ld2_nt(src + 16 * (k >> 1) + 2 * (k & 1));
+        }
     };
-    auto compute_store = [&](const f64x2 (&x)[4][2], int64_t tile) {
+    auto compute_store = [&](const f64x2 (&xin)[8], int64_t tile) {
+        if constexpr (IO == 1) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                lds[k * 64 + lane] = xin[k];
+            wave_lds_sync();
+        }
         f64x4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
             acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+            // coefficients 16i + 4g .. 16i + 4g + 3 of block n
+            f64x2 x[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                x[h] = IO == 1 ? lds[f64_pos(n, 8 * i + 2 * g + h)] : xin[2 * i + h];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    acc[t] = mfma_f64(A[t][i][j], x[i][j >> 1][j & 1], acc[t]);
-        const int64_t blk = tile * 16 + n;
-        if (blk < B) {
-            double *dst = out + blk * 64 + 4 * g;
+                    acc[t] = mfma_f64(A[t][i][j], x[j >> 1][j & 1], acc[t]);
+        }
+        if constexpr (IO == 1) {
+            wave_lds_sync();
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                st2_nt(dst + 16 * t, f64x2{acc[t][0], acc[t][1]});
-                st2_nt(dst + 16 * t + 2, f64x2{acc[t][2], acc[t][3]});
+                lds[f64_pos(n, 8 * t + 2 * g)] = f64x2{acc[t][0], acc[t][1]};
+                lds[f64_pos(n, 8 * t + 2 * g + 1)] = f64x2{acc[t][2], acc[t][3]};
+            }
+            wave_lds_sync();
+            const int64_t blk0 = tile * 16;
+            const int64_t nv = B - blk0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int b = 2 * k + (lane >> 5);
+                const f64x2 v = lds[k * 64 + lane];
+                if (b < nv)
+                    st2_nt(out + (blk0 + b) * 64 + 2 * ((lane & 31) ^ b), v);
+            }
+            wave_lds_sync();
+        } else {
+            const int64_t blk = tile * 16 + n;
+            if (blk < B) {
+                double *dst = out + blk * 64 + 4 * g;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    st2_nt(dst + 16 * t, f64x2{acc[t][0], acc[t][1]});
+                    st2_nt(dst + 16 * t + 2, f64x2{acc[t][2], acc[t][3]});
+                }
             }
         }
     };
-    const int64_t mine = (tiles - wave + waves - 1) / waves;
-    f64x2 cur[4][2], nxt[4][2];
-    int64_t tile = wave;
-    load(cur, tile);
-    for (int64_t k = 1; k < mine; ++k) {
-        load(nxt, tile + waves);
-        compute_store(cur, tile);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            cur[i][0] = nxt[i][0];
-            cur[i][1] = nxt[i][1];
-        }
-        tile += waves;
+    for (int64_t tile = wave; tile < tiles; tile += waves) {
+        f64x2 x[8];
+        load(x, tile);
+        compute_store(x, tile);
     }
-    compute_store(cur, tile);
 }
 
 __global__ __launch_bounds__(256) void k_filter_small_f64(const double *H64, const double *in, double *out,
@@ -135,6 +189,7 @@ __global__ __launch_bounds__(256) void k_filter_small_f64(const double *H64, con
 }
 
 constexpr int kF64WavesPerCu = 8;
+constexpr int kF64Io = 1;
 
 }  // namespace
 
@@ -154,7 +209,7 @@ hipError_t launch_filter_f64(int N, const double *H64, const double *in, double 
     int64_t waves = (int64_t)cu_count() * kF64WavesPerCu;
     waves = waves < tiles ? waves : tiles;
     const int64_t groups = (waves + 3) / 4;
-    hipLaunchKernelGGL(k_filter_n8_f64, dim3((unsigned)groups), dim3(256), 0, stream, H64, in, out, B, tiles,
+    hipLaunchKernelGGL(k_filter_n8_f64<kF64Io>, dim3((unsigned)groups), dim3(256), 0, stream, H64, in, out, B, tiles,
                        waves);
     return hipGetLastError();
 }
