@@ -162,14 +162,16 @@ dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_host, double 
  * column H[:,0], which is applied in FP32 VALU arithmetic.  Split-BF16: the
  * low-frequency input coefficients (N = 8: (0,0) (0,1) (0,4) (0,5) (1,0)
  * (1,1) (1,4) (1,5), the two FP32 k-steps of the kernel's first load; N = 16:
- * the first 8 in zigzag order) are multiplied in FP32 MFMA, the others as
- * BF16 hi.hi + hi.lo + lo.hi; both accumulate in FP32.  The split keeps about
- * 16 bits of each operand, so its error grows with the magnitude of the
- * mid- and high-frequency coefficients: the 5e-3 bound holds for natural-image
- * content, not for arbitrary inputs (binary stripe patterns reach ~2e-2).
+ * the first 8 in zigzag order; N = 32: the 16 with u, v < 4, DC excluded)
+ * are multiplied in FP32 MFMA, the others as BF16 hi.hi + hi.lo + lo.hi;
+ * both accumulate in FP32 (N = 32: DC column in FP32 VALU, last).  The
+ * split keeps about 16 bits of each operand, so its error grows with the
+ * magnitude of the mid- and high-frequency coefficients: the 5e-3 bound
+ * holds for natural-image content, not for arbitrary inputs (binary stripe
+ * patterns reach ~2e-2).
  * For N <= 4 both precisions run one FP32 kernel (the operator is at most
- * 16 x 16); for N = 32 both run the FP32 MFMA kernel that streams the
- * 1024 x 1024 operator from L2 (its DC column applied in FP32 VALU).
+ * 16 x 16); at N = 32 the 1024 x 1024 operator is streamed from L2 in
+ * either precision (FP32: DC column applied in FP32 VALU).
  * B = 0 is a no-op.  Each block's result depends only on that
  * block and the operator: it is bit-identical whatever B, the tuning variant
  * or the batch the block belongs to.

@@ -186,9 +186,10 @@ int dctf::mask_rank_factors(const double *W, int kh, int kw, std::vector<double>
 static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, dctf_operator *out)
 {
     const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
-    // split-BF16 images exist for N = 8, 16; the pixel-domain set for N <= 16
-    const bool split = N == 8 || N == 16;
-    const size_t FS = split ? F : 0, FL = split ? frag_lf_elems(N) : 0;
+    // split-BF16 images exist for N = 8, 16 and 32; the pixel-domain set for N <= 16
+    const bool split = N == 8 || N == 16 || N == 32;
+    const size_t FS = split ? F : 0;
+    const size_t FL = N == 32 ? n32_lf_elems : split ? frag_lf_elems(N) : 0;
     const int domains = N <= 16 ? 2 : 1;
     size_t off = 0;
     const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
@@ -267,6 +268,15 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
             args.d[i].rank = op->rank;
         }
         dctf_status st = hip_status(launch_build(args, s));
+        if (st != DCTF_OK)
+            return st;
+    }
+    // the N = 32 split-BF16 images, from the FP64 operator just built
+    for (int i = 0; i < n && (parts & kBuildDct); ++i) {
+        const DenseImages &D = ops[i]->img.dct;
+        if (ops[i]->N != 32)
+            continue;
+        dctf_status st = hip_status(launch_split_n32(D.H64, D.frag_hi, D.frag_lo, D.frag_lf, s));
         if (st != DCTF_OK)
             return st;
     }
@@ -426,7 +436,7 @@ extern "C" dctf_status dctf_filter_blocks(dctf_operator op, int prec, const floa
     int slot;
     timing_begin(s, &slot);
     if (op->N == 32)
-        st = hip_status(launch_filter_n32(a, s));
+        st = hip_status(launch_filter_n32(prec, a, s));
     else
         st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
     timing_end(s, slot);

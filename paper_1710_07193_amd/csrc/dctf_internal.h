@@ -233,9 +233,13 @@ struct FilterArgs {
     const float *H32;
 };
 hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipStream_t stream);
-// n32.hip — the N = 32 filter (FP32 MFMA, operator streamed from L2; uses
-// frag32 and h0 of the DCT-domain images).
-hipError_t launch_filter_n32(const FilterArgs &a, hipStream_t stream);
+// n32.hip — the N = 32 filter, operator streamed from L2: FP32 MFMA (frag32
+// and h0 of the DCT-domain images) or split-BF16 (frag_hi / frag_lo in the
+// N = 32 layout, frag_lf of n32_lf_elems floats, h0).
+hipError_t launch_filter_n32(int prec, const FilterArgs &a, hipStream_t stream);
+// The N = 32 split-BF16 images from the FP64 operator (1024 x 1024, row-major).
+hipError_t launch_split_n32(const double *H64, uint16_t *hi, uint16_t *lo, float *lf, hipStream_t stream);
+constexpr size_t n32_lf_elems = 1024 * 16;
 int variant_count(int N, int prec);
 const char *variant_name(int N, int prec, int v);
 int default_variant(int N, int prec);

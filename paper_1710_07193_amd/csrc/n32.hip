@@ -1,7 +1,10 @@
 // N = 32 filter: Y[b] = H_dct . X[b] with the 1024 x 1024 operator (4 MiB in
 // FP32), too large for any register or LDS residency.  The product over
 // all blocks is a matrix product Y^t = H . X^t (M = 1024 output coefficients,
-// K = 1024, one column per block) with the operator streamed from L2:
+// K = 1024, one column per block) with the operator streamed from L2.
+//
+// FP32 (k_filter_n32; the split-BF16 kernel k_filter_n32s is described
+// with its code below):
 //
 //   a wave owns a unit of MT M-tiles (16 output rows each) x NT N-tiles (16
 //   blocks each) and walks K in 64 chunks of 16 coefficients, from the
@@ -124,12 +127,246 @@ constexpr int kN32Mt = 4;
 constexpr int kN32Nt = 2;
 constexpr int kN32WavesPerCu = 16;
 
+// ---------------------------------------------------------------- split-BF16
+//
+// The same product with the operator in BF16 hi + lo (products hi.hi +
+// hi.lo + lo.hi, FP32 accumulation): three BF16 MFMAs cost less than a
+// quarter of one FP32 MFMA of the same K, which moves N = 32 from the FP32
+// MFMA bound towards the HBM bound.  The 16 lowest-frequency coefficients
+// (u, v < 4: the large terms of smooth image content) are multiplied in
+// FP32 MFMA, and the DC column in FP32 VALU, after all the others.
+//
+// Operator images (from the FP64 operator, k_split32):
+//   hi / lo  A operands of v_mfma_f32_16x16x32_bf16 for k-step s (the 32
+//            coefficients of block row u = s): lane (m, g) of M-tile T holds
+//            H[16T + m][32s + 8g + e], e < 8, at ((T*32 + s)*64 + 16g + m)*8 + e;
+//            hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)); the low-frequency
+//            columns are zero.
+//   lf       A operand of v_mfma_f32_16x16x4_f32 for the low-frequency
+//            columns: k-step j, lane (m, g) holds H[16T + m][32g + j] at
+//            (T*64 + 16g + m)*4 + j; the DC column (g = j = 0) is zero.
+//
+// Work: a workgroup of 4 waves takes a unit of 128 blocks (8 tiles of 16) x
+// one 256-row panel of the operator (wave w: M-tiles 16P + 4w .. + 3).  Per
+// k-step (32 coefficients) the workgroup loads the unit's 128 x 32 FP32
+// coefficients once (1 KiB rows of 8 contiguous float4 per block), splits
+// them into BF16 hi / lo and stores them in LDS, double-buffered with one
+// barrier per k-step, while every wave streams its 4 M-tiles of hi / lo
+// from L2 (the next k-step's fragments in flight during the current one).
+// LDS rows (one block, 32 BF16 = four 16-byte chunks, chunk g holding
+// coefficients 8g .. 8g + 7) are XOR-swizzled, chunk g of block b at
+// g ^ ((b / 4) % 4), which keeps the 16-byte MFMA reads of 16 blocks free
+// of bank conflicts.
+//
+// XCD placement: XCD x serves panels 2 (x / 4) and 2 (x / 4) + 1 (2 MiB of
+// hi / lo, L2-resident) for the block groups g = x (mod 4); the two panels
+// of a group run on neighbouring workgroups of one XCD, so the group's
+// coefficients are read from HBM by two XCDs, once each.
+constexpr int kSteps32 = kNN32 / 32;          // BF16 k-steps
+constexpr int kSMt = 4;                       // M-tiles per wave
+constexpr int kSWavesPerCu = 8;
+
+__device__ __forceinline__ bool low_freq32(int c) { return c < 128 && (c & 31) < 4; }
+
+__global__ __launch_bounds__(256) void k_split32(const double *H64, uint16_t *hi, uint16_t *lo, float *lf)
+{
+    const int r = blockIdx.x, T = r >> 4, m = r & 15;
+    for (int c = threadIdx.x; c < kNN32; c += 256) {
+        const double h = H64[(size_t)r * kNN32 + c];
+        const float h32 = __double2float_rn(h);
+        const int s = c >> 5, g = (c >> 3) & 3, e = c & 7;
+        uint16_t vh = 0, vl = 0;
+        if (low_freq32(c))
+            lf[(T * 64 + 16 * s + m) * 4 + (c & 3)] = c == 0 ? 0.0f : h32;
+        else {
+            vh = bf16_rne(h32);
+            vl = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(vh)));
+        }
+        const size_t fi = (((size_t)T * kSteps32 + s) * 64 + 16 * g + m) * 8 + e;
+        hi[fi] = vh;
+        lo[fi] = vl;
+    }
+}
+
+// position (in BF16) of chunk g of block b in an LDS hi or lo array
+__device__ __forceinline__ int s32_chunk(int b, int g) { return b * 32 + 8 * (g ^ ((b >> 2) & 3)); }
+
+// NT block tiles per unit (16 NT blocks); ADB: the next k-step's operator
+// fragments are loaded during the current one.
+template <int NT, bool ADB>
+__global__ __launch_bounds__(256, 2) void k_filter_n32s(FilterArgs a, int64_t groups)
+{
+    constexpr int kBlocks = 16 * NT;        // blocks per unit
+    constexpr int kQ = kBlocks / 32;        // loader float4 per thread and k-step
+    constexpr int kBuf = 2 * kBlocks * 32;  // BF16 per LDS buffer (hi, lo)
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kBuf];
+    const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4, w = tid >> 6;
+    const int xcd = blockIdx.x % 8;
+    const int64_t L = gridDim.x / 8, l = blockIdx.x / 8;
+    const int64_t B = a.B;
+    const u32x4 *fhi = reinterpret_cast<const u32x4 *>(a.frag_hi);
+    const u32x4 *flo = reinterpret_cast<const u32x4 *>(a.frag_lo);
+    for (int64_t j = l;; j += L) {
+        const int64_t grp = (xcd & 3) + 4 * (j >> 1);
+        if (grp >= groups)
+            break;
+        const int P = 2 * (xcd >> 2) + (int)(j & 1);
+        const int64_t blk0 = grp * kBlocks;
+        const int T0 = 16 * P + 4 * w;
+        // loader: thread t moves float4 c8 = t % 8 (coefficients 4 c8 .. + 3
+        // of the k-step) of blocks 32q + t / 8, q < kQ
+        const float *src[kQ];
+        int ldpos[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int b = 32 * q + (tid >> 3), c8 = tid & 7;
+            int64_t bb = blk0 + b;
+            bb = bb < B ? bb : B - 1;   // clamped: its results are never stored
+            src[q] = a.in + bb * kNN32 + 4 * c8;
+            ldpos[q] = s32_chunk(b, c8 >> 1) + 4 * (c8 & 1);
+        }
+        auto load_x = [&](float4 (&xr)[kQ], int s) {
+#pragma unroll
+            for (int q = 0; q < kQ; ++q)
+                xr[q] = ld4(src[q] + 32 * s);
+        };
+        auto stage_x = [&](const float4 (&xr)[kQ], int buf) {
+            uint16_t *H = lds + buf * kBuf, *Lo = H + kBlocks * 32;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                uint32_t h01, h23, l01, l23;
+                split_bf16(xr[q], h01, h23, l01, l23);
+                *reinterpret_cast<uint2 *>(H + ldpos[q]) = make_uint2(h01, h23);
+                *reinterpret_cast<uint2 *>(Lo + ldpos[q]) = make_uint2(l01, l23);
+            }
+        };
+        auto load_a = [&](u32x4 (&ah)[kSMt], u32x4 (&al)[kSMt], int s) {
+#pragma unroll
+            for (int t = 0; t < kSMt; ++t) {
+                const size_t fi = ((size_t)(T0 + t) * kSteps32 + s) * 64 + lane;
+                ah[t] = fhi[fi];
+                al[t] = flo[fi];
+            }
+        };
+        f32x4 acc[kSMt][NT];
+#pragma unroll
+        for (int t = 0; t < kSMt; ++t)
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+                acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // k-steps from the highest block row (u = 31) to the lowest
+        float4 xr[kQ];
+        u32x4 ah[kSMt], al[kSMt], nh[ADB ? kSMt : 1], nl[ADB ? kSMt : 1];
+        load_x(xr, kSteps32 - 1);
+        if constexpr (ADB)
+            load_a(ah, al, kSteps32 - 1);
+        stage_x(xr, 0);   // the previous unit's reads of both buffers ended at its last barrier
+        __syncthreads();
+        for (int k = 0; k < kSteps32; ++k) {
+            const int s = kSteps32 - 1 - k;
+            if constexpr (!ADB)
+                load_a(ah, al, s);
+            if (s > 0) {
+                load_x(xr, s - 1);
+                if constexpr (ADB)
+                    load_a(nh, nl, s - 1);
+            }
+            const uint16_t *H = lds + (k & 1) * kBuf, *Lo = H + kBlocks * 32;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int pos = s32_chunk(16 * q + n, g);
+                const u32x4 xh = *reinterpret_cast<const u32x4 *>(H + pos);
+                const u32x4 xl = *reinterpret_cast<const u32x4 *>(Lo + pos);
+#pragma unroll
+                for (int t = 0; t < kSMt; ++t) {
+                    acc[t][q] = mfma_bf16(ah[t], xh, acc[t][q]);
+                    acc[t][q] = mfma_bf16(ah[t], xl, acc[t][q]);
+                    acc[t][q] = mfma_bf16(al[t], xh, acc[t][q]);
+                }
+            }
+            if (s > 0) {
+                stage_x(xr, (k + 1) & 1);
+                if constexpr (ADB)
+#pragma unroll
+                    for (int t = 0; t < kSMt; ++t) {
+                        ah[t] = nh[t];
+                        al[t] = nl[t];
+                    }
+            }
+            __syncthreads();
+        }
+        // low-frequency coefficients (u = g, v = 0 .. 3) in FP32 MFMA, then DC
+        float4 alf[kSMt];
+#pragma unroll
+        for (int t = 0; t < kSMt; ++t)
+            alf[t] = ld4(a.frag_lf + ((size_t)(T0 + t) * 64 + lane) * 4);
+        float x0[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            int64_t bb = blk0 + 16 * q + n;
+            bb = bb < B ? bb : B - 1;
+            const float4 xv = ld4(a.in + bb * kNN32 + 32 * g);
+            x0[q] = lane_read(xv.x, n);   // coefficient 0 of block n (lane (n, 0))
+            const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int t = 0; t < kSMt; ++t) {
+                    const float av = jj == 0 ? alf[t].x : (jj == 1 ? alf[t].y : (jj == 2 ? alf[t].z : alf[t].w));
+                    acc[t][q] = mfma_f32(av, xs[jj], acc[t][q]);
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < kSMt; ++t) {
+            const float4 h = ld4(a.h0 + 16 * (T0 + t) + 4 * g);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                acc[t][q][0] = fmaf(h.x, x0[q], acc[t][q][0]);
+                acc[t][q][1] = fmaf(h.y, x0[q], acc[t][q][1]);
+                acc[t][q][2] = fmaf(h.z, x0[q], acc[t][q][2]);
+                acc[t][q][3] = fmaf(h.w, x0[q], acc[t][q][3]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int64_t blk = blk0 + 16 * q + n;
+            if (blk < B) {
+                float *dst = a.out + blk * kNN32 + 4 * g;
+#pragma unroll
+                for (int t = 0; t < kSMt; ++t)
+                    st4(dst + 16 * (T0 + t), acc[t][q]);
+            }
+        }
+    }
+}
+
 }  // namespace
 
-hipError_t launch_filter_n32(const FilterArgs &a, hipStream_t stream)
+constexpr int kSNt = 8;
+constexpr bool kSAdb = false;
+
+hipError_t launch_split_n32(const double *H64, uint16_t *hi, uint16_t *lo, float *lf, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_split32, dim3(kNN32), dim3(256), 0, stream, H64, hi, lo, lf);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_n32(int prec, const FilterArgs &a, hipStream_t stream)
 {
     if (a.B <= 0)
         return hipSuccess;
+    if (prec == DCTF_PREC_SPLIT_BF16) {
+        const int64_t groups = (a.B + 16 * kSNt - 1) / (16 * kSNt);
+        // 2 workgroups per CU (the occupancy), a multiple of the 8 XCDs; the
+        // workgroups past the last unit of their XCD find no work
+        int64_t wgs = (int64_t)cu_count() * kSWavesPerCu / 4;
+        // XCD x has 2 ceil((groups - x % 4) / 4) units: at most that many workgroups each
+        const int64_t need = 8 * 2 * ((groups + 3) / 4);
+        wgs = wgs < need ? wgs : need;
+        wgs = (wgs + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_filter_n32s<kSNt, kSAdb>), dim3((unsigned)wgs), dim3(256), 0, stream, a, groups);
+        return hipGetLastError();
+    }
     const int64_t groups = (a.B + 16 * kN32Nt - 1) / (16 * kN32Nt);
     const int64_t units = groups * (64 / kN32Mt);
     int64_t waves = (int64_t)cu_count() * kN32WavesPerCu;
