@@ -164,7 +164,6 @@ constexpr int kN32WavesPerCu = 16;
 // coefficients are read from HBM by two XCDs, once each.
 constexpr int kSteps32 = kNN32 / 32;          // BF16 k-steps
 constexpr int kSMt = 4;                       // M-tiles per wave
-constexpr int kSWavesPerCu = 8;
 
 __device__ __forceinline__ bool low_freq32(int c) { return c < 128 && (c & 31) < 4; }
 
@@ -192,9 +191,11 @@ __global__ __launch_bounds__(256) void k_split32(const double *H64, uint16_t *hi
 __device__ __forceinline__ int s32_chunk(int b, int g) { return b * 32 + 8 * (g ^ ((b >> 2) & 3)); }
 
 // NT block tiles per unit (16 NT blocks); ADB: the next k-step's operator
-// fragments are loaded during the current one.
-template <int NT, bool ADB>
-__global__ __launch_bounds__(256, 2) void k_filter_n32s(FilterArgs a, int64_t groups)
+// fragments are loaded during the current one; XPF: the next tile's LDS
+// read is issued before the current tile's MFMAs; OCC: waves per SIMD the
+// registers are allocated for.
+template <int NT, bool ADB, bool XPF, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t groups)
 {
     constexpr int kBlocks = 16 * NT;        // blocks per unit
     constexpr int kQ = kBlocks / 32;        // loader float4 per thread and k-step
@@ -272,16 +273,37 @@ __global__ __launch_bounds__(256, 2) void k_filter_n32s(FilterArgs a, int64_t gr
                     load_a(nh, nl, s - 1);
             }
             const uint16_t *H = lds + (k & 1) * kBuf, *Lo = H + kBlocks * 32;
+            u32x4 xh, xl;
+            if constexpr (XPF) {
+                const int pos = s32_chunk(n, g);
+                xh = *reinterpret_cast<const u32x4 *>(H + pos);
+                xl = *reinterpret_cast<const u32x4 *>(Lo + pos);
+            }
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
-                const int pos = s32_chunk(16 * q + n, g);
-                const u32x4 xh = *reinterpret_cast<const u32x4 *>(H + pos);
-                const u32x4 xl = *reinterpret_cast<const u32x4 *>(Lo + pos);
+                u32x4 yh, yl;
+                if constexpr (XPF) {
+                    if (q + 1 < NT) {
+                        const int pos = s32_chunk(16 * (q + 1) + n, g);
+                        yh = *reinterpret_cast<const u32x4 *>(H + pos);
+                        yl = *reinterpret_cast<const u32x4 *>(Lo + pos);
+                    }
+                } else {
+                    const int pos = s32_chunk(16 * q + n, g);
+                    xh = *reinterpret_cast<const u32x4 *>(H + pos);
+                    xl = *reinterpret_cast<const u32x4 *>(Lo + pos);
+                }
 #pragma unroll
                 for (int t = 0; t < kSMt; ++t) {
                     acc[t][q] = mfma_bf16(ah[t], xh, acc[t][q]);
                     acc[t][q] = mfma_bf16(ah[t], xl, acc[t][q]);
                     acc[t][q] = mfma_bf16(al[t], xh, acc[t][q]);
+                }
+                if constexpr (XPF) {
+                    if (q + 1 < NT) {
+                        xh = yh;
+                        xl = yl;
+                    }
                 }
             }
             if (s > 0) {
@@ -342,8 +364,16 @@ __global__ __launch_bounds__(256, 2) void k_filter_n32s(FilterArgs a, int64_t gr
 
 }  // namespace
 
+// Launch shape of the split kernel, measured over 261,120 blocks (ms):
+// NT = 8 at two waves per SIMD 1.62-1.64; the same with the LDS prefetch
+// 1.62; NT = 6 / 4 with the operator double buffer 1.68 / 1.84 (more
+// operator traffic per block); one wave per SIMD with every prefetch and
+// 256 accumulators in AGPRs, NT = 16 / 8: 1.96 / 2.21 (the second wave
+// hides the latencies better than the in-wave pipeline).
 constexpr int kSNt = 8;
 constexpr bool kSAdb = false;
+constexpr bool kSXpf = false;
+constexpr int kSOcc = 2;
 
 hipError_t launch_split_n32(const double *H64, uint16_t *hi, uint16_t *lo, float *lf, hipStream_t stream)
 {
@@ -357,14 +387,14 @@ hipError_t launch_filter_n32(int prec, const FilterArgs &a, hipStream_t stream)
         return hipSuccess;
     if (prec == DCTF_PREC_SPLIT_BF16) {
         const int64_t groups = (a.B + 16 * kSNt - 1) / (16 * kSNt);
-        // 2 workgroups per CU (the occupancy), a multiple of the 8 XCDs; the
-        // workgroups past the last unit of their XCD find no work
-        int64_t wgs = (int64_t)cu_count() * kSWavesPerCu / 4;
+        // kSOcc workgroups per CU (one wave per SIMD each), a multiple of the 8
+        // XCDs; the workgroups past the last unit of their XCD find no work
+        int64_t wgs = (int64_t)cu_count() * kSOcc;
         // XCD x has 2 ceil((groups - x % 4) / 4) units: at most that many workgroups each
         const int64_t need = 8 * 2 * ((groups + 3) / 4);
         wgs = wgs < need ? wgs : need;
         wgs = (wgs + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_filter_n32s<kSNt, kSAdb>), dim3((unsigned)wgs), dim3(256), 0, stream, a, groups);
+        hipLaunchKernelGGL((k_filter_n32s<kSNt, kSAdb, kSXpf, kSOcc>), dim3((unsigned)wgs), dim3(256), 0, stream, a, groups);
         return hipGetLastError();
     }
     const int64_t groups = (a.B + 16 * kN32Nt - 1) / (16 * kN32Nt);
