@@ -295,9 +295,27 @@ def n16_frames(dctf, torch, stream, steps, warmup):
                 ent["dense_%s_ms" % pname] = timed_steps(
                     torch, lambda: dctf.dctf_filter_blocks(o, p, X, Y, stream), steps, warmup, stream)
         res["factored_" + tag] = ent
+    res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y
     torch.cuda.empty_cache()
     return res
+
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def fp64_frames(dctf, torch, stream, op, X, N, steps, warmup):
+    """The same frames with FP64 coefficients through the FP64 filter (the
+    operator streamed from L2; 2 N^4 FP64 flop per block)."""
+    B = X.numel() // (N * N)
+    X64 = X.double()
+    Y64 = torch.empty_like(X64)
+    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream)
+    tf = B * 2.0 * (N * N) ** 2 / (ms * 1e-3) / 1e12
+    del X64, Y64
+    torch.cuda.empty_cache()
+    return {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "fp64_mfma_TFLOPs": tf,
+            "frac_of_fp64_mfma_peak": tf / FP64_MFMA_PEAK_TFLOPS}
 
 
 def n32_frames(dctf, torch, stream, steps, warmup):
@@ -331,6 +349,7 @@ def n32_frames(dctf, torch, stream, steps, warmup):
     res["split_bf16"] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
                          "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "bf16_mfma_TFLOPs": tf,
                          "frac_of_bf16_mfma_peak": tf / BF16_MFMA_PEAK_TFLOPS}
+    res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y
     torch.cuda.empty_cache()
     return res

@@ -289,14 +289,14 @@ dctf_status dctf_filter_image(dctf_image_operator op, int prec, const float *in_
 
 /*
  * Y[b] = H_dct . X[b] in FP64: FP64 coefficients in and out, the FP64
- * operator the builder forms, FP64 arithmetic throughout (N = 8:
- * v_mfma_f64_16x16x4_f64 MFMA; N <= 4: FP64 VALU).  For callers whose
- * coefficients are FP64 (no rounding of the data or the operator to FP32);
- * at 16 bytes per coefficient it moves twice the bytes of the FP32 paths.
+ * operator the builder forms, FP64 arithmetic throughout (N = 8, 16, 32:
+ * v_mfma_f64_16x16x4_f64 MFMA, the operator streamed from L2 for N = 16 and
+ * 32; N <= 4: FP64 VALU).  For callers whose coefficients are FP64 (no
+ * rounding of the data or the operator to FP32); at 16 bytes per
+ * coefficient it moves twice the bytes of the FP32 paths.
  *   in_dev, out_dev  B * N*N doubles each (device, block-contiguous,
  *                    16-byte aligned, non-overlapping).
- * B = 0 is a no-op.  Errors: DCTF_EINVAL, DCTF_EUNSUPPORTED (N = 16),
- * DCTF_EHIP.
+ * B = 0 is a no-op.  Errors: DCTF_EINVAL, DCTF_EHIP.
  */
 dctf_status dctf_filter_blocks_f64(dctf_operator op, const double *in_dev, double *out_dev, int64_t B,
                                    dctf_stream stream);

@@ -487,8 +487,6 @@ extern "C" dctf_status dctf_filter_blocks_f64(dctf_operator op, const double *in
 {
     if (op == nullptr || B < 0)
         return DCTF_EINVAL;
-    if (op->N > 8)
-        return DCTF_EUNSUPPORTED;
     if (B == 0)
         return DCTF_OK;
     const size_t bytes = (size_t)B * op->N * op->N * sizeof(double);

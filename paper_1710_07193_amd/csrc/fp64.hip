@@ -15,9 +15,16 @@
 //           of contiguous memory (two blocks), where the MFMA layout itself
 //           would touch half of every 32-byte span of 16 blocks.
 //   N <= 4: k_filter_small_f64 — one thread per block, FP64 VALU.
+//   N = 16, 32: k_filter_big_f64 — the operator (256^2 or 1024^2 doubles:
+//           512 KiB or 8 MiB) is streamed from L2 as in the FP32 N = 32
+//           kernel: a wave owns 4 M-tiles x 2 block tiles and walks K in
+//           chunks of 16 coefficients, with the same row permutation inside
+//           each M-tile, reading the rows of the FP64 operator directly.
 //
 // With 8 bytes in and 8 out per coefficient the N = 8 kernel is HBM-bound
-// (1 KiB per block against 8192 flop: FP64 MFMA would allow 9.6e9 blocks/s).
+// (1 KiB per block against 8192 flop: FP64 MFMA would allow 9.6e9 blocks/s);
+// at N = 16 and 32 the FP64 MFMA rate bounds (2 N^4 flop against 16 N^2
+// bytes per block: 6.0e8 and 3.7e7 blocks/s at the 78.6 TFLOP/s peak).
 #include "mfma_common.h"
 
 namespace dctf {
@@ -188,8 +195,107 @@ __global__ __launch_bounds__(256) void k_filter_small_f64(const double *H64, con
     }
 }
 
+// N = 16, 32 (NN = N^2 coefficients per block).  Units: one block group
+// (16 NT blocks) x one panel of MT M-tiles, numbered block group first, so
+// the waves of a workgroup share a block group (read once through L2) and
+// every XCD meets a fixed subset of the panels (N = 32: 4 of 16, 2 MiB).
+template <int NN, int MT, int NT>
+__global__ __launch_bounds__(256, 2) void k_filter_big_f64(const double *H64, const double *in, double *out,
+                                                          int64_t B, int64_t groups, int64_t waves)
+{
+    constexpr int kPanels = NN / (16 * MT);
+    constexpr int kChunks = NN / 16;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int srow = 4 * (n & 3) + (n >> 2);   // row permutation, as in k_filter_n8_f64
+    const int64_t units = groups * kPanels;
+    for (int64_t unit = wave; unit < units; unit += waves) {
+        const int64_t grp = unit / kPanels;
+        const int T0 = (int)(unit % kPanels) * MT;
+        int64_t blk[NT];
+        const double *xs[NT];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            blk[s] = grp * (16 * NT) + 16 * s + n;
+            const int64_t bb = blk[s] < B ? blk[s] : B - 1;   // clamped: the store is masked
+            xs[s] = in + bb * NN + 4 * g;
+        }
+        const double *ha = H64 + (size_t)(16 * T0 + srow) * NN + 4 * g;
+        f64x4 acc[MT][NT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int s = 0; s < NT; ++s)
+                acc[t][s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // chunk i: A[t] = H[16(T0 + t) + srow][16i + 4g .. + 3], X[s] = coefficients
+        // 16i + 4g .. + 3 of block blk[s]
+        f64x2 A[MT][2], X[NT][2], An[MT][2], Xn[NT][2];
+        auto load = [&](f64x2 (&Ar)[MT][2], f64x2 (&Xr)[NT][2], int i) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    Ar[t][h] = *reinterpret_cast<const f64x2 *>(ha + (size_t)16 * t * NN + 16 * i + 2 * h);
+#pragma unroll
+            for (int s = 0; s < NT; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    Xr[s][h] = *reinterpret_cast<const f64x2 *>(xs[s] + 16 * i + 2 * h);
+        };
+        load(A, X, 0);
+        for (int i = 0; i < kChunks; ++i) {
+            if (i + 1 < kChunks)
+                load(An, Xn, i + 1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int s = 0; s < NT; ++s)
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+                        acc[t][s] = mfma_f64(A[t][j >> 1][j & 1], X[s][j >> 1][j & 1], acc[t][s]);
+            if (i + 1 < kChunks) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+                        A[t][h] = An[t][h];
+#pragma unroll
+                    for (int s = 0; s < NT; ++s)
+                        X[s][h] = Xn[s][h];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            if (blk[s] < B) {
+                double *dst = out + blk[s] * NN + 4 * g;
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    st2_nt(dst + 16 * (T0 + t), f64x2{acc[t][s][0], acc[t][s][1]});
+                    st2_nt(dst + 16 * (T0 + t) + 2, f64x2{acc[t][s][2], acc[t][s][3]});
+                }
+            }
+        }
+    }
+}
+
 constexpr int kF64WavesPerCu = 8;
 constexpr int kF64Io = 1;
+constexpr int kF64BigMt = 4;
+constexpr int kF64BigNt = 2;
+
+template <int NN>
+hipError_t launch_big_f64(const double *H64, const double *in, double *out, int64_t B, hipStream_t stream)
+{
+    const int64_t groups = (B + 16 * kF64BigNt - 1) / (16 * kF64BigNt);
+    const int64_t units = groups * (NN / (16 * kF64BigMt));
+    int64_t waves = (int64_t)cu_count() * kF64WavesPerCu;
+    waves = waves < units ? waves : units;
+    const int64_t wgs = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_filter_big_f64<NN, kF64BigMt, kF64BigNt>), dim3((unsigned)wgs), dim3(256), 0, stream,
+                       H64, in, out, B, groups, waves);
+    return hipGetLastError();
+}
 
 }  // namespace
 
@@ -203,6 +309,10 @@ hipError_t launch_filter_f64(int N, const double *H64, const double *in, double 
         hipLaunchKernelGGL(k_filter_small_f64, dim3((unsigned)groups), dim3(256), 0, stream, H64, in, out, B, N);
         return hipGetLastError();
     }
+    if (N == 16)
+        return launch_big_f64<256>(H64, in, out, B, stream);
+    if (N == 32)
+        return launch_big_f64<1024>(H64, in, out, B, stream);
     if (N != 8)
         return hipErrorInvalidValue;
     const int64_t tiles = (B + 15) / 16;

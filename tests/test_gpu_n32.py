@@ -132,7 +132,6 @@ def test_n32_unsupported_paths(dctf):
     pix = torch.zeros(2 * N * N, dtype=torch.uint8, device="cuda")
     assert lib.dctf_filter_blocks_u8(op.handle, 0, X.data_ptr(), pix.data_ptr(), 2, None) == -2
     assert lib.dctf_filter_blocks_factored(op.handle, X.data_ptr(), Y.data_ptr(), 2, None) == -2
-    assert lib.dctf_filter_blocks_f64(op.handle, X.data_ptr(), Y.data_ptr(), 1, None) == -2
     with pytest.raises(dctf.DctfError):
         dctf.dctf_operator_factors_fp64(op)
     with pytest.raises(dctf.DctfError):
