@@ -147,7 +147,7 @@ constexpr int kN32WavesPerCu = 16;
 //            (T*64 + 16g + m)*4 + j; the DC column (g = j = 0) is zero.
 //
 // Work: a workgroup of 4 waves takes a unit of 128 blocks (8 tiles of 16) x
-// one 256-row panel of the operator (wave w: M-tiles 16P + 4w .. + 3).  Per
+// one 256-row panel P of the operator (wave w: M-tiles 16P + 4w .. + 3).  Per
 // k-step (32 coefficients) the workgroup loads the unit's 128 x 32 FP32
 // coefficients once (1 KiB rows of 8 contiguous float4 per block), splits
 // them into BF16 hi / lo and stores them in LDS, double-buffered with one
@@ -163,7 +163,6 @@ constexpr int kN32WavesPerCu = 16;
 // of a group run on neighbouring workgroups of one XCD, so the group's
 // coefficients are read from HBM by two XCDs, once each.
 constexpr int kSteps32 = kNN32 / 32;          // BF16 k-steps
-constexpr int kSMt = 4;                       // M-tiles per wave
 
 __device__ __forceinline__ bool low_freq32(int c) { return c < 128 && (c & 31) < 4; }
 
@@ -194,12 +193,17 @@ __device__ __forceinline__ int s32_chunk(int b, int g) { return b * 32 + 8 * (g 
 // fragments are loaded during the current one; XPF: the next tile's LDS
 // read is issued before the current tile's MFMAs; OCC: waves per SIMD the
 // registers are allocated for.
-template <int NT, bool ADB, bool XPF, int OCC>
-__global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t groups)
+// MT M-tiles per wave and W waves per workgroup cover the 256-row panel
+// (MT W = 16).
+template <int MT, int W, int NT, bool ADB, bool XPF, int OCC>
+__global__ __launch_bounds__(64 * W, OCC) void k_filter_n32s(FilterArgs a, int64_t groups)
 {
-    constexpr int kBlocks = 16 * NT;        // blocks per unit
-    constexpr int kQ = kBlocks / 32;        // loader float4 per thread and k-step
-    constexpr int kBuf = 2 * kBlocks * 32;  // BF16 per LDS buffer (hi, lo)
+    static_assert(MT * W == 16, "a workgroup covers one 256-row panel");
+    constexpr int kThreads = 64 * W;
+    constexpr int kBlocks = 16 * NT;               // blocks per unit
+    constexpr int kQ = kBlocks * 8 / kThreads;     // loader float4 per thread and k-step
+    constexpr int kBuf = 2 * kBlocks * 32;         // BF16 per LDS buffer (hi, lo)
+    static_assert(kQ * kThreads == kBlocks * 8, "the loader covers the unit");
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kBuf];
     const int tid = threadIdx.x, lane = tid & 63, n = lane & 15, g = lane >> 4, w = tid >> 6;
     const int xcd = blockIdx.x % 8;
@@ -213,14 +217,14 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
             break;
         const int P = 2 * (xcd >> 2) + (int)(j & 1);
         const int64_t blk0 = grp * kBlocks;
-        const int T0 = 16 * P + 4 * w;
+        const int T0 = 16 * P + MT * w;
         // loader: thread t moves float4 c8 = t % 8 (coefficients 4 c8 .. + 3
-        // of the k-step) of blocks 32q + t / 8, q < kQ
+        // of the k-step) of blocks (kThreads / 8) q + t / 8, q < kQ
         const float *src[kQ];
         int ldpos[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-            const int b = 32 * q + (tid >> 3), c8 = tid & 7;
+            const int b = (kThreads / 8) * q + (tid >> 3), c8 = tid & 7;
             int64_t bb = blk0 + b;
             bb = bb < B ? bb : B - 1;   // clamped: its results are never stored
             src[q] = a.in + bb * kNN32 + 4 * c8;
@@ -241,23 +245,23 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
                 *reinterpret_cast<uint2 *>(Lo + ldpos[q]) = make_uint2(l01, l23);
             }
         };
-        auto load_a = [&](u32x4 (&ah)[kSMt], u32x4 (&al)[kSMt], int s) {
+        auto load_a = [&](u32x4 (&ah)[MT], u32x4 (&al)[MT], int s) {
 #pragma unroll
-            for (int t = 0; t < kSMt; ++t) {
+            for (int t = 0; t < MT; ++t) {
                 const size_t fi = ((size_t)(T0 + t) * kSteps32 + s) * 64 + lane;
                 ah[t] = fhi[fi];
                 al[t] = flo[fi];
             }
         };
-        f32x4 acc[kSMt][NT];
+        f32x4 acc[MT][NT];
 #pragma unroll
-        for (int t = 0; t < kSMt; ++t)
+        for (int t = 0; t < MT; ++t)
 #pragma unroll
             for (int q = 0; q < NT; ++q)
                 acc[t][q] = f32x4{0.f, 0.f, 0.f, 0.f};
         // k-steps from the highest block row (u = 31) to the lowest
         float4 xr[kQ];
-        u32x4 ah[kSMt], al[kSMt], nh[ADB ? kSMt : 1], nl[ADB ? kSMt : 1];
+        u32x4 ah[MT], al[MT], nh[ADB ? MT : 1], nl[ADB ? MT : 1];
         load_x(xr, kSteps32 - 1);
         if constexpr (ADB)
             load_a(ah, al, kSteps32 - 1);
@@ -294,7 +298,7 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
                     xl = *reinterpret_cast<const u32x4 *>(Lo + pos);
                 }
 #pragma unroll
-                for (int t = 0; t < kSMt; ++t) {
+                for (int t = 0; t < MT; ++t) {
                     acc[t][q] = mfma_bf16(ah[t], xh, acc[t][q]);
                     acc[t][q] = mfma_bf16(ah[t], xl, acc[t][q]);
                     acc[t][q] = mfma_bf16(al[t], xh, acc[t][q]);
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
                 stage_x(xr, (k + 1) & 1);
                 if constexpr (ADB)
 #pragma unroll
-                    for (int t = 0; t < kSMt; ++t) {
+                    for (int t = 0; t < MT; ++t) {
                         ah[t] = nh[t];
                         al[t] = nl[t];
                     }
@@ -318,9 +322,9 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
             __syncthreads();
         }
         // low-frequency coefficients (u = g, v = 0 .. 3) in FP32 MFMA, then DC
-        float4 alf[kSMt];
+        float4 alf[MT];
 #pragma unroll
-        for (int t = 0; t < kSMt; ++t)
+        for (int t = 0; t < MT; ++t)
             alf[t] = ld4(a.frag_lf + ((size_t)(T0 + t) * 64 + lane) * 4);
         float x0[NT];
 #pragma unroll
@@ -333,13 +337,13 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-                for (int t = 0; t < kSMt; ++t) {
+                for (int t = 0; t < MT; ++t) {
                     const float av = jj == 0 ? alf[t].x : (jj == 1 ? alf[t].y : (jj == 2 ? alf[t].z : alf[t].w));
                     acc[t][q] = mfma_f32(av, xs[jj], acc[t][q]);
                 }
         }
 #pragma unroll
-        for (int t = 0; t < kSMt; ++t) {
+        for (int t = 0; t < MT; ++t) {
             const float4 h = ld4(a.h0 + 16 * (T0 + t) + 4 * g);
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
             if (blk < B) {
                 float *dst = a.out + blk * kNN32 + 4 * g;
 #pragma unroll
-                for (int t = 0; t < kSMt; ++t)
+                for (int t = 0; t < MT; ++t)
                     st4(dst + 16 * (T0 + t), acc[t][q]);
             }
         }
@@ -369,7 +373,10 @@ __global__ __launch_bounds__(256, OCC) void k_filter_n32s(FilterArgs a, int64_t 
 // 1.62; NT = 6 / 4 with the operator double buffer 1.68 / 1.84 (more
 // operator traffic per block); one wave per SIMD with every prefetch and
 // 256 accumulators in AGPRs, NT = 16 / 8: 1.96 / 2.21 (the second wave
-// hides the latencies better than the in-wave pipeline).
+// hides the latencies better than the in-wave pipeline); 8 waves of 2
+// M-tiles per workgroup with both prefetches, NT = 8 / 16: 2.03 / 1.61.
+constexpr int kSMt = 4;
+constexpr int kSW = 4;
 constexpr int kSNt = 8;
 constexpr bool kSAdb = false;
 constexpr bool kSXpf = false;
@@ -387,14 +394,15 @@ hipError_t launch_filter_n32(int prec, const FilterArgs &a, hipStream_t stream)
         return hipSuccess;
     if (prec == DCTF_PREC_SPLIT_BF16) {
         const int64_t groups = (a.B + 16 * kSNt - 1) / (16 * kSNt);
-        // kSOcc workgroups per CU (one wave per SIMD each), a multiple of the 8
-        // XCDs; the workgroups past the last unit of their XCD find no work
-        int64_t wgs = (int64_t)cu_count() * kSOcc;
+        // kSOcc waves per SIMD (4 kSOcc / kSW workgroups per CU), a multiple of
+        // the 8 XCDs; the workgroups past the last unit of their XCD find no work
+        int64_t wgs = (int64_t)cu_count() * kSOcc * 4 / kSW;
         // XCD x has 2 ceil((groups - x % 4) / 4) units: at most that many workgroups each
         const int64_t need = 8 * 2 * ((groups + 3) / 4);
         wgs = wgs < need ? wgs : need;
         wgs = (wgs + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_filter_n32s<kSNt, kSAdb, kSXpf, kSOcc>), dim3((unsigned)wgs), dim3(256), 0, stream, a, groups);
+        hipLaunchKernelGGL((k_filter_n32s<kSMt, kSW, kSNt, kSAdb, kSXpf, kSOcc>), dim3((unsigned)wgs),
+                           dim3(64 * kSW), 0, stream, a, groups);
         return hipGetLastError();
     }
     const int64_t groups = (a.B + 16 * kN32Nt - 1) / (16 * kN32Nt);
