@@ -5,6 +5,8 @@
 // The forward transform runs one thread per pixel; the verify kernel one
 // thread per row segment of up to four coefficients.  The N x N DCT matrix
 // is formed in LDS from its closed form.
+#include <atomic>
+
 #include "dctf_internal.h"
 
 #include <math.h>
@@ -69,40 +71,84 @@ __global__ __launch_bounds__(kMaxDctThreads) void k_forward_dct_u8(const uint8_t
 }
 
 // pix[i][j] = sum_u C[u][i] (sum_v Y[u][v] C[v][j]) in FP32.  Each thread
-// owns V consecutive coefficients of one block row (V = min(N, 4)); a
-// workgroup step covers G blocks and the workgroups stride over the steps,
-// so the DCT matrix is formed once per workgroup and the counters are
-// reduced once per wave at the end.
+// owns V consecutive coefficients (V = min(N, 4)) of one row of two blocks;
+// a workgroup step covers G blocks and the workgroups stride over the
+// steps, so the DCT matrix is formed once per workgroup and the counters
+// are reduced once per wave at the end.  Two register buffers take turns:
+// each is refilled with the step two strides ahead as soon as its rows are
+// staged in LDS, so every load has two steps of work to hide in (the kernel
+// is bound by the bytes it keeps in flight).  For N <= 8 the thread's part
+// of the DCT matrix (C[v][j0 .. j0 + V - 1] and C[u][i], for all u, v) sits
+// in registers instead of being read from LDS in both passes.
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int64_t B, uint8_t *pix,
                                                              const uint8_t *expected,
                                                              unsigned long long *counters, int vec_bytes)
 {
-    constexpr int NN = N * N, V = N < 4 ? N : 4, TPB = NN / V, G = kThreads / TPB;
+    // V coefficients per thread and block row, TPB threads per block, R blocks
+    // per thread and step, G = R kThreads / TPB blocks per step
+    constexpr int NN = N * N, V = N < 4 ? N : 4, TPB = NN / V, R = 2, GR = kThreads / TPB, G = R * GR;
+    constexpr bool kCreg = N <= 8;
     __shared__ __attribute__((aligned(16))) float sC[NN];
     __shared__ __attribute__((aligned(16))) float sy[G * NN];
     __shared__ __attribute__((aligned(16))) float st[G * NN];
     fill_dct(sC, N);
     __syncthreads();
     const int local = threadIdx.x / TPB, e0 = (threadIdx.x % TPB) * V;
-    const int i = e0 / N, j0 = e0 % N, base = local * NN;
+    const int i = e0 / N, j0 = e0 % N;
+    float crow[kCreg ? N : 1][V], ccol[kCreg ? N : 1];   // C[v][j0 + q], C[u][i]
+    if constexpr (kCreg) {
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                crow[v][q] = sC[v * N + j0 + q];
+            ccol[v] = sC[v * N + i];
+        }
+    }
     unsigned long long bad = 0, near = 0;
     const int64_t steps = (B + G - 1) / G;
-    for (int64_t step = blockIdx.x; step < steps; step += gridDim.x) {
-        const int64_t blk = step * G + local;
-        const bool active = blk < B;
-        const int64_t off = blk * NN + e0;
-        if (active) {
-            if constexpr (V == 4) {
-                *reinterpret_cast<float4 *>(sy + base + e0) = *reinterpret_cast<const float4 *>(Y + off);
-            } else {
+    // block of row r of this thread in a step: step G + r GR + local
+    auto load = [&](float (&y)[R][V], int64_t step) {
 #pragma unroll
-                for (int q = 0; q < V; ++q)
-                    sy[base + e0 + q] = Y[off + q];
+        for (int r = 0; r < R; ++r) {
+            const int64_t blk = step * G + r * GR + local;
+            if (blk < B) {
+                if constexpr (V == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(Y + blk * NN + e0);
+                    y[r][0] = v.x;
+                    y[r][1] = v.y;
+                    y[r][2] = v.z;
+                    y[r][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        y[r][q] = Y[blk * NN + e0 + q];
+                }
             }
         }
+    };
+    const int64_t stride = gridDim.x;
+    // One step: stage y in LDS, refill y with the step two strides ahead (its
+    // load stays in flight through this step and the next), transform.
+    auto process = [&](float (&y)[R][V], int64_t step) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int base = (r * GR + local) * NN;
+            if (step * G + r * GR + local < B) {
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    sy[base + e0 + q] = y[r][q];
+            }
+        }
+        if (step + 2 * stride < steps)
+            load(y, step + 2 * stride);
         __syncthreads();
-        if (active) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int base = (r * GR + local) * NN;
+            if (step * G + r * GR + local >= B)
+                continue;
             float t[V];
 #pragma unroll
             for (int q = 0; q < V; ++q)
@@ -110,28 +156,22 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
 #pragma unroll
             for (int v = 0; v < N; ++v) {
                 const float yv = sy[base + i * N + v];
-                if constexpr (V == 4) {
-                    const float4 c = *reinterpret_cast<const float4 *>(sC + v * N + j0);
-                    t[0] = fmaf(yv, c.x, t[0]);
-                    t[1] = fmaf(yv, c.y, t[1]);
-                    t[2] = fmaf(yv, c.z, t[2]);
-                    t[3] = fmaf(yv, c.w, t[3]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < V; ++q)
-                        t[q] = fmaf(yv, sC[v * N + j0 + q], t[q]);
-                }
-            }
-            if constexpr (V == 4) {
-                *reinterpret_cast<float4 *>(st + base + e0) = make_float4(t[0], t[1], t[2], t[3]);
-            } else {
 #pragma unroll
                 for (int q = 0; q < V; ++q)
-                    st[base + e0 + q] = t[q];
+                    t[q] = fmaf(yv, kCreg ? crow[v][q] : sC[v * N + j0 + q], t[q]);
             }
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                st[base + e0 + q] = t[q];
         }
         __syncthreads();
-        if (active) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int base = (r * GR + local) * NN;
+            const int64_t blk = step * G + r * GR + local;
+            if (blk >= B)
+                continue;
+            const int64_t off = blk * NN + e0;
             uint8_t qv[V];
             bool nh[V];
             float pv[V];
@@ -140,24 +180,16 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
                 pv[q] = 0.0f;
 #pragma unroll
             for (int u = 0; u < N; ++u) {
-                const float c = sC[u * N + i];
-                if constexpr (V == 4) {
-                    const float4 t4 = *reinterpret_cast<const float4 *>(st + base + u * N + j0);
-                    pv[0] = fmaf(c, t4.x, pv[0]);
-                    pv[1] = fmaf(c, t4.y, pv[1]);
-                    pv[2] = fmaf(c, t4.z, pv[2]);
-                    pv[3] = fmaf(c, t4.w, pv[3]);
-                } else {
+                const float c = kCreg ? ccol[u] : sC[u * N + i];
 #pragma unroll
-                    for (int q = 0; q < V; ++q)
-                        pv[q] = fmaf(c, st[base + u * N + j0 + q], pv[q]);
-                }
+                for (int q = 0; q < V; ++q)
+                    pv[q] = fmaf(c, st[base + u * N + j0 + q], pv[q]);
             }
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 const float p = pv[q];
-                const float r = floorf(p + 0.5f);
-                qv[q] = (uint8_t)(r > 0.0f ? (r > 255.0f ? 255.0f : r) : 0.0f);
+                const float rr = floorf(p + 0.5f);
+                qv[q] = (uint8_t)(rr > 0.0f ? (rr > 255.0f ? 255.0f : rr) : 0.0f);
                 nh[q] = fabsf(p - floorf(p) - 0.5f) < 1e-3f;
                 near += nh[q] ? 1 : 0;
             }
@@ -182,6 +214,18 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
         }
         // the next step writes sy before its first barrier: every read of
         // sy in this step happened before this step's second barrier
+    };
+    // two register buffers used in turn, so no load result is ever copied
+    // (a copy would wait for the load)
+    float ya[R][V], yb[R][V];
+    if (blockIdx.x < steps)
+        load(ya, blockIdx.x);
+    if (blockIdx.x + stride < steps)
+        load(yb, blockIdx.x + stride);
+    for (int64_t step = blockIdx.x; step < steps; step += 2 * stride) {
+        process(ya, step);
+        if (step + stride < steps)
+            process(yb, step + stride);
     }
     if (counters != nullptr) {
         // per-wave sums, one atomic per wave and counter
@@ -255,17 +299,33 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
                                  hipStream_t stream)
 {
     const int V = N < 4 ? N : 4;
-    const int64_t G = kThreads / (N * N / V);
+    const int64_t G = 2 * (kThreads / (N * N / V));   // blocks per step (R = 2 per thread)
     const int64_t steps = (B + G - 1) / G;
-    int64_t groups = (int64_t)cu_count() * 8;
-    groups = groups < steps ? groups : steps;
     const int vec = ((uintptr_t)pix & 3u) == 0 && ((uintptr_t)expected & 3u) == 0;
+    // A persistent grid: as many workgroups as can be resident at once (the
+    // block sizes differ in registers per thread, so in occupancy).
+    // (queried once per block size; concurrent first calls store the same value)
+    static std::atomic<int> resident[6];
+    auto launch = [&](auto kernel) {
+        std::atomic<int> &slot = resident[__builtin_ctz((unsigned)N)];
+        int per_cu = slot.load(std::memory_order_relaxed);
+        if (per_cu == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            slot.store(per_cu, std::memory_order_relaxed);
+        }
+        int64_t groups = (int64_t)cu_count() * per_cu;
+        groups = groups < steps ? groups : steps;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters,
+                           vec);
+    };
     switch (N) {
-    case 2: hipLaunchKernelGGL(k_idct_u8_verify<2>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
-    case 4: hipLaunchKernelGGL(k_idct_u8_verify<4>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
-    case 8: hipLaunchKernelGGL(k_idct_u8_verify<8>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
-    case 16: hipLaunchKernelGGL(k_idct_u8_verify<16>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
-    default: hipLaunchKernelGGL(k_idct_u8_verify<32>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters, vec); break;
+    case 2: launch(k_idct_u8_verify<2>); break;
+    case 4: launch(k_idct_u8_verify<4>); break;
+    case 8: launch(k_idct_u8_verify<8>); break;
+    case 16: launch(k_idct_u8_verify<16>); break;
+    default: launch(k_idct_u8_verify<32>); break;
     }
     return hipGetLastError();
 }
