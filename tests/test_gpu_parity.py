@@ -268,6 +268,28 @@ def test_verify_kernel_all_sizes_strided(dctf, N):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("B", [1, 63, 64, 65, 4097, 98313])
+def test_verify_kernel_without_counters_same_pixels(dctf, B):
+    """A call without counters (the N = 8 kernel then skips the near-1/2 and
+    mismatch tests) writes the same pixels as one with counters, and those
+    match the oracle outside the 1/2 band."""
+    N = 8
+    rng = np.random.default_rng(B)
+    Y = (rng.standard_normal((B, N, N)) * 40).astype(np.float32)
+    Y[:, 0, 0] += np.float32(128 * N)
+    Yd = dev(Y.reshape(-1))
+    a = torch.zeros(Y.size, dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    dctf.dctf_idct_u8_verify(N, Yd, a, None, cnt)
+    dctf.dctf_idct_u8_verify(N, Yd, b, None, None)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    u8ref, nh = oracle.idct_u8(Y)
+    got = b.cpu().numpy().reshape(Y.shape)
+    assert np.array_equal(got[~nh], u8ref[~nh])
+
+
 def test_verify_kernel_counts(dctf):
     N = 8
     px = oracle.tile_u8(syn.image_u8(9, 256, 256), N)
