@@ -278,11 +278,27 @@ __global__ __launch_bounds__(LOPS ? 512 : 256) void k_filter_image8(ImageFilterA
             for (int t = 0; t < 4; ++t)
                 acc[tt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
         float x0s[T][9];
+        // tile tt of the neighbour at offset o.  FP32 path: the first tile of each
+        // offset is loaded during the last tile of the offset before (no wait at the
+        // switch; 3.18 -> 3.11 ms); the split path has no registers left for it (3
+        // spilled, slower) and loads it at the switch.
+        constexpr bool kCross = PREC == DCTF_PREC_FP32;
+        auto shift_of = [&](int o) { return (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1); };
+        auto load = [&](float4 (&x)[4], int tt, int64_t shift) {
+            const float *src = X + (blk[tt] + shift) * kNN + 4 * g;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                x[i] = ld4(src + 16 * i);
+        };
+        float4 cur[4], nxt[4];
+        if constexpr (kCross)
+            load(cur, 0, shift_of(__builtin_ctz((unsigned)rc.offsets)));   // the centre is always present
 #pragma unroll
         for (int o = 0; o < 9; ++o) {
             if (!((rc.offsets >> o) & 1))
                 continue;
-            const int64_t shift = (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1);
+            const int64_t shift = shift_of(o);
+            const unsigned rest = (unsigned)rc.offsets >> (o + 1);   // offsets still to come
             const size_t opi = (size_t)rc.cp * 9 + o;
             float A[4][4][4];
             OpRegs8BF16 R;
@@ -305,20 +321,16 @@ __global__ __launch_bounds__(LOPS ? 512 : 256) void k_filter_image8(ImageFilterA
                 load_op8(R, a.frag_hi + opi * kNN * kNN, a.frag_lo + opi * kNN * kNN,
                          a.frag_lf + opi * kNN * lf_count(kN), lane);
             }
-            float4 cur[4], nxt[4];
-            auto load = [&](float4 (&x)[4], int tt) {
-                const float *src = X + (blk[tt] + shift) * kNN + 4 * g;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    x[i] = ld4(src + 16 * i);
-            };
-            load(cur, 0);
+            if constexpr (!kCross)
+                load(cur, 0, shift);
 #pragma unroll
             for (int tt = 0; tt < T; ++tt) {
                 if (tt >= nt)
                     break;
                 if (tt + 1 < nt)
-                    load(nxt, tt + 1);
+                    load(nxt, tt + 1, shift);
+                else if (kCross && rest != 0)
+                    load(nxt, 0, shift_of(o + 1 + __builtin_ctz(rest)));
                 // DC of the neighbour block (lane (n, 0) holds coefficient 0 of block n),
                 // applied after every AC product
                 x0s[tt][o] = lane_read(cur[0].x, n);
