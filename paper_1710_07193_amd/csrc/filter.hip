@@ -244,7 +244,11 @@ struct Variant16 {
 };
 // The FP32 kernel keeps the whole FP32 operator slice in registers; three
 // tiles in flight push it past the register file, so its table stops at two.
-const Variant16 kVariants16Split[] = {{2, "wg8_ahead2"}, {3, "wg8_ahead3"}, {1, "wg8_ahead1"}};
+// Split (1,036,800 blocks of the N = 16 frames): 4 tiles ahead 0.49 ms, 5:
+// 0.49, 3: 0.52, 2: 0.59, 1: 0.62; 6 spills (0.78).  One workgroup per CU
+// keeps 16 KiB per tile in flight, so the depth sets the bytes in flight.
+const Variant16 kVariants16Split[] = {{4, "wg8_ahead4"}, {5, "wg8_ahead5"}, {3, "wg8_ahead3"}, {2, "wg8_ahead2"},
+                                      {1, "wg8_ahead1"}};
 const Variant16 kVariants16F32[] = {{2, "wg8_ahead2"}, {1, "wg8_ahead1"}};
 constexpr int kNumVariants16Split = sizeof(kVariants16Split) / sizeof(kVariants16Split[0]);
 constexpr int kNumVariants16F32 = sizeof(kVariants16F32) / sizeof(kVariants16F32[0]);
@@ -269,7 +273,9 @@ hipError_t dispatch16_split(int variant, const FilterArgs &a, hipStream_t stream
     switch (variant16(DCTF_PREC_SPLIT_BF16, variant).depth) {
     case 1: return run16<DCTF_PREC_SPLIT_BF16, 1>(a, stream);
     case 2: return run16<DCTF_PREC_SPLIT_BF16, 2>(a, stream);
-    default: return run16<DCTF_PREC_SPLIT_BF16, 3>(a, stream);
+    case 3: return run16<DCTF_PREC_SPLIT_BF16, 3>(a, stream);
+    case 4: return run16<DCTF_PREC_SPLIT_BF16, 4>(a, stream);
+    default: return run16<DCTF_PREC_SPLIT_BF16, 5>(a, stream);
     }
 }
 
