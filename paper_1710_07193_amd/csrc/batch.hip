@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
         float4 *lds = reinterpret_cast<float4 *>(smem) + (IO ? wave * 256 : 0);
         worker8<PREC, IO, NT>(a, (int64_t)blockIdx.x * (kBatchThreads / 64) + wave, lane, lds);
     } else {
-        worker16<PREC, kBatchDepth16>(a, (int64_t)blockIdx.x - a.groups8, smem);
+        worker16<PREC, batch_depth16(PREC)>(a, (int64_t)blockIdx.x - a.groups8, smem);
     }
 }
 
@@ -265,7 +265,7 @@ template <int PREC>
 __global__ __launch_bounds__(kBatchThreads) void k_batch16(BatchArgs a)
 {
     __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split];
-    worker16<PREC, kBatchDepth16>(a, blockIdx.x, smem);
+    worker16<PREC, batch_depth16(PREC)>(a, blockIdx.x, smem);
 }
 
 template <int PREC, int IO, bool NT>

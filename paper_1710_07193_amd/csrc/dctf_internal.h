@@ -296,7 +296,9 @@ constexpr int kBatchThreads = 512;    // mixed and N = 16 batch workgroups
 constexpr int kBatch8Threads = 256;   // N = 8-only batch workgroups
 constexpr int kUnitBlocks8 = 16;    // blocks per N = 8 work unit (one MFMA tile)
 constexpr int kUnitBlocks16 = 16;   // blocks per N = 16 work unit
-constexpr int kBatchDepth16 = 2;    // N = 16 tiles of loads in flight
+// N = 16 tiles of loads in flight (as the single-operator N = 16 filter: the
+// FP32 operator slice leaves room for 2, the split one for 4)
+constexpr int batch_depth16(int prec) { return prec == DCTF_PREC_FP32 ? 2 : 4; }
 
 hipError_t launch_batch(const BatchArgs &a, hipStream_t stream);
 // Workgroups per CU of the batch kernel for kind 8 (N = 8 only), 16 (N = 16
