@@ -385,8 +385,9 @@ dctf_status dctf_stream_copy(const float *in_dev, float *out_dev, int64_t n, dct
 
 /*
  * Kernel variants for (N, precision): a variant fixes the blocks each wave
- * carries per iteration and the persistent grid size.  Every variant
- * computes bit-identical results.  dctf_autotune times each variant on the
+ * carries per iteration and the persistent grid size (N = 8), or how many
+ * tiles of loads run ahead of the MFMA work (N = 16).  Variant 0 is the
+ * default.  Every variant computes bit-identical results.  dctf_autotune times each variant on the
  * caller's buffers (in_dev/out_dev, B blocks, operator op) with HIP events
  * and selects the fastest for subsequent calls; the choice can be read and
  * set explicitly so that a table persisted by the caller can be re-applied.
