@@ -402,8 +402,10 @@ dctf_status dctf_set_variant(int N, int prec, int variant);
  * units are cut at operator boundaries into `fronts` runs of about equal
  * size; the waves of a run stride over it together and reload their operator
  * when they reach the next operator's units.  1 = one front over all units;
- * 0 = one front per operator (each wave loads one operator); default 2.
- * Errors: DCTF_EINVAL outside [0, 4096].
+ * 0 = one front per operator (each wave loads one operator); -1 = the
+ * default of the plan's precision (split-BF16 2, FP32 4), which is also the
+ * initial setting (dctf_get_batch_fronts then returns -1).
+ * Errors: DCTF_EINVAL outside [-1, 4096].
  */
 dctf_status dctf_set_batch_fronts(int fronts);
 int dctf_get_batch_fronts(void);

@@ -23,7 +23,7 @@ std::atomic<int> g_cu[kMaxDevices];
 
 std::mutex g_variant_mu;
 int g_variant[17][2];   // [N][prec]; zero-initialised = default variant 0
-std::atomic<int> g_batch_fronts{2};
+std::atomic<int> g_batch_fronts{-1};   // -1: the default of each precision
 
 // Block sizes of the kernels around the filter (forward DCT, verify,
 // tuning) and of every operator path but the N = 32 dense filter.
@@ -107,6 +107,15 @@ int cu_count()
 }
 
 int batch_fronts() { return g_batch_fronts.load(); }
+
+// Fronts for a plan of the given precision: the set value, or the default
+// (split-BF16 2, FP32 4: the FP32 batch reloads a larger operator at each
+// crossing and prefers more, shorter fronts).
+static int plan_fronts(int prec)
+{
+    const int f = batch_fronts();
+    return f >= 0 ? f : (prec == DCTF_PREC_FP32 ? 4 : 2);
+}
 void set_batch_fronts(int fronts) { g_batch_fronts.store(fronts); }
 
 }  // namespace dctf
@@ -921,7 +930,7 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<ch
         return segs;
     };
     const std::vector<SegDesc> s8 = j8.empty() ? std::vector<SegDesc>()
-                                               : cut(j8, u8, (int64_t)g8 * wpg8, batch_fronts());
+                                               : cut(j8, u8, (int64_t)g8 * wpg8, plan_fronts(prec));
     const std::vector<SegDesc> s16 = j16.empty() ? std::vector<SegDesc>() : cut(j16, u16, g16, 0);
     const int64_t workers8 = s8.empty() ? 0 : s8.back().worker_begin + s8.back().nworkers;
     const int64_t workers16 = s16.empty() ? 0 : s16.back().worker_begin + s16.back().nworkers;
@@ -1173,7 +1182,7 @@ extern "C" dctf_status dctf_set_variant(int N, int prec, int variant)
 
 extern "C" dctf_status dctf_set_batch_fronts(int fronts)
 {
-    if (fronts < 0 || fronts > 4096)
+    if (fronts < -1 || fronts > 4096)
         return DCTF_EINVAL;
     set_batch_fronts(fronts);
     return DCTF_OK;

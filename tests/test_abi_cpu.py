@@ -130,6 +130,19 @@ def test_variant_table(lib):
     assert dctf.dctf_get_variant(8, 1) == 0
 
 
+def test_batch_fronts_setting(lib):
+    f0 = lib.dctf_get_batch_fronts()
+    try:
+        assert lib.dctf_set_batch_fronts(-2) == -1
+        assert lib.dctf_set_batch_fronts(4097) == -1
+        assert lib.dctf_set_batch_fronts(3) == 0 and lib.dctf_get_batch_fronts() == 3
+        assert lib.dctf_set_batch_fronts(0) == 0 and lib.dctf_get_batch_fronts() == 0
+        # -1: each plan takes its precision's default
+        assert lib.dctf_set_batch_fronts(-1) == 0 and lib.dctf_get_batch_fronts() == -1
+    finally:
+        lib.dctf_set_batch_fronts(f0)
+
+
 def test_server_config_validation(lib):
     import paper_1710_07193_amd as dctf
     out = ctypes.c_void_p()
