@@ -325,4 +325,17 @@ hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_
 // Device properties cached per device.
 int cu_count();
 
+// Workgroups of `threads` threads of `kernel` that one CU holds at once (the
+// runtime's occupancy for its registers and LDS; at least 1).  Persistent
+// grids are sized with it: a workgroup beyond it would start only when
+// another ends and run as a tail at low occupancy.
+template <typename K>
+inline int resident_groups(K kernel, int threads)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
 }  // namespace dctf

@@ -368,7 +368,8 @@ hipError_t run_factored16(const float *P32, const float *Q32, const float *in, f
 {
     constexpr int U = 4;
     const int64_t units = (B + U - 1) / U;
-    int64_t waves = (int64_t)cu_count() * 16;
+    static const int per_cu = resident_groups(k_filter_factored16<R, U>, 256);
+    int64_t waves = (int64_t)cu_count() * per_cu * 4;
     waves = waves < units ? waves : units;
     const int64_t groups = (waves + 3) / 4;
     hipLaunchKernelGGL((k_filter_factored16<R, U>), dim3((unsigned)groups), dim3(256), 0, stream, in, out, B,
