@@ -33,6 +33,10 @@
  *     later call that synchronises.
  *   - Device pointers must be 16-byte aligned.  The library never aborts,
  *     throws or prints; every call returns a dctf_status.
+ *   - An operator is read-only once built: it may be used from several
+ *     streams and host threads at once (a rebuild must not overlap its use),
+ *     and operators may be built concurrently.  Results do not depend on
+ *     the stream or on what runs beside the call.
  */
 #ifndef DCTF_H
 #define DCTF_H
