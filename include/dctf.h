@@ -73,9 +73,9 @@ typedef struct dctf_batch_s *dctf_batch;
 typedef struct dctf_image_operator_s *dctf_image_operator;
 
 /* Supported block sizes N: 2, 4, 8, 16, and 32 for the operator build, its
- * FP64 read-back, dctf_filter_blocks, the forward DCT and the verify kernel
- * (the other calls return DCTF_EUNSUPPORTED for N = 32).  Mask sides:
- * 1 <= kh, kw <= 2N + 1. */
+ * FP64 read-back, dctf_filter_blocks, dctf_filter_blocks_f64, the forward
+ * DCT and the verify kernel (the other calls return DCTF_EUNSUPPORTED for
+ * N = 32).  Mask sides: 1 <= kh, kw <= 2N + 1. */
 
 /* ------------------------------------------------------------------ operators */
 
@@ -88,7 +88,7 @@ typedef struct dctf_image_operator_s *dctf_image_operator;
  * its BF16 hi/lo split (hi = bf16(fp32(H)), lo = bf16(fp32(H - hi))) and the
  * FP32 DC column H[:, 0], all in the layouts the filter kernels read.
  *   mask_host  kh*kw doubles, row-major, host memory; copied before return.
- *   N          block size (2, 4, 8 or 16).
+ *   N          block size (2, 4, 8, 16 or 32).
  *   border     dctf_border.
  *   out        receives a handle owning device memory until destroyed.
  * Errors: DCTF_EINVAL (null, kh/kw out of [1, 2N+1], non-finite entry, bad
