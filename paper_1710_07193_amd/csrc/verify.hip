@@ -26,6 +26,45 @@ __device__ inline void fill_dct(T *sC, int N)
     }
 }
 
+// One output x_k = sum_v C[v][k] z_v of the 8-point inverse DCT along one axis
+// (eq. 3), from the symmetries of the DCT basis.  C[v][7 - k] = (-1)^v C[v][k]
+// splits the sum into an even part (z0, z2, z4, z6) and an odd part
+// (z1, z3, z5, z7), both shared by outputs k and 7 - k; within the even part
+// C[2w][3 - h] = (-1)^w C[2w][h] splits it again into (z0, z4) and (z2, z6),
+// shared by h and 3 - h.  With h = min(k, 7 - k) and m = min(h, 3 - h):
+//   ce = C[0][m], C[4][m], C[2][m], C[6][m];  co = C[1][h], C[3][h], C[5][h], C[7][h];
+//   neg_e = (h >= 2), neg_o = (k >= 4).
+// 36 operations per 8 outputs against 64 products for the plain sum.  Every
+// 8-point inverse transform below evaluates an output in exactly this order,
+// so the kernels give the same pixels bit for bit.
+__device__ __forceinline__ float idct8_point(const float z[8], const float ce[4], const float co[4], bool neg_e,
+                                             bool neg_o)
+{
+    const float ee = fmaf(z[4], ce[1], z[0] * ce[0]);
+    const float eo = fmaf(z[6], ce[3], z[2] * ce[2]);
+    const float e = neg_e ? ee - eo : ee + eo;
+    const float o = fmaf(z[7], co[3], fmaf(z[5], co[2], fmaf(z[3], co[1], z[1] * co[0])));
+    return neg_o ? e - o : e + o;
+}
+
+// The coefficients and signs of idct8_point for output k, from C[v * 8 + n] = C[v][n].
+template <typename Tab>
+__device__ __forceinline__ void idct8_coeffs(const Tab &C, int k, float ce[4], float co[4], bool &neg_e,
+                                             bool &neg_o)
+{
+    const int h = k < 4 ? k : 7 - k, m = h < 2 ? h : 3 - h;
+    ce[0] = C[m];
+    ce[1] = C[32 + m];
+    ce[2] = C[16 + m];
+    ce[3] = C[48 + m];
+    co[0] = C[8 + h];
+    co[1] = C[24 + h];
+    co[2] = C[40 + h];
+    co[3] = C[56 + h];
+    neg_e = h >= 2;
+    neg_o = k >= 4;
+}
+
 // X[u][v] = sum_i C[u][i] (sum_j x[i][j] C[v][j]) in FP64, rounded once to FP32.
 // One thread per pixel; workgroups of max(256, N*N) threads.
 constexpr int kMaxDctThreads = 1024;
@@ -77,9 +116,11 @@ __global__ __launch_bounds__(kMaxDctThreads) void k_forward_dct_u8(const uint8_t
 // are reduced once per wave at the end.  Two register buffers take turns:
 // each is refilled with the step two strides ahead as soon as its rows are
 // staged in LDS, so every load has two steps of work to hide in (the kernel
-// is bound by the bytes it keeps in flight).  For N <= 8 the thread's part
+// is bound by the bytes it keeps in flight).  For N <= 4 the thread's part
 // of the DCT matrix (C[v][j0 .. j0 + V - 1] and C[u][i], for all u, v) sits
-// in registers instead of being read from LDS in both passes.
+// in registers instead of being read from LDS in both passes; N = 8 keeps
+// the coefficients of idct8_point for its outputs there and uses it in both
+// passes.
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int64_t B, uint8_t *pix,
                                                              const uint8_t *expected,
@@ -88,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
     // V coefficients per thread and block row, TPB threads per block, R blocks
     // per thread and step, G = R kThreads / TPB blocks per step
     constexpr int NN = N * N, V = N < 4 ? N : 4, TPB = NN / V, R = 2, GR = kThreads / TPB, G = R * GR;
-    constexpr bool kCreg = N <= 8;
+    constexpr bool kCreg = N <= 4, kBfly = N == 8;
     __shared__ __attribute__((aligned(16))) float sC[NN];
     __shared__ __attribute__((aligned(16))) float sy[G * NN];
     __shared__ __attribute__((aligned(16))) float st[G * NN];
@@ -105,6 +146,15 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
                 crow[v][q] = sC[v * N + j0 + q];
             ccol[v] = sC[v * N + i];
         }
+    }
+    // N = 8: outputs j0 + q of the first pass, output i of the second
+    float ce1[kBfly ? V : 1][4], co1[kBfly ? V : 1][4], ce2[4], co2[4];
+    bool ne1[kBfly ? V : 1], no1[kBfly ? V : 1], ne2 = false, no2 = false;
+    if constexpr (kBfly) {
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+            idct8_coeffs(sC, j0 + q, ce1[q], co1[q], ne1[q], no1[q]);
+        idct8_coeffs(sC, i, ce2, co2, ne2, no2);
     }
     unsigned long long bad = 0, near = 0;
     const int64_t steps = (B + G - 1) / G;
@@ -150,15 +200,25 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
             if (step * G + r * GR + local >= B)
                 continue;
             float t[V];
+            if constexpr (kBfly) {
+                float z[8];
 #pragma unroll
-            for (int q = 0; q < V; ++q)
-                t[q] = 0.0f;
-#pragma unroll
-            for (int v = 0; v < N; ++v) {
-                const float yv = sy[base + i * N + v];
+                for (int v = 0; v < 8; ++v)
+                    z[v] = sy[base + i * 8 + v];
 #pragma unroll
                 for (int q = 0; q < V; ++q)
-                    t[q] = fmaf(yv, kCreg ? crow[v][q] : sC[v * N + j0 + q], t[q]);
+                    t[q] = idct8_point(z, ce1[q], co1[q], ne1[q], no1[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    t[q] = 0.0f;
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    const float yv = sy[base + i * N + v];
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        t[q] = fmaf(yv, kCreg ? crow[v][q] : sC[v * N + j0 + q], t[q]);
+                }
             }
 #pragma unroll
             for (int q = 0; q < V; ++q)
@@ -175,15 +235,29 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
             uint8_t qv[V];
             bool nh[V];
             float pv[V];
+            if constexpr (kBfly) {
+                float z[8][V];
 #pragma unroll
-            for (int q = 0; q < V; ++q)
-                pv[q] = 0.0f;
+                for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int u = 0; u < N; ++u) {
-                const float c = kCreg ? ccol[u] : sC[u * N + i];
+                    for (int q = 0; q < V; ++q)
+                        z[u][q] = st[base + u * 8 + j0 + q];
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const float zc[8] = {z[0][q], z[1][q], z[2][q], z[3][q], z[4][q], z[5][q], z[6][q], z[7][q]};
+                    pv[q] = idct8_point(zc, ce2, co2, ne2, no2);
+                }
+            } else {
 #pragma unroll
                 for (int q = 0; q < V; ++q)
-                    pv[q] = fmaf(c, st[base + u * N + j0 + q], pv[q]);
+                    pv[q] = 0.0f;
+#pragma unroll
+                for (int u = 0; u < N; ++u) {
+                    const float c = kCreg ? ccol[u] : sC[u * N + i];
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        pv[q] = fmaf(c, st[base + u * N + j0 + q], pv[q]);
+                }
             }
 #pragma unroll
             for (int q = 0; q < V; ++q) {
@@ -272,11 +346,11 @@ __global__ __launch_bounds__(256) void k_stream_copy(const f32x4c *__restrict__ 
 // accesses (float4 k of block b at 16 b + (k ^ b mod 16)), and each lane
 // runs its block's two passes in registers with the DCT matrix in scalar
 // registers: no barrier, and LDS carries each byte once in and once out.
-// The arithmetic is that of k_idct_u8_verify (same products, same order),
-// so pixels and counters are identical.  The kernel is bound by VALU issue
-// (a wave64 instruction takes 4 cycles of a 16-lane SIMD; ~1.7k lane
-// operations per block), so COUNT = false, for calls without counters,
-// leaves out the near-1/2 and mismatch tests.
+// The arithmetic is that of k_idct_u8_verify (idct8_point for every output
+// of both passes), so pixels and counters are identical.  The kernel is
+// bound by VALU issue (a wave64 instruction takes 4 cycles of a 16-lane
+// SIMD), so COUNT = false, for calls without counters, leaves out the
+// near-1/2 and mismatch tests.
 template <bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_idct_u8_verify8(const float *Y, int64_t B, uint8_t *pix,
                                                               const uint8_t *expected,
@@ -328,20 +402,40 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify8(const float *Y, in
         // t[u][j] = sum_v Y[u][v] C[v][j], row by row in place
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            float t[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                t[j] = 0.0f;
+            float z[8], t[8];
 #pragma unroll
             for (int v = 0; v < 8; ++v)
+                z[v] = y[8 * u + v];
 #pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    t[j] = fmaf(y[8 * u + v], C[8 * v + j], t[j]);
+            for (int j = 0; j < 8; ++j) {
+                float ce[4], co[4];
+                bool ne, no;
+                idct8_coeffs(C, j, ce, co, ne, no);
+                t[j] = idct8_point(z, ce, co, ne, no);
+            }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 y[8 * u + j] = t[j];
         }
-        // p[i][j] = sum_u C[u][i] t[u][j], then uint8 and the counters
+        // p[i][j] = sum_u C[u][i] t[u][j], column by column in place
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float z[8], pc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                z[u] = y[8 * u + j];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float ce[4], co[4];
+                bool ne, no;
+                idct8_coeffs(C, i, ce, co, ne, no);
+                pc[i] = idct8_point(z, ce, co, ne, no);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                y[8 * i + j] = pc[i];
+        }
+        // uint8 and the counters
         const unsigned mine = lane < nv ? 1u : 0u;
         uint32_t packed[16];
         uint4 ex[4] = {};
@@ -353,25 +447,16 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify8(const float *Y, in
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            float pv[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                pv[j] = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    pv[j] = fmaf(C[8 * u + i], y[8 * u + j], pv[j]);
+            const float *pv = y + 8 * i;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                uint32_t w = 0;
+                // the same bytes as the general kernel's clamp for every finite value
+                const uint32_t w = pack_u8x4(pv[4 * h], pv[4 * h + 1], pv[4 * h + 2], pv[4 * h + 3]);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float pq = pv[4 * h + q];
-                    const float rr = floorf(pq + 0.5f);
-                    const uint32_t qv = (uint32_t)(rr > 0.0f ? (rr > 255.0f ? 255.0f : rr) : 0.0f);
-                    w |= qv << (8 * q);
                     if constexpr (COUNT) {
+                        const float pq = pv[4 * h + q];
+                        const uint32_t qv = (w >> (8 * q)) & 0xffu;
                         const unsigned nh = fabsf(pq - floorf(pq) - 0.5f) < 1e-3f ? 1u : 0u;
                         near += nh & mine;
                         if (expected != nullptr) {
