@@ -316,6 +316,123 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
     }
 }
 
+// N = 16 and 32: both passes on FP32 MFMA 16x16x4, one block per wave at a
+// time, no data moved between lanes.  Lane (n, g) = (lane % 16, lane / 16)
+// loads Y[n][4g .. 4g + 3] of a 16 x 16 tile (one 16-byte load): those are the
+// A operand of the four k-steps s of T = Y C, k-step s taking contraction index
+// 4g + s from lane group g; the B operand is C[4g + s][n], constants of the
+// lane.  The result holds T[4g + r][n] in lane (n, g), which is the A operand of
+// k-step r of P^t = T^t C, again with C[4g + s][n] as B; that result holds
+// P[n][4g .. 4g + 3], four consecutive pixels of row n, converted and stored as
+// one 32-bit word (four bytes when the pixel buffers are not 4-byte aligned).
+// N = 32 runs the same on 2 x 2 tiles (8 k-steps per output tile).  NB blocks
+// per wave step: all their loads are issued first.  The sums run in MFMA order
+// (k-steps of tile V = 0 first), so every call gives the same pixels.
+template <int N, int NB, bool COUNT>
+__global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y, int64_t B, uint8_t *pix,
+                                                                  const uint8_t *expected,
+                                                                  unsigned long long *counters, int vec)
+{
+    constexpr int NT = N / 16, NN = N * N;
+    __shared__ float sC[NN];
+    fill_dct(sC, N);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    float cb[NT][NT][4];   // C[16 V + 4g + s][16 J + n]
+#pragma unroll
+    for (int V = 0; V < NT; ++V)
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                cb[V][J][k] = sC[(16 * V + 4 * g + k) * N + 16 * J + n];
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), waves = (int64_t)gridDim.x * 4;
+    const int64_t units = (B + NB - 1) / NB;
+    unsigned bad = 0, near = 0;
+    for (int64_t unit = wave; unit < units; unit += waves) {
+        f32x4 y[NB][NT][NT];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            int64_t blk = unit * NB + b;
+            blk = blk < B ? blk : B - 1;   // clamped: nothing is stored for it
+#pragma unroll
+            for (int U = 0; U < NT; ++U)
+#pragma unroll
+                for (int V = 0; V < NT; ++V)
+                    y[b][U][V] = *reinterpret_cast<const f32x4 *>(Y + blk * NN + (16 * U + n) * N + 16 * V + 4 * g);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t blk = unit * NB + b;
+            f32x4 t[NT][NT];   // tile (U, J) of T = Y C
+#pragma unroll
+            for (int U = 0; U < NT; ++U)
+#pragma unroll
+                for (int J = 0; J < NT; ++J) {
+                    t[U][J] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int V = 0; V < NT; ++V)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            t[U][J] = mfma_f32(y[b][U][V][k], cb[V][J][k], t[U][J]);
+                }
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+#pragma unroll
+                for (int I = 0; I < NT; ++I) {
+                    f32x4 p = f32x4{0.f, 0.f, 0.f, 0.f};   // tile (J, I) of P^t = T^t C
+#pragma unroll
+                    for (int U = 0; U < NT; ++U)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            p = mfma_f32(t[U][J][k], cb[U][I][k], p);
+                    if (blk >= B)
+                        continue;
+                    const int64_t off = blk * NN + (16 * I + n) * N + 16 * J + 4 * g;
+                    const uint32_t w = pack_u8x4(p[0], p[1], p[2], p[3]);
+                    uint32_t ex = 0;
+                    if (vec) {
+                        *reinterpret_cast<uint32_t *>(pix + off) = w;
+                        if (COUNT && expected != nullptr)
+                            ex = *reinterpret_cast<const uint32_t *>(expected + off);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            pix[off + r] = (uint8_t)(w >> (8 * r));
+                            if (COUNT && expected != nullptr)
+                                ex |= (uint32_t)expected[off + r] << (8 * r);
+                        }
+                    }
+                    if constexpr (COUNT) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const unsigned nh = fabsf(p[r] - floorf(p[r]) - 0.5f) < 1e-3f ? 1u : 0u;
+                            near += nh;
+                            if (expected != nullptr)
+                                bad += ((((ex ^ w) >> (8 * r)) & 0xffu) != 0u ? 1u : 0u) & (nh ^ 1u);
+                        }
+                    }
+                }
+        }
+    }
+    if (COUNT && counters != nullptr) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            bad += __shfl_xor(bad, d);
+            near += __shfl_xor(near, d);
+        }
+        if (lane == 0) {
+            if (bad)
+                atomicAdd(&counters[0], (unsigned long long)bad);
+            if (near)
+                atomicAdd(&counters[1], (unsigned long long)near);
+        }
+    }
+}
+
+// blocks per wave step of k_idct_u8_verify_mfma
+constexpr int kVerifyNb16 = 4;
+constexpr int kVerifyNb32 = 2;
+
 // Plain streaming copy: each wave moves 4 KiB per step (4 x 1 KiB contiguous
 // 16-byte-per-lane accesses, nontemporal), waves stride over the buffer.
 typedef float f32x4c __attribute__((ext_vector_type(4)));
@@ -582,12 +699,43 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
                                pix, expected, counters);
         return hipGetLastError();
     }
+    if (N == 16 || N == 32) {
+        // every call of these sizes, aligned or not, runs the MFMA kernel (same pixels)
+        const bool count = counters != nullptr;
+        static std::atomic<int> resident_m[4];
+        auto launch_m = [&](auto kernel, int slot_id, int nb) {
+            std::atomic<int> &slot = resident_m[slot_id];
+            int per_cu = slot.load(std::memory_order_relaxed);
+            if (per_cu == 0) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                slot.store(per_cu, std::memory_order_relaxed);
+            }
+            const int64_t units = (B + nb - 1) / nb;
+            int64_t groups = (int64_t)cu_count() * per_cu;
+            const int64_t need = (units + 3) / 4;
+            groups = groups < need ? groups : need;
+            hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected,
+                               counters, vec);
+        };
+        if (N == 16) {
+            if (count)
+                launch_m(k_idct_u8_verify_mfma<16, kVerifyNb16, true>, 0, kVerifyNb16);
+            else
+                launch_m(k_idct_u8_verify_mfma<16, kVerifyNb16, false>, 1, kVerifyNb16);
+        } else {
+            if (count)
+                launch_m(k_idct_u8_verify_mfma<32, kVerifyNb32, true>, 2, kVerifyNb32);
+            else
+                launch_m(k_idct_u8_verify_mfma<32, kVerifyNb32, false>, 3, kVerifyNb32);
+        }
+        return hipGetLastError();
+    }
     switch (N) {
     case 2: launch(k_idct_u8_verify<2>); break;
     case 4: launch(k_idct_u8_verify<4>); break;
-    case 8: launch(k_idct_u8_verify<8>); break;
-    case 16: launch(k_idct_u8_verify<16>); break;
-    default: launch(k_idct_u8_verify<32>); break;
+    default: launch(k_idct_u8_verify<8>); break;
     }
     return hipGetLastError();
 }
