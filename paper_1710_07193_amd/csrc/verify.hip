@@ -316,18 +316,19 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
     }
 }
 
-// N = 16 and 32: both passes on FP32 MFMA 16x16x4, one block per wave at a
-// time, no data moved between lanes.  Lane (n, g) = (lane % 16, lane / 16)
-// loads Y[n][4g .. 4g + 3] of a 16 x 16 tile (one 16-byte load): those are the
-// A operand of the four k-steps s of T = Y C, k-step s taking contraction index
-// 4g + s from lane group g; the B operand is C[4g + s][n], constants of the
-// lane.  The result holds T[4g + r][n] in lane (n, g), which is the A operand of
-// k-step r of P^t = T^t C, again with C[4g + s][n] as B; that result holds
+// N = 16 and 32: both passes on FP32 MFMA 16x16x4, one 16 x 16 tile per wave
+// at a time, no data moved between lanes.  Lane (n, g) = (lane % 16,
+// lane / 16) loads Y[n][4g .. 4g + 3] of the tile (one 16-byte load): those
+// are the A operand of the four k-steps s of T = Y C, k-step s taking
+// contraction index 4g + s from lane group g; the B operand is C[4g + s][n],
+// constants of the lane.  The result holds T[4g + r][n] in lane (n, g), which
+// is the A operand of k-step r of P^t = T^t C, again with C[4g + s][n] as B;
+// that result holds
 // P[n][4g .. 4g + 3], four consecutive pixels of row n, converted and stored as
 // one 32-bit word (four bytes when the pixel buffers are not 4-byte aligned).
-// N = 32 runs the same on 2 x 2 tiles (8 k-steps per output tile).  NB blocks
-// per wave step: all their loads are issued first.  The sums run in MFMA order
-// (k-steps of tile V = 0 first), so every call gives the same pixels.
+// N = 16: a tile is a block.  N = 32: a block is 2 x 2 tiles (8 k-steps per
+// output tile).  NB blocks per wave step: all their loads are issued first.
+// The sums run in MFMA order, so every call gives the same pixels.
 template <int N, int NB, bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y, int64_t B, uint8_t *pix,
                                                                   const uint8_t *expected,
@@ -346,6 +347,8 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 cb[V][J][k] = sC[(16 * V + 4 * g + k) * N + 16 * J + n];
+    // this lane's element offset in tile (U, V) of a block
+    auto offset = [&](int U, int V) { return (16 * U + n) * N + 16 * V + 4 * g; };
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), waves = (int64_t)gridDim.x * 4;
     const int64_t units = (B + NB - 1) / NB;
     unsigned bad = 0, near = 0;
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y
             for (int U = 0; U < NT; ++U)
 #pragma unroll
                 for (int V = 0; V < NT; ++V)
-                    y[b][U][V] = *reinterpret_cast<const f32x4 *>(Y + blk * NN + (16 * U + n) * N + 16 * V + 4 * g);
+                    y[b][U][V] = *reinterpret_cast<const f32x4 *>(Y + blk * NN + offset(U, V));
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
@@ -388,7 +391,8 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y
                             p = mfma_f32(t[U][J][k], cb[U][I][k], p);
                     if (blk >= B)
                         continue;
-                    const int64_t off = blk * NN + (16 * I + n) * N + 16 * J + 4 * g;
+                    // P[16 I + n][16 J + 4g + r]: tile (I, J) of the block
+                    const int64_t off = blk * NN + offset(I, J);
                     const uint32_t w = pack_u8x4(p[0], p[1], p[2], p[3]);
                     uint32_t ex = 0;
                     if (vec) {
@@ -672,33 +676,6 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
         hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix, expected, counters,
                            vec);
     };
-    const bool aligned = ((uintptr_t)pix & 15u) == 0 && ((uintptr_t)expected & 15u) == 0;
-    if (N == 8 && aligned) {
-        // the counting kernel when counters are asked for (a mismatch count needs them)
-        const bool count = counters != nullptr;
-        static std::atomic<int> resident8[2];
-        std::atomic<int> &slot = resident8[count ? 1 : 0];
-        int per_cu = slot.load(std::memory_order_relaxed);
-        if (per_cu == 0) {
-            const hipError_t e =
-                count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_idct_u8_verify8<true>, kThreads, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_idct_u8_verify8<false>, kThreads, 0);
-            if (e != hipSuccess || per_cu < 1)
-                per_cu = 1;
-            slot.store(per_cu, std::memory_order_relaxed);
-        }
-        const int64_t units = (B + 63) / 64;
-        int64_t groups = (int64_t)cu_count() * per_cu;
-        const int64_t need = (units + 3) / 4;
-        groups = groups < need ? groups : need;
-        if (count)
-            hipLaunchKernelGGL(k_idct_u8_verify8<true>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix,
-                               expected, counters);
-        else
-            hipLaunchKernelGGL(k_idct_u8_verify8<false>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B,
-                               pix, expected, counters);
-        return hipGetLastError();
-    }
     if (N == 16 || N == 32) {
         // every call of these sizes, aligned or not, runs the MFMA kernel (same pixels)
         const bool count = counters != nullptr;
@@ -730,6 +707,33 @@ hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
             else
                 launch_m(k_idct_u8_verify_mfma<32, kVerifyNb32, false>, 3, kVerifyNb32);
         }
+        return hipGetLastError();
+    }
+    const bool aligned = ((uintptr_t)pix & 15u) == 0 && ((uintptr_t)expected & 15u) == 0;
+    if (N == 8 && aligned) {
+        // the counting kernel when counters are asked for (a mismatch count needs them)
+        const bool count = counters != nullptr;
+        static std::atomic<int> resident8[2];
+        std::atomic<int> &slot = resident8[count ? 1 : 0];
+        int per_cu = slot.load(std::memory_order_relaxed);
+        if (per_cu == 0) {
+            const hipError_t e =
+                count ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_idct_u8_verify8<true>, kThreads, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_idct_u8_verify8<false>, kThreads, 0);
+            if (e != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            slot.store(per_cu, std::memory_order_relaxed);
+        }
+        const int64_t units = (B + 63) / 64;
+        int64_t groups = (int64_t)cu_count() * per_cu;
+        const int64_t need = (units + 3) / 4;
+        groups = groups < need ? groups : need;
+        if (count)
+            hipLaunchKernelGGL(k_idct_u8_verify8<true>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B, pix,
+                               expected, counters);
+        else
+            hipLaunchKernelGGL(k_idct_u8_verify8<false>, dim3((unsigned)groups), dim3(kThreads), 0, stream, Y, B,
+                               pix, expected, counters);
         return hipGetLastError();
     }
     switch (N) {
