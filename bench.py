@@ -295,6 +295,7 @@ def n16_frames(dctf, torch, stream, steps, warmup):
                 ent["dense_%s_ms" % pname] = timed_steps(
                     torch, lambda: dctf.dctf_filter_blocks(o, p, X, Y, stream), steps, warmup, stream)
         res["factored_" + tag] = ent
+    res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y
     torch.cuda.empty_cache()
@@ -302,6 +303,15 @@ def n16_frames(dctf, torch, stream, steps, warmup):
 
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def verify_frames(dctf, torch, stream, Y, N, steps, warmup):
+    """The verify kernel (inverse DCT + uint8, no counters) over the filtered
+    frames: 4 B read and 1 B written per coefficient."""
+    pix = torch.empty(Y.numel(), dtype=torch.uint8, device="cuda")
+    ms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None, stream), steps, warmup, stream)
+    del pix
+    return {"ms_per_launch": ms, "GBps": Y.numel() * 5 / (ms * 1e-3) / 1e9}
 
 
 def fp64_frames(dctf, torch, stream, op, X, N, steps, warmup):
@@ -349,6 +359,7 @@ def n32_frames(dctf, torch, stream, steps, warmup):
     res["split_bf16"] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
                          "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "bf16_mfma_TFLOPs": tf,
                          "frac_of_bf16_mfma_peak": tf / BF16_MFMA_PEAK_TFLOPS}
+    res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y
     torch.cuda.empty_cache()
