@@ -83,6 +83,25 @@ def make_inputs(dctf, torch, images, side, N=8, seed0=1000):
     return X, nblk
 
 
+def forward_dct_ingest(dctf, torch, stream, images, side, N, out, steps, warmup):
+    """uint8 pixels -> FP32 coefficients for the workload's images, one call
+    per image, as an application ingesting them would run it (1 B read and
+    4 B written per pixel)."""
+    import synthetic as syn
+    imgs = [torch.from_numpy(syn.image_u8(1000 + i, side, side)).cuda() for i in range(images)]
+    per = (side // N) ** 2 * N * N
+
+    def run():
+        for i, img in enumerate(imgs):
+            dctf.dctf_forward_dct_u8(img, N, out[i * per:(i + 1) * per], stream)
+
+    ms = timed_steps(torch, run, steps, warmup, stream)
+    px = images * side * side
+    del imgs
+    return {"calls": images, "ms_per_pass": ms, "pixels_per_s": px / (ms * 1e-3),
+            "GBps": px * 5 / (ms * 1e-3) / 1e9}
+
+
 def progress(msg):
     """One line per finished stage, on stderr (the JSON line stays alone on stdout)."""
     print("bench: %s (%.0f s)" % (msg, time.perf_counter() - T0), file=sys.stderr, flush=True)
@@ -632,7 +651,8 @@ def main():
         extras["verify_kernel_ms"] = vms
         out["extras"] = extras
         del pix
-        progress("FP64 filter, verify kernel")
+        extras["forward_dct_ingest"] = forward_dct_ingest(dctf, torch, stream, args.images, args.side, N, Y, 5, 2)
+        progress("FP64 filter, verify kernel, forward DCT")
         extras["n16_frames"] = n16_frames(dctf, torch, stream, max(10, args.steps // 5), max(5, args.warmup // 6))
         extras["n32_frames"] = n32_frames(dctf, torch, stream, max(5, args.steps // 10), 3)
         progress("N = 16 and N = 32 frames")

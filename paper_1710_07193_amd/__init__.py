@@ -414,14 +414,19 @@ def dctf_filter_batch(jobs, prec: int, stream=None):
 
 
 def dctf_forward_dct_u8(img: torch.Tensor, N: int, coeffs: torch.Tensor, stream=None):
-    """uint8 image (h, w) on the device -> coefficient blocks (raster order)."""
+    """uint8 image (h, w) on the device -> coefficient blocks (raster order).
+    The rows may be a view of a wider buffer: the row pitch is img.stride(0)."""
+    if not isinstance(img, torch.Tensor) or not img.is_cuda or img.dtype != torch.uint8:
+        raise TypeError("img must be a uint8 device tensor")
     if img.dim() != 2:
         raise ValueError("img must be 2-D")
     h, w = img.shape
+    if img.stride(1) != 1 or img.stride(0) < w:
+        raise ValueError("img rows must be contiguous, with a row pitch of at least the width")
     nblk = -(-h // N) * -(-w // N)
     if coeffs.numel() != nblk * N * N:
         raise ValueError("coeffs must hold %d blocks" % nblk)
-    _check(_lib.dctf_forward_dct_u8(_dptr(img, torch.uint8, "img"), h, w, img.stride(0), N,
+    _check(_lib.dctf_forward_dct_u8(_P(img.data_ptr()), h, w, img.stride(0), N,
                                     _dptr(coeffs, torch.float32, "coeffs"), _stream(stream)),
            "dctf_forward_dct_u8")
 

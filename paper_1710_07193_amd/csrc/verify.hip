@@ -1,10 +1,13 @@
 // Kernels around the filter path:
-//   k_forward_dct_u8   uint8 image -> FP32 coefficient blocks (eq. 1, FP64 arithmetic)
-//   k_idct_u8_verify   FP32 coefficients -> uint8 pixels (eq. 3 in FP32, then the
-//                      Sec. III uint8 conversion) with mismatch / near-1/2 counters
-// The forward transform runs one thread per pixel; the verify kernel one
-// thread per row segment of up to four coefficients.  The N x N DCT matrix
-// is formed in LDS from its closed form.
+//   k_forward_dct_mfma   uint8 image -> FP32 coefficient blocks (eq. 1) for
+//                        N = 8, 16, 32: FP64 MFMA, rounded once to FP32
+//   k_forward_dct_u8     the same for N = 2, 4: one thread per pixel, FP64
+//   k_idct_u8_verify8    FP32 coefficients -> uint8 pixels (eq. 3 in FP32, then
+//                        the Sec. III uint8 conversion) with mismatch / near-1/2
+//                        counters, N = 8: one block per lane
+//   k_idct_u8_verify_mfma  the same for N = 16, 32 on FP32 MFMA
+//   k_idct_u8_verify     the same for N = 2, 4 and unaligned N = 8 buffers
+// The N x N DCT matrix is formed in LDS from its closed form.
 #include <atomic>
 
 #include "mfma_common.h"
@@ -106,6 +109,160 @@ __global__ __launch_bounds__(kMaxDctThreads) void k_forward_dct_u8(const uint8_t
         for (int ii = 0; ii < N; ++ii)
             s += sC[i * N + ii] * st[base + ii * N + j];
         coeffs[blk * NN + e] = __double2float_rn(s);
+    }
+}
+
+typedef double f64x4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4v mfma_f64x4(double a, double b, f64x4v c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Forward DCT for N = 8, 16 and 32 on FP64 MFMA 16x16x4, one unit of S x S
+// pixels per wave at a time (S = 16 for N = 8 and 16, 32 for N = 32), no data
+// moved between lanes.  The MFMA returns row g + 4r of its 16 x 16 result in
+// register r of lane (n, g) = (lane % 16, lane / 16).  Pass 1, T = x C^t:
+// lane (n, g) supplies pixels x[n][4g + s] of a 16 x 16 tile as the A operand
+// of k-step s and C[sigma(n)][4g + s] as B, sigma(m) = 4 (m % 4) + m / 4, so
+// register r holds T[g + 4r][sigma(n)].  That is the A operand of k-step r of
+// pass 2, X^t = T^t C^t, with C[n][g + 4r] as B; its register r then holds
+// X[n][sigma(g + 4r)] = X[n][4g + r]: four consecutive coefficients, stored as
+// one 16-byte write.  N = 32: a block is 2 x 2 tiles (8 k-steps per output
+// tile).  N = 8: a unit is 2 x 2 blocks and C is diag(C8, C8), so the tile's
+// result holds the four blocks' coefficients in the same arrangement (the
+// off-diagonal products add exact zeros).  Pixels past the image repeat the
+// last row / column; blocks past the block grid (N = 8, odd counts) are not
+// stored.  A unit inside the image reads its four pixels per lane and tile
+// row as one 32-bit load when the image and its pitch are 4-byte aligned
+// (aligned4), others pixel by pixel with clamped indices.  FP64 products and
+// sums, rounded once to FP32.
+template <int N, int NB>
+__global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *img, int h, int w, int64_t pitch,
+                                                               float *coeffs, int64_t bh, int64_t bw, int64_t ubw,
+                                                               int64_t units, int aligned4)
+{
+    constexpr int S = N < 16 ? 16 : N, NT = S / 16;
+    __shared__ double sC[N * N];
+    fill_dct(sC, N);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int sn = 4 * (n & 3) + (n >> 2);
+    // element (a, b) of C (N = 8: of diag(C8, C8))
+    auto cval = [&](int a, int b) -> double {
+        if constexpr (N == 8)
+            return (a >> 3) == (b >> 3) ? sC[(a & 7) * 8 + (b & 7)] : 0.0;
+        else
+            return sC[a * N + b];
+    };
+    double c1[NT][NT][4], c2[NT][NT][4];   // c1[J][V][s], c2[I][U][r]
+#pragma unroll
+    for (int P = 0; P < NT; ++P)
+#pragma unroll
+        for (int Q = 0; Q < NT; ++Q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                c1[P][Q][k] = cval(16 * Q + sn, 16 * P + 4 * g + k);
+                c2[P][Q][k] = cval(16 * Q + n, 16 * P + g + 4 * k);
+            }
+    // the wave index as a scalar: the unit bookkeeping below runs on the scalar unit
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    // per lane, relative to a unit's corner: pixel (16 I + n, 16 J + 4g) and the
+    // output place of X[16 U + n][16 V + 4g]
+    int64_t loff[NT][NT], soff[NT][NT];
+#pragma unroll
+    for (int P = 0; P < NT; ++P)
+#pragma unroll
+        for (int Q = 0; Q < NT; ++Q) {
+            loff[P][Q] = (int64_t)(16 * P + n) * pitch + 16 * Q + 4 * g;
+            if constexpr (N == 8)
+                soff[P][Q] = ((n >> 3) * bw + (g >> 1)) * 64 + (n & 7) * 8 + 4 * (g & 1);
+            else
+                soff[P][Q] = (16 * P + n) * N + 16 * Q + 4 * g;
+        }
+    for (int64_t unit0 = wave * NB; unit0 < units; unit0 += waves * NB) {
+        const int64_t uy0 = unit0 / ubw, ux0 = unit0 % ubw;
+        // px[b][I][J] byte s = pixel (16 I + n, 16 J + 4g + s) of unit unit0 + b: four pixels
+        // per register, so that many units' loads fit in flight
+        uint32_t px[NB][NT][NT];
+        {
+            int64_t uy = uy0, ux = ux0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const bool live = unit0 + b < units;
+                const int64_t ly = live ? uy : 0, lx = live ? ux : 0;   // a unit past the end reads unit 0
+                if (aligned4 && (ly + 1) * S <= h && (lx + 1) * S <= w) {   // uniform over the wave
+                    const uint8_t *base = img + ly * S * pitch + lx * S;
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int J = 0; J < NT; ++J)
+                            px[b][I][J] = *reinterpret_cast<const uint32_t *>(base + loff[I][J]);
+                } else {
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) {
+                        int64_t row = ly * S + 16 * I + n;
+                        row = row < h ? row : h - 1;
+#pragma unroll
+                        for (int J = 0; J < NT; ++J) {
+                            uint32_t v = 0;
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) {
+                                int64_t col = lx * S + 16 * J + 4 * g + k;
+                                col = col < w ? col : w - 1;
+                                v |= (uint32_t)img[row * pitch + col] << (8 * k);
+                            }
+                            px[b][I][J] = v;
+                        }
+                    }
+                }
+                if (++ux == ubw) {
+                    ux = 0;
+                    ++uy;
+                }
+            }
+        }
+        int64_t uy = uy0, ux = ux0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const bool live = unit0 + b < units;
+            const int64_t cy = uy, cx = ux;
+            if (++ux == ubw) {
+                ux = 0;
+                ++uy;
+            }
+            f64x4v t[NT][NT];   // t[I][V]
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int V = 0; V < NT; ++V) {
+                    t[I][V] = f64x4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int J = 0; J < NT; ++J)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            t[I][V] = mfma_f64x4((double)((px[b][I][J] >> (8 * k)) & 0xffu), c1[J][V][k], t[I][V]);
+                }
+            if (!live)
+                continue;
+            float *out = coeffs + (N == 8 ? (2 * cy * bw + 2 * cx) * 64 : (cy * bw + cx) * (N * N));
+            const bool mine = N != 8 || (2 * cy + (n >> 3) < bh && 2 * cx + (g >> 1) < bw);
+#pragma unroll
+            for (int V = 0; V < NT; ++V)
+#pragma unroll
+                for (int U = 0; U < NT; ++U) {
+                    f64x4v p = f64x4v{0.0, 0.0, 0.0, 0.0};   // X[16 U + n][16 V + 4g + r]
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            p = mfma_f64x4(t[I][V][k], c2[I][U][k], p);
+                    if (mine)
+                        *reinterpret_cast<float4 *>(out + soff[U][V]) =
+                            make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+                }
+        }
     }
 }
 
@@ -433,6 +590,10 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y
     }
 }
 
+// units per wave step of k_forward_dct_mfma: N = 8 and 16 (16 x 16 pixels
+// each; 4 and 32 were 2-8 % slower), N = 32 (32 x 32; 2 and 8 were slower)
+constexpr int kFdctNb = 8;
+constexpr int kFdctNb32 = 4;
 // blocks per wave step of k_idct_u8_verify_mfma
 constexpr int kVerifyNb16 = 4;
 constexpr int kVerifyNb32 = 2;
@@ -641,6 +802,35 @@ hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_
 hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
                                  float *coeffs, hipStream_t stream)
 {
+    if (N == 8 || N == 16 || N == 32) {
+        const int64_t bh = (h + N - 1) / N, bw = (w + N - 1) / N;
+        const int64_t ubh = N == 8 ? (bh + 1) / 2 : bh, ubw = N == 8 ? (bw + 1) / 2 : bw;
+        const int64_t units = ubh * ubw;
+        const int aligned4 = ((uintptr_t)img & 3u) == 0 && (pitch & 3) == 0;
+        auto launch = [&](auto kernel, int nb) {
+            static std::atomic<int> resident[3];
+            std::atomic<int> &slot = resident[N == 8 ? 0 : N == 16 ? 1 : 2];
+            int per_cu = slot.load(std::memory_order_relaxed);
+            if (per_cu == 0) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
+                    per_cu < 1)
+                    per_cu = 1;
+                slot.store(per_cu, std::memory_order_relaxed);
+            }
+            int64_t groups = (int64_t)cu_count() * per_cu;
+            const int64_t need = (units + 4 * nb - 1) / (4 * nb);
+            groups = groups < need ? groups : need;
+            hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, img, h, w, pitch, coeffs,
+                               bh, bw, ubw, units, aligned4);
+        };
+        if (N == 8)
+            launch(k_forward_dct_mfma<8, kFdctNb>, kFdctNb);
+        else if (N == 16)
+            launch(k_forward_dct_mfma<16, kFdctNb>, kFdctNb);
+        else
+            launch(k_forward_dct_mfma<32, kFdctNb32>, kFdctNb32);
+        return hipGetLastError();
+    }
     const int64_t nblocks = (int64_t)((h + N - 1) / N) * ((w + N - 1) / N);
     const int threads = N * N > kThreads ? N * N : kThreads;   // <= kMaxDctThreads (N <= 32)
     const int per = threads / (N * N);

@@ -222,7 +222,7 @@ def test_device_argument_errors(dctf):
 
 # ------------------------------------------------------- around the path
 
-@pytest.mark.parametrize("N", [2, 4, 8, 16])
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
 def test_forward_dct_matches_oracle(dctf, N):
     img = syn.image_u8(8, 100, 75)   # ragged for every N but 2 and 4 (rows)
     X = torch.empty(-(-100 // N) * -(-75 // N) * N * N, dtype=torch.float32, device="cuda")
@@ -232,6 +232,31 @@ def test_forward_dct_matches_oracle(dctf, N):
     got = X.cpu().numpy()
     diff = np.abs(got.astype(np.float64) - ref)
     # both sides round an FP64 sum once to FP32; only the summation order differs
+    assert diff.max() <= 4 * np.spacing(np.float32(255 * N))
+    big = np.abs(ref) > 1e-3
+    assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
+
+
+@pytest.mark.parametrize("pad", [37, 40])
+@pytest.mark.parametrize("N", [8, 16, 32])
+@pytest.mark.parametrize("h,w", [(1000, 1496), (1016, 1000), (17, 9), (1, 1)])
+def test_forward_dct_strided_image(dctf, N, h, w, pad):
+    """Images held as a view of a wider buffer (row pitch w + pad: odd, or a
+    multiple of 4 where w is, so that units inside the image take the 32-bit
+    pixel loads), block counts odd and even in both directions, sides not
+    multiples of N, and a single pixel: every block against the oracle."""
+    img = syn.image_u8(20 + N, h, w)
+    pitch = w + pad
+    buf = torch.zeros((h, pitch), dtype=torch.uint8, device="cuda")
+    buf[:, :w] = dev(img)
+    view = buf[:, :w]
+    nb = -(-h // N) * -(-w // N)
+    X = torch.full((nb * N * N,), float("nan"), dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8(view, N, X)
+    torch.cuda.synchronize()
+    ref = oracle.coeffs_fp32(oracle.tile_u8(img, N)).reshape(-1)
+    got = X.cpu().numpy()
+    diff = np.abs(got.astype(np.float64) - ref)
     assert diff.max() <= 4 * np.spacing(np.float32(255 * N))
     big = np.abs(ref) > 1e-3
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
