@@ -807,9 +807,9 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
         const int64_t ubh = N == 8 ? (bh + 1) / 2 : bh, ubw = N == 8 ? (bw + 1) / 2 : bw;
         const int64_t units = ubh * ubw;
         const int aligned4 = ((uintptr_t)img & 3u) == 0 && (pitch & 3) == 0;
-        auto launch = [&](auto kernel, int nb) {
-            static std::atomic<int> resident[3];
-            std::atomic<int> &slot = resident[N == 8 ? 0 : N == 16 ? 1 : 2];
+        auto launch = [&](auto kernel, int nb, int slot_id) {
+            static std::atomic<int> resident[4];
+            std::atomic<int> &slot = resident[slot_id];
             int per_cu = slot.load(std::memory_order_relaxed);
             if (per_cu == 0) {
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess ||
@@ -823,12 +823,18 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
             hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, img, h, w, pitch, coeffs,
                                bh, bw, ubw, units, aligned4);
         };
-        if (N == 8)
-            launch(k_forward_dct_mfma<8, kFdctNb>, kFdctNb);
+        // images too small to give every resident wave a few steps of kFdctNb
+        // units (one 2048 x 2048 image at N = 8 is 16,384 units) take two units
+        // per step: more waves share the image, and each waits on fewer loads
+        const bool small = units < (int64_t)cu_count() * 64 * kFdctNb;
+        if (N == 8 && small)
+            launch(k_forward_dct_mfma<8, 2>, 2, 3);
+        else if (N == 8)
+            launch(k_forward_dct_mfma<8, kFdctNb>, kFdctNb, 0);
         else if (N == 16)
-            launch(k_forward_dct_mfma<16, kFdctNb>, kFdctNb);
+            launch(k_forward_dct_mfma<16, kFdctNb>, kFdctNb, 1);
         else
-            launch(k_forward_dct_mfma<32, kFdctNb32>, kFdctNb32);
+            launch(k_forward_dct_mfma<32, kFdctNb32>, kFdctNb32, 2);
         return hipGetLastError();
     }
     const int64_t nblocks = (int64_t)((h + N - 1) / N) * ((w + N - 1) / N);

@@ -237,6 +237,23 @@ def test_forward_dct_matches_oracle(dctf, N):
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
 
 
+def test_forward_dct_large_image(dctf):
+    """An image large enough for the N = 8 forward DCT's long-step launch
+    (6144 x 6144: 147,456 units of 2 x 2 blocks), every block against the
+    oracle."""
+    N, side = 8, 6144
+    img = syn.image_u8(31, side, side)
+    X = torch.full(((side // N) ** 2 * N * N,), float("nan"), dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8(dev(img), N, X)
+    torch.cuda.synchronize()
+    ref = oracle.coeffs_fp32(oracle.tile_u8(img, N)).reshape(-1)
+    got = X.cpu().numpy()
+    diff = np.abs(got.astype(np.float64) - ref)
+    assert diff.max() <= 4 * np.spacing(np.float32(255 * N))
+    big = np.abs(ref) > 1e-3
+    assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
+
+
 @pytest.mark.parametrize("pad", [37, 40])
 @pytest.mark.parametrize("N", [8, 16, 32])
 @pytest.mark.parametrize("h,w", [(1000, 1496), (1016, 1000), (17, 9), (1, 1)])
