@@ -112,6 +112,17 @@ __global__ __launch_bounds__(kMaxDctThreads) void k_forward_dct_u8(const uint8_t
     }
 }
 
+// v from lane 15 - i of the lane's 16-lane row (DPP row_mirror)
+__device__ __forceinline__ float row_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ f32x4 row_mirror4(f32x4 v)
+{
+    return f32x4{row_mirror(v[0]), row_mirror(v[1]), row_mirror(v[2]), row_mirror(v[3])};
+}
+
 typedef double f64x4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f64x4v mfma_f64x4(double a, double b, f64x4v c)
@@ -483,9 +494,15 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify(const float *Y, int
 // that result holds
 // P[n][4g .. 4g + 3], four consecutive pixels of row n, converted and stored as
 // one 32-bit word (four bytes when the pixel buffers are not 4-byte aligned).
-// N = 16: a tile is a block.  N = 32: a block is 2 x 2 tiles (8 k-steps per
-// output tile).  NB blocks per wave step: all their loads are issued first.
-// The sums run in MFMA order, so every call gives the same pixels.
+// N = 16: a tile is a block.  N = 32: a block is 2 x 2 tiles, and each pass
+// uses the basis symmetry C[v][31 - j] = (-1)^v C[v][j]: the even and odd
+// contraction slices (k-steps 0, 2 and 1, 3 of each tile, the same C[16V +
+// 4g + k][n] as B) give E and O for output columns j < 16, and then
+// T[.][j] = E + O and T[.][31 - j] = E - O; column 31 - j sits in lane
+// 15 - j of the other tile, so that half moves across the lane's 16-lane
+// row (DPP row_mirror).  16 MFMAs per pass instead of 32.  NB blocks per
+// wave step: all their loads are issued first.  The sums run in a fixed
+// order, so every call gives the same pixels.
 template <int N, int NB, bool COUNT>
 __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y, int64_t B, uint8_t *pix,
                                                                   const uint8_t *expected,
@@ -525,27 +542,63 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify_mfma(const float *Y
         for (int b = 0; b < NB; ++b) {
             const int64_t blk = unit * NB + b;
             f32x4 t[NT][NT];   // tile (U, J) of T = Y C
+            f32x4 pt[NT][NT];  // tile (J, I) of P^t = T^t C
+            if constexpr (N == 32) {
 #pragma unroll
-            for (int U = 0; U < NT; ++U)
+                for (int U = 0; U < 2; ++U) {
+                    f32x4 e = f32x4{0.f, 0.f, 0.f, 0.f}, o = e;
 #pragma unroll
-                for (int J = 0; J < NT; ++J) {
-                    t[U][J] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    for (int V = 0; V < 2; ++V)
 #pragma unroll
-                    for (int V = 0; V < NT; ++V)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            t[U][J] = mfma_f32(y[b][U][V][k], cb[V][J][k], t[U][J]);
+                        for (int k = 0; k < 4; k += 2) {
+                            e = mfma_f32(y[b][U][V][k], cb[V][0][k], e);
+                            o = mfma_f32(y[b][U][V][k + 1], cb[V][0][k + 1], o);
+                        }
+                    t[U][0] = e + o;
+                    t[U][1] = row_mirror4(e - o);
                 }
+#pragma unroll
+                for (int J = 0; J < 2; ++J) {
+                    f32x4 e = f32x4{0.f, 0.f, 0.f, 0.f}, o = e;
+#pragma unroll
+                    for (int U = 0; U < 2; ++U)
+#pragma unroll
+                        for (int k = 0; k < 4; k += 2) {
+                            e = mfma_f32(t[U][J][k], cb[U][0][k], e);
+                            o = mfma_f32(t[U][J][k + 1], cb[U][0][k + 1], o);
+                        }
+                    pt[J][0] = e + o;
+                    pt[J][1] = row_mirror4(e - o);
+                }
+            } else {
+#pragma unroll
+                for (int U = 0; U < NT; ++U)
+#pragma unroll
+                    for (int J = 0; J < NT; ++J) {
+                        t[U][J] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int V = 0; V < NT; ++V)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                t[U][J] = mfma_f32(y[b][U][V][k], cb[V][J][k], t[U][J]);
+                    }
+#pragma unroll
+                for (int J = 0; J < NT; ++J)
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) {
+                        pt[J][I] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int U = 0; U < NT; ++U)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                pt[J][I] = mfma_f32(t[U][J][k], cb[U][I][k], pt[J][I]);
+                    }
+            }
 #pragma unroll
             for (int J = 0; J < NT; ++J)
 #pragma unroll
                 for (int I = 0; I < NT; ++I) {
-                    f32x4 p = f32x4{0.f, 0.f, 0.f, 0.f};   // tile (J, I) of P^t = T^t C
-#pragma unroll
-                    for (int U = 0; U < NT; ++U)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            p = mfma_f32(t[U][J][k], cb[U][I][k], p);
+                    const f32x4 p = pt[J][I];
                     if (blk >= B)
                         continue;
                     // P[16 I + n][16 J + 4g + r]: tile (I, J) of the block

@@ -155,7 +155,7 @@ def test_quantized_pixels_past_2_31(dctf, prec):
     assert_u8_exact(sample(pix, N, idx), oracle.dequantize(sample(qc, N, idx), q, dc), W, Z)
 
 
-@pytest.mark.parametrize("N,B", [(8, 2 ** 25 + 37), (16, 2 ** 23 + 5)])
+@pytest.mark.parametrize("N,B", [(8, 2 ** 25 + 37), (16, 2 ** 23 + 5), (32, 2 ** 21 + 3)])
 def test_verify_past_2_31(dctf, N, B):
     """Pixels of sampled blocks against the oracle; then an expected image
     that differs in chosen pixels (all past the 2^31 boundary, none in the

@@ -279,7 +279,7 @@ def test_forward_dct_strided_image(dctf, N, h, w, pad):
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
 
 
-@pytest.mark.parametrize("N", [2, 4, 8, 16])
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
 def test_verify_kernel_all_sizes_strided(dctf, N):
     """Every block size, with enough blocks that each workgroup walks several
     steps and a ragged last one, through byte buffers at odd and at aligned
