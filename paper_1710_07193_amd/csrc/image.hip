@@ -242,7 +242,8 @@ __global__ __launch_bounds__(LOPS ? 512 : 256) void k_filter_image8(ImageFilterA
     }
     const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
     // consecutive units (the same and adjacent block rows) run on one XCD
-    const int64_t wave = xcd_wave(LOPS ? 8 : 4);
+    // a scalar: the unit decode below (image, rectangle, tiles) runs on the scalar unit
+    const int64_t wave = __builtin_amdgcn_readfirstlane((int)xcd_wave(LOPS ? 8 : 4));
     if (wave >= waves)
         return;
     const int64_t per_img_blocks = (int64_t)a.Bh * a.Bw;
