@@ -112,6 +112,22 @@ def test_verify_and_forward_dct_validation(lib):
     assert lib.dctf_forward_dct_u8(None, 8, 8, 8, 8, None, None) == -1
 
 
+def test_forward_dct_binding_checks_the_image():
+    """The binding passes a row-pitched view's stride as the pitch, and refuses
+    host tensors, other dtypes, non-2-D images and rows that are not contiguous
+    before any library call."""
+    import torch
+
+    import paper_1710_07193_amd as dctf
+    X = torch.empty(64)
+    with pytest.raises(TypeError):
+        dctf.dctf_forward_dct_u8(torch.zeros(8, 8, dtype=torch.uint8), 8, X)   # host tensor
+    with pytest.raises(TypeError):
+        dctf.dctf_forward_dct_u8(torch.zeros(8, 8), 8, X)                     # float32 image
+    with pytest.raises(TypeError):
+        dctf.dctf_forward_dct_u8(None, 8, X)
+
+
 def test_variant_table(lib):
     import paper_1710_07193_amd as dctf
     for N in (2, 4, 8, 16):

@@ -237,6 +237,17 @@ def test_forward_dct_matches_oracle(dctf, N):
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
 
 
+def test_forward_dct_rejects_unusable_views(dctf):
+    img = dev(syn.image_u8(5, 64, 48))
+    X = torch.empty(64 * 48, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        dctf.dctf_forward_dct_u8(img.t(), 8, X)          # columns as rows: not contiguous
+    with pytest.raises(ValueError):
+        dctf.dctf_forward_dct_u8(img.reshape(-1), 8, X)  # not 2-D
+    with pytest.raises(ValueError):
+        dctf.dctf_forward_dct_u8(img, 8, X[:64])          # wrong coefficient count
+
+
 def test_forward_dct_large_image(dctf):
     """An image large enough for the N = 8 forward DCT's long-step launch
     (6144 x 6144: 147,456 units of 2 x 2 blocks), every block against the
