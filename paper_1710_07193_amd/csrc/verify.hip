@@ -166,14 +166,19 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
         else
             return sC[a * N + b];
     };
-    double c1[NT][NT][4], c2[NT][NT][4];   // c1[J][V][s], c2[I][U][r]
+    // c1[J][V][s] (N = 32: c1[0][P][s] = C[2 sigma(n) + P][4g + s], the even / odd
+    // halves of pass 1), c2[I][U][r]
+    double c1[NT][NT][4], c2[NT][NT][4];
 #pragma unroll
     for (int P = 0; P < NT; ++P)
 #pragma unroll
         for (int Q = 0; Q < NT; ++Q)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                c1[P][Q][k] = cval(16 * Q + sn, 16 * P + 4 * g + k);
+                if constexpr (N == 32)
+                    c1[P][Q][k] = cval(2 * sn + Q, 4 * g + k);
+                else
+                    c1[P][Q][k] = cval(16 * Q + sn, 16 * P + 4 * g + k);
                 c2[P][Q][k] = cval(16 * Q + n, 16 * P + g + 4 * k);
             }
     // the wave index as a scalar: the unit bookkeeping below runs on the scalar unit
@@ -186,7 +191,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
     for (int P = 0; P < NT; ++P)
 #pragma unroll
         for (int Q = 0; Q < NT; ++Q) {
-            loff[P][Q] = (int64_t)(16 * P + n) * pitch + 16 * Q + 4 * g;
+            // N = 32: word Q = 1 holds the mirror columns 28 - 4g .. 31 - 4g
+            loff[P][Q] = (int64_t)(16 * P + n) * pitch + (N == 32 && Q == 1 ? 28 - 4 * g : 16 * Q + 4 * g);
             if constexpr (N == 8)
                 soff[P][Q] = ((n >> 3) * bw + (g >> 1)) * 64 + (n & 7) * 8 + 4 * (g & 1);
             else
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
                             uint32_t v = 0;
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
-                                int64_t col = lx * S + 16 * J + 4 * g + k;
+                                int64_t col = lx * S + (N == 32 && J == 1 ? 28 - 4 * g : 16 * J + 4 * g) + k;
                                 col = col < w ? col : w - 1;
                                 v |= (uint32_t)img[row * pitch + col] << (8 * k);
                             }
@@ -243,36 +249,74 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
                 ux = 0;
                 ++uy;
             }
-            f64x4v t[NT][NT];   // t[I][V]
+            f64x4v t[NT][NT];   // t[I][V]; N = 32: t[I][P], columns v = 2 sigma(n) + P
+            if constexpr (N == 32) {
+                // x[j] + x[31 - j] and x[j] - x[31 - j] for j = 4g + s < 16 (exact integers)
 #pragma unroll
-            for (int I = 0; I < NT; ++I)
+                for (int I = 0; I < 2; ++I) {
+                    t[I][0] = f64x4v{0.0, 0.0, 0.0, 0.0};
+                    t[I][1] = t[I][0];
 #pragma unroll
-                for (int V = 0; V < NT; ++V) {
-                    t[I][V] = f64x4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int J = 0; J < NT; ++J)
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            t[I][V] = mfma_f64x4((double)((px[b][I][J] >> (8 * k)) & 0xffu), c1[J][V][k], t[I][V]);
+                    for (int k = 0; k < 4; ++k) {
+                        const int xa = (int)((px[b][I][0] >> (8 * k)) & 0xffu);
+                        const int xm = (int)((px[b][I][1] >> (8 * (3 - k))) & 0xffu);
+                        t[I][0] = mfma_f64x4((double)(xa + xm), c1[0][0][k], t[I][0]);
+                        t[I][1] = mfma_f64x4((double)(xa - xm), c1[0][1][k], t[I][1]);
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int I = 0; I < NT; ++I)
+#pragma unroll
+                    for (int V = 0; V < NT; ++V) {
+                        t[I][V] = f64x4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int J = 0; J < NT; ++J)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                t[I][V] = mfma_f64x4((double)((px[b][I][J] >> (8 * k)) & 0xffu), c1[J][V][k],
+                                                     t[I][V]);
+                    }
+            }
             if (!live)
                 continue;
             float *out = coeffs + (N == 8 ? (2 * cy * bw + 2 * cx) * 64 : (cy * bw + cx) * (N * N));
             const bool mine = N != 8 || (2 * cy + (n >> 3) < bh && 2 * cx + (g >> 1) < bw);
+            if constexpr (N == 32) {
 #pragma unroll
-            for (int V = 0; V < NT; ++V)
+                for (int U = 0; U < 2; ++U) {
+                    f64x4v p[2];   // p[P]: X[16 U + n][8g + 2r + P]
 #pragma unroll
-                for (int U = 0; U < NT; ++U) {
-                    f64x4v p = f64x4v{0.0, 0.0, 0.0, 0.0};   // X[16 U + n][16 V + 4g + r]
+                    for (int P = 0; P < 2; ++P) {
+                        p[P] = f64x4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int I = 0; I < NT; ++I)
+                        for (int I = 0; I < 2; ++I)
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            p = mfma_f64x4(t[I][V][k], c2[I][U][k], p);
-                    if (mine)
-                        *reinterpret_cast<float4 *>(out + soff[U][V]) =
-                            make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+                            for (int k = 0; k < 4; ++k)
+                                p[P] = mfma_f64x4(t[I][P][k], c2[I][U][k], p[P]);
+                    }
+                    float *dst = out + (16 * U + n) * 32 + 8 * g;
+                    *reinterpret_cast<float4 *>(dst) =
+                        make_float4((float)p[0][0], (float)p[1][0], (float)p[0][1], (float)p[1][1]);
+                    *reinterpret_cast<float4 *>(dst + 4) =
+                        make_float4((float)p[0][2], (float)p[1][2], (float)p[0][3], (float)p[1][3]);
                 }
+            } else {
+#pragma unroll
+                for (int V = 0; V < NT; ++V)
+#pragma unroll
+                    for (int U = 0; U < NT; ++U) {
+                        f64x4v p = f64x4v{0.0, 0.0, 0.0, 0.0};   // X[16 U + n][16 V + 4g + r]
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                p = mfma_f64x4(t[I][V][k], c2[I][U][k], p);
+                        if (mine)
+                            *reinterpret_cast<float4 *>(out + soff[U][V]) =
+                                make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+                    }
+            }
         }
     }
 }
