@@ -79,16 +79,17 @@ __device__ __forceinline__ uint32_t pixel_u8(float p)
 }
 
 // Four pixels -> one little-endian word (first pixel in the low byte), the
-// rule of pixel_u8 for finite values: floor(p + 1/2) clamped to [0, 255] by
-// v_med3_f32 is an exact integer in range, which v_cvt_pk_u8_f32 converts
-// exactly and packs into its byte.
+// rule of pixel_u8 for finite values: floor(p + 1/2) is an exact integer,
+// which v_cvt_pk_u8_f32 converts exactly, saturating to [0, 255] by itself
+// (measured on gfx950: 256, 300, 1e9 and +inf give 255; -0.5, -300 and -inf
+// give 0; NaN gives 0), and packs into its byte.
 __device__ __forceinline__ uint32_t pack_u8x4(float a, float b, float c, float d)
 {
     const float v[4] = {a, b, c, d};
     uint32_t w = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(floorf(v[k] + 0.5f), 0.0f, 255.0f), k, w);
+        w = __builtin_amdgcn_cvt_pk_u8_f32(floorf(v[k] + 0.5f), k, w);
     return w;
 }
 
