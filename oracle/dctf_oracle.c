@@ -27,10 +27,10 @@
  *     back to the spatial domain, Sec. III);
  *   - the image-level variant: the whole image filtered across block
  *     boundaries (only the image border padded), then cut into blocks again;
- *   - the uint8 conversion of a filtered pixel (Sec. III): saturate to
- *     [0, 255] after rounding half up, the decision taken in FP32 (the
- *     precision the GPU verify kernel decides in); pixels whose FP64 value
- *     lies within 1e-3 of a .5 boundary are flagged.
+ *   - the uint8 conversion of a filtered pixel (Sec. III): the FP64
+ *     filtered value rounded half up and saturated to [0, 255]; pixels whose
+ *     FP64 value lies within 1e-3 of a .5 boundary are flagged (either
+ *     neighbouring integer is accepted for them).
  *
  * Loops over independent blocks carry an OpenMP pragma; nothing else is
  * blocked, fused or reordered.
@@ -136,13 +136,13 @@ static void filter_block(int N, const double *x, const double *W, int kh, int kw
         }
 }
 
-/* Sec. III uint8 conversion, decided in FP32. */
+/* Sec. III uint8 conversion of the FP64 filtered value. */
 static uint8_t to_u8(double f)
 {
-    float v = floorf((float)f + 0.5f);
-    if (!(v > 0.0f))
+    double v = floor(f + 0.5);
+    if (!(v > 0.0))
         return 0;
-    if (v > 255.0f)
+    if (v > 255.0)
         return 255;
     return (uint8_t)v;
 }

@@ -367,8 +367,10 @@ def test_paper_symmetric_shortcut_eq12():
 
 def test_u8_rounding_rule():
     # one pixel per case through the identity mask, read back through the rule
-    vals = np.array([2.5, 2.4999, -0.5, -3.0, 255.49, 255.5, 300.0, 0.49, 127.5])
-    want = np.array([3, 2, 0, 0, 255, 255, 255, 0, 128], np.uint8)
+    # (Sec. III: the floating filtered value, rounded half up and saturated).
+    # 2.5 - 2e-8 is decided in FP64: an FP32 rounding of it would be 2.5 -> 3.
+    vals = np.array([2.5, 2.4999, -0.5, -3.0, 255.49, 255.5, 300.0, 0.49, 127.5, 2.5 - 2e-8])
+    want = np.array([3, 2, 0, 0, 255, 255, 255, 0, 128, 2], np.uint8)
     N = 2
     Y = np.zeros((len(vals), N, N))
     # a constant block of value v has DC = N * v and no AC
