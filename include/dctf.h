@@ -70,6 +70,24 @@ typedef enum {
 typedef void *dctf_stream;                 /* hipStream_t */
 typedef struct dctf_operator_s *dctf_operator;
 typedef struct dctf_batch_s *dctf_batch;
+
+/* Launch configuration of a batch plan (results are bit-identical for every
+ * configuration; only the time differs).
+ *   fronts        : sweep fronts of the N = 8 work (see dctf_set_batch_fronts);
+ *                   -1 = the process-wide fronts setting
+ *   io, nt        : N = 8 tile I/O path: 0 registers in the MFMA layout,
+ *                   1 coalesced 1 KiB accesses staged through LDS, 2 coalesced
+ *                   loads written straight into LDS (buffer loads to LDS);
+ *                   nt = 1 adds the nontemporal hint; io = -1 takes the path
+ *                   of the current N = 8 variant (dctf_set_variant)
+ *   groups_per_cu : persistent workgroups per CU, 1..64; 0 = as many as the
+ *                   kernel's registers and LDS allow (more are never used) */
+typedef struct {
+    int fronts;
+    int io;
+    int nt;
+    int groups_per_cu;
+} dctf_batch_config;
 typedef struct dctf_image_operator_s *dctf_image_operator;
 
 /* Supported block sizes N: 2, 4, 8, 16, and 32 for the operator build, its
@@ -393,8 +411,14 @@ dctf_status dctf_stream_copy(const float *in_dev, float *out_dev, int64_t n, dct
  * tiles of loads run ahead of the MFMA work (N = 16).  Variant 0 is the
  * default.  Every variant computes bit-identical results.  dctf_autotune times each variant on the
  * caller's buffers (in_dev/out_dev, B blocks, operator op) with HIP events
- * and selects the fastest for subsequent calls; the choice can be read and
- * set explicitly so that a table persisted by the caller can be re-applied.
+ * (32 warm-up launches, then three passes of `iters` launches per variant,
+ * each variant's best pass kept) and selects the fastest for subsequent
+ * calls; the choice can be read and set explicitly so that a table persisted
+ * by the caller can be re-applied (paper_1710_07193_amd/tuning.py keeps one).
+ * N = 8 variants: lds_* stage coalesced loads through LDS in registers,
+ * dma_* load them straight into LDS, u<k>_w<w> are registers in the MFMA
+ * layout; u = tiles per step, w = waves per CU of the persistent grid,
+ * _nt = nontemporal loads and stores.
  */
 int dctf_variant_count(int N, int prec);
 const char *dctf_variant_name(int N, int prec, int variant);
@@ -418,19 +442,59 @@ dctf_status dctf_autotune(dctf_operator op, int prec, const float *in_dev, float
                           int64_t B, int iters, dctf_stream stream, int *best_variant,
                           float *best_ms);
 
+/*
+ * Batch configuration.  New plans of precision `prec` take the process-wide
+ * configuration (initially {-1, -1, 0, 0}); an existing plan can be re-planned
+ * with another one (its work table is rebuilt after the device has finished
+ * the plan's launches, a captured graph is dropped: capture again).
+ * dctf_batch_get_config returns the configuration the plan was made with
+ * and/or what it resolved to (I/O path, number of N = 8 fronts actually cut,
+ * workgroups per CU of its grid).  Errors: DCTF_EINVAL for a field outside
+ * the ranges above.
+ */
+dctf_status dctf_set_batch_config(int prec, const dctf_batch_config *cfg);
+dctf_status dctf_get_batch_config(int prec, dctf_batch_config *cfg);
+dctf_status dctf_batch_set_config(dctf_batch batch, const dctf_batch_config *cfg);
+dctf_status dctf_batch_get_config(dctf_batch batch, dctf_batch_config *cfg, dctf_batch_config *resolved);
+
+/*
+ * Batch autotuner.  Times each candidate configuration on the plan itself
+ * (its own jobs and buffers, so the outputs are overwritten with identical
+ * results): after 64 warm-up launches of the current plan, `rounds` passes
+ * over all candidates, each pass re-planning the batch and timing `iters`
+ * launches (flags as dctf_batch_run) after 2 untimed ones with HIP events on
+ * `stream`; a candidate's time is its best pass.  The plan is left with the
+ * fastest candidate; *best is its index and ms_out[i] (ncand entries, or as
+ * many as the built-in list holds) the time per launch of candidate i (-1 if
+ * skipped).  candidates = NULL, ncand = 0: the built-in list, which
+ * dctf_batch_autotune_candidates copies out (returns its length; max = 0 just
+ * counts): every I/O path x fronts {1, 2, 3, 4, 6, 8} x the largest grid or
+ * one workgroup per CU fewer (groups_per_cu = -1 in the list; skipped when
+ * the largest grid has one workgroup per CU).  Synchronous.
+ * Errors: DCTF_EINVAL (bad arguments or candidate), DCTF_EHIP.
+ */
+dctf_status dctf_batch_autotune(dctf_batch batch, unsigned flags, int iters, int rounds,
+                                const dctf_batch_config *candidates, int ncand, dctf_stream stream,
+                                float *ms_out, int *best);
+int dctf_batch_autotune_candidates(dctf_batch_config *out, int max);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
  * Continuous-batching server (not part of the paper's method: the serving
- * layer around it).  dctf_server_run replays requests in real time on the
- * calling thread: a request is admitted, in arrival order, once its output
- * fits in the server's device arena (the HBM budget) and a launch slot is
- * free; the requests admitted together form one batch (one persistent launch,
- * operators from a device cache keyed by mask bytes, kh, kw, N and border,
- * LRU eviction); up to max_inflight batches run at once on their own streams,
- * so requests that arrive while others are on the GPU overlap with them.
- * Each request's result equals, bit for bit, a dctf_filter_blocks call with
- * the same operator and precision.
+ * layer around it).  Requests are filter jobs of any size, block size (8 or
+ * 16) and mask.  A submitted request waits in a queue; each poll reaps the
+ * batches that have finished and admits queued requests, in submission order,
+ * once a request's output fits in the server's device arena (the HBM budget)
+ * and a launch slot is free.  The requests admitted together form one batch
+ * (one persistent launch, operators from a device cache keyed by mask bytes,
+ * kh, kw, N and border, LRU eviction); up to max_inflight batches run at once
+ * on their own streams, so requests that arrive while others are on the GPU
+ * overlap with them.  Each request's result equals, bit for bit, a
+ * dctf_filter_blocks call with the same operator and precision.
+ *
+ * Threading: one server is driven from one host thread at a time (calls on
+ * the same server must not overlap); different servers are independent.
  */
 typedef struct dctf_server_s *dctf_server;
 
@@ -444,34 +508,62 @@ typedef struct {
 
 typedef struct {
     /* set by the caller */
-    double arrival_s;          /* seconds after the start of the run; non-decreasing */
-    const double *mask_host;   /* kh*kw doubles (host) */
-    int kh, kw, N, border;     /* N = 8 or 16 */
-    const float *in_dev;       /* B*N*N coefficients, device-resident, 16-byte aligned */
+    double arrival_s;          /* dctf_server_run: arrival time, seconds after the start of the run,
+                                  non-decreasing; not read by dctf_server_submit */
+    const double *mask_host;   /* kh*kw doubles (host), all finite; copied at submission */
+    int kh, kw, N, border;     /* N = 8 or 16; 1 <= kh, kw <= 2N+1 */
+    const float *in_dev;       /* B*N*N coefficients, device-resident, 16-byte aligned; must stay
+                                  valid and unchanged until the request completes */
     int64_t B;                 /* >= 1 */
     float *out_dev;            /* NULL: the output is written to the arena and dropped at
                                   completion; else also copied here (device, 16-byte aligned)
                                   before the request completes */
-    /* set by dctf_server_run (seconds after the start; -1 if never reached) */
+    /* set by the server, on its clock (dctf_server_clock; -1 if never reached) */
     double admit_s, launch_s, done_s;
-    int status;                /* DCTF_OK, or DCTF_EBUSY: the output alone exceeds the arena */
-    int batch;                 /* index of the launch that carried it */
+    int status;                /* DCTF_OK; DCTF_EBUSY: the output alone exceeds the arena;
+                                  DCTF_ENOMEM / DCTF_EHIP: its operator could not be built, or the
+                                  device failed while it was in flight */
+    int batch;                 /* index of the launch that carried it, -1 if none */
 } dctf_request;
 
 typedef struct {
     int64_t batches, cache_hits, cache_misses, cache_evictions;
     int64_t peak_arena_bytes, peak_inflight_batches, rejected;
+    int64_t failed;            /* requests completed with an error other than DCTF_EBUSY */
     double busy_s;             /* wall time spent in dctf_server_run */
 } dctf_server_stats;
 
 /* Errors: DCTF_EINVAL (bad config), DCTF_ENOMEM (arena), DCTF_EHIP. */
 dctf_status dctf_server_create(const dctf_server_config *cfg, dctf_server *out);
-/* Runs until every request has completed or been rejected.  Returns
- * DCTF_EINVAL for a malformed request list (nothing runs), DCTF_EHIP on a
- * device error (in-flight work is drained first). */
+
+/* Seconds on the server's clock: since creation, or since the start of the
+ * last dctf_server_run.  -1 for a NULL server. */
+double dctf_server_clock(dctf_server s);
+
+/* Online interface.  Queues one request; nothing is launched until the next
+ * poll.  The server keeps `req` (the caller's record: it must stay valid and
+ * is written by the server) until a poll returns it.  Returns DCTF_EINVAL for
+ * a malformed request (bad N, mask shape or non-finite mask entry, border,
+ * NULL or unaligned pointer, B < 1); then nothing is queued. */
+dctf_status dctf_server_submit(dctf_server s, dctf_request *req);
+/* Makes progress: reaps finished batches, admits and launches queued
+ * requests, and returns up to max_done completed requests in `done` (in
+ * completion order; *n_done = their count).  If none has completed, it keeps
+ * polling for up to wait_s seconds (0: return at once).  Completed requests
+ * carry their status; DCTF_EHIP is also returned when the device failed. */
+dctf_status dctf_server_poll(dctf_server s, double wait_s, dctf_request **done, int max_done, int *n_done);
+
+/* Replays a request list with known arrival times in real time on the
+ * calling thread (submitting each request at its arrival time and polling)
+ * until every request has completed.  Returns DCTF_EINVAL for a malformed list
+ * (any request invalid as for dctf_server_submit, or arrival times not
+ * non-decreasing and >= 0): nothing runs.  DCTF_EBUSY if requests submitted
+ * through the online interface are still in the server.  DCTF_EHIP on a
+ * device error (requests not yet run then complete with that status). */
 dctf_status dctf_server_run(dctf_server s, dctf_request *reqs, int n);
 dctf_status dctf_server_stats_get(dctf_server s, dctf_server_stats *out);
-/* Waits for the server's streams, then frees everything it owns. */
+/* Waits for the server's streams, then frees everything it owns; requests
+ * still queued are dropped. */
 void dctf_server_destroy(dctf_server s);
 
 /* ------------------------------------------------------------------ misc */

@@ -40,6 +40,10 @@ class _Job(ctypes.Structure):
     _fields_ = [("op", _P), ("in_", _P), ("out", _P), ("B", _I64)]
 
 
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("fronts", _I), ("io", _I), ("nt", _I), ("groups_per_cu", _I)]
+
+
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("arena_bytes", _I64), ("max_inflight", _I), ("max_batch_jobs", _I),
                 ("max_cached_ops", _I), ("prec", _I)]
@@ -54,7 +58,7 @@ class _Request(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("batches", _I64), ("cache_hits", _I64), ("cache_misses", _I64), ("cache_evictions", _I64),
                 ("peak_arena_bytes", _I64), ("peak_inflight_batches", _I64), ("rejected", _I64),
-                ("busy_s", ctypes.c_double)]
+                ("failed", _I64), ("busy_s", ctypes.c_double)]
 
 
 _SIGS = {
@@ -92,9 +96,19 @@ _SIGS = {
     "dctf_set_variant": ([_I, _I, _I], _I),
     "dctf_autotune": ([_P, _I, _P, _P, _I64, _I, _P, _P, _P], _I),
     "dctf_set_batch_fronts": ([_I], _I),
+    "dctf_set_batch_config": ([_I, ctypes.POINTER(_BatchConfig)], _I),
+    "dctf_get_batch_config": ([_I, ctypes.POINTER(_BatchConfig)], _I),
+    "dctf_batch_set_config": ([_P, ctypes.POINTER(_BatchConfig)], _I),
+    "dctf_batch_get_config": ([_P, ctypes.POINTER(_BatchConfig), ctypes.POINTER(_BatchConfig)], _I),
+    "dctf_batch_autotune": ([_P, ctypes.c_uint, _I, _I, ctypes.POINTER(_BatchConfig), _I, _P,
+                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_I)], _I),
+    "dctf_batch_autotune_candidates": ([ctypes.POINTER(_BatchConfig), _I], _I),
     "dctf_get_batch_fronts": ([], _I),
     "dctf_server_create": ([ctypes.POINTER(_ServerConfig), ctypes.POINTER(_P)], _I),
     "dctf_server_run": ([_P, ctypes.POINTER(_Request), _I], _I),
+    "dctf_server_submit": ([_P, ctypes.POINTER(_Request)], _I),
+    "dctf_server_poll": ([_P, ctypes.c_double, ctypes.POINTER(ctypes.POINTER(_Request)), _I, ctypes.POINTER(_I)], _I),
+    "dctf_server_clock": ([_P], ctypes.c_double),
     "dctf_server_stats_get": ([_P, ctypes.POINTER(_ServerStats)], _I),
     "dctf_server_destroy": ([_P], None),
     "dctf_status_string": ([_I], ctypes.c_char_p),
@@ -493,11 +507,72 @@ def dctf_get_batch_fronts() -> int:
     return int(_lib.dctf_get_batch_fronts())
 
 
+BATCH_CONFIG_FIELDS = ("fronts", "io", "nt", "groups_per_cu")
+
+
+def _cfg_struct(cfg) -> _BatchConfig:
+    return _BatchConfig(*(int(cfg[k]) for k in BATCH_CONFIG_FIELDS))
+
+
+def _cfg_dict(c: _BatchConfig) -> dict:
+    return {k: int(getattr(c, k)) for k in BATCH_CONFIG_FIELDS}
+
+
+def dctf_set_batch_config(prec: int, cfg: dict):
+    """Process-wide configuration new batch plans of `prec` take (dict with
+    fronts, io, nt, groups_per_cu)."""
+    c = _cfg_struct(cfg)
+    _check(_lib.dctf_set_batch_config(prec, ctypes.byref(c)), "dctf_set_batch_config")
+
+
+def dctf_get_batch_config(prec: int) -> dict:
+    c = _BatchConfig()
+    _check(_lib.dctf_get_batch_config(prec, ctypes.byref(c)), "dctf_get_batch_config")
+    return _cfg_dict(c)
+
+
+def dctf_batch_set_config(batch: Batch, cfg: dict):
+    c = _cfg_struct(cfg)
+    _check(_lib.dctf_batch_set_config(batch, ctypes.byref(c)), "dctf_batch_set_config")
+
+
+def dctf_batch_get_config(batch: Batch):
+    """(configuration the plan was made with, what it resolved to)."""
+    c, r = _BatchConfig(), _BatchConfig()
+    _check(_lib.dctf_batch_get_config(batch, ctypes.byref(c), ctypes.byref(r)), "dctf_batch_get_config")
+    return _cfg_dict(c), _cfg_dict(r)
+
+
+def dctf_batch_autotune_candidates() -> list:
+    n = int(_lib.dctf_batch_autotune_candidates(None, 0))
+    arr = (_BatchConfig * n)()
+    _lib.dctf_batch_autotune_candidates(arr, n)
+    return [_cfg_dict(arr[i]) for i in range(n)]
+
+
+def dctf_batch_autotune(batch: Batch, flags: int = 0, iters: int = 10, rounds: int = 3, candidates=None,
+                        stream=None):
+    """Times each candidate configuration on the plan and leaves it with the
+    fastest.  Returns (index of the best, list of (candidate, ms per launch or
+    -1 when skipped))."""
+    cands = list(candidates) if candidates is not None else dctf_batch_autotune_candidates()
+    arr = (_BatchConfig * max(len(cands), 1))(*[_cfg_struct(c) for c in cands])
+    ms = (ctypes.c_float * max(len(cands), 1))()
+    best = _I(-1)
+    _check(_lib.dctf_batch_autotune(batch, flags, iters, rounds, arr if candidates is not None else None,
+                                    len(cands) if candidates is not None else 0, _stream(stream), ms,
+                                    ctypes.byref(best)), "dctf_batch_autotune")
+    return best.value, [(c, float(ms[i])) for i, c in enumerate(cands)]
+
+
 class Server:
-    """Owning handle of a continuous-batching server."""
+    """Owning handle of a continuous-batching server.  Requests submitted
+    through the online interface are kept here (their records, masks and
+    tensors) until a poll hands them back."""
 
     def __init__(self, handle: int):
         self.handle = handle
+        self.live = {}
 
     @property
     def _as_parameter_(self):
@@ -507,12 +582,62 @@ class Server:
         if self.handle:
             _lib.dctf_server_destroy(_P(self.handle))
             self.handle = 0
+            self.live.clear()
 
     def __del__(self):
         try:
             self.destroy()
         except Exception:
             pass
+
+
+class ServerRequest:
+    """One request of the online interface (its record is written by the
+    server: admit_s, launch_s, done_s on the server clock, status, batch)."""
+
+    def __init__(self, rec, keep):
+        self.rec = rec
+        self.keep = keep
+
+    def __getattr__(self, name):
+        if name in ("admit_s", "launch_s", "done_s", "status", "batch", "arrival_s", "B", "N"):
+            return getattr(self.rec, name)
+        raise AttributeError(name)
+
+
+def _request(mask, N, border, X, Y, arrival_s, what):
+    m = _mask_array(mask)
+    if X.numel() % (N * N) or X.numel() == 0:
+        raise ValueError("%s: X must hold a whole, positive number of N*N blocks" % what)
+    if Y is not None and Y.numel() != X.numel():
+        raise ValueError("%s: Y has the wrong size" % what)
+    rec = _Request(arrival_s, m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, border,
+                   _dptr(X, torch.float32, "X"), X.numel() // (N * N), _dptr(Y, torch.float32, "Y"),
+                   -1.0, -1.0, -1.0, 0, -1)
+    return rec, m
+
+
+def dctf_server_submit(server: Server, mask, N: int, border: int, X: torch.Tensor, Y=None,
+                       arrival_s: float = -1.0) -> ServerRequest:
+    """Queue one request (online interface).  X (and Y, if given) are device
+    float32 tensors of B*N*N elements; they are kept alive with the request."""
+    rec, m = _request(mask, N, border, X, Y, arrival_s, "request")
+    _check(_lib.dctf_server_submit(server, ctypes.byref(rec)), "dctf_server_submit")
+    req = ServerRequest(rec, (m, X, Y))
+    server.live[ctypes.addressof(rec)] = req
+    return req
+
+
+def dctf_server_poll(server: Server, wait_s: float = 0.0, max_done: int = 64) -> list:
+    """Progress the server; the requests that completed (at most max_done)."""
+    arr = (ctypes.POINTER(_Request) * max(max_done, 1))()
+    n = _I()
+    _check(_lib.dctf_server_poll(server, float(wait_s), arr, int(max_done), ctypes.byref(n)), "dctf_server_poll")
+    return [server.live.pop(ctypes.addressof(arr[i].contents)) for i in range(n.value)]
+
+
+def dctf_server_clock(server: Server) -> float:
+    return float(_lib.dctf_server_clock(server))
 
 
 def dctf_server_create(arena_bytes: int, max_inflight: int = 4, max_batch_jobs: int = 64,
@@ -531,18 +656,8 @@ def dctf_server_run(server: Server, requests):
     arr = (_Request * max(len(requests), 1))()
     keep = []
     for i, r in enumerate(requests):
-        m = _mask_array(r["mask"])
+        arr[i], m = _request(r["mask"], r["N"], r["border"], r["X"], r.get("Y"), r["arrival_s"], "request %d" % i)
         keep.append(m)
-        N = r["N"]
-        X = r["X"]
-        Y = r.get("Y")
-        if X.numel() % (N * N) or X.numel() == 0:
-            raise ValueError("request %d: X must hold a whole, positive number of N*N blocks" % i)
-        if Y is not None and Y.numel() != X.numel():
-            raise ValueError("request %d: Y has the wrong size" % i)
-        arr[i] = _Request(r["arrival_s"], m.ctypes.data_as(_P), m.shape[0], m.shape[1], N, r["border"],
-                          _dptr(X, torch.float32, "X"), X.numel() // (N * N), _dptr(Y, torch.float32, "Y"),
-                          -1.0, -1.0, -1.0, 0, -1)
     _check(_lib.dctf_server_run(server, arr, len(requests)), "dctf_server_run")
     return [dict(admit_s=arr[i].admit_s, launch_s=arr[i].launch_s, done_s=arr[i].done_s,
                  status=arr[i].status, batch=arr[i].batch) for i in range(len(requests))]

@@ -24,6 +24,11 @@ std::atomic<int> g_cu[kMaxDevices];
 std::mutex g_variant_mu;
 int g_variant[17][2];   // [N][prec]; zero-initialised = default variant 0
 std::atomic<int> g_batch_fronts{-1};   // -1: the default of each precision
+std::mutex g_batch_cfg_mu;
+// Process-wide batch configuration per precision ([prec]); -1 / 0 fields:
+// fronts from dctf_set_batch_fronts (or the precision's default), I/O path
+// of the current N = 8 variant, as many workgroups per CU as fit.
+dctf_batch_config g_batch_cfg[2] = {{-1, -1, 0, 0}, {-1, -1, 0, 0}};
 
 // Block sizes of the kernels around the filter (forward DCT, verify,
 // tuning) and of every operator path but the N = 32 dense filter.
@@ -117,6 +122,12 @@ static int plan_fronts(int prec)
     return f >= 0 ? f : (prec == DCTF_PREC_FP32 ? 4 : 2);
 }
 void set_batch_fronts(int fronts) { g_batch_fronts.store(fronts); }
+
+dctf_batch_config batch_config(int prec)
+{
+    std::lock_guard<std::mutex> lk(g_batch_cfg_mu);
+    return g_batch_cfg[prec == DCTF_PREC_FP32 ? 0 : 1];
+}
 
 }  // namespace dctf
 
@@ -759,8 +770,11 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
 
 struct dctf_batch_s {
     int prec = 0;
+    std::vector<dctf_job> jobs;       // the caller's jobs (kept for re-planning)
+    dctf_batch_config cfg{};          // configuration of the current plan
     std::vector<dctf_operator> ops;   // distinct operators, in table order
     void *dev = nullptr;              // JobDesc[njobs8] | JobDesc[njobs16] | OpDesc[nops]
+    size_t dev_bytes = 0;
     BatchArgs args{};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -800,8 +814,8 @@ bool jobs_conflict(const dctf_job *jobs, int n)
 
 namespace dctf {
 
-dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<char> &table, BatchArgs &a,
-                       std::vector<dctf_operator> &ops)
+dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_batch_config &cfg,
+                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops)
 {
     if (njobs < 0 || (njobs > 0 && jobs == nullptr))
         return DCTF_EINVAL;
@@ -866,14 +880,21 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<ch
 
     a = BatchArgs{};
     a.prec = prec;
-    variant_io(8, prec, current_variant(8, prec), &a.io, &a.nt);
+    if (cfg.io >= 0) {
+        a.io = cfg.io;
+        a.nt = cfg.nt != 0;
+    } else {
+        variant_io(8, prec, current_variant(8, prec), &a.io, &a.nt);
+    }
 
     // One block size: a kernel holding only that worker, one persistent
     // grid.  Both: the combined kernel, its grid split in proportion to the
     // estimated time (bytes for the HBM-bound cases, MFMA work for N = 16 in
     // FP32).
     const int kind = (u16 == 0) ? 8 : (u8 == 0 ? 16 : 0);
-    const int occ = std::max(1, batch_occupancy(prec, a.io, a.nt, kind));
+    int occ = std::max(1, batch_occupancy(prec, a.io, a.nt, kind));
+    if (cfg.groups_per_cu > 0)
+        occ = std::min(occ, cfg.groups_per_cu);
     const int G = std::max(1, cu_count() * occ);
     const int wpg8 = (kind == 8 ? kBatch8Threads : kBatchThreads) / 64;   // waves per N = 8 workgroup
     const double c16 = (prec == DCTF_PREC_FP32) ? 16.0 : 4.0;
@@ -930,7 +951,8 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<ch
         return segs;
     };
     const std::vector<SegDesc> s8 = j8.empty() ? std::vector<SegDesc>()
-                                               : cut(j8, u8, (int64_t)g8 * wpg8, plan_fronts(prec));
+                                               : cut(j8, u8, (int64_t)g8 * wpg8,
+                                                     cfg.fronts >= 0 ? cfg.fronts : plan_fronts(prec));
     const std::vector<SegDesc> s16 = j16.empty() ? std::vector<SegDesc>() : cut(j16, u16, g16, 0);
     const int64_t workers8 = s8.empty() ? 0 : s8.back().worker_begin + s8.back().nworkers;
     const int64_t workers16 = s16.empty() ? 0 : s16.back().worker_begin + s16.back().nworkers;
@@ -970,35 +992,122 @@ void rebase_batch(BatchArgs &a, const void *dev)
 
 }  // namespace dctf
 
-extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out)
+static bool batch_config_valid(const dctf_batch_config *c)
 {
-    if (out == nullptr)
-        return DCTF_EINVAL;
+    return c != nullptr && c->fronts >= -1 && c->fronts <= 4096 && c->io >= -1 && c->io <= 2 &&
+           (c->nt == 0 || c->nt == 1) && c->groups_per_cu >= 0 && c->groups_per_cu <= 64;
+}
+
+// Plans `b` with `cfg` and uploads its work table (the previous table and
+// any captured graph are released).
+static dctf_status batch_plan(dctf_batch b, const dctf_batch_config &cfg)
+{
     std::vector<char> table;
     BatchArgs a;
     std::vector<dctf_operator> ops;
-    dctf_status st = plan_batch(jobs, njobs, prec, table, a, ops);
+    dctf_status st = plan_batch(b->jobs.data(), (int)b->jobs.size(), b->prec, cfg, table, a, ops);
     if (st != DCTF_OK)
         return st;
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (b->dev) {
+        // A re-plan: launches of the previous plan may still read its table.
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
+    if (table.size() > b->dev_bytes) {
+        if (b->dev)
+            (void)hipFree(b->dev);
+        b->dev = nullptr;
+        b->dev_bytes = 0;
+        hipError_t e = hipMalloc(&b->dev, table.size());
+        if (e != hipSuccess) {
+            b->dev = nullptr;
+            return hip_status(e);
+        }
+        b->dev_bytes = table.size();
+    }
+    if (!table.empty()) {
+        hipError_t e = hipMemcpy(b->dev, table.data(), table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
+    rebase_batch(a, b->dev);
+    b->args = a;
+    b->ops = ops;
+    b->cfg = cfg;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_batch_create(const dctf_job *jobs, int njobs, int prec, dctf_batch *out)
+{
+    if (out == nullptr || njobs < 0 || (njobs > 0 && jobs == nullptr))
+        return DCTF_EINVAL;
     dctf_batch b = new (std::nothrow) dctf_batch_s();
     if (!b)
         return DCTF_ENOMEM;
     b->prec = prec;
-    b->ops = ops;
-    if (!table.empty()) {
-        hipError_t e = hipMalloc(&b->dev, table.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(b->dev, table.data(), table.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            if (b->dev)
-                (void)hipFree(b->dev);
-            delete b;
-            return hip_status(e);
-        }
+    try {
+        b->jobs.assign(jobs, jobs + njobs);
+    } catch (...) {
+        delete b;
+        return DCTF_ENOMEM;
     }
-    rebase_batch(a, b->dev);
-    b->args = a;
+    dctf_status st = batch_plan(b, batch_config(prec));
+    if (st != DCTF_OK) {
+        dctf_batch_destroy(b);
+        return st;
+    }
     *out = b;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_set_batch_config(int prec, const dctf_batch_config *cfg)
+{
+    if ((prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16) || !batch_config_valid(cfg))
+        return DCTF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_batch_cfg_mu);
+    g_batch_cfg[prec == DCTF_PREC_FP32 ? 0 : 1] = *cfg;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_get_batch_config(int prec, dctf_batch_config *cfg)
+{
+    if ((prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16) || cfg == nullptr)
+        return DCTF_EINVAL;
+    *cfg = batch_config(prec);
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_batch_set_config(dctf_batch b, const dctf_batch_config *cfg)
+{
+    if (b == nullptr || !batch_config_valid(cfg))
+        return DCTF_EINVAL;
+    return batch_plan(b, *cfg);
+}
+
+extern "C" dctf_status dctf_batch_get_config(dctf_batch b, dctf_batch_config *cfg, dctf_batch_config *resolved)
+{
+    if (b == nullptr || (cfg == nullptr && resolved == nullptr))
+        return DCTF_EINVAL;
+    if (cfg)
+        *cfg = b->cfg;
+    if (resolved) {
+        // What the plan runs: its N = 8 I/O path, the number of N = 8 fronts
+        // it cut and its workgroups per CU.
+        resolved->io = b->args.io;
+        resolved->nt = b->args.nt ? 1 : 0;
+        resolved->fronts = b->args.nsegs8;
+        const int groups = b->args.groups8 + b->args.groups16;
+        resolved->groups_per_cu = groups > 0 ? (groups + cu_count() - 1) / cu_count() : 0;
+    }
     return DCTF_OK;
 }
 
@@ -1212,28 +1321,38 @@ extern "C" dctf_status dctf_autotune(dctf_operator op, int prec, const float *in
             hipEventDestroy(e0);
         return DCTF_EHIP;
     }
+    // Warm-up (the chip raises its clocks under a new load over tens of
+    // launches), then three passes over all variants, each variant's best
+    // pass kept, so that a clock drift over the sweep favours no variant.
+    for (int w = 0; w < 32 && st == DCTF_OK; ++w)
+        st = hip_status(launch_filter(op->N, prec, 0, a, s));
+    std::vector<float> t(nv, 0.0f);
+    for (int r = 0; r < 3 && st == DCTF_OK; ++r)
+        for (int v = 0; v < nv && st == DCTF_OK; ++v) {
+            for (int w = 0; w < 2 && st == DCTF_OK; ++w)
+                st = hip_status(launch_filter(op->N, prec, v, a, s));
+            if (st == DCTF_OK)
+                st = hip_status(hipEventRecord(e0, s));
+            for (int i = 0; i < iters && st == DCTF_OK; ++i)
+                st = hip_status(launch_filter(op->N, prec, v, a, s));
+            if (st == DCTF_OK)
+                st = hip_status(hipEventRecord(e1, s));
+            if (st == DCTF_OK)
+                st = hip_status(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            if (st == DCTF_OK)
+                st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+            ms /= iters;
+            if (st == DCTF_OK && (r == 0 || ms < t[v]))
+                t[v] = ms;
+        }
     int best = -1;
     float best_t = 0.0f;
-    for (int v = 0; v < nv && st == DCTF_OK; ++v) {
-        for (int w = 0; w < 2 && st == DCTF_OK; ++w)
-            st = hip_status(launch_filter(op->N, prec, v, a, s));
-        if (st == DCTF_OK)
-            st = hip_status(hipEventRecord(e0, s));
-        for (int i = 0; i < iters && st == DCTF_OK; ++i)
-            st = hip_status(launch_filter(op->N, prec, v, a, s));
-        if (st == DCTF_OK)
-            st = hip_status(hipEventRecord(e1, s));
-        if (st == DCTF_OK)
-            st = hip_status(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        if (st == DCTF_OK)
-            st = hip_status(hipEventElapsedTime(&ms, e0, e1));
-        ms /= iters;
-        if (st == DCTF_OK && (best < 0 || ms < best_t)) {
+    for (int v = 0; v < nv && st == DCTF_OK; ++v)
+        if (best < 0 || t[v] < best_t) {
             best = v;
-            best_t = ms;
+            best_t = t[v];
         }
-    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st != DCTF_OK)
@@ -1244,6 +1363,116 @@ extern "C" dctf_status dctf_autotune(dctf_operator op, int prec, const float *in
     if (best_ms)
         *best_ms = best_t;
     return DCTF_OK;
+}
+
+// Candidates of the batch tuner: every N = 8 I/O path (registers in the MFMA
+// layout, LDS-staged coalesced, loaded straight into LDS; with and without
+// the nontemporal hint where it applies) x fronts 1, 2, 3, 4, 6, 8 x the
+// largest grid or one workgroup per CU less.
+static std::vector<dctf_batch_config> batch_candidates()
+{
+    std::vector<dctf_batch_config> c;
+    const int io_nt[][2] = {{1, 1}, {2, 1}, {2, 0}, {1, 0}, {0, 0}};
+    const int fronts[] = {1, 2, 3, 4, 6, 8};
+    for (const auto &p : io_nt)
+        for (int f : fronts)
+            for (int g : {0, -1})
+                c.push_back({f, p[0], p[1], g});
+    return c;
+}
+
+extern "C" dctf_status dctf_batch_autotune(dctf_batch b, unsigned flags, int iters, int rounds,
+                                           const dctf_batch_config *candidates, int ncand, dctf_stream stream,
+                                           float *ms_out, int *best)
+{
+    if (b == nullptr || iters < 1 || rounds < 1 || ncand < 0 || (ncand > 0 && candidates == nullptr) ||
+        (flags & ~DCTF_RUN_REBUILD_OPERATORS))
+        return DCTF_EINVAL;
+    std::vector<dctf_batch_config> cand;
+    if (ncand > 0)
+        cand.assign(candidates, candidates + ncand);
+    else
+        cand = batch_candidates();
+    // groups_per_cu = -1 in the built-in list: one workgroup per CU fewer
+    // than the occupancy allows (skipped where that is 1).
+    std::vector<int> usable(cand.size(), 1);
+    for (size_t i = 0; i < cand.size(); ++i) {
+        if (!batch_config_valid(&cand[i]) && cand[i].groups_per_cu != -1)
+            return DCTF_EINVAL;
+        if (cand[i].groups_per_cu == -1) {
+            const dctf_batch_config probe = {cand[i].fronts, cand[i].io, cand[i].nt, 0};
+            dctf_status st = batch_plan(b, probe);
+            if (st != DCTF_OK)
+                return st;
+            const int groups = b->args.groups8 + b->args.groups16;
+            const int per_cu = (groups + cu_count() - 1) / cu_count();
+            cand[i].groups_per_cu = per_cu - 1;
+            usable[i] = per_cu > 1;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            hipEventDestroy(e0);
+        return DCTF_EHIP;
+    }
+    const dctf_batch_config orig = b->cfg;
+    std::vector<float> t(cand.size(), 0.0f);
+    dctf_status st = DCTF_OK;
+    // Warm-up: the chip raises its clocks under a new load over tens of
+    // launches; the first candidate would otherwise run in that phase.
+    for (int i = 0; i < 64 && st == DCTF_OK; ++i)
+        st = batch_enqueue(b, flags, s);
+    // Rounds over all candidates, each candidate's best round kept, so that a
+    // drift of the clock over the sweep does not favour one end of the list.
+    for (int r = 0; r < rounds && st == DCTF_OK; ++r)
+        for (size_t i = 0; i < cand.size() && st == DCTF_OK; ++i) {
+            if (!usable[i])
+                continue;
+            st = batch_plan(b, cand[i]);
+            for (int w = 0; w < 2 && st == DCTF_OK; ++w)
+                st = batch_enqueue(b, flags, s);
+            if (st == DCTF_OK)
+                st = hip_status(hipEventRecord(e0, s));
+            for (int k = 0; k < iters && st == DCTF_OK; ++k)
+                st = batch_enqueue(b, flags, s);
+            if (st == DCTF_OK)
+                st = hip_status(hipEventRecord(e1, s));
+            if (st == DCTF_OK)
+                st = hip_status(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            if (st == DCTF_OK)
+                st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+            ms /= iters;
+            if (st == DCTF_OK && (r == 0 || ms < t[i]))
+                t[i] = ms;
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != DCTF_OK) {
+        (void)batch_plan(b, orig);
+        return st;
+    }
+    int bi = -1;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (usable[i] && (bi < 0 || t[i] < t[bi]))
+            bi = (int)i;
+    if (ms_out)
+        for (size_t i = 0; i < cand.size(); ++i)
+            ms_out[i] = usable[i] ? t[i] : -1.0f;
+    if (best)
+        *best = bi;
+    return batch_plan(b, bi >= 0 ? cand[bi] : orig);
+}
+
+extern "C" int dctf_batch_autotune_candidates(dctf_batch_config *out, int max)
+{
+    const std::vector<dctf_batch_config> c = batch_candidates();
+    if (out)
+        for (int i = 0; i < max && i < (int)c.size(); ++i)
+            out[i] = c[i];
+    return (int)c.size();
 }
 
 // ===================================================================== misc

@@ -43,11 +43,14 @@ __device__ __forceinline__ int find_segment(const SegDesc *segs, int nsegs, int6
 
 // Walks the job table forward as the unit index grows.  The end of the
 // current job follows from its own descriptor.  The next job's descriptor is
-// requested by refill() with a vector load (lane k loads dword k) issued just
-// before a step's data loads: a scalar load would share its wait counter with
-// the LDS accesses of the tile pipeline and stall them, while the vector load
-// completes in order ahead of the data it precedes.  At the crossing the
-// fields are read back from the lanes.
+// requested by refill() with a vector load (lane k loads dword k) issued once
+// per step, unconditionally, just before the step's data loads: a scalar load
+// would share its wait counter with the LDS accesses of the tile pipeline and
+// stall them, while the vector load completes in order ahead of the data it
+// precedes; and since it is issued at the same point of every step, the
+// compiler can wait for it alone at a crossing (a conditional request would
+// make it wait for every load in flight).  At the crossing the fields are
+// read back from the lanes.
 template <int BPU>   // blocks per work unit
 struct JobCursor {
     static_assert(sizeof(JobDesc) == 40, "JobDesc is 10 dwords");
@@ -56,13 +59,15 @@ struct JobCursor {
     int end, j;
     JobDesc cur;
     int64_t cur_end;   // first unit after the current job
-    uint32_t nextv;    // lane k < 10: dword k of jobs[j + 1]
-    bool have_next;
+    uint32_t nextv;    // lane k < 10: dword k of jobs[min(j + 1, end - 1)] as of the last refill()
 
     __device__ __forceinline__ int64_t units_of(const JobDesc &d) const
     {
         return (d.B + blocks_per_unit - 1) / blocks_per_unit;
     }
+    // Positions the cursor on the job of `unit` (reading the table directly),
+    // then requests the descriptor after it: refill() must always follow the
+    // last move, or a crossing would take a stale descriptor.
     __device__ __forceinline__ void start(const JobDesc *t, int job_begin, int job_end, int64_t unit)
     {
         jobs = t;
@@ -70,17 +75,19 @@ struct JobCursor {
         j = job_begin;
         cur = t[j];
         cur_end = cur.unit_begin + units_of(cur);
-        have_next = false;
-        at(unit);
+        while (unit >= cur_end && j + 1 < end) {
+            ++j;
+            cur = t[j];
+            cur_end = cur.unit_begin + units_of(cur);
+        }
+        refill();
     }
     __device__ __forceinline__ void refill()
     {
-        if (!have_next && j + 1 < end) {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(jobs + j + 1);
-            const int lane = __lane_id();
-            nextv = p[lane < 10 ? lane : 0];
-            have_next = true;
-        }
+        const int nj = j + 1 < end ? j + 1 : j;
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(jobs + nj);
+        const int lane = __lane_id();
+        nextv = ldg_u32(p + (lane < 10 ? lane : 0));
     }
     __device__ __forceinline__ JobDesc unpack() const
     {
@@ -92,14 +99,20 @@ struct JobCursor {
         __builtin_memcpy(&d, w, sizeof(d));
         return d;
     }
+    __device__ __forceinline__ void advance()
+    {
+        cur = unpack();
+        ++j;
+        cur_end = cur.unit_begin + units_of(cur);
+    }
     __device__ __forceinline__ UnitRef at(int64_t unit)
     {
-        while (unit >= cur_end && j + 1 < end) {
-            refill();   // no-op when the descriptor was requested earlier
-            cur = unpack();
-            ++j;
-            have_next = false;
-            cur_end = cur.unit_begin + units_of(cur);
+        if (unit >= cur_end && j + 1 < end) {
+            advance();   // the descriptor the last refill() requested
+            while (unit >= cur_end && j + 1 < end) {
+                refill();   // the unit skipped a whole job: read the next descriptor now
+                advance();
+            }
         }
         UnitRef r;
         r.in = cur.in;
@@ -115,7 +128,8 @@ struct JobCursor {
 // units together; a wave reloads its operator fragments when the unit it
 // reaches belongs to another operator.
 template <int PREC, int IO, bool NT>
-__device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
+__device__ __forceinline__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds, float4 *t0,
+                                        float4 *t1)
 {
     if (gw >= a.workers8)
         return;
@@ -126,79 +140,158 @@ __device__ void worker8(const BatchArgs &a, int64_t gw, int lane, float4 *lds)
     if (first >= end)
         return;
     const int64_t my_units = (end - first + stride - 1) / stride;
-    const int n = lane & 15, g = lane >> 4;
 
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8BF16>::type Regs;
     Regs R;
-    int loaded_op = -1;
     auto op_load = [&](int op) {
         const OpDesc &o = a.ops[op];
         if constexpr (PREC == DCTF_PREC_FP32)
             load_op8(R, o.frag32, o.h0, lane);
         else
             load_op8(R, o.frag_hi, o.frag_lo, o.frag_lf, lane);
-        loaded_op = op;
     };
+
+    uint32_t off[4];
+    if constexpr (IO >= 1)
+        coalesced_offsets(off, lane);
+    else
+        mfma_offsets(off, lane);
+
+    if constexpr (IO == 2) {
+        // Tiles loaded straight into LDS: the wave's two tile buffers t0, t1
+        // alternate.  A run of one operator is code of its own for each
+        // buffer its first unit sits in, so that every access names its
+        // buffer statically (the compiler then waits for that buffer's loads
+        // only); a run returns the buffer of the next run's first unit.
+        // In flight after a tile's loads when the step reading it waits: the
+        // 4 stores of the step before (4 dropped stores before the first
+        // step), the job descriptor request and the 4 loads of the next tile
+        // (every step issues them; past the wave's last unit an empty tile).
+        // Operator loads at the start of a run add to them and are waited
+        // for as well.
+        auto dma_unit = [&](float4 *t, const UnitRef &r) { dma_tile8<NT>(t, tile_rsrc8(r.in, r.blk0, r.B), off); };
+        auto compute_lds = [&](float4 *t, const UnitRef &r) {
+            tile8_from_lds<9, NT>(R, t, tile_rsrc8(r.out, r.blk0, r.B), off, lane);
+        };
+        JobCursor<kUnitBlocks8> jc;
+        int64_t unit = first, k = 0;
+        jc.start(a.jobs8, job_begin, job_end, unit);
+        UnitRef rc = jc.at(unit), rn;
+        dma_unit(t0, rc);
+        dummy_stores8<NT>(rc.out, off);
+        auto step = [&](float4 *cb, float4 *nb) -> bool {
+            const bool more = k + 1 < my_units;
+            if (more) {
+                unit += stride;
+                rn = jc.at(unit);
+            } else {
+                rn = rc;
+                rn.B = 0;   // past the wave's last unit: an empty tile
+            }
+            jc.refill();
+            dma_unit(nb, rn);
+            compute_lds(cb, rc);
+            ++k;
+            rc = rn;
+            return more;
+        };
+        auto run = [&](auto P) -> int {
+            constexpr int p = decltype(P)::value;
+            float4 *ta = p ? t1 : t0, *tb = p ? t0 : t1;
+            const int op = rc.op;
+            op_load(op);
+            if (!step(ta, tb))
+                return -1;
+            if (rc.op != op)
+                return 1 - p;
+            for (;;) {
+                if (!step(tb, ta))
+                    return -1;
+                if (rc.op != op)
+                    return p;
+                if (!step(ta, tb))
+                    return -1;
+                if (rc.op != op)
+                    return 1 - p;
+            }
+        };
+        for (int par = 0; par >= 0;)
+            par = par ? run(std::integral_constant<int, 1>()) : run(std::integral_constant<int, 0>());
+        return;
+    }
 
     auto load_unit = [&](float4 (&x)[4], const UnitRef &r) {
-        if constexpr (IO == 1) {
-            load_tile_coalesced<NT>(x, r.in + r.blk0 * 64, r.B - r.blk0, lane);
-        } else {
-            int64_t blk = r.blk0 + n;
-            blk = blk < r.B ? blk : r.B - 1;
-            const float *src = r.in + blk * 64 + 4 * g;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                x[i] = NT ? ld4_nt(src + 16 * i) : ld4(src + 16 * i);
-        }
-    };
-    // Operator fragments are requested before the data loads of the unit
-    // after, so the wait for them does not also drain that unit's loads.
-    auto ensure_op = [&](int op) {
-        if (op != loaded_op)
-            op_load(op);
+        load_tile_buf<NT>(x, tile_rsrc8(r.in, r.blk0, r.B), off);
     };
     auto compute_store = [&](float4 (&x)[4], const UnitRef &r) {
-        if constexpr (IO == 1) {
-            tile8_coalesced<NT>(R, x, lds, r.out + r.blk0 * 64, r.B - r.blk0, lane);
-        } else {
-            f32x4 acc[4];
-            tile8(R, x, lane, acc);
-            const int64_t blk = r.blk0 + n;
-            if (blk < r.B) {
-                float *dst = r.out + blk * 64 + 4 * g;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (NT)
-                        st4_nt(dst + 16 * t, acc[t]);
-                    else
-                        st4(dst + 16 * t, acc[t]);
-                }
-            }
-        }
+        const rsrc_t out = tile_rsrc8(r.out, r.blk0, r.B);
+        if constexpr (IO == 1)
+            tile8_buf<NT>(R, x, lds, out, off, lane);
+        else
+            tile8_buf_direct<NT>(R, x, out, off, lane);
     };
 
+    // The wave's units form runs of one operator.  Each run starts with the
+    // operator's fragments loaded (requested after the data loads of the
+    // run's first unit and before those of the unit after, so the wait for
+    // them does not drain that unit's loads); that first step is peeled off
+    // the loop, so the loop never waits for operator loads.  Inside a run two
+    // register buffers alternate (the body is unrolled twice): the loads of
+    // the next unit stay in flight across the loop back-edge, and the
+    // operator registers are not carried around the loop (a conditional
+    // reload there would make the compiler copy all of them, and wait for
+    // the copies, on every iteration).  Every step issues the same loads
+    // (past the wave's last unit, an empty tile that loads nothing), so the
+    // compiler's memory-counter waits are exact.  A run that ends on the
+    // second buffer hands its next unit to the first one with a copy.
     JobCursor<kUnitBlocks8> jc;
-    int64_t unit = first;
+    int64_t unit = first, k = 0;
     jc.start(a.jobs8, job_begin, job_end, unit);
-    UnitRef rc = jc.at(unit);
-    float4 cur[4], nxt[4];
-    ensure_op(rc.op);
-    load_unit(cur, rc);
-    for (int64_t k = 1; k < my_units; ++k) {
-        unit += stride;
-        const UnitRef rn = jc.at(unit);
+    UnitRef rc = jc.at(unit), rn;
+    float4 b0[4], b1[4];
+    load_unit(b0, rc);
+    auto step = [&](float4 (&cb)[4], float4 (&nb)[4]) -> bool {
+        const bool more = k + 1 < my_units;
+        if (more) {
+            unit += stride;
+            rn = jc.at(unit);
+        } else {
+            rn = rc;
+            rn.B = 0;
+        }
         jc.refill();
-        ensure_op(rc.op);
-        load_unit(nxt, rn);
-        compute_store(cur, rc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            cur[i] = nxt[i];
+        load_unit(nb, rn);
+        compute_store(cb, rc);
+        ++k;
         rc = rn;
+        return more;
+    };
+    for (;;) {
+        const int op = rc.op;
+        op_load(op);
+        if (!step(b0, b1))
+            return;
+        if (rc.op != op) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                b0[i] = b1[i];
+            continue;
+        }
+        for (;;) {
+            if (!step(b1, b0))
+                return;
+            if (rc.op != op)
+                break;
+            if (!step(b0, b1))
+                return;
+            if (rc.op != op) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    b0[i] = b1[i];
+                break;
+            }
+        }
     }
-    ensure_op(rc.op);
-    compute_store(cur, rc);
 }
 
 template <int PREC, int D>
@@ -230,12 +323,13 @@ __device__ void worker16(const BatchArgs &a, int64_t wg, char *smem)
         else
             load_op16(R, o.frag_hi, o.frag_lo, o.frag_lf, wave, lane);
     };
-    run_tiles16<PREC, D, UnitRef>(count, ref, op_load, R, smem);
+    run_tiles16<PREC, D, UnitRef, 0, 0, true>(count, ref, op_load, R, smem);
 }
 
 template <int PREC, int IO, bool NT>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
 {
+    static_assert(IO != 2, "the mixed kernel stages N = 8 tiles through registers");
     // N = 16 workgroups use the LDS for their double-buffered tiles, N = 8
     // workgroups for the per-wave staging of the coalesced I/O.
     constexpr int k16 = PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split;
@@ -245,7 +339,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if ((int)blockIdx.x < a.groups8) {
         float4 *lds = reinterpret_cast<float4 *>(smem) + (IO ? wave * 256 : 0);
-        worker8<PREC, IO, NT>(a, (int64_t)blockIdx.x * (kBatchThreads / 64) + wave, lane, lds);
+        worker8<PREC, IO, NT>(a, uniform_i64((int64_t)blockIdx.x * (kBatchThreads / 64) + wave), lane, lds, nullptr,
+                              nullptr);
     } else {
         worker16<PREC, batch_depth16(PREC)>(a, (int64_t)blockIdx.x - a.groups8, smem);
     }
@@ -256,9 +351,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a)
 template <int PREC, int IO, bool NT>
 __global__ __launch_bounds__(kBatch8Threads) void k_batch8(BatchArgs a)
 {
-    __shared__ __attribute__((aligned(16))) float4 lds_all[IO ? (kBatch8Threads / 64) * 256 : 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    worker8<PREC, IO, NT>(a, (int64_t)blockIdx.x * (kBatch8Threads / 64) + wave, lane, lds_all + (IO ? wave * 256 : 0));
+    constexpr int W = kBatch8Threads / 64;
+    __shared__ __attribute__((aligned(16))) float4 lds_all[IO == 1 ? W * 256 : 1];
+    __shared__ __attribute__((aligned(16))) float4 lds_t0[IO == 2 ? W : 1][256];
+    __shared__ __attribute__((aligned(16))) float4 lds_t1[IO == 2 ? W : 1][256];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    worker8<PREC, IO, NT>(a, uniform_i64((int64_t)blockIdx.x * W + wave), lane, lds_all + (IO == 1 ? wave * 256 : 0),
+                          lds_t0[IO == 2 ? wave : 0], lds_t1[IO == 2 ? wave : 0]);
 }
 
 template <int PREC>
@@ -268,6 +367,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch16(BatchArgs a)
     worker16<PREC, batch_depth16(PREC)>(a, blockIdx.x, smem);
 }
 
+// The mixed kernel has no LDS-load path: a plan of both block sizes runs
+// its N = 8 work through the LDS-staged register path instead.
+constexpr int mixed_io(int io) { return io == 2 ? 1 : io; }
+
 template <int PREC, int IO, bool NT>
 hipError_t launch_batch_t(const BatchArgs &a, hipStream_t stream)
 {
@@ -276,7 +379,8 @@ hipError_t launch_batch_t(const BatchArgs &a, hipStream_t stream)
     else if (a.groups8 == 0)
         hipLaunchKernelGGL((k_batch16<PREC>), dim3(a.groups16), dim3(kBatchThreads), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_batch<PREC, IO, NT>), dim3(a.groups8 + a.groups16), dim3(kBatchThreads), 0, stream, a);
+        hipLaunchKernelGGL((k_batch<PREC, mixed_io(IO), NT>), dim3(a.groups8 + a.groups16), dim3(kBatchThreads), 0,
+                           stream, a);
     return hipGetLastError();
 }
 
@@ -295,7 +399,7 @@ int occupancy_t(int kind)
         return occ(k_batch8<PREC, IO, NT>, kBatch8Threads);
     if (kind == 16)
         return occ(k_batch16<PREC>, kBatchThreads);
-    return occ(k_batch<PREC, IO, NT>, kBatchThreads);
+    return occ(k_batch<PREC, mixed_io(IO), NT>, kBatchThreads);
 }
 
 }  // namespace
@@ -310,7 +414,9 @@ hipError_t launch_batch(const BatchArgs &a, hipStream_t stream)
     case 0: return f32 ? launch_batch_t<DCTF_PREC_FP32, 0, false>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 0, false>(a, stream);
     case 1: return f32 ? launch_batch_t<DCTF_PREC_FP32, 0, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 0, true>(a, stream);
     case 2: return f32 ? launch_batch_t<DCTF_PREC_FP32, 1, false>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 1, false>(a, stream);
-    default: return f32 ? launch_batch_t<DCTF_PREC_FP32, 1, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 1, true>(a, stream);
+    case 3: return f32 ? launch_batch_t<DCTF_PREC_FP32, 1, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 1, true>(a, stream);
+    case 4: return f32 ? launch_batch_t<DCTF_PREC_FP32, 2, false>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 2, false>(a, stream);
+    default: return f32 ? launch_batch_t<DCTF_PREC_FP32, 2, true>(a, stream) : launch_batch_t<DCTF_PREC_SPLIT_BF16, 2, true>(a, stream);
     }
 }
 
@@ -321,7 +427,9 @@ int batch_occupancy(int prec, int io, bool nt, int kind)
     case 0: return f32 ? occupancy_t<DCTF_PREC_FP32, 0, false>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 0, false>(kind);
     case 1: return f32 ? occupancy_t<DCTF_PREC_FP32, 0, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 0, true>(kind);
     case 2: return f32 ? occupancy_t<DCTF_PREC_FP32, 1, false>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 1, false>(kind);
-    default: return f32 ? occupancy_t<DCTF_PREC_FP32, 1, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 1, true>(kind);
+    case 3: return f32 ? occupancy_t<DCTF_PREC_FP32, 1, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 1, true>(kind);
+    case 4: return f32 ? occupancy_t<DCTF_PREC_FP32, 2, false>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 2, false>(kind);
+    default: return f32 ? occupancy_t<DCTF_PREC_FP32, 2, true>(kind) : occupancy_t<DCTF_PREC_SPLIT_BF16, 2, true>(kind);
     }
 }
 

@@ -307,8 +307,12 @@ int batch_occupancy(int prec, int io, bool nt, int kind);
 // Batch planning: validates the jobs, groups them, cuts fronts and sizes the
 // grid.  The work table is written to `table`; the pointers in `a` hold
 // offsets into it until rebase_batch() adds the table's device address.
-dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, std::vector<char> &table, BatchArgs &a,
-                       std::vector<dctf_operator> &ops);
+// `cfg` fixes the fronts, N = 8 I/O path and grid size (fields < 0 / 0 take
+// the process-wide setting of the precision, see dctf_set_batch_config).
+dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_batch_config &cfg,
+                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops);
+// The process-wide configuration of a precision.
+dctf_batch_config batch_config(int prec);
 void rebase_batch(BatchArgs &a, const void *dev);
 
 // I/O mode of the current N = 8 variant (used by the batch kernel's N = 8 work).

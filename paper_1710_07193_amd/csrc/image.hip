@@ -317,7 +317,7 @@ __global__ __launch_bounds__(LOPS ? 512 : 256) void k_filter_image8(ImageFilterA
                     }
             } else if (LOPS && rc.cp == lds_cp && o != 4) {
                 const int q = o < 4 ? o : o - 1;
-                load_op8(R, s_hl + 2 * q * kOpHalf, s_hl + (2 * q + 1) * kOpHalf, s_lf + q * kOpLf, lane);
+                load_op8_lds(R, s_hl + 2 * q * kOpHalf, s_hl + (2 * q + 1) * kOpHalf, s_lf + q * kOpLf, lane);
             } else {
                 load_op8(R, a.frag_hi + opi * kNN * kNN, a.frag_lo + opi * kNN * kNN,
                          a.frag_lf + opi * kNN * lf_count(kN), lane);

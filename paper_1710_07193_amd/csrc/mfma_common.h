@@ -49,26 +49,39 @@ __device__ __forceinline__ float lane_read(float v, int src)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
+// Accesses of device (global) memory.  The pointers reach the kernels inside
+// argument structures and work tables, where the compiler cannot tell their
+// address space; the explicit global space keeps them off the flat path,
+// whose loads also count against the LDS wait counter (every LDS wait would
+// then wait for the loads in flight as well).
+typedef __attribute__((address_space(1))) f32x4 g_f32x4;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) f32x2 g_f32x2;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+
+__device__ __forceinline__ const g_f32x4 *gp4(const float *p) { return (const g_f32x4 *)p; }
+__device__ __forceinline__ g_f32x4 *gp4(float *p) { return (g_f32x4 *)p; }
+
 __device__ __forceinline__ float4 ld4(const float *p)
 {
-    return *reinterpret_cast<const float4 *>(p);
+    const f32x4 v = *gp4(p);
+    return make_float4(v[0], v[1], v[2], v[3]);
 }
 
 __device__ __forceinline__ float4 ld4_nt(const float *p)
 {
-    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    const f32x4 v = __builtin_nontemporal_load(gp4(p));
     return make_float4(v[0], v[1], v[2], v[3]);
 }
 
-__device__ __forceinline__ void st4(float *p, f32x4 v)
-{
-    *reinterpret_cast<f32x4 *>(p) = v;
-}
+__device__ __forceinline__ void st4(float *p, f32x4 v) { *gp4(p) = v; }
 
-__device__ __forceinline__ void st4_nt(float *p, f32x4 v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(p));
-}
+__device__ __forceinline__ void st4_nt(float *p, f32x4 v) { __builtin_nontemporal_store(v, gp4(p)); }
+
+// 16 bytes / 8 bytes / 4 bytes of device memory.
+__device__ __forceinline__ u32x4 ldg_u32x4(const void *p) { return *(const g_u32x4 *)p; }
+__device__ __forceinline__ f32x2 ldg_f32x2(const float *p) { return *(const g_f32x2 *)p; }
+__device__ __forceinline__ uint32_t ldg_u32(const void *p) { return *(const g_u32 *)p; }
 
 // uint8 conversion of a filtered pixel (Sec. III): round half up, saturate
 // to [0, 255], decided in FP32 (NaN gives 0).
@@ -154,6 +167,7 @@ __device__ __forceinline__ void load_op8(OpRegs8F32 &R, const float *frag32, con
     }
 }
 
+// From device memory (the operator's fragment images).
 __device__ __forceinline__ void load_op8(OpRegs8BF16 &R, const uint16_t *fhi, const uint16_t *flo,
                                          const float *flf, int lane)
 {
@@ -161,14 +175,37 @@ __device__ __forceinline__ void load_op8(OpRegs8BF16 &R, const uint16_t *fhi, co
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            R.hi[t][s] = *reinterpret_cast<const u32x4 *>(fhi + ((t * 2 + s) * 64 + lane) * 8);
-            R.lo[t][s] = *reinterpret_cast<const u32x4 *>(flo + ((t * 2 + s) * 64 + lane) * 8);
+            R.hi[t][s] = ldg_u32x4(fhi + ((t * 2 + s) * 64 + lane) * 8);
+            R.lo[t][s] = ldg_u32x4(flo + ((t * 2 + s) * 64 + lane) * 8);
         }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const float2 v = *reinterpret_cast<const float2 *>(flf + (t * 64 + lane) * 2);
-        R.lf[t][0] = v.x;
-        R.lf[t][1] = v.y;
+        const f32x2 v = ldg_f32x2(flf + (t * 64 + lane) * 2);
+        R.lf[t][0] = v[0];
+        R.lf[t][1] = v[1];
+    }
+}
+
+// The same fragments from copies in LDS (the pointers point into __shared__
+// arrays; device-memory loads must not be used on them).
+typedef __attribute__((address_space(3))) const u32x4 l_u32x4;
+typedef __attribute__((address_space(3))) const f32x2 l_f32x2;
+
+__device__ __forceinline__ void load_op8_lds(OpRegs8BF16 &R, const uint16_t *fhi, const uint16_t *flo,
+                                             const float *flf, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            R.hi[t][s] = *(l_u32x4 *)(fhi + ((t * 2 + s) * 64 + lane) * 8);
+            R.lo[t][s] = *(l_u32x4 *)(flo + ((t * 2 + s) * 64 + lane) * 8);
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x2 v = *(l_f32x2 *)(flf + (t * 64 + lane) * 2);
+        R.lf[t][0] = v[0];
+        R.lf[t][1] = v[1];
     }
 }
 
@@ -347,6 +384,204 @@ __device__ __forceinline__ void tile8_coalesced(const Regs &R, const float4 xin[
     wave_lds_sync();
 }
 
+// ------------------------------------------- N = 8, buffer-resource tile I/O
+//
+// The same tile layouts through raw buffer instructions over a resource that
+// covers exactly the valid blocks of the tile: loads past the end return
+// zeros and stores past the end are dropped by the hardware, so a ragged
+// tile needs neither clamped addresses nor branches around its stores.  The
+// tile base lives in scalar registers and every lane's byte offset is a
+// constant of the lane, which leaves no 64-bit address arithmetic in the
+// loop; and since every store is issued on every path, the memory counter
+// waits stay exact (a skipped store would make the compiler wait for all).
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+// Descriptor word 3 of a raw buffer (32-bit data format) on gfx9-family chips.
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) { return (int64_t)uniform_u64((uint64_t)v); }
+
+// Resource over the blocks [blk0, min(blk0 + 16, B)) of an array of blocks of
+// `block_bytes` bytes; empty when blk0 >= B (and, as a guard, when blk0 < 0).
+// Arguments are wave-uniform.
+__device__ __forceinline__ rsrc_t tile_rsrc(const void *base, int64_t blk0, int64_t B, int block_bytes)
+{
+    const int64_t nv = B - blk0;
+    const bool ok = nv > 0 && blk0 >= 0;
+    const int bytes = !ok ? 0 : (nv >= 16 ? 16 * block_bytes : (int)nv * block_bytes);
+    const char *p = static_cast<const char *>(base) + (ok ? blk0 : 0) * block_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, bytes, kRsrcWord3);
+}
+
+// N = 8 blocks of FP32 coefficients (256 bytes).
+__device__ __forceinline__ rsrc_t tile_rsrc8(const float *base, int64_t blk0, int64_t B)
+{
+    return tile_rsrc(base, blk0, B, 256);
+}
+
+// Waits until at most n vector memory accesses of the wave are in flight
+// (they complete in issue order for this count).
+template <int n>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// Waits for every vector memory access of the wave in flight.  After a
+// conditional reload (operator fragments), this lets the compiler know at
+// the join that nothing of it is pending: otherwise it would wait for all
+// loads at the next use of those registers on every path.
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// 16 bytes at byte offset `off` of the resource (the b128 buffer builtins
+// move four 32-bit words; the floats are reinterpreted, not converted).
+template <bool NT>
+__device__ __forceinline__ float4 buf_ld4(rsrc_t r, uint32_t off)
+{
+    const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, NT ? 2 : 0));
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
+template <bool NT>
+__device__ __forceinline__ void buf_st4(rsrc_t r, uint32_t off, f32x4 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, NT ? 2 : 0);
+}
+
+// Byte offsets of a lane's four 16-byte chunks in the coalesced layout
+// (instruction i: block b = 4i + lane/16, chunk (lane % 16) ^ b) ...
+__device__ __forceinline__ void coalesced_offsets(uint32_t off[4], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int b = 4 * i + (lane >> 4);
+        off[i] = (uint32_t)(b * 256 + 16 * ((lane & 15) ^ b));
+    }
+}
+
+// ... and in the MFMA layout (chunk 4i + g of block n).
+__device__ __forceinline__ void mfma_offsets(uint32_t off[4], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        off[i] = (uint32_t)((lane & 15) * 256 + 64 * i + 16 * (lane >> 4));
+}
+
+template <bool NT>
+__device__ __forceinline__ void load_tile_buf(float4 x[4], rsrc_t r, const uint32_t off[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        x[i] = buf_ld4<NT>(r, off[i]);
+}
+
+// One 16-block tile through the coalesced path with buffer I/O: registers
+// (coalesced layout) -> LDS -> MFMA -> LDS -> device memory.
+template <bool NT, typename Regs>
+__device__ __forceinline__ void tile8_buf(const Regs &R, const float4 xin[4], float4 *lds, rsrc_t out,
+                                         const uint32_t off[4], int lane)
+{
+    stage_in(lds, xin, lane);
+    wave_lds_sync();
+    float4 xm[4];
+    read_mfma(lds, xm, lane);
+    f32x4 acc[4];
+    tile8(R, xm, lane, acc);
+    wave_lds_sync();
+    stage_out(lds, acc, lane);
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 v = lds[i * 64 + lane];
+        buf_st4<NT>(out, off[i], f32x4{v.x, v.y, v.z, v.w});
+    }
+    wave_lds_sync();
+}
+
+// The same tile with loads and stores in the MFMA layout (no LDS).
+template <bool NT, typename Regs>
+__device__ __forceinline__ void tile8_buf_direct(const Regs &R, float4 x[4], rsrc_t out, const uint32_t off[4],
+                                                 int lane)
+{
+    f32x4 acc[4];
+    tile8(R, x, lane, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        buf_st4<NT>(out, off[t], acc[t]);
+}
+
+// ------------------------------------------- N = 8, tiles loaded into LDS
+//
+// The coalesced-layout loads can write LDS directly (buffer_load ... lds):
+// lane l of instruction i deposits its 16 bytes at slot i*64 + l of the
+// wave's tile buffer, the layout stage_in() writes, without passing through
+// VGPRs.  The tile then goes LDS -> MFMA layout -> MFMA -> LDS -> device
+// memory as in tile8_buf.  Two LDS tile buffers per wave alternate; they are
+// separate __shared__ arrays, so the compiler can tell a read of one from
+// the loads in flight into the other and waits for the right loads only.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// The loads are kept ahead of everything after them (the scheduler would
+// otherwise sink them below the next tile's LDS reads, shortening the time
+// they have to arrive).
+// Four stores into an empty resource (dropped by the hardware; they still
+// count as vector memory accesses): they stand in for the stores of a step
+// before the first, so that every step finds the same count in flight.
+template <bool NT>
+__device__ __forceinline__ void dummy_stores8(const float *base, const uint32_t off[4])
+{
+    const rsrc_t none = tile_rsrc8(base, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        buf_st4<NT>(none, off[i], f32x4{0.f, 0.f, 0.f, 0.f});
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <bool NT>
+__device__ __forceinline__ void dma_tile8(float4 *lds, rsrc_t r, const uint32_t off[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)(lds + i * 64), 16, off[i], 0, 0, NT ? 2 : 0);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// The compiler does not reliably order reads of a tile buffer after the
+// loads into it (its tracking of loads to LDS missed some of the reads of a
+// tile, which then read stale data), so the tile loop waits itself: it keeps
+// the number of vector memory accesses issued after a tile's loads fixed
+// (the stores of the step before, the next tile's loads, and per-step
+// extras), and each step waits with that count (WAIT) before reading its
+// tile.
+template <int WAIT, bool NT, typename Regs>
+__device__ __forceinline__ void tile8_from_lds(const Regs &R, float4 *lds, rsrc_t out, const uint32_t off[4],
+                                               int lane)
+{
+    wait_vm<WAIT>();
+    __builtin_amdgcn_sched_barrier(0);
+    float4 xm[4];
+    read_mfma(lds, xm, lane);
+    f32x4 acc[4];
+    tile8(R, xm, lane, acc);
+    wave_lds_sync();
+    stage_out(lds, acc, lane);
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 v = lds[i * 64 + lane];
+        buf_st4<NT>(out, off[i], f32x4{v.x, v.y, v.z, v.w});
+    }
+    wave_lds_sync();
+}
+
 // ----------------------------------------------------------------- N = 16
 //
 // Weight-stationary: a workgroup of 8 waves holds the 256 x 256 operator in
@@ -420,12 +655,12 @@ __device__ __forceinline__ void load_op16(OpRegs16BF16 &R, const uint16_t *fhi, 
         const int T = 2 * wave + t;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            R.hi[t][s] = *reinterpret_cast<const u32x4 *>(fhi + ((T * 8 + s) * 64 + lane) * 8);
-            R.lo[t][s] = *reinterpret_cast<const u32x4 *>(flo + ((T * 8 + s) * 64 + lane) * 8);
+            R.hi[t][s] = ldg_u32x4(fhi + ((T * 8 + s) * 64 + lane) * 8);
+            R.lo[t][s] = ldg_u32x4(flo + ((T * 8 + s) * 64 + lane) * 8);
         }
-        const float2 v = *reinterpret_cast<const float2 *>(flf + (T * 64 + lane) * 2);
-        R.lf[t][0] = v.x;
-        R.lf[t][1] = v.y;
+        const f32x2 v = ldg_f32x2(flf + (T * 64 + lane) * 2);
+        R.lf[t][0] = v[0];
+        R.lf[t][1] = v[1];
     }
 }
 
@@ -475,22 +710,21 @@ __device__ __forceinline__ void stage16_pos(int tid, int h, int &b, int &c)
     }
 }
 
-__device__ __forceinline__ void stage16_load_q(Stage16<1> &S, const int16_t *qin, int64_t B, int tid)
+// Tile loads through a resource over the tile's valid blocks (blocks past
+// the end read as zeros; their results are never stored).
+__device__ __forceinline__ void stage16_load_q(Stage16<1> &S, rsrc_t r, int tid)
 {
-    int64_t blk = tid >> 5;
-    blk = blk < B ? blk : B - 1;
-    S.raw = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(qin + blk * 256 + 8 * (tid & 31)));
+    // int16 block: 512 bytes; thread q: coefficients 8(q % 32) .. +7 of block q / 32
+    S.raw = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                          r, (uint32_t)((tid >> 5) * 512 + 16 * (tid & 31)), 0, 2));
 }
 
-__device__ __forceinline__ void stage16_load(Stage16<0> &S, const float *in, int64_t B, int64_t tile,
-                                             int tid)
+__device__ __forceinline__ void stage16_load(Stage16<0> &S, rsrc_t r, int tid)
 {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int q = tid + 512 * h;
-        int64_t blk = tile * 16 + (q >> 6);
-        blk = blk < B ? blk : B - 1;
-        S.v[h] = ld4(in + blk * 256 + 4 * (q & 63));
+        S.v[h] = buf_ld4<false>(r, (uint32_t)((q >> 6) * 1024 + 16 * (q & 63)));
     }
 }
 
@@ -600,12 +834,20 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // Global loads run D tiles ahead of the MFMA work (a ring of D register
 // stages); LDS tiles are double-buffered with one barrier per tile.
 // ref(t) returns the UnitRef-like descriptor of the t-th tile (called in
-// increasing t); op_load(op) loads the operator fragments into R.
+// increasing t, also for t >= count: such a tile must be past the end of its
+// job, so that it reads nothing); op_load(op) loads the operator fragments
+// into R.  MULTI_OP = false: every tile has the operator of tile 0, loaded
+// once before the loop; true: a tile of another operator reloads it (then
+// every load in flight is waited for, so that no later wait has to assume
+// the reload pending).  Every step issues the same loads and stores (past
+// the end, through empty resources), so the compiler's memory-counter waits
+// let the D tiles ahead stay in flight.
 // IN = 0: FP32 coefficients from r.in; IN = 1: int16 coefficients from
 // r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term.
 // OUT = 0: FP32 results to r.out; OUT = 1: uint8 pixels to r.pix (the
 // operator is then the pixel-domain one).
-template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, typename RefFn, typename OpFn, typename Regs>
+template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, typename RefFn,
+          typename OpFn, typename Regs>
 __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
                                             const float *qtab = nullptr, float dc_offset = 0.0f)
 {
@@ -635,59 +877,110 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
     };
     auto stage = [&](Stage16<IN> &S, const Ref &r) {
         if constexpr (IN == 0)
-            stage16_load(S, r.in + r.blk0 * 256, r.B - r.blk0, 0, tid);
+            stage16_load(S, tile_rsrc(r.in, r.blk0, r.B, 1024), tid);
         else
-            stage16_load_q(S, r.qin + r.blk0 * 256, r.B - r.blk0, tid);
+            stage16_load_q(S, tile_rsrc(r.qin, r.blk0, r.B, 512), tid);
     };
+    // Output offsets of the lane (block n, rows 32 wave + 4g .. and + 16).
+    const uint32_t out_off = (uint32_t)(n * (OUT == 0 ? 1024 : 256) + (OUT == 0 ? 4 : 1) * (32 * wave + 4 * g));
 
     Stage16<IN> S[D];
     Ref Rf[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d)
-        if (d < count) {
-            Rf[d] = ref(d);
-            stage(S[d], Rf[d]);
-        }
+    for (int d = 0; d < D; ++d) {
+        Rf[d] = ref(d);
+        stage(S[d], Rf[d]);
+    }
+    int loaded_op = -1;
+    if constexpr (!MULTI_OP) {
+        op_load(Rf[0].op);
+        loaded_op = Rf[0].op;
+        wait_vm_all();   // the loop then never waits for the operator loads
+    }
     put(S[0], 0);
     __syncthreads();
-    int loaded_op = -1;
-    for (int64_t t0 = 0;; t0 += D) {
-#pragma unroll
-        for (int p = 0; p < D; ++p) {
-            const int64_t t = t0 + p;
-            const Ref rc = Rf[p];
-            if (rc.op != loaded_op) {     // requested ahead of the newest tile's loads
+    // One tile: (operator reload,) loads of the tile D ahead into its free
+    // stage, MFMA work from LDS, stores, and (unless it is the last tile) the
+    // next tile's stage into the other LDS buffer.
+    auto step = [&](auto P, int64_t t, bool last) {
+        constexpr int p = decltype(P)::value;
+        const Ref rc = Rf[p];
+        if constexpr (MULTI_OP) {
+            if (rc.op != loaded_op) {
                 op_load(rc.op);
                 loaded_op = rc.op;
+                wait_vm_all();
             }
-            if (t + D < count) {          // S[p] is free: its tile is in LDS
-                Rf[p] = ref(t + D);
-                stage(S[p], Rf[p]);
-            }
-            const int buf = (int)(t & 1);
-            f32x4 acc[2];
-            if constexpr (PREC == DCTF_PREC_FP32)
-                tile16(R, lf + buf * kF32, lane, acc);
-            else
-                tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
-            const int64_t blk = rc.blk0 + n;
-            if (blk < rc.B) {
-                if constexpr (OUT == 0) {
-                    float *dst = rc.out + blk * 256 + 32 * wave + 4 * g;
-                    st4(dst, acc[0]);
-                    st4(dst + 16, acc[1]);
-                } else {
-                    uint32_t *dst = reinterpret_cast<uint32_t *>(rc.pix + blk * 256 + 32 * wave + 4 * g);
-                    dst[0] = pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
-                    dst[4] = pack_u8x4(acc[1][0], acc[1][1], acc[1][2], acc[1][3]);
-                }
-            }
-            if (t + 1 >= count)
-                return;
+        }
+        // S[p] is free (its tile is in LDS): load the tile D ahead into it,
+        // kept ahead of the MFMA work by a scheduling barrier
+        Rf[p] = ref(t + D);
+        stage(S[p], Rf[p]);
+        __builtin_amdgcn_sched_barrier(0);
+        const int buf = (int)(t & 1);
+        f32x4 acc[2];
+        if constexpr (PREC == DCTF_PREC_FP32)
+            tile16(R, lf + buf * kF32, lane, acc);
+        else
+            tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
+        if constexpr (OUT == 0) {
+            const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 1024);
+            buf_st4<false>(o, out_off, acc[0]);
+            buf_st4<false>(o, out_off + 64, acc[1]);
+        } else {
+            const rsrc_t o = tile_rsrc(rc.pix, rc.blk0, rc.B, 256);
+            __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]), o,
+                                                  out_off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[1][0], acc[1][1], acc[1][2], acc[1][3]), o,
+                                                  out_off + 16, 0, 0);
+        }
+        if (!last) {
             put(S[(p + 1) % D], buf ^ 1);
             __syncthreads();
         }
+    };
+    // Whole rounds of D tiles that are all followed by another tile: a loop
+    // without exits in its body (an exit there would join the loop's latch
+    // and make the compiler's waits assume the exit path's counts); then the
+    // last 1..D tiles.
+    const int64_t full = (count - 1) / D;
+    int64_t t0 = 0;
+    for (int64_t it = 0; it < full; ++it, t0 += D) {
+        step(std::integral_constant<int, 0>(), t0, false);
+        if constexpr (D > 1)
+            step(std::integral_constant<int, (1 % D)>(), t0 + 1, false);
+        if constexpr (D > 2)
+            step(std::integral_constant<int, (2 % D)>(), t0 + 2, false);
+        if constexpr (D > 3)
+            step(std::integral_constant<int, (3 % D)>(), t0 + 3, false);
+        if constexpr (D > 4)
+            step(std::integral_constant<int, (4 % D)>(), t0 + 4, false);
     }
+    static_assert(D >= 1 && D <= 5, "tiles ahead: 1 to 5");
+    bool last = t0 + 1 >= count;
+    step(std::integral_constant<int, 0>(), t0, last);
+    if (last)
+        return;
+    if constexpr (D > 1) {
+        last = t0 + 2 >= count;
+        step(std::integral_constant<int, (1 % D)>(), t0 + 1, last);
+        if (last)
+            return;
+    }
+    if constexpr (D > 2) {
+        last = t0 + 3 >= count;
+        step(std::integral_constant<int, (2 % D)>(), t0 + 2, last);
+        if (last)
+            return;
+    }
+    if constexpr (D > 3) {
+        last = t0 + 4 >= count;
+        step(std::integral_constant<int, (3 % D)>(), t0 + 3, last);
+        if (last)
+            return;
+    }
+    if constexpr (D > 4)
+        step(std::integral_constant<int, (4 % D)>(), t0 + 4, true);
 }
 
 }  // namespace dctf

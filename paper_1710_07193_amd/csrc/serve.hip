@@ -1,12 +1,14 @@
 // Continuous-batching request server over the persistent batched filter.
 //
-// dctf_server_run replays a list of requests in real time on one host thread:
-//   - a request becomes pending at its arrival time;
-//   - pending requests are admitted in arrival order while their output fits
-//     in the server's device arena (first-fit allocation; the arena size is
-//     the HBM budget) and a launch slot is free; a request whose output alone
-//     exceeds the arena is rejected with DCTF_EBUSY;
-//   - the admitted requests of one slot form one batch: their operators come
+// Online interface (dctf_server_submit / dctf_server_poll):
+//   - a submitted request is validated and queued at once (its mask is
+//     copied, so the caller may free it);
+//   - each poll reaps the batches that have finished, then admits queued
+//     requests in submission order while their output fits in the server's
+//     device arena (first-fit allocation; the arena size is the HBM budget)
+//     and a launch slot is free; a request whose output alone exceeds the
+//     arena completes with DCTF_EBUSY;
+//   - the requests admitted together form one batch: their operators come
 //     from a device-resident cache keyed by (mask bytes, kh, kw, N, border)
 //     (LRU eviction of entries no batch in flight uses), the work table is
 //     copied from pinned host memory on the slot's stream and one persistent
@@ -14,7 +16,10 @@
 //   - up to max_inflight batches run at once, one HIP stream each, so work of
 //     requests that arrive while others are on the GPU overlaps on the device;
 //   - completion is observed by polling each slot's event; the slot's arena
-//     ranges and cache references are then released.
+//     ranges and cache references are then released and its requests are
+//     handed back by the poll.
+// dctf_server_run replays a list of requests with known arrival times in real
+// time on top of the same two calls.
 // Each request's blocks go through the same per-block arithmetic as a
 // single-operator call, so its result does not depend on the mix it ran in.
 #include "dctf_internal.h"
@@ -23,6 +28,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <deque>
 #include <list>
 #include <map>
@@ -97,6 +103,13 @@ struct CacheEntry {
     std::list<std::string>::iterator lru;
 };
 
+// A submitted request waiting for admission: the caller's record and the
+// cache key (header + a copy of the mask).
+struct Queued {
+    dctf_request *req;
+    std::string key;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -104,7 +117,7 @@ struct Slot {
     char *table_host = nullptr;
     size_t table_cap = 0;
     bool busy = false;
-    std::vector<int> reqs;
+    std::vector<dctf_request *> reqs;
     std::vector<size_t> offs, sizes;
     std::vector<CacheEntry *> entries;
 };
@@ -122,9 +135,31 @@ struct dctf_server_s {
     std::unordered_map<std::string, CacheEntry> cache;
     std::list<std::string> lru;   // front = most recently used
     dctf_server_stats stats;
+    double t0 = 0.0;              // origin of the server clock (absolute seconds)
+    std::deque<Queued> queue;     // submitted, not yet admitted
+    std::deque<dctf_request *> finished;   // completed, not yet returned by a poll
+    int64_t outstanding = 0;      // submitted and not yet returned by a poll
+    std::vector<dctf_job> jobs;   // scratch of the admission step
+    std::vector<char> table;
+    std::vector<dctf_operator> ops;
 };
 
 namespace {
+
+// Checks one request: block size, mask shape and values (finite), border,
+// pointers and alignment.  arrival_s is not read here.
+bool request_valid(const dctf_request &r)
+{
+    if (r.B < 1 || (r.N != 8 && r.N != 16) || r.mask_host == nullptr || r.kh < 1 || r.kw < 1 ||
+        r.kh > 2 * r.N + 1 || r.kw > 2 * r.N + 1 ||
+        (r.border != DCTF_BORDER_ZERO && r.border != DCTF_BORDER_REPLICATE) || r.in_dev == nullptr ||
+        ((uintptr_t)r.in_dev & 15) || ((uintptr_t)r.out_dev & 15))
+        return false;
+    for (int i = 0; i < r.kh * r.kw; ++i)
+        if (!std::isfinite(r.mask_host[i]))
+            return false;
+    return true;
+}
 
 std::string cache_key(const dctf_request &r)
 {
@@ -135,9 +170,9 @@ std::string cache_key(const dctf_request &r)
     return k;
 }
 
-dctf_status cache_get(dctf_server s, const dctf_request &r, hipStream_t stream, CacheEntry **out)
+// Operator of a cache key (built on `stream` on a miss); takes a reference.
+dctf_status cache_get(dctf_server s, const std::string &key, hipStream_t stream, CacheEntry **out)
 {
-    const std::string key = cache_key(r);
     auto it = s->cache.find(key);
     if (it != s->cache.end()) {
         s->lru.erase(it->second.lru);
@@ -161,8 +196,12 @@ dctf_status cache_get(dctf_server s, const dctf_request &r, hipStream_t stream, 
             ++l;
         }
     }
+    int hdr[4];
+    memcpy(hdr, key.data(), sizeof(hdr));
+    std::vector<double> m((size_t)hdr[0] * hdr[1]);   // aligned copy of the key's mask bytes
+    memcpy(m.data(), key.data() + sizeof(hdr), sizeof(double) * m.size());
     dctf_operator op = nullptr;
-    dctf_status st = dctf_build_operator(r.mask_host, r.kh, r.kw, r.N, r.border, stream, &op);
+    dctf_status st = dctf_build_operator(m.data(), hdr[0], hdr[1], hdr[2], hdr[3], stream, &op);
     if (st != DCTF_OK)
         return st;
     ++s->stats.cache_misses;
@@ -175,12 +214,26 @@ dctf_status cache_get(dctf_server s, const dctf_request &r, hipStream_t stream, 
     return DCTF_OK;
 }
 
-void release_slot(dctf_server s, Slot &sl, dctf_request *reqs, double t)
+double clock_s(dctf_server s) { return now_s() - s->t0; }
+
+// A request leaves the server's hands: it waits in `finished` for a poll.
+void complete(dctf_server s, dctf_request *r, int status, double t)
 {
-    for (int id : sl.reqs) {
-        reqs[id].done_s = t;
-        reqs[id].status = DCTF_OK;
-    }
+    r->status = status;
+    r->done_s = t;
+    if (r->admit_s < 0.0)
+        r->admit_s = t;
+    if (status == DCTF_EBUSY)
+        ++s->stats.rejected;
+    else if (status != DCTF_OK)
+        ++s->stats.failed;
+    s->finished.push_back(r);
+}
+
+void release_slot(dctf_server s, Slot &sl, int status, double t)
+{
+    for (dctf_request *r : sl.reqs)
+        complete(s, r, status, t);
     for (size_t i = 0; i < sl.offs.size(); ++i)
         s->arena.release(sl.offs[i], sl.sizes[i]);
     for (CacheEntry *e : sl.entries)
@@ -190,6 +243,132 @@ void release_slot(dctf_server s, Slot &sl, dctf_request *reqs, double t)
     sl.sizes.clear();
     sl.entries.clear();
     sl.busy = false;
+}
+
+// Reaps finished batches.  A device error fails the slot's requests and is
+// returned (the other slots are still reaped).
+dctf_status reap(dctf_server s)
+{
+    dctf_status err = DCTF_OK;
+    for (Slot &sl : s->slots) {
+        if (!sl.busy)
+            continue;
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipSuccess) {
+            release_slot(s, sl, DCTF_OK, clock_s(s));
+        } else if (q != hipErrorNotReady) {
+            release_slot(s, sl, DCTF_EHIP, clock_s(s));
+            err = DCTF_EHIP;
+        }
+    }
+    return err;
+}
+
+// Fills free slots from the queue and launches them.
+dctf_status admit(dctf_server s)
+{
+    dctf_status err = DCTF_OK;
+    for (Slot &sl : s->slots) {
+        if (sl.busy || s->queue.empty())
+            continue;
+        const double t = clock_s(s);
+        s->jobs.clear();
+        while (!s->queue.empty() && (int)sl.reqs.size() < s->cfg.max_batch_jobs) {
+            dctf_request *r = s->queue.front().req;
+            const size_t bytes = align256((size_t)r->B * r->N * r->N * sizeof(float));
+            if (bytes > (size_t)s->cfg.arena_bytes) {
+                s->queue.pop_front();
+                complete(s, r, DCTF_EBUSY, t);
+                continue;
+            }
+            size_t off;
+            if (!s->arena.alloc(bytes, &off))
+                break;   // admit in submission order: wait for memory
+            CacheEntry *e = nullptr;
+            const dctf_status st = cache_get(s, s->queue.front().key, sl.stream, &e);
+            s->queue.pop_front();
+            if (st != DCTF_OK) {   // this request cannot run (e.g. no memory for its operator)
+                s->arena.release(off, bytes);
+                complete(s, r, st, t);
+                continue;
+            }
+            r->admit_s = t;
+            sl.reqs.push_back(r);
+            sl.offs.push_back(off);
+            sl.sizes.push_back(bytes);
+            sl.entries.push_back(e);
+            s->jobs.push_back({e->op, r->in_dev, reinterpret_cast<float *>(static_cast<char *>(s->arena_dev) + off),
+                               r->B});
+        }
+        if (sl.reqs.empty()) {
+            if (s->queue.empty())
+                continue;   // every candidate completed without running
+            break;          // the head request waits for arena space
+        }
+        BatchArgs a;
+        dctf_status st = plan_batch(s->jobs.data(), (int)s->jobs.size(), s->cfg.prec, batch_config(s->cfg.prec),
+                                    s->table, a, s->ops);
+        if (st == DCTF_OK && s->table.size() > sl.table_cap)
+            st = DCTF_EINVAL;
+        hipError_t e = hipSuccess;
+        if (st == DCTF_OK) {
+            memcpy(sl.table_host, s->table.data(), s->table.size());
+            e = hipMemcpyAsync(sl.table_dev, sl.table_host, s->table.size(), hipMemcpyHostToDevice, sl.stream);
+            rebase_batch(a, sl.table_dev);
+            if (e == hipSuccess)
+                e = launch_batch(a, sl.stream);
+            for (size_t k = 0; k < sl.reqs.size() && e == hipSuccess; ++k) {
+                const dctf_request &r = *sl.reqs[k];
+                if (r.out_dev)
+                    e = hipMemcpyAsync(r.out_dev, s->jobs[k].out, (size_t)r.B * r.N * r.N * sizeof(float),
+                                       hipMemcpyDeviceToDevice, sl.stream);
+            }
+            if (e == hipSuccess)
+                e = hipEventRecord(sl.done, sl.stream);
+        }
+        if (st != DCTF_OK || e != hipSuccess) {
+            // Nothing of this batch is known to have run: wait for whatever
+            // was enqueued, then fail its requests.
+            (void)hipStreamSynchronize(sl.stream);
+            const dctf_status fail = st != DCTF_OK ? st : DCTF_EHIP;
+            release_slot(s, sl, fail, clock_s(s));
+            if (fail == DCTF_EHIP)
+                err = DCTF_EHIP;
+            continue;
+        }
+        const double tl = clock_s(s);
+        for (dctf_request *r : sl.reqs) {
+            r->launch_s = tl;
+            r->batch = (int)s->stats.batches;
+        }
+        ++s->stats.batches;
+        sl.busy = true;
+        int inflight = 0;
+        for (const Slot &o : s->slots)
+            inflight += o.busy ? 1 : 0;
+        s->stats.peak_inflight_batches = std::max<int64_t>(s->stats.peak_inflight_batches, inflight);
+        s->stats.peak_arena_bytes = std::max<int64_t>(s->stats.peak_arena_bytes, (int64_t)s->arena.used());
+    }
+    return err;
+}
+
+// One round of progress: reap, then admit.
+dctf_status step(dctf_server s)
+{
+    const dctf_status e1 = reap(s);
+    const dctf_status e2 = admit(s);
+    return e1 != DCTF_OK ? e1 : e2;
+}
+
+int take_finished(dctf_server s, dctf_request **done, int max_done)
+{
+    int n = 0;
+    while (n < max_done && !s->finished.empty()) {
+        done[n++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    s->outstanding -= n;
+    return n;
 }
 
 }  // namespace
@@ -207,6 +386,7 @@ extern "C" dctf_status dctf_server_create(const dctf_server_config *cfg, dctf_se
         return DCTF_ENOMEM;
     s->cfg = *cfg;
     memset(&s->stats, 0, sizeof(s->stats));
+    s->t0 = now_s();
     hipError_t e = hipMalloc(&s->arena_dev, (size_t)cfg->arena_bytes);
     if (e != hipSuccess) {
         delete s;
@@ -262,136 +442,84 @@ extern "C" dctf_status dctf_server_stats_get(dctf_server s, dctf_server_stats *o
     return DCTF_OK;
 }
 
+extern "C" double dctf_server_clock(dctf_server s) { return s == nullptr ? -1.0 : clock_s(s); }
+
+extern "C" dctf_status dctf_server_submit(dctf_server s, dctf_request *req)
+{
+    if (s == nullptr || req == nullptr || !request_valid(*req))
+        return DCTF_EINVAL;
+    req->admit_s = req->launch_s = req->done_s = -1.0;
+    req->status = DCTF_EBUSY;
+    req->batch = -1;
+    try {
+        s->queue.push_back({req, cache_key(*req)});
+    } catch (...) {
+        return DCTF_ENOMEM;
+    }
+    ++s->outstanding;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_server_poll(dctf_server s, double wait_s, dctf_request **done, int max_done,
+                                        int *n_done)
+{
+    if (s == nullptr || n_done == nullptr || max_done < 0 || (max_done > 0 && done == nullptr) ||
+        !(wait_s >= 0.0))
+        return DCTF_EINVAL;
+    *n_done = 0;
+    const double until = clock_s(s) + wait_s;
+    dctf_status err = step(s);
+    // Wait (polling) until something completes, the time is up, or the
+    // server holds nothing that could complete.
+    while (err == DCTF_OK && s->finished.empty() && max_done > 0 && clock_s(s) < until &&
+           (s->outstanding > 0))
+        err = step(s);
+    *n_done = take_finished(s, done, max_done);
+    return err;
+}
+
 extern "C" dctf_status dctf_server_run(dctf_server s, dctf_request *reqs, int n)
 {
     if (s == nullptr || n < 0 || (n > 0 && reqs == nullptr))
         return DCTF_EINVAL;
-    for (int i = 0; i < n; ++i) {
-        const dctf_request &r = reqs[i];
-        if ((i > 0 && r.arrival_s < reqs[i - 1].arrival_s) || !(r.arrival_s >= 0.0) || r.B < 1 ||
-            (r.N != 8 && r.N != 16) || r.mask_host == nullptr || r.kh < 1 || r.kw < 1 || r.kh > 2 * r.N + 1 ||
-            r.kw > 2 * r.N + 1 || (r.border != DCTF_BORDER_ZERO && r.border != DCTF_BORDER_REPLICATE) ||
-            r.in_dev == nullptr || ((uintptr_t)r.in_dev & 15) || ((uintptr_t)r.out_dev & 15))
+    for (int i = 0; i < n; ++i)
+        if ((i > 0 && reqs[i].arrival_s < reqs[i - 1].arrival_s) || !(reqs[i].arrival_s >= 0.0) ||
+            !request_valid(reqs[i]))
             return DCTF_EINVAL;
-    }
-    for (int i = 0; i < n; ++i) {
-        reqs[i].admit_s = reqs[i].launch_s = reqs[i].done_s = -1.0;
-        reqs[i].status = DCTF_EBUSY;
-        reqs[i].batch = -1;
-    }
-    const int J = s->cfg.max_batch_jobs;
-    std::deque<int> pending;
-    int next = 0, finished = 0;
-    std::vector<dctf_job> jobs;
-    std::vector<char> table;
-    std::vector<dctf_operator> ops;
+    if (s->outstanding > 0)
+        return DCTF_EBUSY;   // requests of the online interface are still in the server
+    const double start = now_s();
+    s->t0 = start;
+    int next = 0, got = 0;
     dctf_status err = DCTF_OK;
-    const double t0 = now_s();
-
-    while (finished < n && err == DCTF_OK) {
-        bool progress = false;
-        double t = now_s() - t0;
-        while (next < n && reqs[next].arrival_s <= t) {
-            pending.push_back(next++);
-            progress = true;
+    dctf_request *done[64];
+    while (got < n) {
+        const double t = clock_s(s);
+        while (next < n && reqs[next].arrival_s <= t && err == DCTF_OK) {
+            const dctf_status st = dctf_server_submit(s, &reqs[next]);
+            if (st != DCTF_OK)
+                err = st;
+            else
+                ++next;
         }
-        int inflight = 0;
-        for (Slot &sl : s->slots) {
-            if (!sl.busy)
-                continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipSuccess) {
-                finished += (int)sl.reqs.size();
-                release_slot(s, sl, reqs, now_s() - t0);
-                progress = true;
-            } else if (q != hipErrorNotReady) {
-                err = DCTF_EHIP;
-            } else {
-                ++inflight;
+        if (err != DCTF_OK && next < n) {
+            // A device error (or no host memory): the rest never runs.
+            for (; next < n; ++next) {
+                reqs[next].admit_s = reqs[next].launch_s = -1.0;
+                reqs[next].done_s = clock_s(s);
+                reqs[next].status = err;
+                reqs[next].batch = -1;
+                ++got;
             }
         }
-        for (Slot &sl : s->slots) {
-            if (sl.busy || pending.empty() || err != DCTF_OK)
-                continue;
-            t = now_s() - t0;
-            jobs.clear();
-            while (!pending.empty() && (int)sl.reqs.size() < J) {
-                const int id = pending.front();
-                dctf_request &r = reqs[id];
-                const size_t bytes = align256((size_t)r.B * r.N * r.N * sizeof(float));
-                if (bytes > (size_t)s->cfg.arena_bytes) {
-                    pending.pop_front();
-                    r.status = DCTF_EBUSY;
-                    r.admit_s = r.done_s = t;
-                    ++s->stats.rejected;
-                    ++finished;
-                    continue;
-                }
-                size_t off;
-                if (!s->arena.alloc(bytes, &off))
-                    break;   // admit in arrival order: wait for memory
-                pending.pop_front();
-                CacheEntry *e = nullptr;
-                err = cache_get(s, r, sl.stream, &e);
-                if (err != DCTF_OK) {
-                    s->arena.release(off, bytes);
-                    break;
-                }
-                r.admit_s = t;
-                sl.reqs.push_back(id);
-                sl.offs.push_back(off);
-                sl.sizes.push_back(bytes);
-                sl.entries.push_back(e);
-                jobs.push_back({e->op, r.in_dev, reinterpret_cast<float *>(static_cast<char *>(s->arena_dev) + off),
-                                r.B});
-            }
-            if (sl.reqs.empty())
-                break;   // the head request waits for arena space
-            BatchArgs a;
-            err = plan_batch(jobs.data(), (int)jobs.size(), s->cfg.prec, table, a, ops);
-            if (err == DCTF_OK && table.size() > sl.table_cap)
-                err = DCTF_EINVAL;
-            if (err == DCTF_OK) {
-                memcpy(sl.table_host, table.data(), table.size());
-                hipError_t e = hipMemcpyAsync(sl.table_dev, sl.table_host, table.size(), hipMemcpyHostToDevice,
-                                              sl.stream);
-                rebase_batch(a, sl.table_dev);
-                if (e == hipSuccess)
-                    e = launch_batch(a, sl.stream);
-                for (size_t k = 0; k < sl.reqs.size() && e == hipSuccess; ++k) {
-                    dctf_request &r = reqs[sl.reqs[k]];
-                    if (r.out_dev)
-                        e = hipMemcpyAsync(r.out_dev, jobs[k].out, (size_t)r.B * r.N * r.N * sizeof(float),
-                                           hipMemcpyDeviceToDevice, sl.stream);
-                }
-                if (e == hipSuccess)
-                    e = hipEventRecord(sl.done, sl.stream);
-                if (e != hipSuccess)
-                    err = DCTF_EHIP;
-            }
-            const double tl = now_s() - t0;
-            for (int id : sl.reqs) {
-                reqs[id].launch_s = tl;
-                reqs[id].batch = (int)s->stats.batches;
-            }
-            ++s->stats.batches;
-            sl.busy = true;
-            ++inflight;
-            progress = true;
-            s->stats.peak_inflight_batches = std::max<int64_t>(s->stats.peak_inflight_batches, inflight);
-            s->stats.peak_arena_bytes = std::max<int64_t>(s->stats.peak_arena_bytes, (int64_t)s->arena.used());
-        }
-        (void)progress;   // the loop polls: arrivals are due at wall-clock times
+        int k = 0;
+        const dctf_status st = dctf_server_poll(s, 0.0, done, 64, &k);
+        got += k;
+        if (st != DCTF_OK && err == DCTF_OK)
+            err = st;
+        if (err != DCTF_OK && s->outstanding == 0)
+            break;
     }
-    // Drain whatever is still in flight (also after an error).
-    for (Slot &sl : s->slots) {
-        if (!sl.busy)
-            continue;
-        const hipError_t e = hipEventSynchronize(sl.done);
-        if (e != hipSuccess && err == DCTF_OK)
-            err = DCTF_EHIP;
-        release_slot(s, sl, reqs, now_s() - t0);
-    }
-    s->stats.busy_s += now_s() - t0;
+    s->stats.busy_s += now_s() - start;
     return err;
 }

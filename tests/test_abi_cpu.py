@@ -169,3 +169,15 @@ def test_server_config_validation(lib):
     assert lib.dctf_server_create(None, ctypes.byref(out)) == -1
     assert lib.dctf_server_run(None, None, 0) == -1
     assert lib.dctf_server_stats_get(None, None) == -1
+
+
+def test_server_online_calls_validate_on_the_host(lib):
+    import paper_1710_07193_amd as dctf
+    lib.dctf_server_clock.restype = ctypes.c_double
+    assert lib.dctf_server_clock(None) == -1.0
+    assert lib.dctf_server_submit(None, None) == -1
+    n = ctypes.c_int(7)
+    assert lib.dctf_server_poll(None, ctypes.c_double(0.0), None, 0, ctypes.byref(n)) == -1
+    # a server handle is needed for the request checks; without a GPU none can be made,
+    # so the request validation is covered by the GPU tests (NaN mask, bad N, alignment)
+    assert dctf.DCTF_EINVAL == -1

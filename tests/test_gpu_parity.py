@@ -358,3 +358,37 @@ def test_verify_kernel_counts(dctf):
     exp.reshape(-1)[flip] ^= 1
     _, cnt2 = gpu_u8(dctf, N, Yref.astype(np.float32), exp)
     assert cnt2[0] == 5
+
+
+@pytest.mark.parametrize("N,prec", [(8, FP32), (8, SPLIT), (16, FP32), (16, SPLIT)])
+def test_every_variant_over_many_steps_per_wave(dctf, N, prec):
+    """An input long enough that every wave of every variant runs its loop
+    for several steps (the prefix tests above stay within a step or two):
+    every variant bit-identical to variant 0, and variant 0 against the
+    oracle on sampled outputs."""
+    B = 1500037 if N == 8 else 400021
+    rng = np.random.default_rng(57)
+    W = syn.random_mask(rng, 5, 5)
+    op = dctf.dctf_build_operator(W, N, R)
+    X = torch.randn(B * N * N, device="cuda") * 40
+    X.view(B, N * N)[:, 0] += 1000.0
+    v0 = dctf.dctf_get_variant(N, prec)
+    try:
+        dctf.dctf_set_variant(N, prec, 0)
+        ref = torch.empty_like(X)
+        dctf.dctf_filter_blocks(op, prec, X, ref)
+        torch.cuda.synchronize()
+        bi = rng.integers(0, B, 3000)
+        ci = rng.integers(0, N * N, 3000)
+        want = oracle.filter_coeffs_sampled(X.view(B, N * N)[torch.from_numpy(bi).cuda()].cpu().numpy(),
+                                            W, R, np.arange(3000), ci)
+        got = ref.view(B, N * N)[torch.from_numpy(bi).cuda(), torch.from_numpy(ci).cuda()].cpu().numpy()
+        assert np.abs(got - want).max() <= TOL[prec]
+        for v in range(1, dctf.dctf_variant_count(N, prec)):
+            dctf.dctf_set_variant(N, prec, v)
+            Y = torch.full_like(X, float("nan"))
+            dctf.dctf_filter_blocks(op, prec, X, Y)
+            torch.cuda.synchronize()
+            assert torch.equal(Y, ref), dctf.dctf_variant_name(N, prec, v)
+    finally:
+        dctf.dctf_set_variant(N, prec, v0)

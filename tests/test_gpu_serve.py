@@ -137,3 +137,88 @@ def test_malformed_request_lists(dctf):
         dctf.dctf_server_run(server, bad_order)
     with pytest.raises(dctf.DctfError):
         dctf.dctf_server_run(server, [dict(arrival_s=0.0, mask=masks[0].mask, N=4, border=0, X=X)])
+
+
+def test_malformed_mask_runs_nothing(dctf):
+    """A NaN in one request's mask makes the whole list malformed: nothing runs."""
+    masks = syn.mask_set_32()[:1]
+    X = torch.randn(300 * 64, device="cuda")
+    Y = torch.full_like(X, float("nan"))
+    bad = masks[0].mask.copy()
+    bad[0, 0] = float("nan")
+    server = dctf.dctf_server_create(arena_bytes=1 << 24)
+    reqs = [dict(arrival_s=0.0, mask=masks[0].mask, N=8, border=0, X=X, Y=Y),
+            dict(arrival_s=0.0, mask=bad, N=8, border=0, X=X)]
+    with pytest.raises(dctf.DctfError) as e:
+        dctf.dctf_server_run(server, reqs)
+    assert e.value.status == dctf.DCTF_EINVAL
+    torch.cuda.synchronize()
+    assert torch.isnan(Y).all()
+    assert dctf.dctf_server_stats(server)["batches"] == 0
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_server_submit(server, bad, 8, 0, X)
+    # the server still serves after the rejected calls
+    res = dctf.dctf_server_run(server, reqs[:1])
+    assert res[0]["status"] == 0 and not torch.isnan(Y).any()
+
+
+@pytest.mark.parametrize("prec", [SPLIT, FP32])
+def test_online_submit_and_poll(dctf, prec):
+    """Requests submitted one by one while earlier ones are on the GPU: every
+    request completes once, with the result of a single-operator call."""
+    masks = syn.mask_set_32()
+    rng = np.random.default_rng(8)
+    server = dctf.dctf_server_create(arena_bytes=1 << 28, max_inflight=3, max_batch_jobs=6, prec=prec)
+    reqs, done = [], []
+    for i in range(40):
+        N = 16 if i % 5 == 0 else 8
+        X = torch.randn(int(rng.integers(1, 20000)) * N * N, device="cuda") * 50
+        m = masks[int(rng.integers(0, len(masks)))]
+        r = dctf.dctf_server_submit(server, m.mask, N, m.border, X, torch.full_like(X, float("nan")))
+        reqs.append((r, m, N, X))
+        if i % 3 == 0:
+            done += dctf.dctf_server_poll(server)
+    while len(done) < len(reqs):
+        got = dctf.dctf_server_poll(server, wait_s=1.0)
+        assert got, "no request completed within a second"
+        done += got
+    assert len({id(r) for r in done}) == len(reqs)
+    assert dctf.dctf_server_poll(server) == []
+    stats = dctf.dctf_server_stats(server)
+    assert stats["batches"] >= 2 and stats["failed"] == 0
+    torch.cuda.synchronize()
+    for r, m, N, X in reqs:
+        assert r.status == 0 and 0 <= r.admit_s <= r.launch_s <= r.done_s
+        op = dctf.dctf_build_operator(m.mask, N, m.border)
+        Y = torch.empty_like(X)
+        dctf.dctf_filter_blocks(op, prec, X, Y)
+        torch.cuda.synchronize()
+        assert torch.equal(r.keep[2], Y)
+
+
+@pytest.mark.parametrize("prec", [SPLIT, FP32])
+def test_served_outputs_match_oracle(dctf, prec):
+    """Requests shaped like the serving workload (image sides that are
+    multiples of 8, N = 8 or 16 with replication padding to whole blocks, the
+    32-mask set): each served output against the FP64 oracle directly."""
+    import oracle
+    tol = 5e-3 if prec == SPLIT else 2e-3
+    masks = syn.mask_set_32()
+    rng = np.random.default_rng(31)
+    reqs, refs = [], []
+    for k in range(10):
+        N = 16 if k % 3 == 0 else 8
+        h, w = int(rng.choice(np.arange(256, 769, 8))), int(rng.choice(np.arange(256, 769, 8)))
+        m = masks[(7 * k) % len(masks)]
+        px = oracle.tile_u8(syn.image_u8(700 + k, h, w), N)
+        X = torch.from_numpy(oracle.coeffs_fp32(px).reshape(-1)).cuda()
+        reqs.append(dict(arrival_s=k * 2e-5, mask=m.mask, N=N, border=m.border, X=X,
+                         Y=torch.full_like(X, float("nan"))))
+        refs.append(oracle.filter_pixels(px, m.mask, m.border)[0])
+    server = dctf.dctf_server_create(arena_bytes=1 << 28, max_inflight=4, max_batch_jobs=4, prec=prec)
+    res = dctf.dctf_server_run(server, reqs)
+    torch.cuda.synchronize()
+    for r, q, ref in zip(res, reqs, refs):
+        assert r["status"] == 0
+        err = np.abs(q["Y"].cpu().numpy().reshape(ref.shape) - ref).max()
+        assert err <= tol, err
