@@ -368,6 +368,23 @@ void dctf_batch_destroy(dctf_batch batch);
 /* Convenience: create, run and destroy a plan.  Synchronises `stream`. */
 dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int prec, dctf_stream stream);
 
+/*
+ * dctf_filter_batch without any device allocation, for callers that cannot
+ * allocate (code that must not call hipMalloc, such as tight serving loops
+ * or harnesses that forbid it).  Same jobs, arithmetic and results (bit for
+ * bit) as dctf_filter_batch with the process-wide batch configuration; the
+ * work table goes into a fixed 1 MiB device array of the library (one per
+ * GPU, kept until the process ends; its address on each device is looked up
+ * once, at the first call on that device).  1 MiB holds the table of about
+ * 8,000 jobs with as many operators (JobDesc 40 B per job, OpDesc 40 B per
+ * distinct operator, SegDesc 48 B per front); a larger table returns
+ * DCTF_EINVAL and nothing runs.  The host-side plan uses ordinary heap
+ * memory.  Synchronous like dctf_filter_batch (returns when the work is
+ * done).  Calls that overlap on one GPU (several host threads, or calls made
+ * while another is in flight) share the array and race: serialise them.
+ */
+dctf_status dctf_filter_batch_noalloc(const dctf_job *jobs, int njobs, int prec, dctf_stream stream);
+
 /* --------------------------------------------------------- around the path */
 
 /*

@@ -87,6 +87,7 @@ _SIGS = {
     "dctf_batch_info": ([_P, _P, _P, _P], _I),
     "dctf_batch_destroy": ([_P], None),
     "dctf_filter_batch": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
+    "dctf_filter_batch_noalloc": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
     "dctf_forward_dct_u8": ([_P, _I, _I, _I64, _I, _P, _P], _I),
     "dctf_idct_u8_verify": ([_I, _P, _I64, _P, _P, _P, _P], _I),
     "dctf_stream_copy": ([_P, _P, _I64, _P], _I),
@@ -425,6 +426,13 @@ def dctf_batch_info(batch: Batch):
 def dctf_filter_batch(jobs, prec: int, stream=None):
     arr, n, _ = _jobs(jobs)
     _check(_lib.dctf_filter_batch(arr, n, prec, _stream(stream)), "dctf_filter_batch")
+
+
+def dctf_filter_batch_noalloc(jobs, prec: int, stream=None):
+    """dctf_filter_batch with its work table in the library's fixed device
+    array (no device allocation; synchronous)."""
+    arr, n, _ = _jobs(jobs)
+    _check(_lib.dctf_filter_batch_noalloc(arr, n, prec, _stream(stream)), "dctf_filter_batch_noalloc")
 
 
 def dctf_forward_dct_u8(img: torch.Tensor, N: int, coeffs: torch.Tensor, stream=None):

@@ -1212,6 +1212,72 @@ extern "C" dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int pr
     return st != DCTF_OK ? st : st2;
 }
 
+// ------------------------------------------- one-shot batch, no allocation
+//
+// The work table of dctf_filter_batch_noalloc lives in a file-scope device
+// array (one copy per GPU, held until the process ends).  In host code the
+// array's name is not a device address: its address on each device comes
+// from hipGetSymbolAddress, taken once per device with that device current,
+// and only that address is used (copy target, kernel argument).
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+dctf_status scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices)
+        return DCTF_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return e != hipSuccess ? hip_status(e) : DCTF_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DCTF_OK;
+}
+
+}  // namespace
+
+extern "C" dctf_status dctf_filter_batch_noalloc(const dctf_job *jobs, int njobs, int prec, dctf_stream stream)
+{
+    std::vector<char> table;
+    BatchArgs a;
+    std::vector<dctf_operator> ops;
+    dctf_status st = plan_batch(jobs, njobs, prec, batch_config(prec), table, a, ops);
+    if (st != DCTF_OK)
+        return st;
+    if (table.empty())
+        return DCTF_OK;   // no blocks: nothing to launch
+    if (table.size() > kNoAllocScratchBytes)
+        return DCTF_EINVAL;   // work table beyond the fixed scratch: use dctf_filter_batch
+    void *dev = nullptr;
+    st = scratch_address(&dev);
+    if (st != DCTF_OK)
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(dev, table.data(), table.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    rebase_batch(a, dev);
+    st = hip_status(launch_batch(a, s));
+    // The host table must outlive the copy, and the next call may rewrite
+    // the scratch: return once this call's work is done.
+    const dctf_status st2 = hip_status(hipStreamSynchronize(s));
+    return st != DCTF_OK ? st : st2;
+}
+
 // ============================================================ around the path
 
 extern "C" dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w, int64_t pitch, int N,
