@@ -42,8 +42,8 @@ def parse():
                     help="offered-load seconds per serving rate (0 skips the serving sweep)")
     ap.add_argument("--no-tuning", action="store_true",
                     help="ignore the persisted tuning table (built-in launch defaults)")
-    ap.add_argument("--tune", action="store_true",
-                    help="run the batch autotuner on the headline plan before timing it")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the batch autotuner on the headline plan (it runs by default before timing)")
     return ap.parse_args()
 
 
@@ -132,9 +132,28 @@ def progress(msg):
 T0 = time.perf_counter()
 
 
-def timed_steps(torch, fn, steps, warmup, stream):
+def settle(torch, fn, stream, min_ms=30.0, min_calls=30):
+    """Runs `fn` until at least `min_calls` calls and `min_ms` of device time
+    have passed: the chip's clock settles for tens of launches after the load
+    changes (the extras measure each kernel at its settled clock)."""
+    calls, t = 0, 0.0
+    while calls < min_calls or t < min_ms:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t += e0.elapsed_time(e1)
+        calls += 10
+
+
+def timed_steps(torch, fn, steps, warmup, stream, settle_first=False):
     for _ in range(warmup):
         fn()
+    if settle_first:
+        settle(torch, fn, stream)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -146,10 +165,12 @@ def timed_steps(torch, fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def replay_times(torch, fn, steps, warmup, stream):
+def replay_times(torch, fn, steps, warmup, stream, settle_first=False):
     """Per-call times (ms) of `steps` calls after `warmup` untimed ones."""
     for _ in range(warmup):
         fn()
+    if settle_first:
+        settle(torch, fn, stream)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
@@ -224,7 +245,7 @@ def pixel_outputs(dctf, torch, stream, X, N, steps, warmup):
         for src, fn, per_coef in (
                 ("coeffs_f32", lambda: dctf.dctf_filter_blocks_u8(op, p, X, pix, stream), 5),
                 ("quantized_s16", lambda: dctf.dctf_filter_quantized_u8(op, p, Q, qt, dc, pix, stream), 3)):
-            ms = timed_steps(torch, fn, steps, warmup, stream)
+            ms = timed_steps(torch, fn, steps, warmup, stream, settle_first=True)
             gbs = B * nn * per_coef / (ms * 1e-3) / 1e9
             res["%s_to_u8_%s" % (src, pname)] = {
                 "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "alg_bytes_per_block": nn * per_coef,
@@ -269,7 +290,7 @@ def image_level(dctf, torch, stream, X, Y, images, side, N, steps, warmup):
         op = dctf.dctf_build_image_operator(W, N, border)
         for pname, p in (("fp32", dctf.DCTF_PREC_FP32), ("split", dctf.DCTF_PREC_SPLIT_BF16)):
             ms = timed_steps(torch, lambda: dctf.dctf_filter_image(op, p, X, Y, Bh, Bw, stream), steps, warmup,
-                             stream)
+                             stream, settle_first=True)
             tf = flops / (ms * 1e-3) / 1e12
             ent = {"ms_per_launch": ms, "blocks_per_s": res["blocks"] / (ms * 1e-3), "TFLOPs": tf}
             if p == dctf.DCTF_PREC_FP32:
@@ -288,9 +309,9 @@ def fp64_filter(dctf, torch, stream, X, N, steps, warmup):
     X64 = X.double()
     Y64 = torch.empty_like(X64)
     op = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, dctf.DCTF_BORDER_REPLICATE)
-    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream)
+    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream, settle_first=True)
     cms = timed_steps(torch, lambda: dctf.dctf_stream_copy(X64.view(torch.float32), Y64.view(torch.float32), stream),
-                      steps, warmup, stream)
+                      steps, warmup, stream, settle_first=True)
     bytes_ = B * nn * 16
     res = {"blocks": B, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": bytes_ / (ms * 1e-3) / 1e9,
            "frac_of_8TBps": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "copy_GBps": bytes_ / (cms * 1e-3) / 1e9,
@@ -318,7 +339,7 @@ def n16_frames(dctf, torch, stream, steps, warmup):
     B = frames * nb
     res = {"blocks": B, "alg_bytes_per_launch": B * N * N * 8}
     for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
-        ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, p, X, Y, stream), steps, warmup, stream)
+        ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, p, X, Y, stream), steps, warmup, stream, settle_first=True)
         res[pname] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
                       "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9,
                       "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
@@ -328,7 +349,7 @@ def n16_frames(dctf, torch, stream, steps, warmup):
     gop = dctf.dctf_build_operator(syn.gaussian_mask(7), N, dctf.DCTF_BORDER_ZERO)
     for tag, o in (("mask7x7", op), ("gauss7x7", gop)):
         rank = dctf.dctf_operator_rank(o)
-        fms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_factored(o, X, Y, stream), steps, warmup, stream)
+        fms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_factored(o, X, Y, stream), steps, warmup, stream, settle_first=True)
         ent = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
                "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
         if tag == "gauss7x7":
@@ -350,7 +371,7 @@ def verify_frames(dctf, torch, stream, Y, N, steps, warmup):
     """The verify kernel (inverse DCT + uint8, no counters) over the filtered
     frames: 4 B read and 1 B written per coefficient."""
     pix = torch.empty(Y.numel(), dtype=torch.uint8, device="cuda")
-    ms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None, stream), steps, warmup, stream)
+    ms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None, stream), steps, warmup, stream, settle_first=True)
     del pix
     return {"ms_per_launch": ms, "GBps": Y.numel() * 5 / (ms * 1e-3) / 1e9}
 
@@ -361,7 +382,7 @@ def fp64_frames(dctf, torch, stream, op, X, N, steps, warmup):
     B = X.numel() // (N * N)
     X64 = X.double()
     Y64 = torch.empty_like(X64)
-    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream)
+    ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_f64(op, X64, Y64, stream), steps, warmup, stream, settle_first=True)
     tf = B * 2.0 * (N * N) ** 2 / (ms * 1e-3) / 1e12
     del X64, Y64
     torch.cuda.empty_cache()
@@ -389,13 +410,13 @@ def n32_frames(dctf, torch, stream, steps, warmup):
     op = dctf.dctf_build_operator(syn.random_mask(np.random.default_rng(7), 7, 7), N, dctf.DCTF_BORDER_ZERO)
     B = frames * nb
     ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, dctf.DCTF_PREC_FP32, X, Y, stream), steps, warmup,
-                     stream)
+                     stream, settle_first=True)
     tf = B * 2.0 * (N * N) ** 2 / (ms * 1e-3) / 1e12
     res = {"blocks": B, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
            "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "fp32_mfma_TFLOPs": tf,
            "frac_of_fp32_mfma_peak": tf / FP32_MFMA_PEAK_TFLOPS}
     ms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op, dctf.DCTF_PREC_SPLIT_BF16, X, Y, stream), steps,
-                     warmup, stream)
+                     warmup, stream, settle_first=True)
     tf = B * 3 * 2.0 * (N * N) ** 2 / (ms * 1e-3) / 1e12
     res["split_bf16"] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
                          "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "bf16_mfma_TFLOPs": tf,
@@ -595,9 +616,13 @@ def main():
     per = nblk * N * N
     batch = dctf.dctf_batch_create(jobs, prec)
     live_tune = None
-    if args.tune:
+    if not args.no_tune:
+        # The autotuner chooses the headline plan's launch configuration on
+        # the plan itself (its jobs and buffers), after its own warm-up.
+        t_tune = time.perf_counter()
         best, table = dctf.dctf_batch_autotune(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, 10, 3)
-        live_tune = {"chosen": table[best][0], "ms_per_launch": table[best][1], "candidates": len(table)}
+        live_tune = {"chosen": table[best][0], "ms_per_launch": table[best][1], "candidates": len(table),
+                     "seconds": round(time.perf_counter() - t_tune, 2)}
     plan_cfg, plan_resolved = dctf.dctf_batch_get_config(batch)
     setup_s = time.perf_counter() - t_setup
     progress("inputs and operators ready")
@@ -673,11 +698,26 @@ def main():
     del pix, cnt
 
     # achievable-HBM reference: a plain copy of the same bytes (X -> Y)
-    cms = timed_steps(torch, lambda: dctf.dctf_stream_copy(X, Y, stream), args.steps, args.warmup, stream)
+    cms = timed_steps(torch, lambda: dctf.dctf_stream_copy(X, Y, stream), args.steps, args.warmup, stream, settle_first=True)
     copy_gbs = alg_bytes / (cms * 1e-3) / 1e9
     out["roofline"]["stream_copy_GBps"] = copy_gbs
     out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     progress("headline timed")
+
+    # The chip's power management lowers the clock for tens of launches after
+    # an idle spell when this load starts (then raises it again): the same
+    # step from idle, one event pair per launch, beside the copy kernel.
+    cold = None
+    if not args.no_extras:
+        time.sleep(2.0)
+        per = replay_times(torch, step, 40, 0, stream)
+        time.sleep(2.0)
+        per_copy = replay_times(torch, lambda: dctf.dctf_stream_copy(X, Y, stream), 40, 0, stream)
+        cold = {"idle_s": 2.0, "step_ms": [round(t, 4) for t in per],
+                "step_ms_mean_first25": float(np.mean(per[:25])), "step_ms_mean_last10": float(np.mean(per[-10:])),
+                "copy_ms_mean_first25": float(np.mean(per_copy[:25])),
+                "copy_ms_mean_last10": float(np.mean(per_copy[-10:]))}
+        progress("cold restart series")
 
     if not args.no_extras:
         extras = {}
@@ -687,7 +727,7 @@ def main():
         with torch.cuda.stream(side_stream):
             dctf.dctf_batch_capture(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, side_stream)
             per_replay = replay_times(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
-                                      args.steps, args.warmup, side_stream)
+                                      args.steps, args.warmup, side_stream, settle_first=True)
         extras["graph_replay"] = {"replays": len(per_replay), "ms_median": float(np.median(per_replay)),
                                   "ms_p99": float(np.percentile(per_replay, 99)),
                                   "blocks_per_s_median": B / (float(np.median(per_replay)) * 1e-3)}
@@ -695,7 +735,7 @@ def main():
         other = dctf.DCTF_PREC_FP32 if prec == dctf.DCTF_PREC_SPLIT_BF16 else dctf.DCTF_PREC_SPLIT_BF16
         ob = dctf.dctf_batch_create(jobs, other)
         oms = timed_steps(torch, lambda: dctf.dctf_batch_run(ob, dctf.DCTF_RUN_REBUILD_OPERATORS, stream),
-                          args.steps, args.warmup, stream)
+                          args.steps, args.warmup, stream, settle_first=True)
         extras["fp32" if other == dctf.DCTF_PREC_FP32 else "split_bf16"] = {
             "ms_per_step": oms, "blocks_per_s": B / (oms * 1e-3),
             "split_over_fp32_speedup": (oms / ms) if other == dctf.DCTF_PREC_FP32 else (ms / oms)}
@@ -706,7 +746,7 @@ def main():
             op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, border)
             for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
                 sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
-                                  args.steps, args.warmup, stream)
+                                  args.steps, args.warmup, stream, settle_first=True)
                 extras["mask5x5_%s_single_op_%s" % (bname, pname)] = {
                     "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
                     "GBps": alg_bytes / (sms * 1e-3) / 1e9,
@@ -721,9 +761,10 @@ def main():
         extras["fp64"] = fp64_filter(dctf, torch, stream, X, N, max(10, args.steps // 2), max(5, args.warmup // 3))
         # optional verify kernel: inverse DCT + uint8 of every output block
         pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
-        vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream)
+        vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream, settle_first=True)
         extras["verify_kernel_ms"] = vms
         out["extras"] = extras
+        extras["cold_restart"] = cold
         del pix
         extras["forward_dct_ingest"] = forward_dct_ingest(dctf, torch, stream, args.images, args.side, N, Y, 5, 2)
         progress("FP64 filter, verify kernel, forward DCT")
