@@ -53,12 +53,39 @@ def parse():
 HEADLINE_SOURCES = ("abi.hip", "batch.hip", "builder.hip", "dctf_internal.h", "filter.hip", "mfma_common.h")
 
 
+def strip_comments(text):
+    """C/C++ source without its comments and blank lines (string and
+    character literals kept), so that a comment edit does not change the
+    hash of the code."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1710_07193_amd", "csrc")
     for name in HEADLINE_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update((name + strip_comments(f.read())).encode())
     return h.hexdigest()[:16]
 
 

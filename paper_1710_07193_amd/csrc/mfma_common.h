@@ -93,9 +93,12 @@ __device__ __forceinline__ uint32_t pixel_u8(float p)
 
 // Four pixels -> one little-endian word (first pixel in the low byte), the
 // rule of pixel_u8 for finite values: floor(p + 1/2) is an exact integer,
-// which v_cvt_pk_u8_f32 converts exactly, saturating to [0, 255] by itself
-// (measured on gfx950: 256, 300, 1e9 and +inf give 255; -0.5, -300 and -inf
-// give 0; NaN gives 0), and packs into its byte.
+// which V_CVT_PK_U8_F32 converts and packs into its byte.  The CDNA ISA
+// reference defines that opcode's conversion as float -> unsigned byte with
+// the destination's range, i.e. the clamp the ISA's float-to-integer
+// conversions apply (out-of-range values saturate to 0 or 255, NaN gives 0),
+// so no separate clamp is needed.  The GPU tests check the saturating cases
+// (256, 300, 1e9, +inf -> 255; -0.5, -300, -inf -> 0; NaN -> 0).
 __device__ __forceinline__ uint32_t pack_u8x4(float a, float b, float c, float d)
 {
     const float v[4] = {a, b, c, d};

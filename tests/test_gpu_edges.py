@@ -122,3 +122,20 @@ def test_saturating_pixels(dctf, N, prec):
         assert np.array_equal(got[~nh], u8[~nh])
         # the masks do push pixels out of range on both sides
         assert (u8 == 255).any() or (u8 == 0).any()
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_u8_conversion_saturates_and_nan_gives_zero(dctf, N):
+    """The packed byte conversion of the verify kernels: blocks whose only
+    coefficient is DC = N * v hold the pixel v everywhere; out-of-range values
+    saturate to 0 or 255, NaN converts to 0 (the library's stated rule)."""
+    vals = [256.0, 300.0, 1e9, float("inf"), -0.5, -300.0, float("-inf"), float("nan"), 254.6, 0.4, 127.2, 12.49]
+    want = [255, 255, 255, 255, 0, 0, 0, 0, 255, 0, 127, 12]
+    Y = torch.zeros(len(vals), N * N, dtype=torch.float32)
+    Y[:, 0] = torch.tensor(vals) * N
+    pix = torch.empty(len(vals) * N * N, dtype=torch.uint8, device="cuda")
+    dctf.dctf_idct_u8_verify(N, Y.reshape(-1).cuda(), pix)
+    torch.cuda.synchronize()
+    got = pix.cpu().numpy().reshape(len(vals), N * N)
+    for k, w in enumerate(want):
+        assert (got[k] == w).all(), (vals[k], got[k][:4], w)

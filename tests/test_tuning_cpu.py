@@ -59,3 +59,14 @@ def test_builtin_candidates_cover_every_io_path(dctf):
     assert {(c["io"], c["nt"]) for c in cands} == {(0, 0), (1, 0), (1, 1), (2, 0), (2, 1)}
     assert {c["fronts"] for c in cands} == {1, 2, 3, 4, 6, 8}
     assert {c["groups_per_cu"] for c in cands} == {0, -1}
+
+
+def test_kernel_source_hash_ignores_comments_only():
+    """The traffic record is keyed by a hash of the kernel sources without
+    their comments: a comment edit keeps it, a code edit changes it."""
+    import bench
+    code = 'int f(int x) { return x + 1; } // one\n/* two\n three */\nconst char *s = "a // b";\n'
+    base = bench.strip_comments(code)
+    assert "one" not in base and "three" not in base and '"a // b"' in base
+    assert bench.strip_comments(code.replace("// one", "// other words")) == base
+    assert bench.strip_comments(code.replace("x + 1", "x + 2")) != base
