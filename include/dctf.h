@@ -273,10 +273,11 @@ dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *
  * class decides which neighbours exist and where reads are clamped.  The
  * builder forms all 16 class pairs x 9 offsets in FP64 on the GPU, with
  * their FP32 and split-BF16 MFMA fragments (N = 8: 4.7 MB FP64 + 2.4 MB
- * FP32 + 2.6 MB split); each operator's DC column is applied in FP32 VALU
- * arithmetic after all other products.
+ * FP32 + 2.6 MB split; N = 16: 75.5 MB + 37.7 MB + 39 MB); each operator's
+ * DC column is applied in FP32 VALU arithmetic after all other products.
  * Masks: 1 <= kh, kw <= 2N + 1 (a mask never reaches past a neighbour).
- * Errors: as dctf_build_operator; DCTF_EUNSUPPORTED for N != 8.
+ * Errors: as dctf_build_operator; DCTF_EUNSUPPORTED for N other than 8
+ * and 16.
  * Synchronises `stream` (the mask copy is from host memory).
  */
 dctf_status dctf_build_image_operator(const double *mask_host, int kh, int kw, int N, int border,
@@ -298,11 +299,12 @@ void dctf_image_operator_destroy(dctf_image_operator op);
  * nimg or on where the block falls in the work partition.
  *   in_dev, out_dev  device, 16-byte aligned, non-overlapping.
  *   prec             DCTF_PREC_FP32, or DCTF_PREC_SPLIT_BF16 (per neighbour
- *                    the split of dctf_filter_blocks at N = 8: 8 low-frequency
- *                    inputs in FP32 MFMA, the others BF16 hi.hi + hi.lo +
- *                    lo.hi).
+ *                    the split of dctf_filter_blocks at the same N: 8
+ *                    low-frequency inputs in FP32 MFMA, the others BF16
+ *                    hi.hi + hi.lo + lo.hi).
  * nimg = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned, overlap,
- * Bh or Bw < 1, nimg < 0), DCTF_EUNSUPPORTED, DCTF_EHIP.
+ * Bh or Bw < 1, nimg < 0), DCTF_EUNSUPPORTED (N = 16 with Bw > 131072),
+ * DCTF_EHIP.
  */
 dctf_status dctf_filter_image(dctf_image_operator op, int prec, const float *in_dev, float *out_dev, int Bh,
                               int Bw, int64_t nimg, dctf_stream stream);

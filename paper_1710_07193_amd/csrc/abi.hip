@@ -595,7 +595,7 @@ extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh
     dctf_status st = validate_mask(mask_host, kh, kw, N, border);
     if (st != DCTF_OK)
         return st;
-    if (N != 8)
+    if (N != 8 && N != 16)
         return DCTF_EUNSUPPORTED;
     const size_t NN = (size_t)N * N, nops = (size_t)kImageClassPairs * kImageOffsets;
     size_t off = 0;
@@ -640,7 +640,7 @@ extern "C" dctf_status dctf_build_image_operator(const double *mask_host, int kh
         a.frag_lo = op->frag_lo;
         a.frag_lf = op->frag_lf;
         a.h0 = op->h0;
-        st = hip_status(launch_build_image(a, s));
+        st = hip_status(launch_build_image(N, a, s));
     }
     // the mask copy is from pageable memory: complete it before returning
     if (st == DCTF_OK)
@@ -723,6 +723,10 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
         return DCTF_EINVAL;
     if (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16)
         return DCTF_EINVAL;
+    // N = 16 addresses a tile's blocks with 32-bit byte offsets from the tile's
+    // first block (16 blocks a block row apart: 16 KiB per block of width)
+    if (op->N == 16 && Bw > kImage16MaxBw)
+        return DCTF_EUNSUPPORTED;
     const int64_t B = (int64_t)Bh * Bw * nimg;
     dctf_status st = validate_io(op->N, in_dev, out_dev, B);
     if (st != DCTF_OK || B == 0)
@@ -741,7 +745,7 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
     a.h0 = op->h0;
     Run rr[3], cr[3];
     const int nr = class_runs(Bh, rr), nc = class_runs(Bw, cr);
-    const int T = image_tiles_per_unit(prec);
+    const int T = image_tiles_per_unit(op->N, prec);
     int64_t units = 0;
     for (int i = 0; i < nr; ++i)
         for (int j = 0; j < nc; ++j) {
@@ -761,7 +765,7 @@ extern "C" dctf_status dctf_filter_image(dctf_image_operator op, int prec, const
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);
-    st = hip_status(launch_filter_image(prec, a, s));
+    st = hip_status(launch_filter_image(op->N, prec, a, s));
     timing_end(s, slot);
     return st;
 }

@@ -180,7 +180,7 @@ struct ImageBuildArgs {
     const double *mask;   // kh * kw (device)
     int kh, kw, border;
     double *H64;          // [cp][o] N^2 x N^2, row-major
-    float *frag32;        // [cp][o] FP32 MFMA A fragments (N = 8 layout), DC column zeroed
+    float *frag32;        // [cp][o] FP32 MFMA A fragments (layout of the block's N), DC column zeroed
     uint16_t *frag_hi;    // [cp][o] BF16 hi / lo fragments, low-frequency columns zeroed
     uint16_t *frag_lo;
     float *frag_lf;       // [cp][o] FP32 fragments of the low-frequency columns, DC zeroed
@@ -212,9 +212,11 @@ struct ImageFilterArgs {
     const float *h0;
 };
 
-hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream);
-hipError_t launch_filter_image(int prec, const ImageFilterArgs &a, hipStream_t stream);
-int image_tiles_per_unit(int prec);
+hipError_t launch_build_image(int N, const ImageBuildArgs &args, hipStream_t stream);
+hipError_t launch_filter_image(int N, int prec, const ImageFilterArgs &a, hipStream_t stream);
+int image_tiles_per_unit(int N, int prec);
+// widest image (blocks) the N = 16 image-level kernel takes
+constexpr int kImage16MaxBw = 131072;
 
 // fp64.hip — FP64 filter (N = 8 MFMA, N <= 4 VALU) from the FP64 operator.
 hipError_t launch_filter_f64(int N, const double *H64, const double *in, double *out, int64_t B,

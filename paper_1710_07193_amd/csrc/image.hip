@@ -65,11 +65,11 @@ inline int64_t xcd_groups(int64_t waves, int per)
 constexpr int kThreads = 256;
 constexpr int kN = 8;
 constexpr int kNN = kN * kN;
-constexpr int kMaxK = 2 * kN + 1;
 
 // Source of output row i shifted by e in a block of class c: the neighbour
 // offset d (-1, 0, 1) and its row m; false if the source is dropped (zero
 // padding outside the image).
+template <int N>
 __device__ inline bool image_source(int i, int e, int c, int border, int *d, int *m)
 {
     int y = i + e;
@@ -78,96 +78,119 @@ __device__ inline bool image_source(int i, int e, int c, int border, int *d, int
             return false;
         y = 0;
     }
-    if (y >= kN && (c & 2)) {
+    if (y >= N && (c & 2)) {
         if (border == DCTF_BORDER_ZERO)
             return false;
-        y = kN - 1;
+        y = N - 1;
     }
-    *d = y < 0 ? -1 : (y >= kN ? 1 : 0);
-    *m = y - *d * kN;
+    *d = y < 0 ? -1 : (y >= N ? 1 : 0);
+    *m = y - *d * N;
     return true;
 }
 
-// One workgroup per (operator, class pair, offset, 16 output rows).
+// One workgroup per (class pair, offset, 16 output rows).  The mask rows p
+// are taken in chunks of PC (T_p, G_p and B_p of a chunk in LDS); the sum
+// over p runs in increasing p in every case, so the chunking does not change
+// a result.  N = 8 takes all rows in one chunk; N = 16 takes 8 at a time
+// (three N^2 arrays of 8 FP64 matrices: 48 KiB).
+template <int N, int PC>
 __global__ __launch_bounds__(kThreads) void k_build_image(ImageBuildArgs args)
 {
+    constexpr int NN = N * N, MaxK = 2 * N + 1;
+    constexpr int E = 16 * NN / kThreads;   // entries per thread
     const int cp = blockIdx.y, o = blockIdx.z;
     const int cr = cp >> 2, cs = cp & 3, dr = o / 3 - 1, ds = o % 3 - 1;
     const int r0 = blockIdx.x * 16;
     const ImageBuildArgs &d = args;
     const int kh = d.kh, kw = d.kw, ah = (kh - 1) / 2, aw = (kw - 1) / 2;
-    __shared__ double sC[kNN];
-    __shared__ double sW[kMaxK * kMaxK];
-    __shared__ double sT[kMaxK * kNN];   // T_p = A^{cr}_{dr, p - ah}
-    __shared__ double sG[kMaxK * kNN];   // G_p[j][l] = sum_q W[p][q] [row j reads m at ds] C[l][m]
-    __shared__ double sB[kMaxK * kNN];   // B_p = C G_p
+    __shared__ double sC[NN];
+    __shared__ double sW[MaxK * MaxK];
+    __shared__ double sT[PC * NN];   // T_p = A^{cr}_{dr, p - ah}
+    __shared__ double sG[PC * NN];   // G_p[j][l] = sum_q W[p][q] [row j reads m at ds] C[l][m]
+    __shared__ double sB[PC * NN];   // B_p = C G_p
     const int tid = threadIdx.x;
-    for (int e = tid; e < kNN; e += kThreads) {
-        const int k = e / kN, n = e % kN;
-        const double alpha = (k == 0) ? sqrt(1.0 / kN) : sqrt(2.0 / kN);
-        sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * kN));
+    for (int e = tid; e < NN; e += kThreads) {
+        const int k = e / N, n = e % N;
+        const double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);
+        sC[e] = alpha * cos(M_PI * (2.0 * n + 1.0) * k / (2.0 * N));
     }
     for (int e = tid; e < kh * kw; e += kThreads)
         sW[e] = d.mask[e];
-    __syncthreads();
-    for (int e = tid; e < 2 * kh * kNN; e += kThreads) {
-        const int which = e / (kh * kNN), rest = e % (kh * kNN);
-        const int p = rest / kNN, idx = rest % kNN, a = idx / kN, b = idx % kN;
-        double s = 0.0;
-        if (which == 0) {
-            // T_p[u][k] = sum_i C[u][i] C[k][m(i)] over rows i that read neighbour dr
-            for (int i = 0; i < kN; ++i) {
-                int dd, m;
-                if (image_source(i, p - ah, cr, d.border, &dd, &m) && dd == dr)
-                    s += sC[a * kN + i] * sC[b * kN + m];
+    double acc[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+        acc[j] = 0.0;
+    for (int p0 = 0; p0 < kh; p0 += PC) {
+        const int np = kh - p0 < PC ? kh - p0 : PC;
+        __syncthreads();
+        for (int e = tid; e < 2 * np * NN; e += kThreads) {
+            const int which = e / (np * NN), rest = e % (np * NN);
+            const int pl = rest / NN, p = p0 + pl, idx = rest % NN, a = idx / N, b = idx % N;
+            double s = 0.0;
+            if (which == 0) {
+                // T_p[u][k] = sum_i C[u][i] C[k][m(i)] over rows i that read neighbour dr
+                for (int i = 0; i < N; ++i) {
+                    int dd, m;
+                    if (image_source<N>(i, p - ah, cr, d.border, &dd, &m) && dd == dr)
+                        s += sC[a * N + i] * sC[b * N + m];
+                }
+                sT[pl * NN + idx] = s;
+            } else {
+                // G_p[j][l] with (j, l) = (a, b)
+                for (int q = 0; q < kw; ++q) {
+                    int dd, m;
+                    if (image_source<N>(a, q - aw, cs, d.border, &dd, &m) && dd == ds)
+                        s += sW[p * kw + q] * sC[b * N + m];
+                }
+                sG[pl * NN + idx] = s;
             }
-            sT[p * kNN + idx] = s;
-        } else {
-            // G_p[j][l] with (j, l) = (a, b)
-            for (int q = 0; q < kw; ++q) {
-                int dd, m;
-                if (image_source(a, q - aw, cs, d.border, &dd, &m) && dd == ds)
-                    s += sW[p * kw + q] * sC[b * kN + m];
-            }
-            sG[p * kNN + idx] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < np * NN; e += kThreads) {
+            const int pl = e / NN, idx = e % NN, v = idx / N, l = idx % N;
+            double s = 0.0;
+            for (int j = 0; j < N; ++j)
+                s += sC[v * N + j] * sG[pl * NN + j * N + l];
+            sB[e] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = tid + j * kThreads;
+            const int r = r0 + e / NN, c = e % NN;
+            const int u = r / N, v = r % N, k = c / N, l = c % N;
+            double s = acc[j];
+            for (int pl = 0; pl < np; ++pl)
+                s += sT[pl * NN + u * N + k] * sB[pl * NN + v * N + l];
+            acc[j] = s;
         }
     }
-    __syncthreads();
-    for (int e = tid; e < kh * kNN; e += kThreads) {
-        const int p = e / kNN, idx = e % kNN, v = idx / kN, l = idx % kN;
-        double s = 0.0;
-        for (int j = 0; j < kN; ++j)
-            s += sC[v * kN + j] * sG[p * kNN + j * kN + l];
-        sB[e] = s;
-    }
-    __syncthreads();
     const size_t opi = (size_t)cp * 9 + o;
-    double *H64 = d.H64 + opi * kNN * kNN;
-    float *F32 = d.frag32 + opi * kNN * kNN;
-    for (int e = tid; e < 16 * kNN; e += kThreads) {
-        const int r = r0 + e / kNN, c = e % kNN;
-        const int u = r / kN, v = r % kN, k = c / kN, l = c % kN;
-        double s = 0.0;
-        for (int p = 0; p < kh; ++p)
-            s += sT[p * kNN + u * kN + k] * sB[p * kNN + v * kN + l];
-        H64[(size_t)r * kNN + c] = s;
+    double *H64 = d.H64 + opi * NN * NN;
+    float *F32 = d.frag32 + opi * NN * NN;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int e = tid + j * kThreads;
+        const int r = r0 + e / NN, c = e % NN;
+        const double s = acc[j];
+        H64[(size_t)r * NN + c] = s;
         // the DC column goes to h0 (FP32 VALU in the filter), not to the MFMA images
         const float h32 = __double2float_rn(s);
-        F32[frag32_index(kN, r, c)] = c == 0 ? 0.0f : h32;
+        F32[frag32_index(N, r, c)] = c == 0 ? 0.0f : h32;
         if (c == 0)
-            d.h0[opi * kNN + r] = h32;
+            d.h0[opi * NN + r] = h32;
         // split images: low-frequency columns (DC zeroed) in FP32, the rest as
         // BF16 hi = bf16(fp32(H)), lo = bf16(fp32(H - hi))
-        const int q = lf_slot(kN, c);
+        const int q = lf_slot(N, c);
         uint16_t hi = 0, lo = 0;
         if (q >= 0) {
             const int t = r >> 4, m = r & 15, lane = 16 * (q >> 1) + m;
-            d.frag_lf[opi * kNN * lf_count(kN) + (t * 64 + lane) * 2 + (q & 1)] = c == 0 ? 0.0f : h32;
+            d.frag_lf[opi * NN * lf_count(N) + (t * 64 + lane) * 2 + (q & 1)] = c == 0 ? 0.0f : h32;
         } else {
             hi = bf16_rne(h32);
             lo = bf16_rne(__double2float_rn(s - (double)bf16_to_f32(hi)));
         }
-        const size_t fi = opi * kNN * kNN + frag16_index(kN, r, c);
+        const size_t fi = opi * NN * NN + frag16_index(N, r, c);
         d.frag_hi[fi] = hi;
         d.frag_lo[fi] = lo;
     }
@@ -393,21 +416,293 @@ constexpr int kImageT32 = 4;
 constexpr int kImageTSplit = 3;
 constexpr int kImageWavesPerCu = 8;
 
+// ------------------------------------------------------- filter, N = 16
+//
+// The block-local N = 16 kernel's structure per neighbour: a workgroup of 8
+// waves holds one 256 x 256 neighbour operator in VGPRs (wave w: output
+// rows 32w .. 32w + 31), and tiles of 16 blocks are staged in LDS once for
+// all 8 waves.  A unit is up to T tiles of one rectangle; for each neighbour
+// offset in turn the workgroup loads that operator (256 KiB, from L2: the 9
+// operators of the interior class pair, 2.25 MiB, stay in each XCD's L2)
+// and runs the unit's T neighbour tiles through it, accumulating into the T
+// tiles' registers.  Tile loads run D steps ahead over the (offset, tile)
+// sequence, also across an offset switch.  The DC coefficients of the
+// neighbour blocks are kept in LDS when a tile is staged and applied with
+// the operators' DC columns in FP32 VALU arithmetic after every MFMA
+// product, in offset order.  Workgroups take units in XCD order, so the
+// units of neighbouring block rows share an L2.
+
+struct ImgOp16F32 {
+    float A[2][16][4];
+};
+
+__device__ __forceinline__ void load_img_op16(ImgOp16F32 &R, const float *frag32, int wave, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float4 v = ld4(frag32 + (((2 * wave + t) * 16 + i) * 64 + lane) * 4);
+            R.A[t][i][0] = v.x;
+            R.A[t][i][1] = v.y;
+            R.A[t][i][2] = v.z;
+            R.A[t][i][3] = v.w;
+        }
+}
+
+// acc += A . X(tile in LDS), highest-frequency inputs first (FP32 path).
+__device__ __forceinline__ void mac16(const ImgOp16F32 &R, const float *lds, int lane, f32x4 acc[2])
+{
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+        const float4 xv4 = *reinterpret_cast<const float4 *>(lds + f32_chunk(n, 4 * i + g));
+        const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
+    }
+}
+
+// Split path: BF16 products from the highest-frequency k-step down, then the
+// low-frequency FP32 products (the operators' DC columns are zero here).
+__device__ __forceinline__ void mac16(const OpRegs16BF16 &R, const uint16_t *lhi, const uint16_t *llo,
+                                      const float *llf, int lane, f32x4 acc[2])
+{
+    const int n = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int s = 7; s >= 0; --s) {
+        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + bf16_chunk(n, 4 * s + g));
+        const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + bf16_chunk(n, 4 * s + g));
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.lo[t][s], bh, acc[t]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bl, acc[t]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
+    }
+    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
+    const float lfv[2] = {lv.x, lv.y};
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
+}
+
+constexpr int kBlk16Bytes = 256 * 4;
+
+// Resource over the `count` blocks of a tile that starts at block `first` of
+// an image and steps `step` blocks (count = 0: an empty resource).  Block b
+// of the tile is at byte b * step * 1 KiB; blocks b >= count fall outside.
+__device__ __forceinline__ rsrc_t tile16_rsrc(const float *img, int64_t first, int64_t step, int count)
+{
+    const int bytes = count <= 0 ? 0 : (int)(((int64_t)(count - 1) * step + 1) * kBlk16Bytes);
+    const float *p = img + (count <= 0 ? 0 : first * 256);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, bytes, kRsrcWord3);
+}
+
+// Thread q of the workgroup loads chunk (block q / 64, coefficients
+// 4(q % 64) .. +3) and the chunk q + 512 (the layout stage16_store takes).
+__device__ __forceinline__ void stage16_load_strided(Stage16<0> &S, rsrc_t r, uint32_t step_bytes, int tid)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h;
+        S.v[h] = buf_ld4<false>(r, (uint32_t)(q >> 6) * step_bytes + 16 * (q & 63));
+    }
+}
+
+template <int PREC, int T, int D>
+__global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64_t units)
+{
+    static_assert(T % D == 0 && D >= 1 && D <= T, "loads ahead must divide the tiles per unit");
+    constexpr int kF32 = 16 * kLd16F32;   // floats of one FP32 tile buffer
+    constexpr int kB16 = 16 * kLd16BF16;  // BF16 of one hi (or lo) tile buffer
+    constexpr int kTileBytes = PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit;
+    __shared__ __attribute__((aligned(16))) char smem[2 * kTileBytes + 64 * 4];
+    __shared__ float sx0[9 * T][16];   // DC coefficient of each staged neighbour block
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    float *lf = reinterpret_cast<float *>(smem);
+    uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
+    uint16_t *llo = lhi + 2 * kB16;
+    float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
+    float *trash = llf + 2 * 16 * kLd16Lf;
+    typedef typename std::conditional<PREC == DCTF_PREC_FP32, ImgOp16F32, OpRegs16BF16>::type Regs;
+    Regs R;
+    const int64_t G = gridDim.x;
+    // consecutive numbers run on one XCD (G is a multiple of 8)
+    const int64_t first = (int64_t)(blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
+    const int64_t per_img_blocks = (int64_t)a.Bh * a.Bw;
+    const uint32_t out_off = (uint32_t)(4 * (32 * wave + 4 * g));
+    const float *qv = nullptr;   // FP32 coefficients: no dequantisation
+    auto put = [&](const Stage16<0> &S, int buf, int slot) {
+        if constexpr (PREC == DCTF_PREC_FP32)
+            stage16_store<0>(S, lf + buf * kF32, tid, qv, 0.0f);
+        else
+            stage16_store<0>(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, trash, tid, qv,
+                             0.0f);
+        // the thread holding coefficients 0..3 of blocks q / 64 and q / 64 + 8
+        if ((tid & 63) == 0) {
+            sx0[slot][tid >> 6] = S.v[0].x;
+            sx0[slot][(tid >> 6) + 8] = S.v[1].x;
+        }
+    };
+    for (int64_t unit = first; unit < units; unit += G) {
+        const int64_t img = unit / a.units_per_image;
+        const int64_t lu = unit % a.units_per_image;
+        int ri = 0;
+        while (ri + 1 < a.nrect && a.rect[ri + 1].unit_begin <= lu)
+            ++ri;
+        const ImageRect &rc = a.rect[ri];
+        const int64_t t0 = (lu - rc.unit_begin) * T;
+        const int nt = (int)min((int64_t)T, rc.tiles - t0);
+        const float *X = a.in + img * per_img_blocks * 256;
+        float *Y = a.out + img * per_img_blocks * 256;
+        int64_t blk0[T];
+        int cnt[T];
+        int64_t step = 1;
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const TileRef r = tile_ref(rc, t0 + (tt < nt ? tt : 0), a.Bw);
+            blk0[tt] = r.blk0;
+            cnt[tt] = tt < nt ? r.count : 0;
+            step = r.step;
+        }
+        const uint32_t step_bytes = (uint32_t)(step * kBlk16Bytes);
+        auto shift_of = [&](int o) { return (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1); };
+        // neighbour tile tt at offset o (o < 0: past the last offset, empty)
+        auto src = [&](int o, int tt) {
+            return tile16_rsrc(X, blk0[tt] + (o < 0 ? 0 : shift_of(o)), step, o < 0 ? 0 : cnt[tt]);
+        };
+        f32x4 acc[T][2];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            acc[tt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acc[tt][1] = acc[tt][0];
+        }
+        Stage16<0> S[D];
+        const int o_first = __builtin_ctz((unsigned)rc.offsets);   // the centre is always present
+        // every reader of the LDS buffers and sx0 in the previous unit is done
+        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            stage16_load_strided(S[d], src(o_first, d), step_bytes, tid);
+        put(S[0], 0, 0);
+        __syncthreads();
+        unsigned rem = (unsigned)rc.offsets;
+        int i = 0;
+        for (;;) {
+            const int o = __builtin_ctz(rem);
+            rem &= rem - 1;
+            const int on = rem ? (int)__builtin_ctz(rem) : -1;
+            const size_t opi = (size_t)rc.cp * 9 + o;
+            if constexpr (PREC == DCTF_PREC_FP32)
+                load_img_op16(R, a.frag32 + opi * 65536, wave, lane);
+            else
+                load_op16(R, a.frag_hi + opi * 65536, a.frag_lo + opi * 65536, a.frag_lf + opi * 256 * lf_count(16),
+                          wave, lane);
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const int st = i * T + tt;
+                // the tile D steps ahead goes into the stage this step's tile left
+                if (tt + D < T)
+                    stage16_load_strided(S[tt % D], src(o, tt + D), step_bytes, tid);
+                else
+                    stage16_load_strided(S[tt % D], src(on, tt + D - T), step_bytes, tid);
+                __builtin_amdgcn_sched_barrier(0);
+                const int buf = st & 1;
+                if (tt < nt) {
+                    if constexpr (PREC == DCTF_PREC_FP32)
+                        mac16(R, lf + buf * kF32, lane, acc[tt]);
+                    else
+                        mac16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc[tt]);
+                }
+                if (on >= 0 || tt + 1 < T) {
+                    put(S[(tt + 1) % D], buf ^ 1, st + 1);
+                    __syncthreads();
+                }
+            }
+            ++i;
+            if (on < 0)
+                break;
+        }
+        // the operators' DC columns, in offset order
+        rem = (unsigned)rc.offsets;
+        i = 0;
+        while (rem) {
+            const int o = __builtin_ctz(rem);
+            rem &= rem - 1;
+            const float *D0 = a.h0 + ((size_t)rc.cp * 9 + o) * 256 + 32 * wave + 4 * g;
+            const float4 h0[2] = {ld4(D0), ld4(D0 + 16)};
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                const float x0 = sx0[i * T + tt][n];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    acc[tt][t][0] = fmaf(h0[t].x, x0, acc[tt][t][0]);
+                    acc[tt][t][1] = fmaf(h0[t].y, x0, acc[tt][t][1]);
+                    acc[tt][t][2] = fmaf(h0[t].z, x0, acc[tt][t][2]);
+                    acc[tt][t][3] = fmaf(h0[t].w, x0, acc[tt][t][3]);
+                }
+            }
+            ++i;
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const rsrc_t out = tile16_rsrc(Y, blk0[tt], step, cnt[tt]);
+            buf_st4<false>(out, (uint32_t)n * step_bytes + out_off, acc[tt][0]);
+            buf_st4<false>(out, (uint32_t)n * step_bytes + out_off + 64, acc[tt][1]);
+        }
+    }
+}
+
+// tiles per unit and tile loads ahead (N = 16): the unit's accumulators
+// (8 VGPRs per tile) share the register file with one operator (128-132
+// VGPRs) and the stages in flight (8 VGPRs each)
+constexpr int kImage16T32 = 4, kImage16D32 = 2;
+constexpr int kImage16TSplit = 4, kImage16DSplit = 2;
+
 }  // namespace
 
-hipError_t launch_build_image(const ImageBuildArgs &args, hipStream_t stream)
+hipError_t launch_build_image(int N, const ImageBuildArgs &args, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_build_image, dim3(kNN / 16, 16, 9), dim3(kThreads), 0, stream, args);
+    if (N == 8)
+        hipLaunchKernelGGL((k_build_image<8, 17>), dim3(64 / 16, 16, 9), dim3(kThreads), 0, stream, args);
+    else
+        hipLaunchKernelGGL((k_build_image<16, 8>), dim3(256 / 16, 16, 9), dim3(kThreads), 0, stream, args);
     return hipGetLastError();
 }
 
-int image_tiles_per_unit(int prec) { return prec == DCTF_PREC_FP32 ? kImageT32 : kImageTSplit; }
+int image_tiles_per_unit(int N, int prec)
+{
+    if (N == 16)
+        return prec == DCTF_PREC_FP32 ? kImage16T32 : kImage16TSplit;
+    return prec == DCTF_PREC_FP32 ? kImageT32 : kImageTSplit;
+}
 
-hipError_t launch_filter_image(int prec, const ImageFilterArgs &a, hipStream_t stream)
+hipError_t launch_filter_image(int N, int prec, const ImageFilterArgs &a, hipStream_t stream)
 {
     const int64_t units = a.units_per_image * a.nimg;
     if (units <= 0)
         return hipSuccess;
+    if (N == 16) {
+        // one 8-wave workgroup per CU (the operator takes most of the registers)
+        const int64_t groups = xcd_groups(units < cu_count() ? units : cu_count(), 1);
+        if (prec == DCTF_PREC_FP32)
+            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_FP32, kImage16T32, kImage16D32>), dim3((unsigned)groups),
+                               dim3(512), 0, stream, a, units);
+        else
+            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_SPLIT_BF16, kImage16TSplit, kImage16DSplit>),
+                               dim3((unsigned)groups), dim3(512), 0, stream, a, units);
+        return hipGetLastError();
+    }
     int64_t waves = (int64_t)cu_count() * kImageWavesPerCu;
     waves = waves < units ? waves : units;
     if (prec == DCTF_PREC_FP32) {

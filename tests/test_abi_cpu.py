@@ -95,7 +95,7 @@ def test_filter_and_batch_validation(lib):
     assert lib.dctf_build_image_operator(None, 3, 3, 8, 0, None, None) == -1
     out = ctypes.c_void_p()
     m, keep = _mask([1.0 / 9] * 9)
-    assert lib.dctf_build_image_operator(m, 3, 3, 16, 0, None, ctypes.byref(out)) == -2   # N = 16
+    assert lib.dctf_build_image_operator(m, 3, 3, 32, 0, None, ctypes.byref(out)) == -2   # N = 32
     assert lib.dctf_build_image_operator(m, 3, 3, 5, 0, None, ctypes.byref(out)) == -2    # N = 5
     assert lib.dctf_filter_blocks_u8(None, 0, None, None, 1, None) == -1
     assert lib.dctf_filter_quantized_u8(None, 0, None, None, ctypes.c_float(0.0), None, 1, None) == -1
