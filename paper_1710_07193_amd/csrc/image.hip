@@ -418,25 +418,28 @@ constexpr int kImageWavesPerCu = 8;
 
 // ------------------------------------------------------- filter, N = 16
 //
-// The block-local N = 16 kernel's structure per neighbour: a workgroup of 8
-// waves holds one 256 x 256 neighbour operator in VGPRs (wave w: output
-// rows 32w .. 32w + 31), and tiles of 16 blocks are staged in LDS once for
-// all 8 waves.  A unit is up to T tiles of one rectangle; for each neighbour
-// offset in turn the workgroup loads that operator (256 KiB, from L2: the 9
-// operators of the interior class pair, 2.25 MiB, stay in each XCD's L2)
-// and runs the unit's T neighbour tiles through it, accumulating into the T
-// tiles' registers.  Tile loads run D steps ahead over the (offset, tile)
-// sequence, also across an offset switch.  The DC coefficients of the
-// neighbour blocks are kept in LDS when a tile is staged and applied with
-// the operators' DC columns in FP32 VALU arithmetic after every MFMA
-// product, in offset order.  Workgroups take units in XCD order, so the
+// A workgroup of 8 waves holds one 256 x 256 neighbour operator in VGPRs
+// (wave w: output rows 32w .. 32w + 31), as the block-local N = 16 kernel
+// does.  A unit is up to T tiles of 16 blocks of one rectangle; one step is
+// one neighbour offset of a unit: its T neighbour tiles are in LDS together
+// (two sets of T tile buffers: the next step's tiles are loaded while this
+// step's are multiplied), and the MFMA work runs k-step by k-step over the
+// T tiles, so that each k-step's operator fragments are free once that
+// k-step is done: they are reloaded with the next step's operator (256 KiB
+// per workgroup, from L2: the 9 operators of the interior class pair,
+// 2.25 MiB, stay in each XCD's L2) while the later k-steps run.  Every step
+// issues the same loads (past the last unit: empty tiles and the current
+// operator again), so no step waits for more than its own data.  The DC
+// coefficients of the neighbour blocks are kept in LDS when a tile set is
+// staged and applied with the operators' DC columns in FP32 VALU after every
+// MFMA product, in offset order.  Workgroups take units in XCD order, so the
 // units of neighbouring block rows share an L2.
 
 struct ImgOp16F32 {
     float A[2][16][4];
 };
 
-__device__ __forceinline__ void load_img_op16(ImgOp16F32 &R, const float *frag32, int wave, int lane)
+__device__ __forceinline__ void load_img_op16_all(ImgOp16F32 &R, const float *frag32, int wave, int lane)
 {
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -448,51 +451,6 @@ __device__ __forceinline__ void load_img_op16(ImgOp16F32 &R, const float *frag32
             R.A[t][i][2] = v.z;
             R.A[t][i][3] = v.w;
         }
-}
-
-// acc += A . X(tile in LDS), highest-frequency inputs first (FP32 path).
-__device__ __forceinline__ void mac16(const ImgOp16F32 &R, const float *lds, int lane, f32x4 acc[2])
-{
-    const int n = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-        const float4 xv4 = *reinterpret_cast<const float4 *>(lds + f32_chunk(n, 4 * i + g));
-        const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-                acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
-    }
-}
-
-// Split path: BF16 products from the highest-frequency k-step down, then the
-// low-frequency FP32 products (the operators' DC columns are zero here).
-__device__ __forceinline__ void mac16(const OpRegs16BF16 &R, const uint16_t *lhi, const uint16_t *llo,
-                                      const float *llf, int lane, f32x4 acc[2])
-{
-    const int n = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int s = 7; s >= 0; --s) {
-        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + bf16_chunk(n, 4 * s + g));
-        const u32x4 bl = *reinterpret_cast<const u32x4 *>(llo + bf16_chunk(n, 4 * s + g));
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma_bf16(R.lo[t][s], bh, acc[t]);
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma_bf16(R.hi[t][s], bl, acc[t]);
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
-    }
-    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
-    const float lfv[2] = {lv.x, lv.y};
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            acc[t] = mfma_f32(R.lf[t][j], lfv[j], acc[t]);
 }
 
 constexpr int kBlk16Bytes = 256 * 4;
@@ -518,156 +476,288 @@ __device__ __forceinline__ void stage16_load_strided(Stage16<0> &S, rsrc_t r, ui
     }
 }
 
-template <int PREC, int T, int D>
+// One unit: image base block, its tiles (first block and valid count; count
+// 0 past the unit's tiles), the block step inside a tile, class pair and
+// neighbour offsets.
+template <int T>
+struct Unit16 {
+    int64_t base;
+    int64_t blk0[T];
+    int cnt[T];
+    int64_t step;
+    int cp, offsets, nt;
+};
+
+template <int T>
+__device__ __forceinline__ Unit16<T> decode_unit16(const ImageFilterArgs &a, int64_t unit)
+{
+    Unit16<T> u;
+    const int64_t img = unit / a.units_per_image;
+    const int64_t lu = unit % a.units_per_image;
+    int ri = 0;
+    while (ri + 1 < a.nrect && a.rect[ri + 1].unit_begin <= lu)
+        ++ri;
+    const ImageRect &rc = a.rect[ri];
+    const int64_t t0 = (lu - rc.unit_begin) * T;
+    u.nt = (int)min((int64_t)T, rc.tiles - t0);
+    u.base = img * a.Bh * a.Bw;
+    u.cp = rc.cp;
+    u.offsets = rc.offsets;
+    u.step = 1;
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const TileRef r = tile_ref(rc, t0 + (tt < u.nt ? tt : 0), a.Bw);
+        u.blk0[tt] = r.blk0;
+        u.cnt[tt] = tt < u.nt ? r.count : 0;
+        u.step = r.step;
+    }
+    return u;
+}
+
+// tiles per unit (N = 16): the unit's accumulators (8 VGPRs per tile) and
+// its tiles in flight (8 VGPRs each) share the register file with one
+// operator (128-132 VGPRs); 4 tiles spill
+constexpr int kImage16T = 3;
+
+template <int PREC, int T>
+constexpr int image16_smem()
+{
+    return 2 * T * (PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit) + 64 * 4 + 2 * 9 * T * 16 * 4;
+}
+
+template <int PREC, int T>
 __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64_t units)
 {
-    static_assert(T % D == 0 && D >= 1 && D <= T, "loads ahead must divide the tiles per unit");
-    constexpr int kF32 = 16 * kLd16F32;   // floats of one FP32 tile buffer
-    constexpr int kB16 = 16 * kLd16BF16;  // BF16 of one hi (or lo) tile buffer
+    constexpr int kB16 = 16 * kLd16BF16;   // BF16 of one hi (or lo) tile
     constexpr int kTileBytes = PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit;
-    __shared__ __attribute__((aligned(16))) char smem[2 * kTileBytes + 64 * 4];
-    __shared__ float sx0[9 * T][16];   // DC coefficient of each staged neighbour block
+    __shared__ __attribute__((aligned(16))) char smem[image16_smem<PREC, T>()];
+    // [2][T] tile buffers, then 64 floats of `trash`, then sx0[2][9 T][16]:
+    // the DC coefficient of each staged neighbour block (two units in flight)
+    float *trash = reinterpret_cast<float *>(smem + 2 * T * kTileBytes);
+    float *sx0 = trash + 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
-    float *lf = reinterpret_cast<float *>(smem);
-    uint16_t *lhi = reinterpret_cast<uint16_t *>(smem);
-    uint16_t *llo = lhi + 2 * kB16;
-    float *llf = reinterpret_cast<float *>(llo + 2 * kB16);
-    float *trash = llf + 2 * 16 * kLd16Lf;
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, ImgOp16F32, OpRegs16BF16>::type Regs;
     Regs R;
     const int64_t G = gridDim.x;
     // consecutive numbers run on one XCD (G is a multiple of 8)
-    const int64_t first = (int64_t)(blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
-    const int64_t per_img_blocks = (int64_t)a.Bh * a.Bw;
+    int64_t unit = (int64_t)(blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds;
+    if (unit >= units)
+        return;
     const uint32_t out_off = (uint32_t)(4 * (32 * wave + 4 * g));
-    const float *qv = nullptr;   // FP32 coefficients: no dequantisation
-    auto put = [&](const Stage16<0> &S, int buf, int slot) {
-        if constexpr (PREC == DCTF_PREC_FP32)
-            stage16_store<0>(S, lf + buf * kF32, tid, qv, 0.0f);
-        else
-            stage16_store<0>(S, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, trash, tid, qv,
-                             0.0f);
-        // the thread holding coefficients 0..3 of blocks q / 64 and q / 64 + 8
-        if ((tid & 63) == 0) {
-            sx0[slot][tid >> 6] = S.v[0].x;
-            sx0[slot][(tid >> 6) + 8] = S.v[1].x;
-        }
+    auto shift_of = [&](int o) { return (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1); };
+    auto tile_lds = [&](int b, int tt) { return smem + (b * T + tt) * kTileBytes; };
+    // neighbour tile tt of unit u at offset o (live = false: an empty tile)
+    auto src = [&](const Unit16<T> &u, int o, int tt, bool live) {
+        return tile16_rsrc(a.in + u.base * 256, u.blk0[tt] + shift_of(o), u.step, live ? u.cnt[tt] : 0);
     };
-    for (int64_t unit = first; unit < units; unit += G) {
-        const int64_t img = unit / a.units_per_image;
-        const int64_t lu = unit % a.units_per_image;
-        int ri = 0;
-        while (ri + 1 < a.nrect && a.rect[ri + 1].unit_begin <= lu)
-            ++ri;
-        const ImageRect &rc = a.rect[ri];
-        const int64_t t0 = (lu - rc.unit_begin) * T;
-        const int nt = (int)min((int64_t)T, rc.tiles - t0);
-        const float *X = a.in + img * per_img_blocks * 256;
-        float *Y = a.out + img * per_img_blocks * 256;
-        int64_t blk0[T];
-        int cnt[T];
-        int64_t step = 1;
+    auto load_tiles = [&](Stage16<0> (&S)[T], const Unit16<T> &u, int o, bool live) {
+        const uint32_t sb = (uint32_t)(u.step * kBlk16Bytes);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            stage16_load_strided(S[tt], src(u, o, tt, live), sb, tid);
+    };
+    auto put_tiles = [&](const Stage16<0> (&S)[T], int b, int par, int slot0) {
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
-            const TileRef r = tile_ref(rc, t0 + (tt < nt ? tt : 0), a.Bw);
-            blk0[tt] = r.blk0;
-            cnt[tt] = tt < nt ? r.count : 0;
-            step = r.step;
+            char *base = tile_lds(b, tt);
+            if constexpr (PREC == DCTF_PREC_FP32) {
+                stage16_store<0>(S[tt], reinterpret_cast<float *>(base), tid, nullptr, 0.0f);
+            } else {
+                uint16_t *lhi = reinterpret_cast<uint16_t *>(base);
+                stage16_store<0>(S[tt], lhi, lhi + kB16, reinterpret_cast<float *>(lhi + 2 * kB16), trash, tid,
+                                 nullptr, 0.0f);
+            }
+            // the thread holding coefficients 0..3 of blocks q / 64 and q / 64 + 8
+            if ((tid & 63) == 0) {
+                float *x0 = sx0 + ((par * 9 * T) + slot0 + tt) * 16;
+                x0[tid >> 6] = S[tt].v[0].x;
+                x0[(tid >> 6) + 8] = S[tt].v[1].x;
+            }
         }
-        const uint32_t step_bytes = (uint32_t)(step * kBlk16Bytes);
-        auto shift_of = [&](int o) { return (int64_t)(o / 3 - 1) * a.Bw + (o % 3 - 1); };
-        // neighbour tile tt at offset o (o < 0: past the last offset, empty)
-        auto src = [&](int o, int tt) {
-            return tile16_rsrc(X, blk0[tt] + (o < 0 ? 0 : shift_of(o)), step, o < 0 ? 0 : cnt[tt]);
-        };
-        f32x4 acc[T][2];
+    };
+    auto load_op = [&](int cp, int o) {
+        const size_t opi = (size_t)cp * 9 + o;
+        if constexpr (PREC == DCTF_PREC_FP32)
+            load_img_op16_all(R, a.frag32 + opi * 65536, wave, lane);
+        else
+            load_op16(R, a.frag_hi + opi * 65536, a.frag_lo + opi * 65536, a.frag_lf + opi * 256 * lf_count(16),
+                      wave, lane);
+    };
+    f32x4 acc[T][2];
+    // the MFMA work of one step over tile set b (nt tiles), reloading each
+    // k-step's operator fragments from operator (cp, o) once they are done
+    auto compute = [&](int b, int nt, int cp, int o) {
+        const size_t opi = (size_t)cp * 9 + o;
+        if constexpr (PREC == DCTF_PREC_FP32) {
+            const float *F = a.frag32 + opi * 65536;
+#pragma unroll
+            for (int i = 15; i >= 0; --i) {
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) {
+                    if (tt < nt) {
+                        const float *lf = reinterpret_cast<const float *>(tile_lds(b, tt));
+                        const float4 xv4 = *reinterpret_cast<const float4 *>(lf + f32_chunk(n, 4 * i + g));
+                        const float xv[4] = {xv4.x, xv4.y, xv4.z, xv4.w};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int t = 0; t < 2; ++t)
+                                acc[tt][t] = mfma_f32(R.A[t][i][j], xv[j], acc[tt][t]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const float4 v = ld4(F + (((2 * wave + t) * 16 + i) * 64 + lane) * 4);
+                    R.A[t][i][0] = v.x;
+                    R.A[t][i][1] = v.y;
+                    R.A[t][i][2] = v.z;
+                    R.A[t][i][3] = v.w;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            const uint16_t *fhi = a.frag_hi + opi * 65536, *flo = a.frag_lo + opi * 65536;
+#pragma unroll
+            for (int s = 7; s >= 0; --s) {
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) {
+                    if (tt < nt) {
+                        const uint16_t *lhi = reinterpret_cast<const uint16_t *>(tile_lds(b, tt));
+                        const u32x4 bh = *reinterpret_cast<const u32x4 *>(lhi + bf16_chunk(n, 4 * s + g));
+                        const u32x4 bl = *reinterpret_cast<const u32x4 *>(lhi + kB16 + bf16_chunk(n, 4 * s + g));
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            acc[tt][t] = mfma_bf16(R.lo[t][s], bh, acc[tt][t]);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            acc[tt][t] = mfma_bf16(R.hi[t][s], bl, acc[tt][t]);
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            acc[tt][t] = mfma_bf16(R.hi[t][s], bh, acc[tt][t]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int T2 = 2 * wave + t;
+                    R.hi[t][s] = ldg_u32x4(fhi + ((T2 * 8 + s) * 64 + lane) * 8);
+                    R.lo[t][s] = ldg_u32x4(flo + ((T2 * 8 + s) * 64 + lane) * 8);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the low-frequency coefficients in FP32 (the DC columns are zero here)
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) {
+                if (tt < nt) {
+                    const float *llf = reinterpret_cast<const float *>(tile_lds(b, tt) + 2 * kB16 * 2);
+                    const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
+                    const float lfv[2] = {lv.x, lv.y};
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            acc[tt][t] = mfma_f32(R.lf[t][j], lfv[j], acc[tt][t]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const float *flf = a.frag_lf + opi * 256 * lf_count(16);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const f32x2 v = ldg_f32x2(flf + ((2 * wave + t) * 64 + lane) * 2);
+                R.lf[t][0] = v[0];
+                R.lf[t][1] = v[1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    Unit16<T> cu = decode_unit16<T>(a, unit);
+    int par = 0;   // sx0 half of the current unit
+    int b = 0;     // tile set of the current step
+    Stage16<0> S[T];
+    {
+        const int o = __builtin_ctz((unsigned)cu.offsets);   // the centre is always present
+        load_tiles(S, cu, o, true);
+        load_op(cu.cp, o);
+        put_tiles(S, 0, 0, 0);
+        // nothing in flight at the loop's entry: its waits then count only the
+        // loads the loop itself issues (the operator reloads of the step before)
+        wait_vm_all();
+        __syncthreads();
+    }
+    for (;;) {
+        const int64_t nunit = unit + G;
+        const bool more = nunit < units;
+        const Unit16<T> nu = more ? decode_unit16<T>(a, nunit) : cu;
+        const int nfirst = __builtin_ctz((unsigned)nu.offsets);
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             acc[tt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
             acc[tt][1] = acc[tt][0];
         }
-        Stage16<0> S[D];
-        const int o_first = __builtin_ctz((unsigned)rc.offsets);   // the centre is always present
-        // every reader of the LDS buffers and sx0 in the previous unit is done
-        __syncthreads();
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            stage16_load_strided(S[d], src(o_first, d), step_bytes, tid);
-        put(S[0], 0, 0);
-        __syncthreads();
-        unsigned rem = (unsigned)rc.offsets;
-        int i = 0;
-        for (;;) {
-            const int o = __builtin_ctz(rem);
+        unsigned rem = (unsigned)cu.offsets;
+        int o = __builtin_ctz(rem);
+        rem &= rem - 1;
+        // every step but the unit's last: the next offset's tiles into the other set
+        for (int oi = 0; rem != 0; ++oi) {
+            const int on = __builtin_ctz(rem);
             rem &= rem - 1;
-            const int on = rem ? (int)__builtin_ctz(rem) : -1;
-            const size_t opi = (size_t)rc.cp * 9 + o;
-            if constexpr (PREC == DCTF_PREC_FP32)
-                load_img_op16(R, a.frag32 + opi * 65536, wave, lane);
-            else
-                load_op16(R, a.frag_hi + opi * 65536, a.frag_lo + opi * 65536, a.frag_lf + opi * 256 * lf_count(16),
-                          wave, lane);
-#pragma unroll
-            for (int tt = 0; tt < T; ++tt) {
-                const int st = i * T + tt;
-                // the tile D steps ahead goes into the stage this step's tile left
-                if (tt + D < T)
-                    stage16_load_strided(S[tt % D], src(o, tt + D), step_bytes, tid);
-                else
-                    stage16_load_strided(S[tt % D], src(on, tt + D - T), step_bytes, tid);
-                __builtin_amdgcn_sched_barrier(0);
-                const int buf = st & 1;
-                if (tt < nt) {
-                    if constexpr (PREC == DCTF_PREC_FP32)
-                        mac16(R, lf + buf * kF32, lane, acc[tt]);
-                    else
-                        mac16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc[tt]);
-                }
-                if (on >= 0 || tt + 1 < T) {
-                    put(S[(tt + 1) % D], buf ^ 1, st + 1);
-                    __syncthreads();
-                }
-            }
-            ++i;
-            if (on < 0)
-                break;
+            load_tiles(S, cu, on, true);
+            compute(b, cu.nt, cu.cp, on);
+            put_tiles(S, b ^ 1, par, (oi + 1) * T);
+            __syncthreads();
+            b ^= 1;
+            o = on;
         }
+        // the unit's last step: the next unit's first tiles and operator (or,
+        // past the last unit, empty tiles and this operator again)
+        load_tiles(S, nu, more ? nfirst : o, more);
+        compute(b, cu.nt, more ? nu.cp : cu.cp, more ? nfirst : o);
         // the operators' DC columns, in offset order
-        rem = (unsigned)rc.offsets;
-        i = 0;
-        while (rem) {
-            const int o = __builtin_ctz(rem);
-            rem &= rem - 1;
-            const float *D0 = a.h0 + ((size_t)rc.cp * 9 + o) * 256 + 32 * wave + 4 * g;
-            const float4 h0[2] = {ld4(D0), ld4(D0 + 16)};
+        {
+            unsigned r2 = (unsigned)cu.offsets;
+            int i = 0;
+            while (r2) {
+                const int od = __builtin_ctz(r2);
+                r2 &= r2 - 1;
+                const float *D0 = a.h0 + ((size_t)cu.cp * 9 + od) * 256 + 32 * wave + 4 * g;
+                const float4 h0[2] = {ld4(D0), ld4(D0 + 16)};
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) {
+                    const float x0 = sx0[((par * 9 * T) + i * T + tt) * 16 + n];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        acc[tt][t][0] = fmaf(h0[t].x, x0, acc[tt][t][0]);
+                        acc[tt][t][1] = fmaf(h0[t].y, x0, acc[tt][t][1]);
+                        acc[tt][t][2] = fmaf(h0[t].z, x0, acc[tt][t][2]);
+                        acc[tt][t][3] = fmaf(h0[t].w, x0, acc[tt][t][3]);
+                    }
+                }
+                ++i;
+            }
+        }
+        {
+            float *Y = a.out + cu.base * 256;
+            const uint32_t sb = (uint32_t)(cu.step * kBlk16Bytes);
 #pragma unroll
             for (int tt = 0; tt < T; ++tt) {
-                const float x0 = sx0[i * T + tt][n];
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    acc[tt][t][0] = fmaf(h0[t].x, x0, acc[tt][t][0]);
-                    acc[tt][t][1] = fmaf(h0[t].y, x0, acc[tt][t][1]);
-                    acc[tt][t][2] = fmaf(h0[t].z, x0, acc[tt][t][2]);
-                    acc[tt][t][3] = fmaf(h0[t].w, x0, acc[tt][t][3]);
-                }
+                const rsrc_t out = tile16_rsrc(Y, cu.blk0[tt], cu.step, cu.cnt[tt]);
+                buf_st4<false>(out, (uint32_t)n * sb + out_off, acc[tt][0]);
+                buf_st4<false>(out, (uint32_t)n * sb + out_off + 64, acc[tt][1]);
             }
-            ++i;
         }
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt) {
-            const rsrc_t out = tile16_rsrc(Y, blk0[tt], step, cnt[tt]);
-            buf_st4<false>(out, (uint32_t)n * step_bytes + out_off, acc[tt][0]);
-            buf_st4<false>(out, (uint32_t)n * step_bytes + out_off + 64, acc[tt][1]);
-        }
+        if (!more)
+            break;
+        put_tiles(S, b ^ 1, par ^ 1, 0);
+        __syncthreads();
+        b ^= 1;
+        par ^= 1;
+        unit = nunit;
+        cu = nu;
     }
 }
-
-// tiles per unit and tile loads ahead (N = 16): the unit's accumulators
-// (8 VGPRs per tile) share the register file with one operator (128-132
-// VGPRs) and the stages in flight (8 VGPRs each)
-constexpr int kImage16T32 = 4, kImage16D32 = 2;
-constexpr int kImage16TSplit = 4, kImage16DSplit = 2;
 
 }  // namespace
 
@@ -683,7 +773,7 @@ hipError_t launch_build_image(int N, const ImageBuildArgs &args, hipStream_t str
 int image_tiles_per_unit(int N, int prec)
 {
     if (N == 16)
-        return prec == DCTF_PREC_FP32 ? kImage16T32 : kImage16TSplit;
+        return kImage16T;
     return prec == DCTF_PREC_FP32 ? kImageT32 : kImageTSplit;
 }
 
@@ -696,11 +786,11 @@ hipError_t launch_filter_image(int N, int prec, const ImageFilterArgs &a, hipStr
         // one 8-wave workgroup per CU (the operator takes most of the registers)
         const int64_t groups = xcd_groups(units < cu_count() ? units : cu_count(), 1);
         if (prec == DCTF_PREC_FP32)
-            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_FP32, kImage16T32, kImage16D32>), dim3((unsigned)groups),
-                               dim3(512), 0, stream, a, units);
+            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_FP32, kImage16T>), dim3((unsigned)groups), dim3(512), 0,
+                               stream, a, units);
         else
-            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_SPLIT_BF16, kImage16TSplit, kImage16DSplit>),
-                               dim3((unsigned)groups), dim3(512), 0, stream, a, units);
+            hipLaunchKernelGGL((k_filter_image16<DCTF_PREC_SPLIT_BF16, kImage16T>), dim3((unsigned)groups),
+                               dim3(512), 0, stream, a, units);
         return hipGetLastError();
     }
     int64_t waves = (int64_t)cu_count() * kImageWavesPerCu;
