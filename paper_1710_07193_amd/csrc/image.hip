@@ -522,7 +522,7 @@ constexpr int kImage16T = 3;
 template <int PREC, int T>
 constexpr int image16_smem()
 {
-    return 2 * T * (PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit) + 64 * 4 + 2 * 9 * T * 16 * 4;
+    return 2 * T * (PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit) + 64 * 4 + 3 * 9 * T * 16 * 4;
 }
 
 template <int PREC, int T>
@@ -531,8 +531,10 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
     constexpr int kB16 = 16 * kLd16BF16;   // BF16 of one hi (or lo) tile
     constexpr int kTileBytes = PREC == DCTF_PREC_FP32 ? kTile16BytesF32 : kTile16BytesSplit;
     __shared__ __attribute__((aligned(16))) char smem[image16_smem<PREC, T>()];
-    // [2][T] tile buffers, then 64 floats of `trash`, then sx0[2][9 T][16]:
-    // the DC coefficient of each staged neighbour block (two units in flight)
+    // [2][T] tile buffers, then 64 floats of `trash`, then sx0[3][9 T][16]:
+    // the DC coefficient of each staged neighbour block, for three units in
+    // turn (a unit's DC pass reads its third while the next two units' tiles
+    // are staged into the others)
     float *trash = reinterpret_cast<float *>(smem + 2 * T * kTileBytes);
     float *sx0 = trash + 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -557,23 +559,21 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
         for (int tt = 0; tt < T; ++tt)
             stage16_load_strided(S[tt], src(u, o, tt, live), sb, tid);
     };
-    auto put_tiles = [&](const Stage16<0> (&S)[T], int b, int par, int slot0) {
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt) {
-            char *base = tile_lds(b, tt);
-            if constexpr (PREC == DCTF_PREC_FP32) {
-                stage16_store<0>(S[tt], reinterpret_cast<float *>(base), tid, nullptr, 0.0f);
-            } else {
-                uint16_t *lhi = reinterpret_cast<uint16_t *>(base);
-                stage16_store<0>(S[tt], lhi, lhi + kB16, reinterpret_cast<float *>(lhi + 2 * kB16), trash, tid,
-                                 nullptr, 0.0f);
-            }
-            // the thread holding coefficients 0..3 of blocks q / 64 and q / 64 + 8
-            if ((tid & 63) == 0) {
-                float *x0 = sx0 + ((par * 9 * T) + slot0 + tt) * 16;
-                x0[tid >> 6] = S[tt].v[0].x;
-                x0[(tid >> 6) + 8] = S[tt].v[1].x;
-            }
+    // tile tt of the stages into tile set b, its DC coefficients into sx0 third par, slot
+    auto put_tile = [&](const Stage16<0> &St, int b, int tt, int par, int slot) {
+        char *base = tile_lds(b, tt);
+        if constexpr (PREC == DCTF_PREC_FP32) {
+            stage16_store<0>(St, reinterpret_cast<float *>(base), tid, nullptr, 0.0f);
+        } else {
+            uint16_t *lhi = reinterpret_cast<uint16_t *>(base);
+            stage16_store<0>(St, lhi, lhi + kB16, reinterpret_cast<float *>(lhi + 2 * kB16), trash, tid, nullptr,
+                             0.0f);
+        }
+        // the thread holding coefficients 0..3 of blocks q / 64 and q / 64 + 8
+        if ((tid & 63) == 0) {
+            float *x0 = sx0 + ((par * 9 * T) + slot) * 16;
+            x0[tid >> 6] = St.v[0].x;
+            x0[(tid >> 6) + 8] = St.v[1].x;
         }
     };
     auto load_op = [&](int cp, int o) {
@@ -585,9 +585,12 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
                       wave, lane);
     };
     f32x4 acc[T][2];
-    // the MFMA work of one step over tile set b (nt tiles), reloading each
-    // k-step's operator fragments from operator (cp, o) once they are done
-    auto compute = [&](int b, int nt, int cp, int o) {
+    // The MFMA work of one step over tile set b (nt tiles).  Each k-step's
+    // operator fragments are reloaded from operator (cp, o) once that k-step
+    // is done, and the stages S go into tile set pb (DC coefficients into
+    // third ppar from slot pslot) one tile after each of the last T k-steps,
+    // so the conversion runs beside the MFMA work.
+    auto compute = [&](int b, int nt, int cp, int o, const Stage16<0> (&S)[T], int pb, int ppar, int pslot) {
         const size_t opi = (size_t)cp * 9 + o;
         if constexpr (PREC == DCTF_PREC_FP32) {
             const float *F = a.frag32 + opi * 65536;
@@ -615,6 +618,8 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
                     R.A[t][i][2] = v.z;
                     R.A[t][i][3] = v.w;
                 }
+                if (i < T)
+                    put_tile(S[T - 1 - i], pb, T - 1 - i, ppar, pslot + T - 1 - i);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -645,6 +650,8 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
                     R.hi[t][s] = ldg_u32x4(fhi + ((T2 * 8 + s) * 64 + lane) * 8);
                     R.lo[t][s] = ldg_u32x4(flo + ((T2 * 8 + s) * 64 + lane) * 8);
                 }
+                if (s < T)
+                    put_tile(S[T - 1 - s], pb, T - 1 - s, ppar, pslot + T - 1 - s);
                 __builtin_amdgcn_sched_barrier(0);
             }
             // the low-frequency coefficients in FP32 (the DC columns are zero here)
@@ -674,14 +681,16 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
     };
 
     Unit16<T> cu = decode_unit16<T>(a, unit);
-    int par = 0;   // sx0 half of the current unit
+    int par = 0;   // sx0 third of the current unit
     int b = 0;     // tile set of the current step
     Stage16<0> S[T];
     {
         const int o = __builtin_ctz((unsigned)cu.offsets);   // the centre is always present
         load_tiles(S, cu, o, true);
         load_op(cu.cp, o);
-        put_tiles(S, 0, 0, 0);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            put_tile(S[tt], 0, tt, 0, tt);
         // nothing in flight at the loop's entry: its waits then count only the
         // loads the loop itself issues (the operator reloads of the step before)
         wait_vm_all();
@@ -692,6 +701,7 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
         const bool more = nunit < units;
         const Unit16<T> nu = more ? decode_unit16<T>(a, nunit) : cu;
         const int nfirst = __builtin_ctz((unsigned)nu.offsets);
+        const int npar = par == 2 ? 0 : par + 1;
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             acc[tt][0] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -705,8 +715,7 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
             const int on = __builtin_ctz(rem);
             rem &= rem - 1;
             load_tiles(S, cu, on, true);
-            compute(b, cu.nt, cu.cp, on);
-            put_tiles(S, b ^ 1, par, (oi + 1) * T);
+            compute(b, cu.nt, cu.cp, on, S, b ^ 1, par, (oi + 1) * T);
             __syncthreads();
             b ^= 1;
             o = on;
@@ -714,7 +723,8 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
         // the unit's last step: the next unit's first tiles and operator (or,
         // past the last unit, empty tiles and this operator again)
         load_tiles(S, nu, more ? nfirst : o, more);
-        compute(b, cu.nt, more ? nu.cp : cu.cp, more ? nfirst : o);
+        compute(b, cu.nt, more ? nu.cp : cu.cp, more ? nfirst : o, S, b ^ 1, npar, 0);
+        __syncthreads();
         // the operators' DC columns, in offset order
         {
             unsigned r2 = (unsigned)cu.offsets;
@@ -750,10 +760,8 @@ __global__ __launch_bounds__(512) void k_filter_image16(ImageFilterArgs a, int64
         }
         if (!more)
             break;
-        put_tiles(S, b ^ 1, par ^ 1, 0);
-        __syncthreads();
         b ^= 1;
-        par ^= 1;
+        par = npar;
         unit = nunit;
         cu = nu;
     }

@@ -775,7 +775,15 @@ __device__ __forceinline__ void stage16_store(const Stage16<IN> &S, uint16_t *lh
     }
 }
 
-__device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, int lane, f32x4 acc[2])
+// `mid` runs once in the middle of the k-steps (the tile loop stages the next
+// tile into the other LDS buffer there, beside the MFMA work).
+struct NoMid {
+    __device__ void operator()() const {}
+};
+
+template <typename Mid = NoMid>
+__device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, int lane, f32x4 acc[2],
+                                       const Mid &mid = Mid())
 {
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -790,6 +798,8 @@ __device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, i
 #pragma unroll
             for (int t = 0; t < 2; ++t)
                 acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
+        if (i == 8)
+            mid();
     }
     const float x0 = lds[f32_chunk(n, 0)];
 #pragma unroll
@@ -799,8 +809,9 @@ __device__ __forceinline__ void tile16(const OpRegs16F32 &R, const float *lds, i
             acc[t][r] = fmaf(R.h0[t][r], x0, acc[t][r]);
 }
 
+template <typename Mid = NoMid>
 __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lhi, const uint16_t *llo,
-                                       const float *llf, int lane, f32x4 acc[2])
+                                       const float *llf, int lane, f32x4 acc[2], const Mid &mid = Mid())
 {
     const int n = lane & 15, g = lane >> 4;
     acc[0] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -820,6 +831,8 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 #pragma unroll
         for (int t = 0; t < 2; ++t)
             acc[t] = mfma_bf16(R.hi[t][s], bh, acc[t]);
+        if (s == 4)
+            mid();
     }
     // low-frequency slots 2g + j of block n, FP32
     const float2 lv = *reinterpret_cast<const float2 *>(llf + (g * 16 + n) * 2);
@@ -836,6 +849,9 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // Runs `count` tiles of one workgroup through the weight-stationary path.
 // Global loads run D tiles ahead of the MFMA work (a ring of D register
 // stages); LDS tiles are double-buffered with one barrier per tile.
+// With one operator, the next tile is written to the other LDS buffer halfway
+// through a tile's MFMA work, so its conversion (the BF16 split) runs beside
+// the MFMAs.
 // ref(t) returns the UnitRef-like descriptor of the t-th tile (called in
 // increasing t, also for t >= count: such a tile must be past the end of its
 // job, so that it reads nothing); op_load(op) loads the operator fragments
@@ -922,10 +938,17 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
         __builtin_amdgcn_sched_barrier(0);
         const int buf = (int)(t & 1);
         f32x4 acc[2];
+        // the next tile's stage goes into the other buffer (free since the
+        // last barrier) halfway through this tile's MFMA work (single-operator
+        // loops; with operator reloads the registers are too tight for it)
+        auto mid = [&]() {
+            if (!MULTI_OP && !last)
+                put(S[(p + 1) % D], buf ^ 1);
+        };
         if constexpr (PREC == DCTF_PREC_FP32)
-            tile16(R, lf + buf * kF32, lane, acc);
+            tile16(R, lf + buf * kF32, lane, acc, mid);
         else
-            tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc);
+            tile16(R, lhi + buf * kB16, llo + buf * kB16, llf + buf * 16 * kLd16Lf, lane, acc, mid);
         if constexpr (OUT == 0) {
             const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 1024);
             buf_st4<false>(o, out_off, acc[0]);
@@ -938,7 +961,8 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
                                                   out_off + 16, 0, 0);
         }
         if (!last) {
-            put(S[(p + 1) % D], buf ^ 1);
+            if constexpr (MULTI_OP)
+                put(S[(p + 1) % D], buf ^ 1);
             __syncthreads();
         }
     };

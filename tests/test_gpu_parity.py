@@ -370,8 +370,13 @@ def test_every_variant_over_many_steps_per_wave(dctf, N, prec):
     rng = np.random.default_rng(57)
     W = syn.random_mask(rng, 5, 5)
     op = dctf.dctf_build_operator(W, N, R)
-    X = torch.randn(B * N * N, device="cuda") * 40
-    X.view(B, N * N)[:, 0] += 1000.0
+    # seeded coefficients whose spread falls with frequency as in natural
+    # images (the content the split-BF16 bound is stated for), DC near 128 N
+    gen = torch.Generator(device="cuda").manual_seed(57)
+    u = torch.arange(N, device="cuda", dtype=torch.float32)
+    decay = (40.0 / (1.0 + u.view(N, 1) + u.view(1, N))).reshape(-1)
+    X = (torch.randn(B, N * N, device="cuda", generator=gen) * decay).reshape(-1)
+    X.view(B, N * N)[:, 0] += 128.0 * N
     v0 = dctf.dctf_get_variant(N, prec)
     try:
         dctf.dctf_set_variant(N, prec, 0)
