@@ -247,7 +247,7 @@ def small_workloads(dctf, torch, stream):
     return res
 
 
-def pixel_outputs(dctf, torch, stream, X, N, steps, warmup):
+def pixel_outputs(dctf, torch, stream, X, N, steps, warmup, images=64, side=2048):
     """Filter + inverse DCT + uint8 in one pass over the same blocks, with the
     5x5 asymmetric mask and border replication: from the FP32 coefficients
     (4 B in, 1 B out per coefficient) and from JPEG-style quantised int16
@@ -277,7 +277,24 @@ def pixel_outputs(dctf, torch, stream, X, N, steps, warmup):
             res["%s_to_u8_%s" % (src, pname)] = {
                 "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "alg_bytes_per_block": nn * per_coef,
                 "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS}
-    del Q, pix
+    # the same into raster images (one call per image, as a decoder would run it)
+    del pix
+    imgs = torch.empty((images, side, side), dtype=torch.uint8, device="cuda")
+    per = (side // N) ** 2 * nn
+    for src, fn, per_coef in (
+            ("coeffs_f32", lambda i: dctf.dctf_filter_blocks_u8_raster(
+                op, dctf.DCTF_PREC_SPLIT_BF16, X[i * per:(i + 1) * per], side, side, imgs[i], stream), 5),
+            ("quantized_s16", lambda i: dctf.dctf_filter_quantized_u8_raster(
+                op, dctf.DCTF_PREC_SPLIT_BF16, Q[i * per:(i + 1) * per], qt, dc, side, side, imgs[i], stream), 3)):
+        def run(fn=fn):
+            for i in range(images):
+                fn(i)
+        ms = timed_steps(torch, run, max(3, steps // 4), max(2, warmup // 4), stream, settle_first=True)
+        gbs = B * nn * per_coef / (ms * 1e-3) / 1e9
+        res["%s_to_raster_u8_split" % src] = {
+            "calls": images, "ms_per_pass": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": gbs,
+            "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+    del Q, imgs
     torch.cuda.empty_cache()
     return res
 
@@ -350,8 +367,9 @@ def fp64_filter(dctf, torch, stream, X, N, steps, warmup):
 
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
-    one 7x7 asymmetric mask with zero border, in both precisions, and the
-    factored FP32 path for that mask and for a separable 7x7 Gaussian."""
+    one 7x7 asymmetric mask with zero border, in both precisions, the
+    factored FP32 path for that mask and for a separable 7x7 Gaussian, and
+    image-level (cross-block) filtering with the same mask."""
     import numpy as np
 
     import synthetic as syn
@@ -386,7 +404,21 @@ def n16_frames(dctf, torch, stream, steps, warmup):
         res["factored_" + tag] = ent
     res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
-    del X, Y
+    # image-level (cross-block) filtering of the same frames with the same mask
+    W = syn.random_mask(np.random.default_rng(7), 7, 7)
+    iop = dctf.dctf_build_image_operator(W, N, dctf.DCTF_BORDER_ZERO)
+    Bh, Bw = h // N, w // N
+    flops = image_level_flops(Bh, Bw, 7, 7, N) * frames
+    il = {"alg_flops_per_launch": flops}
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        ms = timed_steps(torch, lambda: dctf.dctf_filter_image(iop, p, X, Y, Bh, Bw, stream), max(5, steps // 2),
+                         max(3, warmup // 2), stream, settle_first=True)
+        tf = flops / (ms * 1e-3) / 1e12
+        il[pname] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "TFLOPs": tf}
+        if p == dctf.DCTF_PREC_FP32:
+            il[pname]["frac_of_fp32_mfma_peak"] = tf / FP32_MFMA_PEAK_TFLOPS
+    res["image_level"] = il
+    del X, Y, iop
     torch.cuda.empty_cache()
     return res
 
@@ -780,7 +812,8 @@ def main():
                     "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
         progress("graph replay, other precision, single-operator runs")
         extras["small_workloads"] = small_workloads(dctf, torch, stream)
-        extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup)
+        extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup, args.images,
+                                             args.side)
         progress("small workloads, pixel outputs")
         extras["image_level"] = image_level(dctf, torch, stream, X, Y, args.images, args.side, N,
                                             max(10, args.steps // 5), max(5, args.warmup // 6))

@@ -253,6 +253,26 @@ dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *
                                      const float *qtable_dev, float dc_offset, uint8_t *pix_dev,
                                      int64_t B, dctf_stream stream);
 
+/*
+ * The same two calls with the pixels written in their places in an image
+ * instead of block by block: the input holds the ceil(h/N) x ceil(w/N)
+ * blocks of one h x w image in raster block order (as dctf_forward_dct_u8
+ * cuts it), and pixel (y, x) of the filtered image goes to
+ * img_dev[y * pitch + x] for y < h, x < w (the pixels of edge blocks past
+ * the image are not written).  The filtered coefficients and the
+ * block-ordered pixels never reach memory: from a JPEG-style decoder's
+ * quantised blocks to the filtered raster image is one pass.
+ *   img_dev  device, 4-byte aligned; pitch >= w, a multiple of 4.
+ * h = 0 or w = 0 is a no-op.  Errors: DCTF_EINVAL (as above; h or w < 0,
+ * bad pitch, more than 2^31 - 1 blocks, input overlapping the image),
+ * DCTF_EUNSUPPORTED (N = 32), DCTF_EHIP.
+ */
+dctf_status dctf_filter_blocks_u8_raster(dctf_operator op, int prec, const float *in_dev, int h, int w,
+                                         uint8_t *img_dev, int64_t pitch, dctf_stream stream);
+dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int prec, const int16_t *qcoef_dev,
+                                            const float *qtable_dev, float dc_offset, int h, int w,
+                                            uint8_t *img_dev, int64_t pitch, dctf_stream stream);
+
 /* ------------------------------------------------- image-level filtering */
 
 /*

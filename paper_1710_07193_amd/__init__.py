@@ -74,6 +74,8 @@ _SIGS = {
     "dctf_image_operator_destroy": ([_P], None),
     "dctf_filter_image": ([_P, _I, _P, _P, _I, _I, _I64, _P], _I),
     "dctf_filter_quantized_u8": ([_P, _I, _P, _P, ctypes.c_float, _P, _I64, _P], _I),
+    "dctf_filter_blocks_u8_raster": ([_P, _I, _P, _I, _I, _P, _I64, _P], _I),
+    "dctf_filter_quantized_u8_raster": ([_P, _I, _P, _P, ctypes.c_float, _I, _I, _P, _I64, _P], _I),
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
     "dctf_filter_blocks": ([_P, _I, _P, _P, _I64, _P], _I),
@@ -303,6 +305,46 @@ def dctf_filter_quantized_u8(op: Operator, prec: int, qcoef: torch.Tensor, qtabl
                                          _dptr(qtable, torch.float32, "qtable"), float(dc_offset),
                                          _dptr(pix, torch.uint8, "pix"), qcoef.numel() // nn, _stream(stream)),
            "dctf_filter_quantized_u8")
+
+
+def _raster_image(img: torch.Tensor, h: int, w: int):
+    """(pointer, pitch) of a 2-D uint8 device image (rows contiguous, any row
+    pitch, e.g. a column slice of a wider image) of at least h rows of w pixels."""
+    if not isinstance(img, torch.Tensor) or not img.is_cuda:
+        raise TypeError("img must be a device tensor")
+    if img.dtype != torch.uint8 or img.dim() != 2 or img.stride(1) != 1:
+        raise ValueError("img must be a 2-D uint8 tensor with contiguous rows")
+    if img.shape[0] < h or img.shape[1] < w:
+        raise ValueError("img is smaller than h x w")
+    return _P(img.data_ptr()), img.stride(0)
+
+
+def dctf_filter_blocks_u8_raster(op: Operator, prec: int, X: torch.Tensor, h: int, w: int, img: torch.Tensor,
+                                 stream=None):
+    """The filtered pixels of the ceil(h/N) x ceil(w/N) coefficient blocks X
+    written into the h x w uint8 image img (row pitch = img.stride(0))."""
+    nb = -(-h // op.N) * -(-w // op.N)
+    if X.numel() != nb * op.N * op.N:
+        raise ValueError("X must hold the ceil(h/N) x ceil(w/N) blocks of the image")
+    ptr, pitch = _raster_image(img, h, w)
+    _check(_lib.dctf_filter_blocks_u8_raster(op, prec, _dptr(X, torch.float32, "X"), h, w, ptr, pitch,
+                                             _stream(stream)),
+           "dctf_filter_blocks_u8_raster")
+
+
+def dctf_filter_quantized_u8_raster(op: Operator, prec: int, qcoef: torch.Tensor, qtable: torch.Tensor,
+                                    dc_offset: float, h: int, w: int, img: torch.Tensor, stream=None):
+    """As dctf_filter_blocks_u8_raster from quantised int16 blocks."""
+    nb = -(-h // op.N) * -(-w // op.N)
+    if qcoef.numel() != nb * op.N * op.N:
+        raise ValueError("qcoef must hold the ceil(h/N) x ceil(w/N) blocks of the image")
+    if qtable.numel() != op.N * op.N:
+        raise ValueError("qtable must hold N*N factors")
+    ptr, pitch = _raster_image(img, h, w)
+    _check(_lib.dctf_filter_quantized_u8_raster(op, prec, _dptr(qcoef, torch.int16, "qcoef"),
+                                                _dptr(qtable, torch.float32, "qtable"), float(dc_offset), h, w,
+                                                ptr, pitch, _stream(stream)),
+           "dctf_filter_quantized_u8_raster")
 
 
 class ImageOperator:

@@ -164,9 +164,14 @@ struct PxArgs {
     const int16_t *qin;     // IN = 1: B * N*N quantised coefficients
     const float *qtab;      // IN = 1: N*N dequantisation factors (device)
     float dc_offset;        // IN = 1: added to every dequantised DC coefficient
-    uint8_t *pix;           // B * N*N filtered pixels
+    uint8_t *pix;           // B * N*N filtered pixels (raster = 0), or the h x w image (raster = 1)
     int64_t B;
     DenseImages G;          // the pixel-domain images of the operator
+    // raster = 1: the B blocks tile one h x w image in raster order (Bw blocks
+    // per block row); pixel (y, x) goes to pix[y * pitch + x] for y < h, x < w
+    int raster;
+    int h, w, Bw;
+    int64_t pitch;
 };
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
 

@@ -109,6 +109,26 @@ __device__ __forceinline__ uint32_t pack_u8x4(float a, float b, float c, float d
     return w;
 }
 
+// Four pixels (one little-endian word, first pixel at column x) into row y
+// of an h x w raster image with row pitch `pitch` bytes (a multiple of 4):
+// one word store where all four columns are inside the image, byte stores
+// at the right edge, nothing below the last row.
+__device__ __forceinline__ void store_px_raster4(uint8_t *img, int64_t pitch, int h, int w, int y, int x,
+                                                 uint32_t word)
+{
+    if (y >= h)
+        return;
+    uint8_t *row = img + (int64_t)y * pitch;
+    if (x + 3 < w) {
+        *reinterpret_cast<uint32_t *>(row + x) = word;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (x + e < w)
+                row[x + e] = (uint8_t)(word >> (8 * e));
+    }
+}
+
 // Eight quantised coefficients (one 16-byte load, little-endian int16) times
 // their dequantisation factors q[0..7]; `dc` is added to the first one.
 __device__ __forceinline__ void dequant8(u32x4 raw, const float q[8], float dc, float4 &lo, float4 &hi)
@@ -864,7 +884,8 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // IN = 0: FP32 coefficients from r.in; IN = 1: int16 coefficients from
 // r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term.
 // OUT = 0: FP32 results to r.out; OUT = 1: uint8 pixels to r.pix (the
-// operator is then the pixel-domain one).
+// operator is then the pixel-domain one); OUT = 2: the same pixels into the
+// raster image r.pix (r.h x r.w, row pitch r.pitch, r.Bw blocks per row).
 template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, typename RefFn,
           typename OpFn, typename Regs>
 __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
@@ -953,12 +974,22 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
             const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 1024);
             buf_st4<false>(o, out_off, acc[0]);
             buf_st4<false>(o, out_off + 64, acc[1]);
-        } else {
+        } else if constexpr (OUT == 1) {
             const rsrc_t o = tile_rsrc(rc.pix, rc.blk0, rc.B, 256);
             __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]), o,
                                                   out_off, 0, 0);
             __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[1][0], acc[1][1], acc[1][2], acc[1][3]), o,
                                                   out_off + 16, 0, 0);
+        } else {
+            // raster image: pixels 4g .. 4g + 3 of rows 2 wave and 2 wave + 1 of block n
+            if (rc.blk0 + n < rc.B) {
+                const int blk = (int)(rc.blk0 + n);
+                const int by = blk / rc.Bw, bx = blk - by * rc.Bw;
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    store_px_raster4(rc.pix, rc.pitch, rc.h, rc.w, 16 * by + 2 * wave + t, 16 * bx + 4 * g,
+                                     pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
+            }
         }
         if (!last) {
             if constexpr (MULTI_OP)

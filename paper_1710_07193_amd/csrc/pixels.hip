@@ -6,6 +6,9 @@
 // coefficient instead of 4 + 4 for the filter and 4 + 1 for a separate
 // inverse transform.
 //
+// Outputs: the pixels block by block (N*N bytes per block), or in their
+// places in one h x w raster image (row pitch in bytes).
+//
 // Inputs: FP32 coefficient blocks (IN = 0), or quantised int16 coefficient
 // blocks (IN = 1, the entropy-decoded blocks of a JPEG-style codec) that are
 // dequantised in registers, X[k] = q[k] c[k] (+ dc_offset on the DC term):
@@ -168,8 +171,25 @@ __device__ __forceinline__ void store_px8_direct(uint8_t *pix, int64_t nvalid, c
         dst[4 * t] = pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
 }
 
+// SO = 0 into a raster image: lane (n, g) holds pixels 4(g % 2) .. +3 of
+// rows 2t + g / 2 of block n.
+__device__ __forceinline__ void store_px8_raster(const PxArgs &a, int64_t blk0, int64_t nvalid, const f32x4 acc[4],
+                                                 int lane)
+{
+    const int n = lane & 15, g = lane >> 4;
+    if (n >= nvalid)
+        return;
+    const int blk = (int)(blk0 + n);
+    const int by = blk / a.Bw, bx = blk - by * a.Bw;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        store_px_raster4(a.pix, a.pitch, a.h, a.w, 8 * by + 2 * t + (g >> 1), 8 * bx + 4 * (g & 1),
+                         pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
+}
+
 // Wave w takes units (U tiles of 16 blocks) w, w + waves, ...
-template <int PREC, int IN, int U, int LI, int SO>
+// RAST: pixels into the raster image (SO = 0 only).
+template <int PREC, int IN, int U, int LI, int SO, bool RAST = false>
 __global__ __launch_bounds__(256) void k_filter_px8(PxArgs a, int64_t units, int64_t waves)
 {
     constexpr bool kLds = LI == 1 || SO == 1;
@@ -226,7 +246,10 @@ __global__ __launch_bounds__(256) void k_filter_px8(PxArgs a, int64_t units, int
             to_mfma8(t[u], L, lane, q, dc, xm);
             f32x4 acc[4];
             tile8(R, xm, lane, acc);
-            if constexpr (SO == 1) {
+            static_assert(!RAST || SO == 0, "raster stores go straight from the MFMA layout");
+            if constexpr (RAST) {
+                store_px8_raster(a, blk0, B - blk0, acc, lane);
+            } else if constexpr (SO == 1) {
                 wave_lds_sync();
                 stage_out(L, acc, lane);
                 wave_lds_sync();
@@ -262,9 +285,11 @@ struct RefPx16 {
     int64_t B;
     int64_t blk0;
     int op;
+    int h, w, Bw;   // raster output
+    int64_t pitch;
 };
 
-template <int PREC, int IN, int D>
+template <int PREC, int IN, int D, bool RAST = false>
 __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
 {
     const int tid = threadIdx.x;
@@ -284,6 +309,10 @@ __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
         r.B = a.B;
         r.blk0 = (wg + t * G) * 16;
         r.op = 0;
+        r.h = a.h;
+        r.w = a.w;
+        r.Bw = a.Bw;
+        r.pitch = a.pitch;
         return r;
     };
     auto op_load = [&](int) {
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
         else
             load_op16(R, a.G.frag_hi, a.G.frag_lo, a.G.frag_lf, wave, lane);
     };
-    run_tiles16<PREC, D, RefPx16, IN, 1>(count, ref, op_load, R, smem, a.qtab, a.dc_offset);
+    run_tiles16<PREC, D, RefPx16, IN, RAST ? 2 : 1>(count, ref, op_load, R, smem, a.qtab, a.dc_offset);
 }
 
 // ---------------------------------------------------------------- N <= 4
@@ -300,6 +329,7 @@ __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
 template <int IN>
 __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
 {
+    // (raster output: pixel r of block blk goes to its place in the image)
     __shared__ float sG[256];
     const int NN = N * N;
     for (int e = threadIdx.x; e < NN * NN; e += blockDim.x)
@@ -315,11 +345,18 @@ __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
         else
             x[k] = (float)a.qin[blk * NN + k] * a.qtab[k] + (k == 0 ? a.dc_offset : 0.0f);
     }
+    const int by = a.raster ? (int)(blk / a.Bw) : 0, bx = a.raster ? (int)(blk - (int64_t)by * a.Bw) : 0;
     for (int r = 0; r < NN; ++r) {
         float s = 0.0f;
         for (int k = 0; k < NN; ++k)
             s = fmaf(sG[r * NN + k], x[k], s);
-        a.pix[blk * NN + r] = (uint8_t)pixel_u8(s);
+        if (!a.raster) {
+            a.pix[blk * NN + r] = (uint8_t)pixel_u8(s);
+        } else {
+            const int y = by * N + r / N, xx = bx * N + r % N;
+            if (y < a.h && xx < a.w)
+                a.pix[(int64_t)y * a.pitch + xx] = (uint8_t)pixel_u8(s);
+        }
     }
 }
 
@@ -339,8 +376,12 @@ hipError_t run_px8(const PxArgs &a, hipStream_t stream)
     int64_t waves = (int64_t)cu_count() * kPx8WavesPerCu;
     waves = waves < units ? waves : units;
     const int64_t groups = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_filter_px8<PREC, IN, kPx8U, kPx8Li, kPx8So>), dim3((unsigned)groups), dim3(256), 0,
-                       stream, a, units, waves);
+    if (a.raster)
+        hipLaunchKernelGGL((k_filter_px8<PREC, IN, kPx8U, kPx8Li, 0, true>), dim3((unsigned)groups), dim3(256), 0,
+                           stream, a, units, waves);
+    else
+        hipLaunchKernelGGL((k_filter_px8<PREC, IN, kPx8U, kPx8Li, kPx8So>), dim3((unsigned)groups), dim3(256), 0,
+                           stream, a, units, waves);
     return hipGetLastError();
 }
 
@@ -350,8 +391,12 @@ hipError_t run_px16(const PxArgs &a, hipStream_t stream)
     const int64_t tiles = (a.B + 15) / 16;
     int64_t groups = (int64_t)cu_count();
     groups = groups < tiles ? groups : tiles;
-    hipLaunchKernelGGL((k_filter_px16<PREC, IN, kPx16Depth>), dim3((unsigned)groups), dim3(512), 0, stream, a,
-                       tiles);
+    if (a.raster)
+        hipLaunchKernelGGL((k_filter_px16<PREC, IN, kPx16Depth, true>), dim3((unsigned)groups), dim3(512), 0,
+                           stream, a, tiles);
+    else
+        hipLaunchKernelGGL((k_filter_px16<PREC, IN, kPx16Depth>), dim3((unsigned)groups), dim3(512), 0, stream, a,
+                           tiles);
     return hipGetLastError();
 }
 

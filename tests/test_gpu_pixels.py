@@ -190,3 +190,77 @@ def test_pixel_entry_points_reject_bad_arguments(dctf):
 def ctypes_float(v):
     import ctypes
     return ctypes.c_float(v)
+
+
+# ------------------------------------------------------------ raster output
+
+def untile(blocks, h, w, N):
+    """[Bh * Bw, N, N] blocks in raster order -> the h x w image they tile."""
+    bh, bw = -(-h // N), -(-w // N)
+    img = blocks.reshape(bh, bw, N, N).transpose(0, 2, 1, 3).reshape(bh * N, bw * N)
+    return img[:h, :w]
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+@pytest.mark.parametrize("N,h,w,border", [(8, 77, 131, R), (8, 64, 64, Z), (8, 1, 1, Z), (8, 5, 300, R),
+                                          (8, 203, 3, Z), (16, 77, 131, Z), (16, 160, 48, R), (16, 17, 1, R),
+                                          (4, 30, 41, R), (2, 9, 7, Z)])
+def test_raster_output_matches_blocks_and_oracle(dctf, N, h, w, border, prec):
+    """Raster pixels equal the block-ordered pixels of the same call put in
+    their places (bit for bit) and the oracle's uint8 outside the 1/2 band;
+    the image is a column slice of a wider buffer, whose other bytes must stay
+    untouched."""
+    img = syn.image_u8(300 + h + w + N, h, w)
+    px = oracle.tile_u8(img, N)
+    X32 = oracle.coeffs_fp32(px)
+    W = syn.asym_mask_5x5() if N >= 4 else syn.box_mask(3)
+    op = dctf.dctf_build_operator(W, N, border)
+    blocks = gpu_px(dctf, op, X32, prec)
+    pitch = (w + 7) // 4 * 4 + 8
+    buf = torch.full((h + 2, pitch), 77, dtype=torch.uint8, device="cuda")
+    dctf.dctf_filter_blocks_u8_raster(op, prec, dev(X32.reshape(-1)), h, w, buf[:, :w])
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[:h, :w], untile(blocks, h, w, N))
+    assert (got[:h, w:] == 77).all() and (got[h:] == 77).all()
+    _, u8, nh = oracle.filter_coeffs_to_pixels(X32.astype(np.float64), W, border)
+    ref, band = untile(u8, h, w, N), untile(nh, h, w, N)
+    assert np.array_equal(got[:h, :w][~band], ref[~band])
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+@pytest.mark.parametrize("N", [8, 16])
+def test_quantized_raster_output(dctf, N, prec):
+    h, w = 200, 136
+    img = syn.image_u8(310 + N, h, w)
+    px = oracle.tile_u8(img, N)
+    q = syn.quant_table(N)
+    qc = syn.quantize(oracle.dct_pixels(px), q, 128.0 * N)
+    W = syn.asym_mask_5x5()
+    op = dctf.dctf_build_operator(W, N, R)
+    blocks = gpu_qpx(dctf, op, qc, q, 128.0 * N, prec)
+    out = torch.full((h, w), 0, dtype=torch.uint8, device="cuda")
+    dctf.dctf_filter_quantized_u8_raster(op, prec, dev(qc.reshape(-1)), dev(q.astype(np.float32).reshape(-1)),
+                                         128.0 * N, h, w, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), untile(blocks, h, w, N))
+
+
+def test_raster_argument_errors(dctf):
+    N = 8
+    op = dctf.dctf_build_operator(syn.box_mask(3), N, Z)
+    lib = dctf.raw_library()
+    X = torch.zeros(4 * 64, dtype=torch.float32, device="cuda")
+    img = torch.zeros(64 * 64, dtype=torch.uint8, device="cuda")
+    p = img.data_ptr()
+    ok = lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 16, None)
+    assert ok == 0
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 18, None) == -1   # pitch % 4
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 12, None) == -1   # pitch < w
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), -1, 16, p, 16, None) == -1
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p + 2, 16, None) == -1  # align
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 0, 16, p, 16, None) == 0     # no-op
+    # the input overlapping the image
+    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, X.data_ptr(), 16, None) == -1
+    op32 = dctf.dctf_build_operator(syn.box_mask(3), 32, Z)
+    assert lib.dctf_filter_blocks_u8_raster(op32.handle, FP32, X.data_ptr(), 8, 8, p, 16, None) == -2
