@@ -359,8 +359,11 @@ typedef struct {
  * Plan a batch: many jobs (images), operators (masks) and block sizes (N = 8
  * and N = 16 may be mixed) that run in ONE persistent kernel launch.  The plan
  * copies the job list into a device work table (jobs grouped by operator) and
- * records the distinct operators.  Jobs with N <= 4 are rejected
- * (DCTF_EUNSUPPORTED).  Outputs of different jobs must not overlap any input
+ * records the distinct operators.  Jobs of the other block sizes (N = 2, 4
+ * and 32) run after that launch, on the same stream, one single-operator
+ * launch each (the kernels of dctf_filter_blocks: N = 32 in the batch's
+ * precision, N <= 4 in FP32); every run, rebuild and captured graph
+ * includes them.  Outputs of different jobs must not overlap any input
  * or output of another job.  The plan owns device memory until destroyed;
  * operators must outlive it.
  */
@@ -550,7 +553,7 @@ typedef struct {
     double arrival_s;          /* dctf_server_run: arrival time, seconds after the start of the run,
                                   non-decreasing; not read by dctf_server_submit */
     const double *mask_host;   /* kh*kw doubles (host), all finite; copied at submission */
-    int kh, kw, N, border;     /* N = 8 or 16; 1 <= kh, kw <= 2N+1 */
+    int kh, kw, N, border;     /* N = 2, 4, 8, 16 or 32; 1 <= kh, kw <= 2N+1 */
     const float *in_dev;       /* B*N*N coefficients, device-resident, 16-byte aligned; must stay
                                   valid and unchanged until the request completes */
     int64_t B;                 /* >= 1 */

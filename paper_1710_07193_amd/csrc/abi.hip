@@ -824,7 +824,8 @@ struct dctf_batch_s {
     int prec = 0;
     std::vector<dctf_job> jobs;       // the caller's jobs (kept for re-planning)
     dctf_batch_config cfg{};          // configuration of the current plan
-    std::vector<dctf_operator> ops;   // distinct operators, in table order
+    std::vector<dctf_operator> ops;   // distinct operators, in table order (then those of side jobs)
+    std::vector<dctf_job> side;       // jobs of N = 2, 4 and 32: one launch each after the persistent one
     void *dev = nullptr;              // JobDesc[njobs8] | JobDesc[njobs16] | OpDesc[nops]
     size_t dev_bytes = 0;
     BatchArgs args{};
@@ -867,7 +868,8 @@ bool jobs_conflict(const dctf_job *jobs, int n)
 namespace dctf {
 
 dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_batch_config &cfg,
-                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops)
+                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops,
+                       std::vector<dctf_job> *side)
 {
     if (njobs < 0 || (njobs > 0 && jobs == nullptr))
         return DCTF_EINVAL;
@@ -877,7 +879,7 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_bat
         const dctf_job &j = jobs[i];
         if (j.op == nullptr)
             return DCTF_EINVAL;
-        if (j.op->N != 8 && j.op->N != 16)
+        if (j.op->N != 8 && j.op->N != 16 && side == nullptr)
             return DCTF_EUNSUPPORTED;
         dctf_status st = validate_io(j.op->N, j.in, j.out, j.B);
         if (st != DCTF_OK)
@@ -886,11 +888,19 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_bat
     if (jobs_conflict(jobs, njobs))
         return DCTF_EINVAL;
 
-    // Group by N, then operator (stable in the caller's order otherwise).
+    // Group by N, then operator (stable in the caller's order otherwise);
+    // jobs of the other block sizes run after the persistent launch.
     std::vector<int> order;
-    for (int i = 0; i < njobs; ++i)
-        if (jobs[i].B > 0)
+    if (side)
+        side->clear();
+    for (int i = 0; i < njobs; ++i) {
+        if (jobs[i].B <= 0)
+            continue;
+        if (jobs[i].op->N == 8 || jobs[i].op->N == 16)
             order.push_back(i);
+        else
+            side->push_back(jobs[i]);
+    }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         if (jobs[x].op->N != jobs[y].op->N)
             return jobs[x].op->N < jobs[y].op->N;
@@ -1029,6 +1039,23 @@ dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_bat
     a.workers16 = workers16;
     a.groups8 = (int)((workers8 + wpg8 - 1) / wpg8);
     a.groups16 = (int)workers16;
+    // the operators of the other jobs, after those of the table (rebuilt with them)
+    if (side)
+        for (const dctf_job &j : *side)
+            if (std::find(ops.begin(), ops.end(), j.op) == ops.end())
+                ops.push_back(j.op);
+    return DCTF_OK;
+}
+
+dctf_status launch_side_jobs(const std::vector<dctf_job> &side, int prec, hipStream_t s)
+{
+    for (const dctf_job &j : side) {
+        const FilterArgs fa = filter_args(j.op, j.in, j.out, j.B);
+        const hipError_t e = j.op->N == 32 ? launch_filter_n32(prec, fa, s)
+                                           : launch_filter(j.op->N, prec, current_variant(j.op->N, prec), fa, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
     return DCTF_OK;
 }
 
@@ -1057,7 +1084,8 @@ static dctf_status batch_plan(dctf_batch b, const dctf_batch_config &cfg)
     std::vector<char> table;
     BatchArgs a;
     std::vector<dctf_operator> ops;
-    dctf_status st = plan_batch(b->jobs.data(), (int)b->jobs.size(), b->prec, cfg, table, a, ops);
+    std::vector<dctf_job> side;
+    dctf_status st = plan_batch(b->jobs.data(), (int)b->jobs.size(), b->prec, cfg, table, a, ops, &side);
     if (st != DCTF_OK)
         return st;
     if (b->exec) {
@@ -1094,6 +1122,7 @@ static dctf_status batch_plan(dctf_batch b, const dctf_batch_config &cfg)
     rebase_batch(a, b->dev);
     b->args = a;
     b->ops = ops;
+    b->side = side;
     b->cfg = cfg;
     return DCTF_OK;
 }
@@ -1174,6 +1203,8 @@ static dctf_status batch_enqueue(dctf_batch b, unsigned flags, hipStream_t s)
     timing_begin(s, &slot);
     dctf_status st = hip_status(launch_batch(b->args, s));
     timing_end(s, slot);
+    if (st == DCTF_OK)
+        st = launch_side_jobs(b->side, b->prec, s);
     return st;
 }
 
@@ -1307,23 +1338,28 @@ extern "C" dctf_status dctf_filter_batch_noalloc(const dctf_job *jobs, int njobs
     std::vector<char> table;
     BatchArgs a;
     std::vector<dctf_operator> ops;
-    dctf_status st = plan_batch(jobs, njobs, prec, batch_config(prec), table, a, ops);
+    std::vector<dctf_job> side;
+    dctf_status st = plan_batch(jobs, njobs, prec, batch_config(prec), table, a, ops, &side);
     if (st != DCTF_OK)
         return st;
-    if (table.empty())
-        return DCTF_OK;   // no blocks: nothing to launch
     if (table.size() > kNoAllocScratchBytes)
         return DCTF_EINVAL;   // work table beyond the fixed scratch: use dctf_filter_batch
-    void *dev = nullptr;
-    st = scratch_address(&dev);
-    if (st != DCTF_OK)
-        return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(dev, table.data(), table.size(), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess)
-        return hip_status(e);
-    rebase_batch(a, dev);
-    st = hip_status(launch_batch(a, s));
+    if (!table.empty()) {
+        void *dev = nullptr;
+        st = scratch_address(&dev);
+        if (st != DCTF_OK)
+            return st;
+        hipError_t e = hipMemcpyAsync(dev, table.data(), table.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+        rebase_batch(a, dev);
+        st = hip_status(launch_batch(a, s));
+    }
+    if (st == DCTF_OK)
+        st = launch_side_jobs(side, prec, s);   // their kernels use no scratch
+    if (table.empty() && side.empty())
+        return st;   // no blocks: nothing was launched
     // The host table must outlive the copy, and the next call may rewrite
     // the scratch: return once this call's work is done.
     const dctf_status st2 = hip_status(hipStreamSynchronize(s));

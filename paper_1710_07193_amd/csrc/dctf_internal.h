@@ -317,7 +317,10 @@ int batch_occupancy(int prec, int io, bool nt, int kind);
 // `cfg` fixes the fronts, N = 8 I/O path and grid size (fields < 0 / 0 take
 // the process-wide setting of the precision, see dctf_set_batch_config).
 dctf_status plan_batch(const dctf_job *jobs, int njobs, int prec, const dctf_batch_config &cfg,
-                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops);
+                       std::vector<char> &table, BatchArgs &a, std::vector<dctf_operator> &ops,
+                       std::vector<dctf_job> *side);
+// The jobs plan_batch set aside (N = 2, 4, 32): one single-operator launch each.
+dctf_status launch_side_jobs(const std::vector<dctf_job> &side, int prec, hipStream_t s);
 // The process-wide configuration of a precision.
 dctf_batch_config batch_config(int prec);
 void rebase_batch(BatchArgs &a, const void *dev);

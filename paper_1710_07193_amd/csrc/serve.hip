@@ -140,6 +140,7 @@ struct dctf_server_s {
     std::deque<dctf_request *> finished;   // completed, not yet returned by a poll
     int64_t outstanding = 0;      // submitted and not yet returned by a poll
     std::vector<dctf_job> jobs;   // scratch of the admission step
+    std::vector<dctf_job> side;   // its jobs of N = 2, 4, 32 (launched one by one)
     std::vector<char> table;
     std::vector<dctf_operator> ops;
 };
@@ -150,7 +151,8 @@ namespace {
 // pointers and alignment.  arrival_s is not read here.
 bool request_valid(const dctf_request &r)
 {
-    if (r.B < 1 || (r.N != 8 && r.N != 16) || r.mask_host == nullptr || r.kh < 1 || r.kw < 1 ||
+    if (r.B < 1 || (r.N != 2 && r.N != 4 && r.N != 8 && r.N != 16 && r.N != 32) || r.mask_host == nullptr ||
+        r.kh < 1 || r.kw < 1 ||
         r.kh > 2 * r.N + 1 || r.kw > 2 * r.N + 1 ||
         (r.border != DCTF_BORDER_ZERO && r.border != DCTF_BORDER_REPLICATE) || r.in_dev == nullptr ||
         ((uintptr_t)r.in_dev & 15) || ((uintptr_t)r.out_dev & 15))
@@ -307,7 +309,7 @@ dctf_status admit(dctf_server s)
         }
         BatchArgs a;
         dctf_status st = plan_batch(s->jobs.data(), (int)s->jobs.size(), s->cfg.prec, batch_config(s->cfg.prec),
-                                    s->table, a, s->ops);
+                                    s->table, a, s->ops, &s->side);
         if (st == DCTF_OK && s->table.size() > sl.table_cap)
             st = DCTF_EINVAL;
         hipError_t e = hipSuccess;
@@ -317,6 +319,8 @@ dctf_status admit(dctf_server s)
             rebase_batch(a, sl.table_dev);
             if (e == hipSuccess)
                 e = launch_batch(a, sl.stream);
+            if (e == hipSuccess && launch_side_jobs(s->side, s->cfg.prec, sl.stream) != DCTF_OK)
+                e = hipErrorLaunchFailure;
             for (size_t k = 0; k < sl.reqs.size() && e == hipSuccess; ++k) {
                 const dctf_request &r = *sl.reqs[k];
                 if (r.out_dev)

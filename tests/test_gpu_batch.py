@@ -188,6 +188,51 @@ def test_batch_rejections(dctf):
         dctf.dctf_batch_create([(a["op"], a["X"], a["Y"]), (a["op"], a["Y"], b["Y"][: a["Y"].numel()])], SPLIT)
     small = dctf.dctf_build_operator(syn.box_mask(3), 4, Z)
     x4 = torch.zeros(16 * 4, device="cuda")
-    with pytest.raises(dctf.DctfError) as e:  # N = 4 is not a batched block size
-        dctf.dctf_batch_create([(small, x4, torch.zeros_like(x4))], SPLIT)
-    assert e.value.status == dctf.DCTF_EUNSUPPORTED
+    with pytest.raises(dctf.DctfError):       # a side job's output overlapping a table job's input
+        dctf.dctf_batch_create([(a["op"], a["X"], a["Y"]), (small, x4, a["X"][:x4.numel()])], SPLIT)
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_batch_every_block_size(dctf, prec):
+    """Jobs of N = 2, 4, 8, 16 and 32 in one batch (the N = 8 / 16 jobs in the
+    persistent launch, the others one launch each after it): each output
+    equals the job filtered alone, on a run with the operator rebuild, on
+    graph replays and in the one-shot call, and the oracle within tolerance."""
+    rng = np.random.default_rng(44)
+    specs = [(2, 40, 36, syn.box_mask(3), Z), (4, 64, 52, syn.random_mask(rng, 5, 5), R),
+             (8, 200, 264, syn.random_mask(rng, 5, 5), R), (16, 96, 128, syn.gaussian_mask(7), Z),
+             (32, 160, 96, syn.random_mask(rng, 7, 7), Z), (32, 64, 64, syn.gaussian_mask(5), R),
+             (4, 8, 8, syn.box_mask(3), R)]
+    jobs = []
+    for k, (N, h, w, W, border) in enumerate(specs):
+        px = oracle.tile_u8(syn.image_u8(900 + k, h, w), N)
+        X = dev(oracle.coeffs_fp32(px).reshape(-1))
+        jobs.append(dict(N=N, W=W, border=border, px=px, X=X, Y=torch.full_like(X, float("nan"))))
+    ops = dctf.dctf_build_operators([(j["W"], j["N"], j["border"]) for j in jobs])
+    for j, op in zip(jobs, ops):
+        j["op"] = op
+    tol = {2: 2e-3, 4: 2e-3, 8: TOL[prec], 16: TOL[prec], 32: TOL[prec]}
+    b = dctf.dctf_batch_create([(j["op"], j["X"], j["Y"]) for j in jobs], prec)
+    dctf.dctf_batch_run(b, dctf.DCTF_RUN_REBUILD_OPERATORS)
+    torch.cuda.synchronize()
+    for j in jobs:
+        got = j["Y"].cpu().numpy()
+        assert np.array_equal(got, alone(dctf, j, prec)), j["N"]
+        ref, _, _ = oracle.filter_pixels(j["px"], j["W"], j["border"])
+        assert np.abs(got.reshape(ref.shape) - ref).max() <= tol[j["N"]], j["N"]
+    first = [j["Y"].clone() for j in jobs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for j in jobs:
+            j["Y"].fill_(float("nan"))
+        dctf.dctf_batch_capture(b, dctf.DCTF_RUN_REBUILD_OPERATORS, s)
+        for _ in range(3):
+            dctf.dctf_batch_launch_graph(b, s)
+            s.synchronize()
+            for j, f in zip(jobs, first):
+                assert torch.equal(j["Y"], f), j["N"]
+                j["Y"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    dctf.dctf_filter_batch([(j["op"], j["X"], j["Y"]) for j in jobs], prec)
+    for j, f in zip(jobs, first):
+        assert torch.equal(j["Y"], f), j["N"]

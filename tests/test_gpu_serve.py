@@ -136,7 +136,9 @@ def test_malformed_request_lists(dctf):
     with pytest.raises(dctf.DctfError):
         dctf.dctf_server_run(server, bad_order)
     with pytest.raises(dctf.DctfError):
-        dctf.dctf_server_run(server, [dict(arrival_s=0.0, mask=masks[0].mask, N=4, border=0, X=X)])
+        # N = 5 is no block size of the library
+        dctf.dctf_server_run(server, [dict(arrival_s=0.0, mask=masks[0].mask, N=5, border=0,
+                                           X=torch.randn(75, device="cuda"))])
 
 
 def test_malformed_mask_runs_nothing(dctf):
@@ -222,3 +224,29 @@ def test_served_outputs_match_oracle(dctf, prec):
         assert r["status"] == 0
         err = np.abs(q["Y"].cpu().numpy().reshape(ref.shape) - ref).max()
         assert err <= tol, err
+
+
+@pytest.mark.parametrize("prec", [SPLIT, FP32])
+def test_served_block_sizes_2_to_32(dctf, prec):
+    """Requests of N = 2, 4 and 32 beside N = 8 and 16 in the same batches:
+    each served output equals the single-operator call."""
+    rng = np.random.default_rng(12)
+    masks = {2: syn.box_mask(3), 4: syn.random_mask(rng, 5, 5), 8: syn.asym_mask_5x5(),
+             16: syn.gaussian_mask(7), 32: syn.random_mask(rng, 7, 7)}
+    reqs = []
+    for k in range(20):
+        N = (2, 4, 8, 16, 32)[k % 5]
+        B = int(rng.integers(1, 600))
+        X = torch.randn(B * N * N, device="cuda") * 40
+        reqs.append(dict(arrival_s=k * 1e-5, mask=masks[N], N=N, border=k % 2, X=X,
+                         Y=torch.full_like(X, float("nan"))))
+    server = dctf.dctf_server_create(arena_bytes=1 << 28, max_inflight=3, max_batch_jobs=6, prec=prec)
+    res = dctf.dctf_server_run(server, reqs)
+    torch.cuda.synchronize()
+    assert all(r["status"] == 0 for r in res)
+    for r in reqs:
+        op = dctf.dctf_build_operator(r["mask"], r["N"], r["border"])
+        Y = torch.empty_like(r["X"])
+        dctf.dctf_filter_blocks(op, prec, r["X"], Y)
+        torch.cuda.synchronize()
+        assert torch.equal(r["Y"], Y), r["N"]

@@ -65,3 +65,26 @@ def test_noalloc_rejects_a_table_beyond_the_scratch(dctf):
     assert e.value.status == dctf.DCTF_EINVAL
     torch.cuda.synchronize()
     assert torch.isnan(Y).all()
+
+
+@pytest.mark.parametrize("prec", [SPLIT, FP32])
+def test_noalloc_with_jobs_of_every_block_size(dctf, prec):
+    """Jobs of N = 4 and 32 (one launch each, no table entry) beside N = 8
+    and 16: the same results as dctf_filter_batch, and a call of only such
+    jobs runs them with an empty table."""
+    rng = np.random.default_rng(43)
+    ops = dctf.dctf_build_operators([(syn.random_mask(rng, 3, 3), N, 1) for N in (4, 8, 16, 32)])
+    for njobs, max_blocks in ((12, 3000), (5, 200)):
+        jobs = jobs_of(dctf, rng, njobs, max_blocks, ops)
+        want = [torch.empty_like(X) for _, X, _ in jobs]
+        dctf.dctf_filter_batch([(op, X, W) for (op, X, _), W in zip(jobs, want)], prec)
+        dctf.dctf_filter_batch_noalloc(jobs, prec)
+        for (_, _, Y), W in zip(jobs, want):
+            assert torch.equal(Y, W)
+    side_only = jobs_of(dctf, rng, 3, 500, [ops[0], ops[3]])
+    dctf.dctf_filter_batch_noalloc(side_only, prec)
+    for op, X, Y in side_only:
+        W = torch.empty_like(X)
+        dctf.dctf_filter_blocks(op, prec, X, W)
+        torch.cuda.synchronize()
+        assert torch.equal(Y, W)
