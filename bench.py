@@ -480,6 +480,14 @@ def n32_frames(dctf, torch, stream, steps, warmup):
     res["split_bf16"] = {"ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
                          "GBps": B * N * N * 8 / (ms * 1e-3) / 1e9, "bf16_mfma_TFLOPs": tf,
                          "frac_of_bf16_mfma_peak": tf / BF16_MFMA_PEAK_TFLOPS}
+    # the factored (paper-form) FP32 path: this mask (rank 7) and a separable 7x7 Gaussian (rank 1)
+    gop = dctf.dctf_build_operator(syn.gaussian_mask(7), N, dctf.DCTF_BORDER_ZERO)
+    for tag, o in (("mask7x7", op), ("gauss7x7", gop)):
+        rank = dctf.dctf_operator_rank(o)
+        fms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_factored(o, X, Y, stream), steps, warmup, stream,
+                          settle_first=True)
+        res["factored_" + tag] = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
+                                  "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
     res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y

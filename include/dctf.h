@@ -205,13 +205,14 @@ dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, 
 /*
  * Y[b] = sum_r P_r X[b] Q_r^t for b = 0..B-1: the factored form above,
  * FP32 MFMA (v_mfma_f32_16x16x4_f32, two chained products per rank term,
- * FP32 accumulation).  It does 2 R N^3 multiply-adds per block against the
- * dense path's N^4, so at N = 16 it does less MFMA work for R < 8 and keeps
- * low-rank masks (separable, 1-D, symmetric 3 x 3) at the HBM bound.
+ * on 16 x 16 quadrants at N = 32, FP32 accumulation).  It does 2 R N^3
+ * multiply-adds per block against the dense path's N^4, so it does less MFMA
+ * work for R < N/2 (N = 16: R < 8; N = 32: every R <= 8) and keeps low-rank
+ * masks (separable, 1-D, symmetric 3 x 3) at the HBM bound.
  * Results match dctf_filter_blocks(FP32) within FP32 rounding, not bit for
  * bit (different summation order).  Buffers as for dctf_filter_blocks.
- * Errors: DCTF_EINVAL (arguments), DCTF_EUNSUPPORTED (N != 16 or R > 8),
- * DCTF_EHIP.
+ * Errors: DCTF_EINVAL (arguments), DCTF_EUNSUPPORTED (N other than 16 and
+ * 32, or R > 8), DCTF_EHIP.
  */
 dctf_status dctf_filter_blocks_factored(dctf_operator op, const float *in_dev, float *out_dev, int64_t B,
                                         dctf_stream stream);

@@ -475,8 +475,6 @@ extern "C" dctf_status dctf_operator_factors_fp64(dctf_operator op, double *P_ho
 {
     if (op == nullptr || P_host == nullptr || Q_host == nullptr)
         return DCTF_EINVAL;
-    if (op->N > 16)
-        return DCTF_EUNSUPPORTED;
     const size_t bytes = sizeof(double) * op->rank * op->N * op->N;
     dctf_status st = hip_status(hipMemcpy(P_host, op->img.P64, bytes, hipMemcpyDeviceToHost));
     if (st == DCTF_OK)
@@ -489,7 +487,7 @@ extern "C" dctf_status dctf_filter_blocks_factored(dctf_operator op, const float
 {
     if (op == nullptr)
         return DCTF_EINVAL;
-    if (op->N != 16 || op->rank > kFactoredMaxRank)
+    if ((op->N != 16 && op->N != 32) || op->rank > kFactoredMaxRank)
         return DCTF_EUNSUPPORTED;
     dctf_status st = validate_io(op->N, in_dev, out_dev, B);
     if (st != DCTF_OK || B == 0)
@@ -497,7 +495,8 @@ extern "C" dctf_status dctf_filter_blocks_factored(dctf_operator op, const float
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);
-    st = hip_status(launch_filter_factored(op->N, op->rank, op->img.P32, op->img.Q32, in_dev, out_dev, B, s));
+    st = hip_status(launch_filter_factored(op->N, op->rank, op->img.P32, op->img.Q32, op->img.dct.h0, in_dev,
+                                           out_dev, B, s));
     timing_end(s, slot);
     return st;
 }

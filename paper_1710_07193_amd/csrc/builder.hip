@@ -49,6 +49,7 @@ constexpr int kThreads = 256;
 constexpr int kRowsPerGroup = 16;
 constexpr int kMaxN = 16;
 constexpr int kMaxK = 2 * kMaxN + 1;
+constexpr int kMaxFacN = 32;   // the factors are built for every block size
 
 // Source index of row (or column) i under a shift by d.  The returned index
 // is always inside the block (clamped); in zero mode *valid tells whether the
@@ -261,12 +262,12 @@ __global__ __launch_bounds__(kThreads) void k_build_factors(BuildArgs args)
         return;
     const BuildDesc &d = args.d[op];
     const int r = blockIdx.x >> 1, axis = blockIdx.x & 1;
-    if (r >= d.rank || d.N > kMaxN)   // the factored form is built for N <= 16
+    if (r >= d.rank)
         return;
     const int N = d.N, NN = N * N, tid = threadIdx.x;
     const int K = axis ? d.kw : d.kh, anchor = (K - 1) / 2;
     const double *coef = axis ? d.img.fac_b + (size_t)r * d.kw : d.img.fac_a + (size_t)r * d.kh;
-    __shared__ double sC[kMaxN * kMaxN], sM[kMaxN * kMaxN], sT[kMaxN * kMaxN];
+    __shared__ double sC[kMaxFacN * kMaxFacN], sM[kMaxFacN * kMaxFacN], sT[kMaxFacN * kMaxFacN];
     for (int e = tid; e < NN; e += kThreads) {
         const int k = e / N, n = e % N;
         const double alpha = (k == 0) ? sqrt(1.0 / N) : sqrt(2.0 / N);

@@ -150,11 +150,12 @@ hipError_t launch_build(const BuildArgs &args, hipStream_t stream);
 // (at least 1: a zero mask gives one zero term).
 int mask_rank_factors(const double *W, int kh, int kw, std::vector<double> &a, std::vector<double> &b);
 
-// filter.hip — the factored (paper-form) path Y = sum_r P_r X Q_r^t, N = 16,
-// FP32, rank <= kFactoredMaxRank.
+// filter.hip — the factored (paper-form) path Y = sum_r P_r X Q_r^t, N = 16
+// and 32, FP32, rank <= kFactoredMaxRank; h0 (the DC column of H, N = 32
+// only) carries the DC coefficient's term, applied last.
 constexpr int kFactoredMaxRank = 8;
-hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *in,
-                                  float *out, int64_t B, hipStream_t stream);
+hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *h0,
+                                  const float *in, float *out, int64_t B, hipStream_t stream);
 
 // pixels.hip — filter + inverse DCT + uint8 in one pass (pixel-domain images),
 // from FP32 coefficients (IN = 0) or from quantised int16 coefficients that

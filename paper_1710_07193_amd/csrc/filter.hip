@@ -403,15 +403,201 @@ hipError_t run_factored16(const float *P32, const float *Q32, const float *in, f
     return hipGetLastError();
 }
 
+// ------------------------------------------------- N = 32, factored form
+//
+// The same two chained products on 16 x 16 quadrants: block X (32 x 32) is
+// X[a][b] with a = 16 alpha + a', b = 16 beta + b'; lane (n, g) holds
+// X[16 alpha + n][16 beta + 4g .. +3] of every quadrant (four 16-byte loads
+// cover the 4 KiB block).  For each rank term,
+//   stage 1: Z[alpha][gamma] = sum_beta X[alpha][beta] Q[gamma][beta]^t
+//            (8 MFMAs per quadrant, contraction index 16 beta + 4g + k),
+//            D: lane (n, g) holds Z[16 alpha + 4g + i][16 gamma + n];
+//   stage 2: Y^t[gamma][delta] += sum_alpha Z[alpha][gamma]^t P[delta][alpha]^t
+//            (A read straight from stage 1's D registers),
+//            D: lane (n, g) holds Y[16 delta + n][16 gamma + 4g + i],
+// the load layout of quadrant (delta, gamma).  The DC coefficient X[0][0]
+// (the block's largest, up to 4096 for uint8 pixels) is taken out of the
+// products and applied last in FP32 VALU with the operator's DC column
+// H[:, 0] (Y += X[0][0] H[:, 0]), as the dense FP32 path does: in the MFMA
+// chains it would set the rounding step of every other term.  The factors (R terms of two
+// 32 x 32 FP32 matrices, up to 64 KiB) are staged in LDS once per
+// workgroup with rows padded to 36 floats, which keeps the 16 rows a wave
+// reads at once on distinct banks.
+constexpr int kFac32Ld = 36;
+
+template <int R, int U>
+__global__ __launch_bounds__(256) void k_filter_factored32(const float *in, float *out, int64_t B,
+                                                           const float *P32, const float *Q32, const float *h0,
+                                                           int64_t waves)
+{
+    __shared__ __attribute__((aligned(16))) float sP[R * 32 * kFac32Ld];
+    __shared__ __attribute__((aligned(16))) float sQ[R * 32 * kFac32Ld];
+    for (int e = threadIdx.x; e < R * 32 * 8; e += blockDim.x) {   // 16-byte chunks
+        const int r = e / 256, row = (e / 8) % 32, c4 = e % 8;
+        *reinterpret_cast<float4 *>(sP + (r * 32 + row) * kFac32Ld + 4 * c4) = ld4(P32 + r * 1024 + row * 32 + 4 * c4);
+        *reinterpret_cast<float4 *>(sQ + (r * 32 + row) * kFac32Ld + 4 * c4) = ld4(Q32 + r * 1024 + row * 32 + 4 * c4);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= waves)
+        return;
+    // offset of the lane's piece of quadrant (a, b) in a block / in a factor
+    auto blk_off = [&](int a, int b) { return (16 * a + n) * 32 + 16 * b + 4 * g; };
+    auto fac_off = [&](int r, int a, int b) { return (r * 32 + 16 * a + n) * kFac32Ld + 16 * b + 4 * g; };
+    // the lane's pieces of the DC column, as quadrants [gamma][delta] of Y
+    float4 hd[2][2];
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+        for (int de = 0; de < 2; ++de)
+            hd[ga][de] = ld4(h0 + blk_off(de, ga));
+    const int64_t units = (B + U - 1) / U;
+    const int64_t my_units = (units - wave + waves - 1) / waves;
+    auto load = [&](float4 (&x)[U][2][2], int64_t unit) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t b = unit * U + u;
+            b = b < B ? b : B - 1;   // clamped: the store is skipped
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    x[u][a][c] = ld4_nt(in + b * 1024 + blk_off(a, c));
+        }
+    };
+    auto compute_store = [&](const float4 (&x)[U][2][2], int64_t unit) {
+        // The factor reads are the same for every unit; an opaque zero offset
+        // keeps the compiler from hoisting them out of the loop (all R terms
+        // would then stay in VGPRs and cut the waves per SIMD).
+        int fbase = 0;
+        asm volatile("" : "+s"(fbase));
+        f32x4 y[U][2][2];   // [gamma][delta]
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    y[u][a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float4 q[2][2], p[2][2];   // q[gamma][beta], p[delta][alpha]
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    q[a][c] = *reinterpret_cast<const float4 *>(sQ + fbase + fac_off(r, a, c));
+                    p[a][c] = *reinterpret_cast<const float4 *>(sP + fbase + fac_off(r, a, c));
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                f32x4 z[2][2];   // [alpha][gamma]
+#pragma unroll
+                for (int al = 0; al < 2; ++al)
+#pragma unroll
+                    for (int ga = 0; ga < 2; ++ga) {
+                        z[al][ga] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int be = 0; be < 2; ++be) {
+                            // lane 0 holds X[0][0] in quadrant (0, 0): it enters as zero
+                            const float x0 = (al == 0 && be == 0 && lane == 0) ? 0.0f : x[u][al][be].x;
+                            const float xv[4] = {x0, x[u][al][be].y, x[u][al][be].z, x[u][al][be].w};
+                            const float qv[4] = {q[ga][be].x, q[ga][be].y, q[ga][be].z, q[ga][be].w};
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                z[al][ga] = mfma_f32(xv[k], qv[k], z[al][ga]);
+                        }
+                    }
+#pragma unroll
+                for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+                    for (int de = 0; de < 2; ++de)
+#pragma unroll
+                        for (int al = 0; al < 2; ++al) {
+                            const float pv[4] = {p[de][al].x, p[de][al].y, p[de][al].z, p[de][al].w};
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                y[u][ga][de] = mfma_f32(z[al][ga][k], pv[k], y[u][ga][de]);
+                        }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // X[0][0] of the block, held by lane 0
+            const float x00 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x[u][0][0].x)));
+#pragma unroll
+            for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+                for (int de = 0; de < 2; ++de) {
+                    y[u][ga][de][0] = fmaf(hd[ga][de].x, x00, y[u][ga][de][0]);
+                    y[u][ga][de][1] = fmaf(hd[ga][de].y, x00, y[u][ga][de][1]);
+                    y[u][ga][de][2] = fmaf(hd[ga][de].z, x00, y[u][ga][de][2]);
+                    y[u][ga][de][3] = fmaf(hd[ga][de].w, x00, y[u][ga][de][3]);
+                }
+            const int64_t b = unit * U + u;
+            if (b < B)
+#pragma unroll
+                for (int ga = 0; ga < 2; ++ga)
+#pragma unroll
+                    for (int de = 0; de < 2; ++de)
+                        st4_nt(out + b * 1024 + blk_off(de, ga), y[u][ga][de]);
+        }
+    };
+    float4 cur[U][2][2], nxt[U][2][2];
+    int64_t unit = wave;
+    load(cur, unit);
+    for (int64_t k = 1; k < my_units; ++k) {
+        load(nxt, unit + waves);
+        compute_store(cur, unit);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    cur[u][a][c] = nxt[u][a][c];
+        unit += waves;
+    }
+    compute_store(cur, unit);
+}
+
+template <int R>
+hipError_t run_factored32(const float *P32, const float *Q32, const float *h0, const float *in, float *out,
+                          int64_t B, hipStream_t stream)
+{
+    constexpr int U = 2;
+    const int64_t units = (B + U - 1) / U;
+    static const int per_cu = resident_groups(k_filter_factored32<R, U>, 256);
+    int64_t waves = (int64_t)cu_count() * per_cu * 4;
+    waves = waves < units ? waves : units;
+    const int64_t groups = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_filter_factored32<R, U>), dim3((unsigned)groups), dim3(256), 0, stream, in, out, B,
+                       P32, Q32, h0, waves);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *in,
-                                  float *out, int64_t B, hipStream_t stream)
+hipError_t launch_filter_factored(int N, int rank, const float *P32, const float *Q32, const float *h0,
+                                  const float *in, float *out, int64_t B, hipStream_t stream)
 {
     if (B <= 0)
         return hipSuccess;
-    if (N != 16 || rank < 1 || rank > kFactoredMaxRank)
+    if ((N != 16 && N != 32) || rank < 1 || rank > kFactoredMaxRank)
         return hipErrorInvalidValue;
+    if (N == 32) {
+        switch (rank) {
+        case 1: return run_factored32<1>(P32, Q32, h0, in, out, B, stream);
+        case 2: return run_factored32<2>(P32, Q32, h0, in, out, B, stream);
+        case 3: return run_factored32<3>(P32, Q32, h0, in, out, B, stream);
+        case 4: return run_factored32<4>(P32, Q32, h0, in, out, B, stream);
+        case 5: return run_factored32<5>(P32, Q32, h0, in, out, B, stream);
+        case 6: return run_factored32<6>(P32, Q32, h0, in, out, B, stream);
+        case 7: return run_factored32<7>(P32, Q32, h0, in, out, B, stream);
+        default: return run_factored32<8>(P32, Q32, h0, in, out, B, stream);
+        }
+    }
     switch (rank) {
     case 1: return run_factored16<1>(P32, Q32, in, out, B, stream);
     case 2: return run_factored16<2>(P32, Q32, in, out, B, stream);

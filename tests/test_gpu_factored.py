@@ -145,3 +145,54 @@ def test_factored_errors(dctf):
         dctf.dctf_filter_blocks_factored(op, x16[1:257], torch.zeros(256, device="cuda"))
     empty = torch.empty(0, device="cuda")
     dctf.dctf_filter_blocks_factored(op, empty, empty)   # B = 0: no-op
+
+
+# ---------------------------------------------------------------- N = 32
+
+@pytest.mark.parametrize("name,border", [("gauss7", Z), ("asym5", R), ("magic3", Z), ("row1x5", R)])
+def test_kronecker_sum_is_the_oracle_operator_n32(dctf, name, border):
+    W, _ = rng_masks()[name]
+    op = dctf.dctf_build_operator(W, 32, border)
+    P, Q = dctf.dctf_operator_factors_fp64(op)
+    H = sum(np.kron(P[r], Q[r]) for r in range(P.shape[0]))
+    assert np.abs(H - oracle.operator_probe(32, W, border)).max() <= 1e-12
+
+
+@pytest.mark.parametrize("name,border", [("gauss7", Z), ("box3", R), ("asym5", Z), ("asym7", R), ("magic3", R),
+                                         ("outer5x3", Z), ("rank8", R)])
+def test_factored_filter_n32_matches_oracle(dctf, name, border):
+    """32 x 32 blocks (two chained quadrant products per rank term, ranks 1
+    to 8) against the oracle's filter and the dense FP32 path; 15 blocks
+    leave a ragged tail of the two-block units."""
+    if name == "rank8":
+        W = syn.random_mask(np.random.default_rng(8), 8, 8)
+    else:
+        W, _ = rng_masks()[name]
+    px = oracle.tile_u8(syn.image_u8(41, 160, 96), 32)          # 5 x 3 = 15 blocks
+    X32 = oracle.coeffs_fp32(px)
+    op = dctf.dctf_build_operator(W, 32, border)
+    assert dctf.dctf_operator_rank(op) <= 8
+    Y = factored(dctf, op, X32)
+    Yref = oracle.filter_coeffs(X32, W, border)
+    assert np.abs(Y.astype(np.float64) - Yref).max() <= TOL_FP32
+    Xd = dev(X32.reshape(-1))
+    Yd = torch.empty_like(Xd)
+    dctf.dctf_filter_blocks(op, 0, Xd, Yd)
+    torch.cuda.synchronize()
+    assert np.abs(Yd.cpu().numpy().reshape(Y.shape) - Y).max() <= TOL_FP32
+
+
+def test_factored_n32_many_blocks_prefix_identity(dctf):
+    """Every wave strides over several units: sampled outputs against the
+    oracle, and a prefix run bit-identical."""
+    B = 40_001
+    X32 = syn.coeff_like_fp32(9, B, 32)
+    W = syn.random_mask(np.random.default_rng(3), 5, 5)
+    op = dctf.dctf_build_operator(W, 32, Z)
+    Y = factored(dctf, op, X32)
+    rng = np.random.default_rng(4)
+    bi = np.concatenate([rng.integers(0, B, 200), np.arange(B - 3, B)])
+    ref = oracle.filter_coeffs(X32[bi].astype(np.float64), W, Z)
+    assert np.abs(Y[bi].astype(np.float64) - ref).max() <= TOL_FP32
+    Yp = factored(dctf, op, X32[:777])
+    assert np.array_equal(Yp, Y[:777])
