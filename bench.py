@@ -277,22 +277,18 @@ def pixel_outputs(dctf, torch, stream, X, N, steps, warmup, images=64, side=2048
             res["%s_to_u8_%s" % (src, pname)] = {
                 "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "alg_bytes_per_block": nn * per_coef,
                 "GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS}
-    # the same into raster images (one call per image, as a decoder would run it)
+    # the same into the 64 raster images, one launch for all of them
     del pix
     imgs = torch.empty((images, side, side), dtype=torch.uint8, device="cuda")
-    per = (side // N) ** 2 * nn
     for src, fn, per_coef in (
-            ("coeffs_f32", lambda i: dctf.dctf_filter_blocks_u8_raster(
-                op, dctf.DCTF_PREC_SPLIT_BF16, X[i * per:(i + 1) * per], side, side, imgs[i], stream), 5),
-            ("quantized_s16", lambda i: dctf.dctf_filter_quantized_u8_raster(
-                op, dctf.DCTF_PREC_SPLIT_BF16, Q[i * per:(i + 1) * per], qt, dc, side, side, imgs[i], stream), 3)):
-        def run(fn=fn):
-            for i in range(images):
-                fn(i)
-        ms = timed_steps(torch, run, max(3, steps // 4), max(2, warmup // 4), stream, settle_first=True)
+            ("coeffs_f32", lambda: dctf.dctf_filter_blocks_u8_raster(
+                op, dctf.DCTF_PREC_SPLIT_BF16, X, side, side, imgs, stream), 5),
+            ("quantized_s16", lambda: dctf.dctf_filter_quantized_u8_raster(
+                op, dctf.DCTF_PREC_SPLIT_BF16, Q, qt, dc, side, side, imgs, stream), 3)):
+        ms = timed_steps(torch, fn, steps, warmup, stream, settle_first=True)
         gbs = B * nn * per_coef / (ms * 1e-3) / 1e9
         res["%s_to_raster_u8_split" % src] = {
-            "calls": images, "ms_per_pass": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": gbs,
+            "images": images, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": gbs,
             "frac_of_8TBps": gbs / HBM_PEAK_GBS}
     del Q, imgs
     torch.cuda.empty_cache()

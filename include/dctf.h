@@ -255,24 +255,29 @@ dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *
                                      int64_t B, dctf_stream stream);
 
 /*
- * The same two calls with the pixels written in their places in an image
- * instead of block by block: the input holds the ceil(h/N) x ceil(w/N)
- * blocks of one h x w image in raster block order (as dctf_forward_dct_u8
- * cuts it), and pixel (y, x) of the filtered image goes to
- * img_dev[y * pitch + x] for y < h, x < w (the pixels of edge blocks past
- * the image are not written).  The filtered coefficients and the
- * block-ordered pixels never reach memory: from a JPEG-style decoder's
- * quantised blocks to the filtered raster image is one pass.
- *   img_dev  device, 4-byte aligned; pitch >= w, a multiple of 4.
- * h = 0 or w = 0 is a no-op.  Errors: DCTF_EINVAL (as above; h or w < 0,
- * bad pitch, more than 2^31 - 1 blocks, input overlapping the image),
- * DCTF_EUNSUPPORTED (N = 32), DCTF_EHIP.
+ * The same two calls with the pixels written in their places in images
+ * instead of block by block: the input holds nimg images one after another,
+ * each as the ceil(h/N) x ceil(w/N) blocks of an h x w image in raster block
+ * order (as dctf_forward_dct_u8 cuts it), and pixel (y, x) of filtered
+ * image i goes to img_dev[i * img_stride + y * pitch + x] for y < h, x < w
+ * (the pixels of edge blocks past the image are not written).  The
+ * filtered coefficients and the block-ordered pixels never reach memory:
+ * from a JPEG-style decoder's quantised blocks to the filtered raster
+ * images is one pass, one launch for all nimg images.
+ *   img_dev     device, 4-byte aligned; pitch >= w, a multiple of 4.
+ *   img_stride  bytes from one output image to the next (nimg > 1: a
+ *               multiple of 4, >= (h - 1) * pitch + w; ignored for nimg = 1).
+ * h, w or nimg = 0 is a no-op.  Errors: DCTF_EINVAL (as above; h, w or nimg
+ * < 0, bad pitch or stride, more than 2^31 - 1 blocks per image, input
+ * overlapping the images), DCTF_EUNSUPPORTED (N = 32), DCTF_EHIP.
  */
 dctf_status dctf_filter_blocks_u8_raster(dctf_operator op, int prec, const float *in_dev, int h, int w,
-                                         uint8_t *img_dev, int64_t pitch, dctf_stream stream);
+                                         int64_t nimg, uint8_t *img_dev, int64_t pitch, int64_t img_stride,
+                                         dctf_stream stream);
 dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int prec, const int16_t *qcoef_dev,
                                             const float *qtable_dev, float dc_offset, int h, int w,
-                                            uint8_t *img_dev, int64_t pitch, dctf_stream stream);
+                                            int64_t nimg, uint8_t *img_dev, int64_t pitch, int64_t img_stride,
+                                            dctf_stream stream);
 
 /* ------------------------------------------------- image-level filtering */
 

@@ -74,8 +74,8 @@ _SIGS = {
     "dctf_image_operator_destroy": ([_P], None),
     "dctf_filter_image": ([_P, _I, _P, _P, _I, _I, _I64, _P], _I),
     "dctf_filter_quantized_u8": ([_P, _I, _P, _P, ctypes.c_float, _P, _I64, _P], _I),
-    "dctf_filter_blocks_u8_raster": ([_P, _I, _P, _I, _I, _P, _I64, _P], _I),
-    "dctf_filter_quantized_u8_raster": ([_P, _I, _P, _P, ctypes.c_float, _I, _I, _P, _I64, _P], _I),
+    "dctf_filter_blocks_u8_raster": ([_P, _I, _P, _I, _I, _I64, _P, _I64, _I64, _P], _I),
+    "dctf_filter_quantized_u8_raster": ([_P, _I, _P, _P, ctypes.c_float, _I, _I, _I64, _P, _I64, _I64, _P], _I),
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
     "dctf_filter_blocks": ([_P, _I, _P, _P, _I64, _P], _I),
@@ -307,43 +307,49 @@ def dctf_filter_quantized_u8(op: Operator, prec: int, qcoef: torch.Tensor, qtabl
            "dctf_filter_quantized_u8")
 
 
-def _raster_image(img: torch.Tensor, h: int, w: int):
-    """(pointer, pitch) of a 2-D uint8 device image (rows contiguous, any row
-    pitch, e.g. a column slice of a wider image) of at least h rows of w pixels."""
+def _raster_images(img: torch.Tensor, h: int, w: int):
+    """(pointer, nimg, pitch, image stride) of uint8 device images: a 2-D
+    tensor (one image) or a 3-D one (images along dim 0), rows contiguous,
+    any row pitch (e.g. a column slice of wider images), at least h rows of
+    w pixels each."""
     if not isinstance(img, torch.Tensor) or not img.is_cuda:
         raise TypeError("img must be a device tensor")
-    if img.dtype != torch.uint8 or img.dim() != 2 or img.stride(1) != 1:
-        raise ValueError("img must be a 2-D uint8 tensor with contiguous rows")
-    if img.shape[0] < h or img.shape[1] < w:
+    if img.dtype != torch.uint8 or img.dim() not in (2, 3) or img.stride(-1) != 1:
+        raise ValueError("img must be a 2-D or 3-D uint8 tensor with contiguous rows")
+    if img.shape[-2] < h or img.shape[-1] < w:
         raise ValueError("img is smaller than h x w")
-    return _P(img.data_ptr()), img.stride(0)
+    nimg = img.shape[0] if img.dim() == 3 else 1
+    stride = img.stride(0) if img.dim() == 3 else 0
+    return _P(img.data_ptr()), nimg, img.stride(-2), stride
 
 
 def dctf_filter_blocks_u8_raster(op: Operator, prec: int, X: torch.Tensor, h: int, w: int, img: torch.Tensor,
                                  stream=None):
-    """The filtered pixels of the ceil(h/N) x ceil(w/N) coefficient blocks X
-    written into the h x w uint8 image img (row pitch = img.stride(0))."""
+    """The filtered pixels of coefficient blocks X (each image's ceil(h/N) x
+    ceil(w/N) blocks, images one after another) written into the h x w uint8
+    image(s) img: 2-D for one image, 3-D for several (row pitch and image
+    stride from img's strides)."""
+    ptr, nimg, pitch, stride = _raster_images(img, h, w)
     nb = -(-h // op.N) * -(-w // op.N)
-    if X.numel() != nb * op.N * op.N:
-        raise ValueError("X must hold the ceil(h/N) x ceil(w/N) blocks of the image")
-    ptr, pitch = _raster_image(img, h, w)
-    _check(_lib.dctf_filter_blocks_u8_raster(op, prec, _dptr(X, torch.float32, "X"), h, w, ptr, pitch,
-                                             _stream(stream)),
+    if X.numel() != nimg * nb * op.N * op.N:
+        raise ValueError("X must hold the ceil(h/N) x ceil(w/N) blocks of every image")
+    _check(_lib.dctf_filter_blocks_u8_raster(op, prec, _dptr(X, torch.float32, "X"), h, w, nimg, ptr, pitch,
+                                             stride, _stream(stream)),
            "dctf_filter_blocks_u8_raster")
 
 
 def dctf_filter_quantized_u8_raster(op: Operator, prec: int, qcoef: torch.Tensor, qtable: torch.Tensor,
                                     dc_offset: float, h: int, w: int, img: torch.Tensor, stream=None):
     """As dctf_filter_blocks_u8_raster from quantised int16 blocks."""
+    ptr, nimg, pitch, stride = _raster_images(img, h, w)
     nb = -(-h // op.N) * -(-w // op.N)
-    if qcoef.numel() != nb * op.N * op.N:
-        raise ValueError("qcoef must hold the ceil(h/N) x ceil(w/N) blocks of the image")
+    if qcoef.numel() != nimg * nb * op.N * op.N:
+        raise ValueError("qcoef must hold the ceil(h/N) x ceil(w/N) blocks of every image")
     if qtable.numel() != op.N * op.N:
         raise ValueError("qtable must hold N*N factors")
-    ptr, pitch = _raster_image(img, h, w)
     _check(_lib.dctf_filter_quantized_u8_raster(op, prec, _dptr(qcoef, torch.int16, "qcoef"),
                                                 _dptr(qtable, torch.float32, "qtable"), float(dc_offset), h, w,
-                                                ptr, pitch, _stream(stream)),
+                                                nimg, ptr, pitch, stride, _stream(stream)),
            "dctf_filter_quantized_u8_raster")
 
 

@@ -527,6 +527,7 @@ extern "C" dctf_status dctf_filter_blocks_f64(dctf_operator op, const double *in
 struct RasterOut {
     int h = 0, w = 0;
     int64_t pitch = 0;
+    int64_t nimg = 1, img_stride = 0;
 };
 
 static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void *in, const float *qtab,
@@ -546,7 +547,9 @@ static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void
     const size_t nn = (size_t)op->N * op->N;
     const size_t in_bytes = (size_t)B * nn * (in_kind ? sizeof(int16_t) : sizeof(float));
     // bytes of the output: block by block, or the raster image up to its last pixel
-    const size_t out_bytes = raster ? (size_t)(raster->h - 1) * raster->pitch + raster->w : (size_t)B * nn;
+    const size_t out_bytes = raster ? (size_t)(raster->nimg - 1) * raster->img_stride +
+                                          (size_t)(raster->h - 1) * raster->pitch + raster->w
+                                    : (size_t)B * nn;
     const bool out_aligned = raster ? reinterpret_cast<uintptr_t>(pix) % 4 == 0 : aligned16(pix);
     if (in == nullptr || pix == nullptr || !aligned16(in) || !out_aligned)
         return DCTF_EINVAL;
@@ -559,7 +562,9 @@ static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void
     a.h = raster ? raster->h : 0;
     a.w = raster ? raster->w : 0;
     a.Bw = raster ? (raster->w + op->N - 1) / op->N : 0;
+    a.bpi = raster ? (int)(B / raster->nimg) : 0;
     a.pitch = raster ? raster->pitch : 0;
+    a.img_stride = raster ? raster->img_stride : 0;
     a.in = in_kind ? nullptr : static_cast<const float *>(in);
     a.qin = in_kind ? static_cast<const int16_t *>(in) : nullptr;
     a.qtab = qtab;
@@ -591,33 +596,42 @@ extern "C" dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, cons
 // The raster forms: the block count follows from the image size; the image
 // must fit the kernels' 32-bit block and row arithmetic.
 static dctf_status filter_px_raster(dctf_operator op, int prec, int in_kind, const void *in, const float *qtab,
-                                    float dc_offset, int h, int w, uint8_t *img, int64_t pitch, dctf_stream stream)
+                                    float dc_offset, int h, int w, int64_t nimg, uint8_t *img, int64_t pitch,
+                                    int64_t img_stride, dctf_stream stream)
 {
-    if (op == nullptr || h < 0 || w < 0 || pitch < w || pitch % 4 != 0)
+    if (op == nullptr || h < 0 || w < 0 || nimg < 0 || pitch < w || pitch % 4 != 0)
         return DCTF_EINVAL;
-    if (h == 0 || w == 0)
+    if (h == 0 || w == 0 || nimg == 0)
         return DCTF_OK;
-    const int64_t B = (int64_t)((h + op->N - 1) / op->N) * ((w + op->N - 1) / op->N);
-    if (B > INT32_MAX)
+    // images one after another, not overlapping, each 4-byte aligned
+    if (nimg > 1 && (img_stride % 4 != 0 || img_stride < (int64_t)(h - 1) * pitch + w))
+        return DCTF_EINVAL;
+    const int64_t bpi = (int64_t)((h + op->N - 1) / op->N) * ((w + op->N - 1) / op->N);
+    if (bpi > INT32_MAX || nimg > INT64_MAX / bpi)
         return DCTF_EINVAL;
     RasterOut r;
     r.h = h;
     r.w = w;
     r.pitch = pitch;
-    return filter_px(op, prec, in_kind, in, qtab, dc_offset, img, B, stream, &r);
+    r.nimg = nimg;
+    r.img_stride = nimg > 1 ? img_stride : 0;
+    return filter_px(op, prec, in_kind, in, qtab, dc_offset, img, bpi * nimg, stream, &r);
 }
 
 extern "C" dctf_status dctf_filter_blocks_u8_raster(dctf_operator op, int prec, const float *in_dev, int h, int w,
-                                                    uint8_t *img_dev, int64_t pitch, dctf_stream stream)
+                                                    int64_t nimg, uint8_t *img_dev, int64_t pitch,
+                                                    int64_t img_stride, dctf_stream stream)
 {
-    return filter_px_raster(op, prec, 0, in_dev, nullptr, 0.0f, h, w, img_dev, pitch, stream);
+    return filter_px_raster(op, prec, 0, in_dev, nullptr, 0.0f, h, w, nimg, img_dev, pitch, img_stride, stream);
 }
 
 extern "C" dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int prec, const int16_t *qcoef_dev,
                                                        const float *qtable_dev, float dc_offset, int h, int w,
-                                                       uint8_t *img_dev, int64_t pitch, dctf_stream stream)
+                                                       int64_t nimg, uint8_t *img_dev, int64_t pitch,
+                                                       int64_t img_stride, dctf_stream stream)
 {
-    return filter_px_raster(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, h, w, img_dev, pitch, stream);
+    return filter_px_raster(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, h, w, nimg, img_dev, pitch, img_stride,
+                            stream);
 }
 
 // ============================================================ image level

@@ -168,11 +168,13 @@ struct PxArgs {
     uint8_t *pix;           // B * N*N filtered pixels (raster = 0), or the h x w image (raster = 1)
     int64_t B;
     DenseImages G;          // the pixel-domain images of the operator
-    // raster = 1: the B blocks tile one h x w image in raster order (Bw blocks
-    // per block row); pixel (y, x) goes to pix[y * pitch + x] for y < h, x < w
+    // raster = 1: the B blocks tile images of h x w pixels in raster order
+    // (bpi blocks per image, Bw per block row), images one after another;
+    // pixel (y, x) of image i goes to pix[i * img_stride + y * pitch + x]
+    // for y < h, x < w
     int raster;
-    int h, w, Bw;
-    int64_t pitch;
+    int h, w, Bw, bpi;
+    int64_t pitch, img_stride;
 };
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
 

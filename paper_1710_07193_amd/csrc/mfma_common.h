@@ -431,6 +431,21 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) { return (int64_t)uniform_u64((uint64_t)v); }
 
+// Image, block row and block column of block `blk` of images of bpi blocks,
+// Bw per block row; blk0 is the first block of the lane's tile (the same for
+// every lane of the wave) and blk = blk0 + d, d < 16.
+__device__ __forceinline__ void raster_place(int64_t blk0, int d, int bpi, int Bw, int64_t &img, int &by, int &bx)
+{
+    img = uniform_i64(blk0) / bpi;   // on the scalar unit
+    int lb = (int)(blk0 - img * bpi) + d;
+    while (lb >= bpi) {   // a tile that reaches into the next image(s)
+        lb -= bpi;
+        ++img;
+    }
+    by = lb / Bw;
+    bx = lb - by * Bw;
+}
+
 // Resource over the blocks [blk0, min(blk0 + 16, B)) of an array of blocks of
 // `block_bytes` bytes; empty when blk0 >= B (and, as a guard, when blk0 < 0).
 // Arguments are wave-uniform.
@@ -885,7 +900,8 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term.
 // OUT = 0: FP32 results to r.out; OUT = 1: uint8 pixels to r.pix (the
 // operator is then the pixel-domain one); OUT = 2: the same pixels into the
-// raster image r.pix (r.h x r.w, row pitch r.pitch, r.Bw blocks per row).
+// raster images at r.pix (r.h x r.w, row pitch r.pitch, r.Bw blocks per row,
+// r.bpi blocks and r.img_stride bytes per image).
 template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, typename RefFn,
           typename OpFn, typename Regs>
 __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
@@ -983,12 +999,13 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
         } else {
             // raster image: pixels 4g .. 4g + 3 of rows 2 wave and 2 wave + 1 of block n
             if (rc.blk0 + n < rc.B) {
-                const int blk = (int)(rc.blk0 + n);
-                const int by = blk / rc.Bw, bx = blk - by * rc.Bw;
+                int64_t img;
+                int by, bx;
+                raster_place(rc.blk0, n, rc.bpi, rc.Bw, img, by, bx);
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
-                    store_px_raster4(rc.pix, rc.pitch, rc.h, rc.w, 16 * by + 2 * wave + t, 16 * bx + 4 * g,
-                                     pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
+                    store_px_raster4(rc.pix + img * rc.img_stride, rc.pitch, rc.h, rc.w, 16 * by + 2 * wave + t,
+                                     16 * bx + 4 * g, pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
             }
         }
         if (!last) {

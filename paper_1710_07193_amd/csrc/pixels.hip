@@ -179,11 +179,13 @@ __device__ __forceinline__ void store_px8_raster(const PxArgs &a, int64_t blk0, 
     const int n = lane & 15, g = lane >> 4;
     if (n >= nvalid)
         return;
-    const int blk = (int)(blk0 + n);
-    const int by = blk / a.Bw, bx = blk - by * a.Bw;
+    int64_t img;
+    int by, bx;
+    raster_place(blk0, n, a.bpi, a.Bw, img, by, bx);
+    uint8_t *base = a.pix + img * a.img_stride;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-        store_px_raster4(a.pix, a.pitch, a.h, a.w, 8 * by + 2 * t + (g >> 1), 8 * bx + 4 * (g & 1),
+        store_px_raster4(base, a.pitch, a.h, a.w, 8 * by + 2 * t + (g >> 1), 8 * bx + 4 * (g & 1),
                          pack_u8x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
 }
 
@@ -285,8 +287,8 @@ struct RefPx16 {
     int64_t B;
     int64_t blk0;
     int op;
-    int h, w, Bw;   // raster output
-    int64_t pitch;
+    int h, w, Bw, bpi;   // raster output
+    int64_t pitch, img_stride;
 };
 
 template <int PREC, int IN, int D, bool RAST = false>
@@ -312,7 +314,9 @@ __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
         r.h = a.h;
         r.w = a.w;
         r.Bw = a.Bw;
+        r.bpi = a.bpi;
         r.pitch = a.pitch;
+        r.img_stride = a.img_stride;
         return r;
     };
     auto op_load = [&](int) {
@@ -345,7 +349,10 @@ __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
         else
             x[k] = (float)a.qin[blk * NN + k] * a.qtab[k] + (k == 0 ? a.dc_offset : 0.0f);
     }
-    const int by = a.raster ? (int)(blk / a.Bw) : 0, bx = a.raster ? (int)(blk - (int64_t)by * a.Bw) : 0;
+    // (per thread: blk differs between the lanes of a wave)
+    const int64_t img = a.raster ? blk / a.bpi : 0;
+    const int lb = a.raster ? (int)(blk - img * a.bpi) : 0;
+    const int by = a.raster ? lb / a.Bw : 0, bx = a.raster ? lb - by * a.Bw : 0;
     for (int r = 0; r < NN; ++r) {
         float s = 0.0f;
         for (int k = 0; k < NN; ++k)
@@ -355,7 +362,7 @@ __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
         } else {
             const int y = by * N + r / N, xx = bx * N + r % N;
             if (y < a.h && xx < a.w)
-                a.pix[(int64_t)y * a.pitch + xx] = (uint8_t)pixel_u8(s);
+                a.pix[img * a.img_stride + (int64_t)y * a.pitch + xx] = (uint8_t)pixel_u8(s);
         }
     }
 }

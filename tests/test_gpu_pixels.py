@@ -246,21 +246,50 @@ def test_quantized_raster_output(dctf, N, prec):
     assert np.array_equal(out.cpu().numpy(), untile(blocks, h, w, N))
 
 
+def test_raster_many_images_in_one_call(dctf):
+    """Three ragged images in one call, written into a 3-D buffer whose
+    images and rows are padded: equal to one call per image, padding
+    untouched; the same through the quantised input."""
+    N, h, w, n = 8, 45, 70, 3
+    imgs = [syn.image_u8(330 + i, h, w) for i in range(n)]
+    X32 = np.concatenate([oracle.coeffs_fp32(oracle.tile_u8(im, N)) for im in imgs])
+    op = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, R)
+    X = dev(X32.reshape(-1))
+    for prec in (FP32, SPLIT):
+        buf = torch.full((n, h + 3, 76), 55, dtype=torch.uint8, device="cuda")
+        dctf.dctf_filter_blocks_u8_raster(op, prec, X, h, w, buf[:, :, :w])
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        per = X32.shape[0] // n
+        for i in range(n):
+            one = torch.zeros((h, 72), dtype=torch.uint8, device="cuda")   # row pitch a multiple of 4
+            dctf.dctf_filter_blocks_u8_raster(op, prec, dev(X32[i * per:(i + 1) * per].reshape(-1)), h, w,
+                                              one[:, :w])
+            torch.cuda.synchronize()
+            assert np.array_equal(got[i, :h, :w], one[:, :w].cpu().numpy()), (prec, i)
+        assert (got[:, :h, w:] == 55).all() and (got[:, h:] == 55).all()
+
+
 def test_raster_argument_errors(dctf):
     N = 8
     op = dctf.dctf_build_operator(syn.box_mask(3), N, Z)
     lib = dctf.raw_library()
-    X = torch.zeros(4 * 64, dtype=torch.float32, device="cuda")
+    X = torch.zeros(8 * 64, dtype=torch.float32, device="cuda")
     img = torch.zeros(64 * 64, dtype=torch.uint8, device="cuda")
     p = img.data_ptr()
-    ok = lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 16, None)
-    assert ok == 0
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 18, None) == -1   # pitch % 4
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p, 12, None) == -1   # pitch < w
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), -1, 16, p, 16, None) == -1
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, p + 2, 16, None) == -1  # align
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 0, 16, p, 16, None) == 0     # no-op
+    f = lib.dctf_filter_blocks_u8_raster
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 1, p, 16, 0, None) == 0
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 2, p, 16, 256, None) == 0        # two images
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 2, p, 16, 200, None) == -1       # images overlap
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 2, p, 16, 258, None) == -1       # stride % 4
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 1, p, 18, 0, None) == -1         # pitch % 4
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 1, p, 12, 0, None) == -1         # pitch < w
+    assert f(op.handle, FP32, X.data_ptr(), -1, 16, 1, p, 16, 0, None) == -1
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, -1, p, 16, 0, None) == -1
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 1, p + 2, 16, 0, None) == -1     # alignment
+    assert f(op.handle, FP32, X.data_ptr(), 0, 16, 1, p, 16, 0, None) == 0           # no-op
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 0, p, 16, 0, None) == 0          # no-op
     # the input overlapping the image
-    assert lib.dctf_filter_blocks_u8_raster(op.handle, FP32, X.data_ptr(), 16, 16, X.data_ptr(), 16, None) == -1
+    assert f(op.handle, FP32, X.data_ptr(), 16, 16, 1, X.data_ptr(), 16, 0, None) == -1
     op32 = dctf.dctf_build_operator(syn.box_mask(3), 32, Z)
-    assert lib.dctf_filter_blocks_u8_raster(op32.handle, FP32, X.data_ptr(), 8, 8, p, 16, None) == -2
+    assert f(op32.handle, FP32, X.data_ptr(), 8, 8, 1, p, 16, 0, None) == -2
