@@ -416,6 +416,25 @@ dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int prec, dctf_st
  */
 dctf_status dctf_filter_batch_noalloc(const dctf_job *jobs, int njobs, int prec, dctf_stream stream);
 
+/* One FP64 filter job: B blocks of in -> out with operator op. */
+typedef struct {
+    dctf_operator op;
+    const double *in;
+    double *out;
+    int64_t B;
+} dctf_job_f64;
+
+/*
+ * The FP64 filter (dctf_filter_blocks_f64: FP64 coefficients, the FP64
+ * operator, FP64 MFMA) over many jobs of any block sizes and operators,
+ * enqueued on `stream` as one launch per job in job order (a caller may
+ * capture the stream into a graph).  Buffers as for dctf_filter_blocks_f64;
+ * outputs must not overlap any input or output of another job.  Jobs with
+ * B = 0 are skipped.  Asynchronous.  Errors: DCTF_EINVAL (null, misaligned,
+ * overlapping), DCTF_EHIP.
+ */
+dctf_status dctf_filter_batch_f64(const dctf_job_f64 *jobs, int njobs, dctf_stream stream);
+
 /* --------------------------------------------------------- around the path */
 
 /*

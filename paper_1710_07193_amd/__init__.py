@@ -40,6 +40,10 @@ class _Job(ctypes.Structure):
     _fields_ = [("op", _P), ("in_", _P), ("out", _P), ("B", _I64)]
 
 
+class _JobF64(ctypes.Structure):
+    _fields_ = [("op", _P), ("in_", _P), ("out", _P), ("B", _I64)]
+
+
 class _BatchConfig(ctypes.Structure):
     _fields_ = [("fronts", _I), ("io", _I), ("nt", _I), ("groups_per_cu", _I)]
 
@@ -90,6 +94,7 @@ _SIGS = {
     "dctf_batch_destroy": ([_P], None),
     "dctf_filter_batch": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
     "dctf_filter_batch_noalloc": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
+    "dctf_filter_batch_f64": ([ctypes.POINTER(_JobF64), _I, _P], _I),
     "dctf_forward_dct_u8": ([_P, _I, _I, _I64, _I, _P, _P], _I),
     "dctf_idct_u8_verify": ([_I, _P, _I64, _P, _P, _P, _P], _I),
     "dctf_stream_copy": ([_P, _P, _I64, _P], _I),
@@ -474,6 +479,20 @@ def dctf_batch_info(batch: Batch):
 def dctf_filter_batch(jobs, prec: int, stream=None):
     arr, n, _ = _jobs(jobs)
     _check(_lib.dctf_filter_batch(arr, n, prec, _stream(stream)), "dctf_filter_batch")
+
+
+def dctf_filter_batch_f64(jobs, stream=None):
+    """FP64 filter jobs [(op, X, Y)] with float64 device tensors, one launch
+    per job on the stream."""
+    descs = []
+    for op, X, Y in jobs:
+        nn = op.N * op.N
+        if X.numel() % nn or Y.numel() != X.numel():
+            raise ValueError("job tensors must hold the same whole number of N*N blocks")
+        descs.append(_JobF64(op.handle, _dptr(X, torch.float64, "X"), _dptr(Y, torch.float64, "Y"),
+                             X.numel() // nn))
+    arr = (_JobF64 * max(len(descs), 1))(*descs)
+    _check(_lib.dctf_filter_batch_f64(arr, len(descs), _stream(stream)), "dctf_filter_batch_f64")
 
 
 def dctf_filter_batch_noalloc(jobs, prec: int, stream=None):

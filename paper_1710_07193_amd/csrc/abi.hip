@@ -853,17 +853,10 @@ struct Interval {
     bool out;
 };
 
-bool jobs_conflict(const dctf_job *jobs, int n)
+// Whether an output range overlaps any other range (inputs may overlap
+// each other).
+bool intervals_conflict(std::vector<Interval> &iv)
 {
-    std::vector<Interval> iv;
-    iv.reserve(2 * n);
-    for (int i = 0; i < n; ++i) {
-        if (jobs[i].B == 0)
-            continue;
-        const size_t bytes = (size_t)jobs[i].B * jobs[i].op->N * jobs[i].op->N * sizeof(float);
-        iv.push_back({(uintptr_t)jobs[i].in, (uintptr_t)jobs[i].in + bytes, false});
-        iv.push_back({(uintptr_t)jobs[i].out, (uintptr_t)jobs[i].out + bytes, true});
-    }
     std::sort(iv.begin(), iv.end(), [](const Interval &x, const Interval &y) { return x.a < y.a; });
     uintptr_t end_all = 0, end_out = 0;
     for (const auto &v : iv) {
@@ -875,6 +868,23 @@ bool jobs_conflict(const dctf_job *jobs, int n)
     }
     return false;
 }
+
+template <typename Job>
+bool jobs_conflict_t(const Job *jobs, int n, size_t elem_bytes)
+{
+    std::vector<Interval> iv;
+    iv.reserve(2 * n);
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].B == 0)
+            continue;
+        const size_t bytes = (size_t)jobs[i].B * jobs[i].op->N * jobs[i].op->N * elem_bytes;
+        iv.push_back({(uintptr_t)jobs[i].in, (uintptr_t)jobs[i].in + bytes, false});
+        iv.push_back({(uintptr_t)jobs[i].out, (uintptr_t)jobs[i].out + bytes, true});
+    }
+    return intervals_conflict(iv);
+}
+
+bool jobs_conflict(const dctf_job *jobs, int n) { return jobs_conflict_t(jobs, n, sizeof(float)); }
 
 }  // namespace
 
@@ -1306,6 +1316,31 @@ extern "C" dctf_status dctf_filter_batch(const dctf_job *jobs, int njobs, int pr
     dctf_status st2 = hip_status(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     dctf_batch_destroy(b);
     return st != DCTF_OK ? st : st2;
+}
+
+extern "C" dctf_status dctf_filter_batch_f64(const dctf_job_f64 *jobs, int njobs, dctf_stream stream)
+{
+    if (njobs < 0 || (njobs > 0 && jobs == nullptr))
+        return DCTF_EINVAL;
+    for (int i = 0; i < njobs; ++i) {
+        const dctf_job_f64 &j = jobs[i];
+        if (j.op == nullptr || j.B < 0)
+            return DCTF_EINVAL;
+        if (j.B > 0 && (j.in == nullptr || j.out == nullptr || !aligned16(j.in) || !aligned16(j.out)))
+            return DCTF_EINVAL;
+    }
+    if (jobs_conflict_t(jobs, njobs, sizeof(double)))
+        return DCTF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < njobs; ++i) {
+        const dctf_job_f64 &j = jobs[i];
+        if (j.B == 0)
+            continue;
+        const dctf_status st = hip_status(launch_filter_f64(j.op->N, j.op->img.dct.H64, j.in, j.out, j.B, s));
+        if (st != DCTF_OK)
+            return st;
+    }
+    return DCTF_OK;
 }
 
 // ------------------------------------------- one-shot batch, no allocation

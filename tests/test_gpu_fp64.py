@@ -131,3 +131,26 @@ def test_fp64_argument_errors(dctf):
     assert lib.dctf_filter_blocks_f64(op8.handle, X.data_ptr(), Y.data_ptr(), -1, None) == -1
     assert lib.dctf_filter_blocks_f64(op8.handle, X.data_ptr(), X.data_ptr() + 256, 1, None) == -1
     assert lib.dctf_filter_blocks_f64(op8.handle, X.data_ptr() + 8, Y.data_ptr(), 1, None) == -1
+
+
+def test_fp64_batch_matches_single_calls(dctf):
+    """FP64 jobs of N = 4, 8, 16 and 32 in one call equal the single-job
+    FP64 filter bit for bit; overlapping outputs are rejected."""
+    rng = np.random.default_rng(61)
+    jobs, want = [], []
+    for k, (N, B) in enumerate(((4, 300), (8, 5000), (16, 700), (32, 90), (8, 1))):
+        W = syn.random_mask(rng, 5, 5) if N >= 4 else syn.box_mask(3)
+        op = dctf.dctf_build_operator(W, N, k % 2)
+        X = torch.randn(B * N * N, dtype=torch.float64, device="cuda") * 40
+        Y = torch.full_like(X, float("nan"))
+        Wt = torch.empty_like(X)
+        dctf.dctf_filter_blocks_f64(op, X, Wt)
+        jobs.append((op, X, Y))
+        want.append(Wt)
+    dctf.dctf_filter_batch_f64(jobs)
+    torch.cuda.synchronize()
+    for (_, _, Y), Wt in zip(jobs, want):
+        assert torch.equal(Y, Wt)
+    op, X, Y = jobs[1]
+    with pytest.raises(dctf.DctfError):
+        dctf.dctf_filter_batch_f64([(op, X, Y), (op, X, Y)])   # two jobs write the same memory
