@@ -146,6 +146,15 @@ dctf_status dctf_operator_fp64(dctf_operator op, double *host_out);
  * eq. 3.  The builder forms it in FP64 with H_dct.  Synchronous. */
 dctf_status dctf_operator_pixel_fp64(dctf_operator op, double *host_out);
 
+/* Copy the FP64 pixel-to-pixel operator (C (x) C)^t . H_dct . (C (x) C)
+ * (64 x 64, row-major, row = output pixel, column = input pixel) of an
+ * N = 8 operator to host memory: the forward DCT of eq. 1, the filter and
+ * the inverse DCT of eq. 3 as one matrix.  Since H_dct is the orthogonal
+ * similarity of the spatial operator (eq. 7-8), this is the block-local
+ * correlation itself; the builder forms it in FP64 from the same Kronecker
+ * factors (C^t T_p C = S_p).  Synchronous.  DCTF_EUNSUPPORTED for N != 8. */
+dctf_status dctf_operator_pixpix_fp64(dctf_operator op, double *host_out);
+
 /* Block size, mask size and border of an operator (any pointer may be NULL). */
 dctf_status dctf_operator_info(dctf_operator op, int *N, int *kh, int *kw, int *border);
 
@@ -278,6 +287,31 @@ dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int prec, const in
                                             const float *qtable_dev, float dc_offset, int h, int w,
                                             int64_t nimg, uint8_t *img_dev, int64_t pitch, int64_t img_stride,
                                             dctf_stream stream);
+
+/*
+ * uint8 images in, filtered uint8 images out, in one pass (N = 8): every
+ * 8 x 8 block of each image (cut as dctf_forward_dct_u8 cuts it, ragged
+ * sides extended by repeating the last row / column) goes through the
+ * pixel-to-pixel operator above, i.e. the forward DCT (eq. 1), the
+ * DCT-domain filter (eq. 11 / eq. 20) and the inverse DCT (eq. 3), and is
+ * converted to uint8 as in Sec. III (round half up, saturate).  2 bytes of
+ * memory traffic per pixel instead of 1 + 4 + 4 + 1 for the separate passes.
+ *   in_dev, out_dev   nimg images of h x w pixels, row pitch in_pitch /
+ *                     out_pitch bytes (>= w, multiples of 4), in_stride /
+ *                     out_stride bytes from one image to the next (nimg > 1:
+ *                     multiples of 4, at least (h - 1) * pitch + w); device,
+ *                     4-byte aligned, not overlapping.
+ *   prec              DCTF_PREC_FP32: the operator in FP32 MFMA (DC column in
+ *                     FP32 VALU); DCTF_PREC_SPLIT_BF16: uint8 pixels are
+ *                     exact in BF16, so the operator is taken as three BF16
+ *                     terms hi + mid + lo (24 bits) against the exact pixels.
+ * h, w or nimg = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned,
+ * overlapping, bad sizes, pitches or strides), DCTF_EUNSUPPORTED (N != 8),
+ * DCTF_EHIP.
+ */
+dctf_status dctf_filter_u8_raster(dctf_operator op, int prec, const uint8_t *in_dev, int64_t in_pitch,
+                                  int64_t in_stride, int h, int w, int64_t nimg, uint8_t *out_dev,
+                                  int64_t out_pitch, int64_t out_stride, dctf_stream stream);
 
 /* ------------------------------------------------- image-level filtering */
 

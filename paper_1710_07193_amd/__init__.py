@@ -79,6 +79,8 @@ _SIGS = {
     "dctf_filter_image": ([_P, _I, _P, _P, _I, _I, _I64, _P], _I),
     "dctf_filter_quantized_u8": ([_P, _I, _P, _P, ctypes.c_float, _P, _I64, _P], _I),
     "dctf_filter_blocks_u8_raster": ([_P, _I, _P, _I, _I, _I64, _P, _I64, _I64, _P], _I),
+    "dctf_filter_u8_raster": ([_P, _I, _P, _I64, _I64, _I, _I, _I64, _P, _I64, _I64, _P], _I),
+    "dctf_operator_pixpix_fp64": ([_P, _P], _I),
     "dctf_filter_quantized_u8_raster": ([_P, _I, _P, _P, ctypes.c_float, _I, _I, _I64, _P, _I64, _I64, _P], _I),
     "dctf_operator_info": ([_P, _P, _P, _P, _P], _I),
     "dctf_operator_destroy": ([_P], None),
@@ -356,6 +358,26 @@ def dctf_filter_quantized_u8_raster(op: Operator, prec: int, qcoef: torch.Tensor
                                                 _dptr(qtable, torch.float32, "qtable"), float(dc_offset), h, w,
                                                 nimg, ptr, pitch, stride, _stream(stream)),
            "dctf_filter_quantized_u8_raster")
+
+
+def dctf_filter_u8_raster(op: Operator, prec: int, src: torch.Tensor, h: int, w: int, dst: torch.Tensor,
+                          stream=None):
+    """uint8 image(s) src -> filtered uint8 image(s) dst in one pass (N = 8):
+    2-D tensors for one image, 3-D for several (rows contiguous, any row pitch
+    and image stride)."""
+    sp, sn, spitch, sstride = _raster_images(src, h, w)
+    dp, dn, dpitch, dstride = _raster_images(dst, h, w)
+    if sn != dn:
+        raise ValueError("src and dst must hold the same number of images")
+    _check(_lib.dctf_filter_u8_raster(op, prec, sp, spitch, sstride, h, w, sn, dp, dpitch, dstride,
+                                      _stream(stream)), "dctf_filter_u8_raster")
+
+
+def dctf_operator_pixpix_fp64(op: Operator) -> np.ndarray:
+    """The FP64 pixel-to-pixel operator (64 x 64) of an N = 8 operator."""
+    H = np.empty((64, 64), np.float64)
+    _check(_lib.dctf_operator_pixpix_fp64(op, H.ctypes.data_as(_P)), "dctf_operator_pixpix_fp64")
+    return H
 
 
 class ImageOperator:

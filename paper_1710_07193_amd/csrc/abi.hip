@@ -210,11 +210,13 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     const bool split = N == 8 || N == 16 || N == 32;
     const size_t FS = split ? F : 0;
     const size_t FL = N == 32 ? n32_lf_elems : split ? frag_lf_elems(N) : 0;
-    const int domains = N <= 16 ? 2 : 1;
+    // DCT-domain H for every N, the pixel-domain G for N <= 16, the
+    // pixel-to-pixel set for N = 8
+    const int domains = N == 8 ? 3 : (N <= 16 ? 2 : 1);
     size_t off = 0;
     const size_t o_mask = off; off = align_up(off + sizeof(double) * kh * kw);
-    // one dense image set per domain (DCT-domain H, pixel-domain G)
-    size_t o_h64[2], o_h32[2], o_f32[2], o_fhi[2], o_flo[2], o_flf[2], o_h0[2];
+    // one dense image set per domain
+    size_t o_h64[3], o_h32[3], o_f32[3], o_fhi[3], o_flo[3], o_flf[3], o_h0[3], o_flo2 = 0;
     for (int d = 0; d < domains; ++d) {
         o_h64[d] = off; off = align_up(off + sizeof(double) * N4);
         o_h32[d] = off; off = align_up(off + sizeof(float) * N4);
@@ -223,6 +225,9 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
         o_flo[d] = off; off = align_up(off + sizeof(uint16_t) * FS);
         o_flf[d] = off; off = align_up(off + sizeof(float) * FL);
         o_h0[d] = off;  off = align_up(off + sizeof(float) * NN);
+        if (d == 2) {
+            o_flo2 = off; off = align_up(off + sizeof(uint16_t) * FS);
+        }
     }
     const size_t o_fa = off;   off = align_up(off + sizeof(double) * rank * kh);
     const size_t o_fb = off;   off = align_up(off + sizeof(double) * rank * kw);
@@ -249,9 +254,11 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     op->base = base;
     op->bytes = off;
     op->img.mask = reinterpret_cast<double *>(b + o_mask);
+    op->img.dct = DenseImages{};
     op->img.pix = DenseImages{};
+    op->img.pp = DenseImages{};
     for (int d = 0; d < domains; ++d) {
-        DenseImages &D = d == 0 ? op->img.dct : op->img.pix;
+        DenseImages &D = d == 0 ? op->img.dct : (d == 1 ? op->img.pix : op->img.pp);
         D.H64 = reinterpret_cast<double *>(b + o_h64[d]);
         D.H32 = reinterpret_cast<float *>(b + o_h32[d]);
         D.frag32 = F ? reinterpret_cast<float *>(b + o_f32[d]) : nullptr;
@@ -259,6 +266,7 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
         D.frag_lo = FS ? reinterpret_cast<uint16_t *>(b + o_flo[d]) : nullptr;
         D.frag_lf = FL ? reinterpret_cast<float *>(b + o_flf[d]) : nullptr;
         D.h0 = reinterpret_cast<float *>(b + o_h0[d]);
+        D.frag_lo2 = d == 2 ? reinterpret_cast<uint16_t *>(b + o_flo2) : nullptr;
     }
     op->rank = rank;
     op->img.fac_a = reinterpret_cast<double *>(b + o_fa);
@@ -632,6 +640,60 @@ extern "C" dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int pre
 {
     return filter_px_raster(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, h, w, nimg, img_dev, pitch, img_stride,
                             stream);
+}
+
+// One pass from uint8 images to filtered uint8 images (N = 8).
+extern "C" dctf_status dctf_filter_u8_raster(dctf_operator op, int prec, const uint8_t *in_dev, int64_t in_pitch,
+                                             int64_t in_stride, int h, int w, int64_t nimg, uint8_t *out_dev,
+                                             int64_t out_pitch, int64_t out_stride, dctf_stream stream)
+{
+    if (op == nullptr || (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16))
+        return DCTF_EINVAL;
+    if (op->N != 8 || op->img.pp.H64 == nullptr)
+        return DCTF_EUNSUPPORTED;
+    if (h < 0 || w < 0 || nimg < 0 || in_pitch < w || out_pitch < w || in_pitch % 4 != 0 || out_pitch % 4 != 0)
+        return DCTF_EINVAL;
+    if (h == 0 || w == 0 || nimg == 0)
+        return DCTF_OK;
+    const int64_t span = (int64_t)(h - 1) * in_pitch + w, ospan = (int64_t)(h - 1) * out_pitch + w;
+    if (nimg > 1 && (in_stride % 4 != 0 || out_stride % 4 != 0 || in_stride < span || out_stride < ospan))
+        return DCTF_EINVAL;
+    if (in_dev == nullptr || out_dev == nullptr || reinterpret_cast<uintptr_t>(in_dev) % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(out_dev) % 4 != 0)
+        return DCTF_EINVAL;
+    const int64_t bpi = (int64_t)((h + 7) / 8) * ((w + 7) / 8);
+    if (bpi > INT32_MAX || nimg > INT64_MAX / bpi)
+        return DCTF_EINVAL;
+    const int64_t istr = nimg > 1 ? in_stride : 0, ostr = nimg > 1 ? out_stride : 0;
+    if (ranges_overlap(in_dev, (size_t)((nimg - 1) * istr + span), out_dev, (size_t)((nimg - 1) * ostr + ospan)))
+        return DCTF_EINVAL;
+    PxArgs a;
+    memset(&a, 0, sizeof(a));
+    a.pix = out_dev;
+    a.B = bpi * nimg;
+    a.G = op->img.pp;
+    a.raster = 1;
+    a.h = h;
+    a.w = w;
+    a.Bw = (w + 7) / 8;
+    a.bpi = (int)bpi;
+    a.pitch = out_pitch;
+    a.img_stride = ostr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    dctf_status st = hip_status(launch_filter_u8_raster8(prec, a, in_dev, in_pitch, istr, s));
+    timing_end(s, slot);
+    return st;
+}
+
+extern "C" dctf_status dctf_operator_pixpix_fp64(dctf_operator op, double *host_out)
+{
+    if (op == nullptr || host_out == nullptr)
+        return DCTF_EINVAL;
+    if (op->img.pp.H64 == nullptr)
+        return DCTF_EUNSUPPORTED;
+    return hip_status(hipMemcpy(host_out, op->img.pp.H64, sizeof(double) * 4096, hipMemcpyDeviceToHost));
 }
 
 // ============================================================ image level

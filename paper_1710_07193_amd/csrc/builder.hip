@@ -76,8 +76,13 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
     constexpr int per_thread = (owned + kThreads - 1) / kThreads;
     const int kh = d.kh, kw = d.kw, border = d.border;
     const int ah = (kh - 1) / 2, aw = (kw - 1) / 2;
-    const bool pix = domain == 1;   // pixel-domain operator G instead of H_dct
-    const DenseImages &out = pix ? d.img.pix : d.img.dct;
+    // domain 1: pixel-domain G (coefficients -> pixels); domain 2 (N = 8):
+    // pixels -> pixels, whose factors are S_p and sum_q W[p][q] S_q
+    // (C^t T_p C = S_p), the spatial operator the method's H_dct is the
+    // orthogonal similarity of
+    const bool pix = domain >= 1;
+    const bool pp = domain == 2;
+    const DenseImages &out = pp ? d.img.pp : (pix ? d.img.pix : d.img.dct);
 
     // N = 32 masks (up to 65 x 65) are read from global memory instead of LDS
     constexpr bool kMaskInLds = N <= 16;
@@ -109,12 +114,17 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
         // T_p[u][k] = sum_i C[u][i] C[k][s_{p-ah}(i)];  G_p[j][l] = sum_q W[p][q] C[l][s_{q-aw}(j)]
         for (int e = tid; e < 2 * np * NN; e += kThreads) {
             const int which = e / (np * NN), rest = e % (np * NN);
-            const int pp = rest / NN, idx = rest % NN;
+            const int pr = rest / NN, idx = rest % NN;
             const int a = idx / N, b = idx % N;
             double s = 0.0;
             if (which == 0) {
-                const int dp = p0 + pp - ah;
-                if (pix) {
+                const int dp = p0 + pr - ah;
+                if (pp) {
+                    // S_p[i][m] with (i, m) = (a, b)
+                    bool ok;
+                    const int m = src_index(a, dp, N, border, &ok);
+                    s = (ok && m == b) ? 1.0 : 0.0;
+                } else if (pix) {
                     // (S_p C^t)[i][k] with (i, k) = (a, b)
                     bool ok;
                     const int m = src_index(a, dp, N, border, &ok);
@@ -127,26 +137,27 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
                         s += ok ? sC[a * N + i] * sC[b * N + m] : 0.0;
                     }
                 }
-                sT[pp * NN + idx] = s;
+                sT[pr * NN + idx] = s;
             } else {
-                const double *w = Wm + (p0 + pp) * kw;
+                const double *w = Wm + (p0 + pr) * kw;
                 for (int q = 0; q < kw; ++q) {
                     bool ok;
                     const int m = src_index(a, q - aw, N, border, &ok);
-                    s += ok ? w[q] * sC[b * N + m] : 0.0;
+                    // pixels in: sum_q W[p][q] S_q[j][n] instead of C[l][s_q(j)]
+                    s += ok ? w[q] * (pp ? (m == b ? 1.0 : 0.0) : sC[b * N + m]) : 0.0;
                 }
-                sG[pp * NN + idx] = s;
+                sG[pr * NN + idx] = s;
             }
         }
         __syncthreads();
         // B_p[v][l] = sum_j C[v][j] G_p[j][l] (the pixel domain uses G_p itself)
         if (!pix) {
             for (int e = tid; e < np * NN; e += kThreads) {
-                const int pp = e / NN, idx = e % NN, v = idx / N, l = idx % N;
+                const int pr = e / NN, idx = e % NN, v = idx / N, l = idx % N;
                 double s = 0.0;
 #pragma unroll
                 for (int j = 0; j < N; ++j)
-                    s += sC[v * N + j] * sG[pp * NN + j * N + l];
+                    s += sC[v * N + j] * sG[pr * NN + j * N + l];
                 sB[e] = s;
             }
         }
@@ -160,8 +171,8 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
                 const int r = r0 + e / NN, c = e % NN;
                 const int u = r / N, v = r % N, k = c / N, l = c % N;
                 double s = acc[o];
-                for (int pp = 0; pp < np; ++pp)
-                    s += sT[pp * NN + u * N + k] * sR[pp * NN + v * N + l];
+                for (int pr = 0; pr < np; ++pr)
+                    s += sT[pr * NN + u * N + k] * sR[pr * NN + v * N + l];
                 acc[o] = s;
             }
         }
@@ -184,7 +195,18 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
             // FP32 MFMA image: the operator without its DC column, which the
             // FP32 filter applies separately in VALU arithmetic.
             out.frag32[frag32_index(N, r, c)] = (c == 0) ? 0.0f : h32;
-        if constexpr (N == 8 || N == 16) {
+        if (pp) {
+            // pixels -> pixels: every column as three BF16 terms (pixels are
+            // exact in BF16, so the operator's 24 bits carry the precision)
+            const uint16_t hi = bf16_rne(h32);
+            const double r1 = h - (double)bf16_to_f32(hi);
+            const uint16_t mid = bf16_rne(__double2float_rn(r1));
+            const uint16_t lo = bf16_rne(__double2float_rn(r1 - (double)bf16_to_f32(mid)));
+            const int fi = frag16_index(N, r, c);
+            out.frag_hi[fi] = hi;
+            out.frag_lo[fi] = mid;
+            out.frag_lo2[fi] = lo;
+        } else if constexpr (N == 8 || N == 16) {
             // Split path: low-frequency columns (DC included) go to the FP32
             // MFMA image frag_lf; every other column is split into BF16
             // hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
@@ -225,8 +247,16 @@ __global__ __launch_bounds__(kThreads) void k_build(BuildArgs args)
     if (r0 >= NN)
         return;
     __shared__ double lds[kLdsDoubles];
-    // z = 0: H_dct, z = 1: pixel-domain G (only the parts requested are in the grid)
-    const int domain = (args.parts & kBuildDct) ? (int)blockIdx.z : 1;
+    // z enumerates the requested domains in the order H_dct, pixel-domain G,
+    // pixels -> pixels (that one for N = 8 only)
+    const bool want[3] = {(args.parts & kBuildDct) != 0, (args.parts & kBuildPix) != 0,
+                          (args.parts & kBuildPixPix) != 0};
+    int domain = -1;
+    for (int k = 0, z = 0; k < 3; ++k)
+        if (want[k] && z++ == (int)blockIdx.z)
+            domain = k;
+    if (domain < 0 || (domain == 2 && d.N != 8))
+        return;
     switch (d.N) {
     case 2: build_op<2>(d, r0, lds, domain); break;
     case 4: build_op<4>(d, r0, lds, domain); break;
@@ -318,7 +348,8 @@ hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
         maxRank = args.d[i].rank > maxRank ? args.d[i].rank : maxRank;
     }
     const int groups = (maxN * maxN + kRowsPerGroup - 1) / kRowsPerGroup;
-    const int domains = ((args.parts & kBuildDct) ? 1 : 0) + ((args.parts & kBuildPix) ? 1 : 0);
+    const int domains = ((args.parts & kBuildDct) ? 1 : 0) + ((args.parts & kBuildPix) ? 1 : 0) +
+                        ((args.parts & kBuildPixPix) ? 1 : 0);
     if (domains > 0 && maxN > 0) {
         hipLaunchKernelGGL(k_build, dim3(groups, args.n, domains), dim3(kThreads), 0, stream, args);
         hipError_t e = hipGetLastError();

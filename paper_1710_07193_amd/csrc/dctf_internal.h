@@ -22,6 +22,7 @@ struct DenseImages {
     uint16_t *frag_lo;   // BF16 lo fragments
     float *frag_lf;      // FP32 A fragments of the low-frequency columns (split path)
     float *h0;           // DC column H[:, 0] in FP32 (N^2 floats)
+    uint16_t *frag_lo2;  // pixel-to-pixel set only: third BF16 term (see OpImages::pp)
 };
 
 // Device image of one operator, all in a single allocation.
@@ -30,6 +31,11 @@ struct OpImages {
     DenseImages dct;     // H_dct: coefficients -> filtered coefficients (row u*N+v)
     DenseImages pix;     // G = (C (x) C)^t H_dct: coefficients -> filtered pixels
                          // (row i*N+j), the filter followed by the inverse DCT
+    DenseImages pp;      // N = 8 only: (C (x) C)^t H_dct (C (x) C), pixels -> filtered
+                         // pixels (the forward DCT, the filter and the inverse DCT
+                         // in one operator); its split images take every column
+                         // as three BF16 terms hi + mid + lo (frag_hi, frag_lo,
+                         // frag_lo2), since uint8 pixels are exact in BF16
     // Rank factors of the mask, W = sum_r fac_a[r] (outer) fac_b[r], and the
     // matching DCT-domain factors H = sum_r P_r (x) Q_r (paper form F =
     // sum A . BLOCK . B^t): P_r = C (sum_p fac_a[r][p] S_{p-a_h}) C^t over
@@ -130,7 +136,8 @@ struct BuildDesc {
 constexpr unsigned kBuildDct = 1u;       // H_dct images (dense filter, batches, server)
 constexpr unsigned kBuildPix = 2u;       // pixel-domain images (filter + inverse DCT)
 constexpr unsigned kBuildFactors = 4u;   // rank factors P_r, Q_r (factored filter)
-constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors;
+constexpr unsigned kBuildPixPix = 8u;    // pixel-to-pixel images (N = 8 one-pass uint8 filter)
+constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors | kBuildPixPix;
 
 struct BuildArgs {
     BuildDesc d[kMaxBuildPerLaunch];
@@ -177,6 +184,10 @@ struct PxArgs {
     int64_t pitch, img_stride;
 };
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
+// uint8 raster images in (row pitch in_pitch, in_stride bytes per image) and
+// out (a.pix, a.pitch, a.img_stride), N = 8, a.G = the pixel-to-pixel set.
+hipError_t launch_filter_u8_raster8(int prec, const PxArgs &a, const uint8_t *in_img, int64_t in_pitch,
+                                   int64_t in_stride, hipStream_t stream);
 
 // image.hip — image-level (cross-block) filtering, N = 8.  Operators are
 // indexed [class pair cp = 4 cr + cs][offset o = 3 (dr + 1) + (ds + 1)], each

@@ -278,6 +278,145 @@ __global__ __launch_bounds__(256) void k_filter_px8(PxArgs a, int64_t units, int
     compute_store(cur, unit);
 }
 
+// ------------------------------------------ N = 8, uint8 raster in and out
+//
+// One pass from uint8 images to filtered uint8 images: the operator is the
+// pixel-to-pixel set (the forward DCT, the filter and the inverse DCT in one
+// 64 x 64 matrix), held in VGPRs as in the kernels above.  Lane (n, g) of a
+// 16-block tile reads pixels 16i + 4g .. +3 of block n (row 2i + g / 2,
+// columns 4(g % 2) .. +3: one 32-bit load, bytes at the right edge, rows and
+// columns past the image repeat the last one, as the forward DCT extends
+// them), converts them to FP32 (exact), and the result goes to the output
+// image with the raster stores.  Split path: the pixels are exact in BF16,
+// so Y = G_hi x + G_mid x + G_lo x carries the operator's 24 bits.
+
+struct OpRegs8PP {
+    u32x4 hi[4][2];
+    u32x4 mid[4][2];
+    u32x4 lo[4][2];
+};
+
+__device__ __forceinline__ void load_op8_pp(OpRegs8PP &R, const DenseImages &D, int lane)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int o = ((t * 2 + s) * 64 + lane) * 8;
+            R.hi[t][s] = ldg_u32x4(D.frag_hi + o);
+            R.mid[t][s] = ldg_u32x4(D.frag_lo + o);
+            R.lo[t][s] = ldg_u32x4(D.frag_lo2 + o);
+        }
+}
+
+// acc = G . x, three BF16 terms per k-step, the smallest first.
+__device__ __forceinline__ void tile8_pp(const OpRegs8PP &R, const float4 x[4], f32x4 acc[4])
+{
+    u32x4 b[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        uint32_t h0, h1, h2, h3, l0, l1, l2, l3;   // the lo halves are zero (exact pixels)
+        split_bf16(x[2 * s], h0, h1, l0, l1);
+        split_bf16(x[2 * s + 1], h2, h3, l2, l3);
+        b[s] = u32x4{h0, h1, h2, h3};
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 1; s >= 0; --s) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.lo[t][s], b[s], acc[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.mid[t][s], b[s], acc[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            acc[t] = mfma_bf16(R.hi[t][s], b[s], acc[t]);
+    }
+}
+
+struct RasterIn {
+    const uint8_t *img;
+    int64_t pitch, img_stride;
+};
+
+// The lane's 16 pixels of the tile starting at block blk0 (block n of the
+// lane: blk0 + n, or the last block when that is past the end).
+__device__ __forceinline__ void load_px8_raster(const RasterIn &in, const PxArgs &a, int64_t blk0, int lane,
+                                                uint32_t w4[4])
+{
+    const int n = lane & 15, g = lane >> 4;
+    const int64_t nv = a.B - blk0;
+    int64_t img;
+    int by, bx;
+    raster_place(blk0, n < nv ? n : (int)(nv - 1), a.bpi, a.Bw, img, by, bx);
+    const uint8_t *base = in.img + img * in.img_stride;
+    const int x0 = 8 * bx + 4 * (g & 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = min(8 * by + 2 * i + (g >> 1), a.h - 1);
+        const uint8_t *row = base + (int64_t)y * in.pitch;
+        if (x0 + 3 < a.w) {
+            w4[i] = *reinterpret_cast<const uint32_t *>(row + x0);
+        } else {
+            uint32_t v = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v |= (uint32_t)row[min(x0 + e, a.w - 1)] << (8 * e);
+            w4[i] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ void unpack_px(const uint32_t w4[4], float4 x[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        x[i] = make_float4((float)(w4[i] & 0xffu), (float)((w4[i] >> 8) & 0xffu), (float)((w4[i] >> 16) & 0xffu),
+                           (float)(w4[i] >> 24));
+}
+
+// Wave w takes tiles w, w + waves, ...; the next tile's pixels are loaded
+// while the current one is multiplied.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_filter_u8r8(PxArgs a, RasterIn in, int64_t tiles, int64_t waves)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = uniform_i64((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    if (wave >= waves)   // waves <= tiles
+        return;
+    typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8PP>::type Regs;
+    Regs R;
+    if constexpr (PREC == DCTF_PREC_FP32)
+        load_op8(R, a.G.frag32, a.G.h0, lane);
+    else
+        load_op8_pp(R, a.G, lane);
+    const int64_t my_tiles = (tiles - wave + waves - 1) / waves;
+    uint32_t cur[4], nxt[4];
+    int64_t tile = wave;
+    load_px8_raster(in, a, tile * 16, lane, cur);
+    for (int64_t k = 0; k < my_tiles; ++k) {
+        // every step loads (the last one its own tile again): no conditional
+        // loads in the loop, whose waits would then count conservatively
+        const bool more = k + 1 < my_tiles;
+        load_px8_raster(in, a, (more ? tile + waves : tile) * 16, lane, nxt);
+        float4 x[4];
+        unpack_px(cur, x);
+        f32x4 acc[4];
+        if constexpr (PREC == DCTF_PREC_FP32)
+            tile8(R, x, lane, acc);
+        else
+            tile8_pp(R, x, acc);
+        store_px8_raster(a, tile * 16, a.B - tile * 16, acc, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            cur[i] = nxt[i];
+        tile += waves;
+    }
+}
+
 // ---------------------------------------------------------------- N = 16
 
 struct RefPx16 {
@@ -416,6 +555,28 @@ hipError_t dispatch_px(int N, int in_kind, const PxArgs &a, hipStream_t stream)
 }
 
 }  // namespace
+
+hipError_t launch_filter_u8_raster8(int prec, const PxArgs &a, const uint8_t *in_img, int64_t in_pitch,
+                                   int64_t in_stride, hipStream_t stream)
+{
+    if (a.B <= 0)
+        return hipSuccess;
+    RasterIn in;
+    in.img = in_img;
+    in.pitch = in_pitch;
+    in.img_stride = in_stride;
+    const int64_t tiles = (a.B + 15) / 16;
+    int64_t waves = (int64_t)cu_count() * kPx8WavesPerCu;
+    waves = waves < tiles ? waves : tiles;
+    const int64_t groups = (waves + 3) / 4;
+    if (prec == DCTF_PREC_FP32)
+        hipLaunchKernelGGL((k_filter_u8r8<DCTF_PREC_FP32>), dim3((unsigned)groups), dim3(256), 0, stream, a, in,
+                           tiles, waves);
+    else
+        hipLaunchKernelGGL((k_filter_u8r8<DCTF_PREC_SPLIT_BF16>), dim3((unsigned)groups), dim3(256), 0, stream, a,
+                           in, tiles, waves);
+    return hipGetLastError();
+}
 
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream)
 {
