@@ -290,7 +290,21 @@ def pixel_outputs(dctf, torch, stream, X, N, steps, warmup, images=64, side=2048
         res["%s_to_raster_u8_split" % src] = {
             "images": images, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3), "GBps": gbs,
             "frac_of_8TBps": gbs / HBM_PEAK_GBS}
-    del Q, imgs
+    del Q
+    # uint8 images straight to filtered uint8 images (one pass, 2 B per pixel),
+    # from the same seeded images the coefficients were made of
+    import synthetic as syn
+    src = torch.empty_like(imgs)
+    for i in range(images):
+        src[i] = torch.from_numpy(syn.image_u8(1000 + i, side, side)).cuda()
+    px = images * side * side
+    for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+        ms = timed_steps(torch, lambda: dctf.dctf_filter_u8_raster(op, p, src, side, side, imgs, stream), steps,
+                         warmup, stream, settle_first=True)
+        res["u8_images_to_u8_images_%s" % pname] = {
+            "images": images, "ms_per_launch": ms, "blocks_per_s": B / (ms * 1e-3),
+            "GBps": 2 * px / (ms * 1e-3) / 1e9, "frac_of_8TBps": 2 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del src, imgs
     torch.cuda.empty_cache()
     return res
 
