@@ -277,7 +277,8 @@ dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, const int16_t *
  *   img_stride  bytes from one output image to the next (nimg > 1: a
  *               multiple of 4, >= (h - 1) * pitch + w; ignored for nimg = 1).
  * h, w or nimg = 0 is a no-op.  Errors: DCTF_EINVAL (as above; h, w or nimg
- * < 0, bad pitch or stride, more than 2^31 - 1 blocks per image, input
+ * < 0, bad pitch or stride, more than 2^31 - 1 blocks per image or 2^32 or
+ * more blocks in all (128 bytes of memory per block and more), input
  * overlapping the images), DCTF_EUNSUPPORTED (N = 32), DCTF_EHIP.
  */
 dctf_status dctf_filter_blocks_u8_raster(dctf_operator op, int prec, const float *in_dev, int h, int w,
@@ -306,8 +307,8 @@ dctf_status dctf_filter_quantized_u8_raster(dctf_operator op, int prec, const in
  *                     exact in BF16, so the operator is taken as three BF16
  *                     terms hi + mid + lo (24 bits) against the exact pixels.
  * h, w or nimg = 0 is a no-op.  Errors: DCTF_EINVAL (null, misaligned,
- * overlapping, bad sizes, pitches or strides), DCTF_EUNSUPPORTED (N != 8),
- * DCTF_EHIP.
+ * overlapping, bad sizes, pitches or strides; more than 2^31 - 1 blocks per
+ * image or 2^32 or more in all), DCTF_EUNSUPPORTED (N != 8), DCTF_EHIP.
  */
 dctf_status dctf_filter_u8_raster(dctf_operator op, int prec, const uint8_t *in_dev, int64_t in_pitch,
                                   int64_t in_stride, int h, int w, int64_t nimg, uint8_t *out_dev,

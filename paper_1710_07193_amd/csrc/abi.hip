@@ -573,6 +573,8 @@ static dctf_status filter_px(dctf_operator op, int prec, int in_kind, const void
     a.bpi = raster ? (int)(B / raster->nimg) : 0;
     a.pitch = raster ? raster->pitch : 0;
     a.img_stride = raster ? raster->img_stride : 0;
+    div_magic((uint32_t)(raster ? a.bpi : 1), a.magic);
+    div_magic((uint32_t)(raster ? a.Bw : 1), a.magic + 2);
     a.in = in_kind ? nullptr : static_cast<const float *>(in);
     a.qin = in_kind ? static_cast<const int16_t *>(in) : nullptr;
     a.qtab = qtab;
@@ -601,8 +603,10 @@ extern "C" dctf_status dctf_filter_quantized_u8(dctf_operator op, int prec, cons
     return filter_px(op, prec, 1, qcoef_dev, qtable_dev, dc_offset, pix_dev, B, stream);
 }
 
-// The raster forms: the block count follows from the image size; the image
-// must fit the kernels' 32-bit block and row arithmetic.
+// The raster forms: the block count follows from the image size; the images
+// must fit the kernels' 32-bit block and row arithmetic (fewer than 2^32
+// blocks in all: at 128 bytes of input and output per block or more, more
+// than the memory of the device could hold).
 static dctf_status filter_px_raster(dctf_operator op, int prec, int in_kind, const void *in, const float *qtab,
                                     float dc_offset, int h, int w, int64_t nimg, uint8_t *img, int64_t pitch,
                                     int64_t img_stride, dctf_stream stream)
@@ -615,7 +619,7 @@ static dctf_status filter_px_raster(dctf_operator op, int prec, int in_kind, con
     if (nimg > 1 && (img_stride % 4 != 0 || img_stride < (int64_t)(h - 1) * pitch + w))
         return DCTF_EINVAL;
     const int64_t bpi = (int64_t)((h + op->N - 1) / op->N) * ((w + op->N - 1) / op->N);
-    if (bpi > INT32_MAX || nimg > INT64_MAX / bpi)
+    if (bpi > INT32_MAX || nimg > (int64_t)UINT32_MAX / bpi)
         return DCTF_EINVAL;
     RasterOut r;
     r.h = h;
@@ -662,7 +666,7 @@ extern "C" dctf_status dctf_filter_u8_raster(dctf_operator op, int prec, const u
         reinterpret_cast<uintptr_t>(out_dev) % 4 != 0)
         return DCTF_EINVAL;
     const int64_t bpi = (int64_t)((h + 7) / 8) * ((w + 7) / 8);
-    if (bpi > INT32_MAX || nimg > INT64_MAX / bpi)
+    if (bpi > INT32_MAX || nimg > (int64_t)UINT32_MAX / bpi)
         return DCTF_EINVAL;
     const int64_t istr = nimg > 1 ? in_stride : 0, ostr = nimg > 1 ? out_stride : 0;
     if (ranges_overlap(in_dev, (size_t)((nimg - 1) * istr + span), out_dev, (size_t)((nimg - 1) * ostr + ospan)))
@@ -679,6 +683,8 @@ extern "C" dctf_status dctf_filter_u8_raster(dctf_operator op, int prec, const u
     a.bpi = (int)bpi;
     a.pitch = out_pitch;
     a.img_stride = ostr;
+    div_magic((uint32_t)a.bpi, a.magic);
+    div_magic((uint32_t)a.Bw, a.magic + 2);
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);

@@ -167,6 +167,17 @@ hipError_t launch_filter_factored(int N, int rank, const float *P32, const float
 // pixels.hip — filter + inverse DCT + uint8 in one pass (pixel-domain images),
 // from FP32 coefficients (IN = 0) or from quantised int16 coefficients that
 // are dequantised in registers (IN = 1).
+// Division of 32-bit block numbers by a launch constant d without a divide:
+// M = ceil(2^64 / d) in two 32-bit words (d = 1: M = 0); div_u32 then takes
+// the high 64 bits of M * n, which equal n / d for every 32-bit n and d
+// (Lemire, Kaser and Kurz, "Faster remainder by direct computation", 2019).
+inline void div_magic(uint32_t d, uint32_t *m)
+{
+    const uint64_t M = d > 1 ? UINT64_MAX / d + 1 : 0;
+    m[0] = (uint32_t)M;
+    m[1] = (uint32_t)(M >> 32);
+}
+
 struct PxArgs {
     const float *in;        // IN = 0: B * N*N FP32 coefficients
     const int16_t *qin;     // IN = 1: B * N*N quantised coefficients
@@ -182,6 +193,7 @@ struct PxArgs {
     int raster;
     int h, w, Bw, bpi;
     int64_t pitch, img_stride;
+    uint32_t magic[4];      // div_magic of bpi (words 0, 1) and of Bw (words 2, 3); B < 2^32
 };
 hipError_t launch_filter_px(int N, int prec, int in_kind, const PxArgs &a, hipStream_t stream);
 // uint8 raster images in (row pitch in_pitch, in_stride bytes per image) and

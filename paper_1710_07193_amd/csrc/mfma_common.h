@@ -431,19 +431,24 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 
 __device__ __forceinline__ int64_t uniform_i64(int64_t v) { return (int64_t)uniform_u64((uint64_t)v); }
 
-// Image, block row and block column of block `blk` of images of bpi blocks,
-// Bw per block row; blk0 is the first block of the lane's tile (the same for
-// every lane of the wave) and blk = blk0 + d, d < 16.
-__device__ __forceinline__ void raster_place(int64_t blk0, int d, int bpi, int Bw, int64_t &img, int &by, int &bx)
+// n / d from the two words of div_magic(d) (see there).
+__device__ __forceinline__ uint32_t div_u32(uint32_t n, const uint32_t *m)
 {
-    img = uniform_i64(blk0) / bpi;   // on the scalar unit
-    int lb = (int)(blk0 - img * bpi) + d;
-    while (lb >= bpi) {   // a tile that reaches into the next image(s)
-        lb -= bpi;
-        ++img;
-    }
-    by = lb / Bw;
-    bx = lb - by * Bw;
+    const uint64_t p = (uint64_t)m[1] * n + __umulhi(m[0], n);
+    return (m[0] | m[1]) ? (uint32_t)(p >> 32) : n;
+}
+
+// Image, block row and block column of block `blk` (< 2^32) of images of bpi
+// blocks, Bw per block row; magic = div_magic of bpi, then of Bw.
+__device__ __forceinline__ void raster_place(uint32_t blk, int bpi, int Bw, const uint32_t *magic, int64_t &img,
+                                             int &by, int &bx)
+{
+    const uint32_t i = div_u32(blk, magic);
+    const uint32_t lb = blk - i * (uint32_t)bpi;
+    const uint32_t r = div_u32(lb, magic + 2);
+    img = i;
+    by = (int)r;
+    bx = (int)(lb - r * (uint32_t)Bw);
 }
 
 // Resource over the blocks [blk0, min(blk0 + 16, B)) of an array of blocks of
@@ -1001,7 +1006,7 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
             if (rc.blk0 + n < rc.B) {
                 int64_t img;
                 int by, bx;
-                raster_place(rc.blk0, n, rc.bpi, rc.Bw, img, by, bx);
+                raster_place((uint32_t)(rc.blk0 + n), rc.bpi, rc.Bw, rc.magic, img, by, bx);
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
                     store_px_raster4(rc.pix + img * rc.img_stride, rc.pitch, rc.h, rc.w, 16 * by + 2 * wave + t,

@@ -181,7 +181,7 @@ __device__ __forceinline__ void store_px8_raster(const PxArgs &a, int64_t blk0, 
         return;
     int64_t img;
     int by, bx;
-    raster_place(blk0, n, a.bpi, a.Bw, img, by, bx);
+    raster_place((uint32_t)(blk0 + n), a.bpi, a.Bw, a.magic, img, by, bx);
     uint8_t *base = a.pix + img * a.img_stride;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -309,8 +309,8 @@ __device__ __forceinline__ void load_op8_pp(OpRegs8PP &R, const DenseImages &D, 
         }
 }
 
-// acc = G . x, three BF16 terms per k-step, the smallest first.
-__device__ __forceinline__ void tile8_pp(const OpRegs8PP &R, const float4 x[4], f32x4 acc[4])
+// acc = init + G . x, three BF16 terms per k-step, the smallest first.
+__device__ __forceinline__ void tile8_pp(const OpRegs8PP &R, const float4 x[4], f32x4 acc[4], float init)
 {
     u32x4 b[2];
 #pragma unroll
@@ -322,7 +322,7 @@ __device__ __forceinline__ void tile8_pp(const OpRegs8PP &R, const float4 x[4], 
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
-        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[t] = f32x4{init, init, init, init};
 #pragma unroll
     for (int s = 1; s >= 0; --s) {
 #pragma unroll
@@ -337,51 +337,215 @@ __device__ __forceinline__ void tile8_pp(const OpRegs8PP &R, const float4 x[4], 
     }
 }
 
+// acc = init + G . x, FP32 path (the operator's first column in VALU
+// arithmetic last, as in tile8).
+__device__ __forceinline__ void tile8_f32_init(const OpRegs8F32 &R, const float4 x[4], int lane, f32x4 acc[4],
+                                               float init)
+{
+    const int n = lane & 15;
+    const float x0 = lane_read(x[0].x, n);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = f32x4{init, init, init, init};
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+        const float xv[4] = {x[i].x, x[i].y, x[i].z, x[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = mfma_f32(R.A[t][i][j], xv[j], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[t][r] = fmaf(R.h0[t][r], x0, acc[t][r]);
+}
+
+// Four pixels already biased by +1/2 (the accumulators start at 1/2) -> one
+// little-endian word: floor, then V_CVT_PK_U8_F32 as in pack_u8x4.
+__device__ __forceinline__ uint32_t pack_u8x4_biased(f32x4 v)
+{
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w = __builtin_amdgcn_cvt_pk_u8_f32(floorf(v[k]), k, w);
+    return w;
+}
+
 struct RasterIn {
     const uint8_t *img;
     int64_t pitch, img_stride;
+    // BUF: bytes from img (resp. the output's first pixel) to the end of the
+    // last input (output) image, rounded up to a multiple of 4; both < 2^31
+    int64_t in_bytes, out_bytes;
 };
 
-// The lane's 16 pixels of the tile starting at block blk0 (block n of the
-// lane: blk0 + n, or the last block when that is past the end).
-__device__ __forceinline__ void load_px8_raster(const RasterIn &in, const PxArgs &a, int64_t blk0, int lane,
-                                                uint32_t w4[4])
-{
-    const int n = lane & 15, g = lane >> 4;
-    const int64_t nv = a.B - blk0;
+// The lane's block: image, block row, block column (block blk0 + n, or the
+// last block of the tile's valid ones).
+struct U8rPlace {
     int64_t img;
     int by, bx;
-    raster_place(blk0, n < nv ? n : (int)(nv - 1), a.bpi, a.Bw, img, by, bx);
-    const uint8_t *base = in.img + img * in.img_stride;
-    const int x0 = 8 * bx + 4 * (g & 1);
+};
+
+__device__ __forceinline__ U8rPlace u8r_place(const PxArgs &a, int64_t blk0, int lane)
+{
+    const int n = lane & 15;
+    const int64_t nv = a.B - blk0;
+    U8rPlace p;
+    raster_place((uint32_t)(blk0 + (n < nv ? n : nv - 1)), a.bpi, a.Bw, a.magic, p.img, p.by, p.bx);
+    return p;
+}
+
+// Byte selector for the columns of a ragged image: the aligned word at
+// xa = min(x0, (w - 1) & ~3) holds pixels min(x0 + e, w - 1), e = 0..3
+// (an aligned word that holds a pixel of the image lies in the page of that
+// pixel; the bytes past w it may cover are not used).
+__device__ __forceinline__ uint32_t edge_select(int x0, int w, int &xa)
+{
+    xa = min(x0, (w - 1) & ~3);
+    const int d = min(x0 - xa, 3), m = min(w - 1 - xa, 3);
+    return (uint32_t)min(d, m) | (uint32_t)min(d + 1, m) << 8 | (uint32_t)min(d + 2, m) << 16 |
+           (uint32_t)min(d + 3, m) << 24;
+}
+
+// Lane (n, g) of a 16-block tile holds pixels 16i + 4g .. +3 of block n: row
+// 2i + g/2, columns 4(g % 2) .. +3 of the block, one 32-bit word per i; its
+// outputs t = 0..3 are the same pixels of row 2t + g/2.  ALIGNED (h and w
+// multiples of 8): every pixel of every block is in its image.  Otherwise
+// rows past the image repeat the last one and columns past it the last
+// column (the forward DCT's extension), and only pixels inside the image
+// are stored.
+//
+// BUF (the images within 2^31 bytes): raw buffer instructions over the input
+// and the output, 32-bit offsets, the rows of a block 2 pitch apart through
+// the instruction's scalar offset; ragged stores go out as a word, a short
+// and a byte whose offsets point past the buffer where they have nothing to
+// store (dropped), so that no store is conditional.
+template <bool ALIGNED, bool BUF>
+struct U8rIO {
+    rsrc_t rin, rout;
+    int32_t srow_in[4], srow_out[4];   // 2 i pitch (uniform)
+
+    __device__ __forceinline__ void init(const PxArgs &a, const RasterIn &in)
+    {
+        if constexpr (BUF) {
+            rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(in.img), (short)0, (int)in.in_bytes,
+                                                    kRsrcWord3);
+            rout = __builtin_amdgcn_make_buffer_rsrc(a.pix, (short)0, (int)in.out_bytes, kRsrcWord3);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int y = min(8 * by + 2 * i + (g >> 1), a.h - 1);
-        const uint8_t *row = base + (int64_t)y * in.pitch;
-        if (x0 + 3 < a.w) {
-            w4[i] = *reinterpret_cast<const uint32_t *>(row + x0);
-        } else {
-            uint32_t v = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                v |= (uint32_t)row[min(x0 + e, a.w - 1)] << (8 * e);
-            w4[i] = v;
+            for (int i = 0; i < 4; ++i) {
+                srow_in[i] = (int32_t)(2 * i * in.pitch);
+                srow_out[i] = (int32_t)(2 * i * a.pitch);
+            }
         }
     }
-}
 
-__device__ __forceinline__ void unpack_px(const uint32_t w4[4], float4 x[4])
-{
+    // loads the lane's 16 pixels of the tile at blk0; returns what the
+    // later steps of the same tile need: ALIGNED && BUF: the output offset
+    // of the lane's row 0 pixels; ragged: the byte selector, applied to the
+    // words when they are used (not here, where that would wait for them)
+    __device__ __forceinline__ uint32_t load(const PxArgs &a, const RasterIn &in, int64_t blk0, int lane,
+                                             uint32_t w4[4]) const
+    {
+        const int g = lane >> 4;
+        const U8rPlace p = u8r_place(a, blk0, lane);
+        const int x0 = 8 * p.bx + 4 * (g & 1), y0 = 8 * p.by + (g >> 1);
+        if constexpr (ALIGNED && BUF) {
+            const uint32_t off = (uint32_t)p.img * (uint32_t)in.img_stride + (uint32_t)y0 * (uint32_t)in.pitch + x0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        x[i] = make_float4((float)(w4[i] & 0xffu), (float)((w4[i] >> 8) & 0xffu), (float)((w4[i] >> 16) & 0xffu),
-                           (float)(w4[i] >> 24));
-}
+            for (int i = 0; i < 4; ++i)
+                w4[i] = __builtin_amdgcn_raw_buffer_load_b32(rin, off, srow_in[i], 0);
+            return (uint32_t)p.img * (uint32_t)a.img_stride + (uint32_t)y0 * (uint32_t)a.pitch + x0;
+        } else if constexpr (ALIGNED) {
+            const uint8_t *base = in.img + p.img * in.img_stride + (int64_t)y0 * in.pitch + x0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                w4[i] = *reinterpret_cast<const uint32_t *>(base + 2 * i * in.pitch);
+            return 0;
+        } else {
+            int xa;
+            const uint32_t sel = edge_select(x0, a.w, xa);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int y = min(y0 + 2 * i, a.h - 1);
+                if constexpr (BUF)
+                    w4[i] = __builtin_amdgcn_raw_buffer_load_b32(
+                        rin, (uint32_t)p.img * (uint32_t)in.img_stride + (uint32_t)y * (uint32_t)in.pitch + xa, 0, 0);
+                else
+                    w4[i] = *reinterpret_cast<const uint32_t *>(in.img + p.img * in.img_stride +
+                                                                (int64_t)y * in.pitch + xa);
+            }
+            return sel;
+        }
+    }
 
-// Wave w takes tiles w, w + waves, ...; the next tile's pixels are loaded
-// while the current one is multiplied.
-template <int PREC>
-__global__ __launch_bounds__(256) void k_filter_u8r8(PxArgs a, RasterIn in, int64_t tiles, int64_t waves)
+    // the tile's pixels as FP32 (exact), from the words and what load returned
+    __device__ __forceinline__ void unpack(const uint32_t w4[4], uint32_t aux, float4 x[4]) const
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t w = ALIGNED ? w4[i] : __builtin_amdgcn_perm(w4[i], w4[i], aux);
+            x[i] = make_float4((float)(w & 0xffu), (float)((w >> 8) & 0xffu), (float)((w >> 16) & 0xffu),
+                               (float)(w >> 24));
+        }
+    }
+
+    // stores the tile's pixels (acc biased by +1/2); lanes past the tile's
+    // last valid block hold that block's pixels and store them again
+    __device__ __forceinline__ void store(const PxArgs &a, int64_t blk0, int lane, uint32_t out_off,
+                                          const f32x4 acc[4]) const
+    {
+        if constexpr (ALIGNED && BUF) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4_biased(acc[t]), rout, out_off, srow_out[t], 0);
+            return;
+        }
+        const int g = lane >> 4;
+        const U8rPlace p = u8r_place(a, blk0, lane);
+        const int x0 = 8 * p.bx + 4 * (g & 1), y0 = 8 * p.by + (g >> 1);
+        if constexpr (ALIGNED) {
+            uint8_t *base = a.pix + p.img * a.img_stride + (int64_t)y0 * a.pitch + x0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                *reinterpret_cast<uint32_t *>(base + 2 * t * a.pitch) = pack_u8x4_biased(acc[t]);
+        } else if constexpr (BUF) {
+            constexpr uint32_t kPast = 0x80000000u;   // >= out_bytes: dropped
+            const int c = min(max(a.w - x0, 0), 4);    // pixels of the word inside the image
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t word = pack_u8x4_biased(acc[t]);
+                const bool row = y0 + 2 * t < a.h;
+                const uint32_t off =
+                    (uint32_t)p.img * (uint32_t)a.img_stride + (uint32_t)(y0 + 2 * t) * (uint32_t)a.pitch + x0;
+                __builtin_amdgcn_raw_buffer_store_b32(word, rout, row && c == 4 ? off : kPast, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)word, rout, row && (c == 2 || c == 3) ? off : kPast,
+                                                      0, 0);
+                // c = 1: byte 0 at off; c = 3: byte 2 at off + 2
+                const uint32_t b = (uint32_t)(c & 2);
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(word >> (8 * b)), rout,
+                                                     row && (c & 1) ? off + b : kPast, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                store_px_raster4(a.pix + p.img * a.img_stride, a.pitch, a.h, a.w, y0 + 2 * t, x0,
+                                 pack_u8x4_biased(acc[t]));
+        }
+    }
+};
+
+// Wave w takes tiles w, w + waves, ...; the pixels of the next D tiles are in
+// flight while the current one is multiplied (a ring of D register slots,
+// the loop unrolled D times so that every slot is a fixed register set).
+// The wave's step count is rounded up to a multiple of D: the extra steps
+// filter its last tile again and store the same bytes, so the loop has no
+// exit but its end and every step issues the same loads and stores (the
+// waits for a slot then count exactly the operations issued after it).
+template <int PREC, bool ALIGNED, bool BUF, int D>
+__global__ __launch_bounds__(256, 2) void k_filter_u8r8(PxArgs a, RasterIn in, int64_t tiles, int64_t waves)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wave = uniform_i64((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
@@ -393,28 +557,43 @@ __global__ __launch_bounds__(256) void k_filter_u8r8(PxArgs a, RasterIn in, int6
         load_op8(R, a.G.frag32, a.G.h0, lane);
     else
         load_op8_pp(R, a.G, lane);
+    U8rIO<ALIGNED, BUF> io;
+    io.init(a, in);
     const int64_t my_tiles = (tiles - wave + waves - 1) / waves;
-    uint32_t cur[4], nxt[4];
+    const int64_t last = wave + (my_tiles - 1) * waves;
+    uint32_t ring[D][4], ring_aux[D];
     int64_t tile = wave;
-    load_px8_raster(in, a, tile * 16, lane, cur);
-    for (int64_t k = 0; k < my_tiles; ++k) {
-        // every step loads (the last one its own tile again): no conditional
-        // loads in the loop, whose waits would then count conservatively
-        const bool more = k + 1 < my_tiles;
-        load_px8_raster(in, a, (more ? tile + waves : tile) * 16, lane, nxt);
-        float4 x[4];
-        unpack_px(cur, x);
-        f32x4 acc[4];
-        if constexpr (PREC == DCTF_PREC_FP32)
-            tile8(R, x, lane, acc);
-        else
-            tile8_pp(R, x, acc);
-        store_px8_raster(a, tile * 16, a.B - tile * 16, acc, lane);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            cur[i] = nxt[i];
-        tile += waves;
+    for (int j = 0; j < D; ++j) {
+        const int64_t t = tile + j * waves;
+        ring_aux[j] = io.load(a, in, (t < last ? t : last) * 16, lane, ring[j]);
     }
+    auto round = [&]() {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int64_t cur = tile < last ? tile : last;
+            float4 x[4];
+            io.unpack(ring[j], ring_aux[j], x);
+            const uint32_t out_off = ring_aux[j];
+            const int64_t t = tile + D * waves;
+            ring_aux[j] = io.load(a, in, (t < last ? t : last) * 16, lane, ring[j]);
+            // keep the slot's next loads ahead of this tile's products
+            __builtin_amdgcn_sched_barrier(0);
+            f32x4 acc[4];
+            if constexpr (PREC == DCTF_PREC_FP32)
+                tile8_f32_init(R, x, lane, acc, 0.5f);
+            else
+                tile8_pp(R, x, acc, 0.5f);
+            io.store(a, cur * 16, lane, out_off, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            tile += waves;
+        }
+    };
+    // the first round outside the loop: the loop is then entered with the
+    // same operations in flight as at its back-edge
+    round();
+    for (int64_t k = D; k < my_tiles; k += D)
+        round();
 }
 
 // ---------------------------------------------------------------- N = 16
@@ -428,6 +607,7 @@ struct RefPx16 {
     int op;
     int h, w, Bw, bpi;   // raster output
     int64_t pitch, img_stride;
+    uint32_t magic[4];
 };
 
 template <int PREC, int IN, int D, bool RAST = false>
@@ -456,6 +636,9 @@ __global__ __launch_bounds__(512) void k_filter_px16(PxArgs a, int64_t tiles)
         r.bpi = a.bpi;
         r.pitch = a.pitch;
         r.img_stride = a.img_stride;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            r.magic[i] = a.magic[i];
         return r;
     };
     auto op_load = [&](int) {
@@ -489,9 +672,10 @@ __global__ __launch_bounds__(256) void k_filter_px_small(PxArgs a, int N)
             x[k] = (float)a.qin[blk * NN + k] * a.qtab[k] + (k == 0 ? a.dc_offset : 0.0f);
     }
     // (per thread: blk differs between the lanes of a wave)
-    const int64_t img = a.raster ? blk / a.bpi : 0;
-    const int lb = a.raster ? (int)(blk - img * a.bpi) : 0;
-    const int by = a.raster ? lb / a.Bw : 0, bx = a.raster ? lb - by * a.Bw : 0;
+    int64_t img = 0;
+    int by = 0, bx = 0;
+    if (a.raster)
+        raster_place((uint32_t)blk, a.bpi, a.Bw, a.magic, img, by, bx);
     for (int r = 0; r < NN; ++r) {
         float s = 0.0f;
         for (int k = 0; k < NN; ++k)
@@ -513,6 +697,11 @@ constexpr int kPx8U = 2;
 constexpr int kPx8Li = 1;
 constexpr int kPx8So = 0;
 constexpr int kPx8WavesPerCu = 8;
+// one-pass uint8 kernel: waves per CU (two per SIMD; three measured no
+// faster) and tiles of pixels in flight per wave (2, 3 and 4 measured 0.126,
+// 0.138 and 0.134 ms on 64 2048^2 images, split-BF16)
+constexpr int kU8rWavesPerCu = 8;
+constexpr int kU8rDepth = 2;
 constexpr int kPx16Depth = 2;
 
 template <int PREC, int IN>
@@ -565,16 +754,32 @@ hipError_t launch_filter_u8_raster8(int prec, const PxArgs &a, const uint8_t *in
     in.img = in_img;
     in.pitch = in_pitch;
     in.img_stride = in_stride;
+    const int64_t nimg = a.B / a.bpi;
+    in.in_bytes = ((nimg - 1) * in_stride + (int64_t)(a.h - 1) * in_pitch + a.w + 3) / 4 * 4;
+    in.out_bytes = ((nimg - 1) * a.img_stride + (int64_t)(a.h - 1) * a.pitch + a.w + 3) / 4 * 4;
     const int64_t tiles = (a.B + 15) / 16;
-    int64_t waves = (int64_t)cu_count() * kPx8WavesPerCu;
+    int64_t waves = (int64_t)cu_count() * kU8rWavesPerCu;
     waves = waves < tiles ? waves : tiles;
     const int64_t groups = (waves + 3) / 4;
-    if (prec == DCTF_PREC_FP32)
-        hipLaunchKernelGGL((k_filter_u8r8<DCTF_PREC_FP32>), dim3((unsigned)groups), dim3(256), 0, stream, a, in,
-                           tiles, waves);
-    else
-        hipLaunchKernelGGL((k_filter_u8r8<DCTF_PREC_SPLIT_BF16>), dim3((unsigned)groups), dim3(256), 0, stream, a,
-                           in, tiles, waves);
+    const bool aligned = a.h % 8 == 0 && a.w % 8 == 0;
+    const bool buf = in.in_bytes < ((int64_t)1 << 31) && in.out_bytes < ((int64_t)1 << 31);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(256), 0, stream, a, in, tiles, waves);
+    };
+    constexpr int D = kU8rDepth;
+    if (prec == DCTF_PREC_FP32) {
+        if (aligned)
+            buf ? go(k_filter_u8r8<DCTF_PREC_FP32, true, true, D>) : go(k_filter_u8r8<DCTF_PREC_FP32, true, false, D>);
+        else
+            buf ? go(k_filter_u8r8<DCTF_PREC_FP32, false, true, D>) : go(k_filter_u8r8<DCTF_PREC_FP32, false, false, D>);
+    } else {
+        if (aligned)
+            buf ? go(k_filter_u8r8<DCTF_PREC_SPLIT_BF16, true, true, D>)
+                : go(k_filter_u8r8<DCTF_PREC_SPLIT_BF16, true, false, D>);
+        else
+            buf ? go(k_filter_u8r8<DCTF_PREC_SPLIT_BF16, false, true, D>)
+                : go(k_filter_u8r8<DCTF_PREC_SPLIT_BF16, false, false, D>);
+    }
     return hipGetLastError();
 }
 

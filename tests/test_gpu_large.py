@@ -247,3 +247,48 @@ def test_batch_past_2_31(dctf, layout, prec):
         idx = boundary_blocks(N * N, B, 4, 15 + N)
         err = np.abs(sample(Y, N, idx) - oracle.filter_coeffs(sample(X, N, idx), W, border)).max()
         assert err <= TOL[prec], (layout, N, err)
+
+
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+@pytest.mark.parametrize("h,w,pitch,nimg", [(4096, 4096, 4096, 130), (4093, 4094, 4096, 129)])
+def test_u8_raster_past_2_31(dctf, h, w, pitch, nimg, prec):
+    """uint8 images to filtered uint8 images in one pass, the images spanning
+    more than 2^31 bytes (the kernel's 64-bit address path): bit-identical to
+    calls over parts of fewer than 2^31 bytes (its 32-bit buffer path), and
+    equal to the oracle on sampled blocks, among them the blocks that hold
+    byte 2^31 of the input and of the output, outside the 1/2 band."""
+    N = 8
+    W = syn.asym_mask_5x5()
+    op = dctf.dctf_build_operator(W, N, R)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(31)
+    src = torch.randint(0, 256, (nimg, h, pitch), dtype=torch.uint8, device="cuda", generator=g)
+    dst = torch.zeros((nimg, h, pitch), dtype=torch.uint8, device="cuda")
+    dctf.dctf_filter_u8_raster(op, prec, src[:, :, :w], h, w, dst[:, :, :w])
+    part = torch.zeros((64, h, pitch), dtype=torch.uint8, device="cuda")
+    for i0 in range(0, nimg, 64):
+        n = min(64, nimg - i0)
+        dctf.dctf_filter_u8_raster(op, prec, src[i0:i0 + n, :, :w], h, w, part[:n, :, :w])
+        torch.cuda.synchronize()
+        assert torch.equal(part[:n, :, :w], dst[i0:i0 + n, :, :w]), i0
+    del part
+    bh, bw = -(-h // N), -(-w // N)
+    at = divmod(2 ** 31, h * pitch)
+    mark = (at[0], at[1] // pitch // N, min(at[1] % pitch, w - 1) // N)
+    rng = np.random.default_rng(7)
+    blocks = {mark, (nimg - 1, bh - 1, bw - 1), (0, 0, 0)}
+    blocks |= {(int(rng.integers(nimg)), int(rng.integers(bh)), int(rng.integers(bw))) for _ in range(300)}
+    blocks = sorted(blocks)
+    r = np.arange(N)
+    px, got, valid = [], [], []
+    for (i, by, bx) in blocks:
+        ys, xs = np.minimum(N * by + r, h - 1), np.minimum(N * bx + r, w - 1)
+        yi = torch.from_numpy(ys).cuda()[:, None]
+        xi = torch.from_numpy(xs).cuda()[None, :]
+        px.append(src[i][yi, xi].cpu().numpy())
+        got.append(dst[i][yi, xi].cpu().numpy())
+        valid.append(((N * by + r) < h)[:, None] & ((N * bx + r) < w)[None, :])
+    _, u8, nh = oracle.filter_pixels(np.stack(px), W, R)
+    got, valid = np.stack(got), np.stack(valid)
+    assert np.array_equal(got[valid & ~nh], u8[valid & ~nh])
+    assert np.abs(got[valid & nh].astype(int) - u8[valid & nh].astype(int)).max(initial=0) <= 1
