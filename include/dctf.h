@@ -212,6 +212,36 @@ dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, 
                                int64_t B, dctf_stream stream);
 
 /*
+ * Mirror-symmetric masks.  A mask that is mirror-symmetric on both axes
+ * (W[i][j] = W[kh-1-i][j] = W[i][kw-1-j], kh and kw odd) filters a block and
+ * its mirror images alike (both borders), while the DCT basis vectors are
+ * even or odd under a mirror; so H_dct[(u1,v1),(u2,v2)] = 0 unless u1 + u2
+ * and v1 + v2 are even (the DCT-domain form of the paper's observation that
+ * symmetric masks need fewer products, Sec. II.B-C, eq. 12 and the remark
+ * after eq. 20).  H_dct is then four (N^2/4) x (N^2/4) operators, one per
+ * parity class (u % 2, v % 2).  At N = 16 the builder forms these four 64 x 64
+ * operators (in FP64, taken from H_dct) when the mask has the symmetry to
+ * 1e-12 of its largest entry (the coupling that such a difference leaves
+ * between classes is of the same relative size and is left out).
+ *
+ * dctf_operator_parity_classes: 4 when the operator has the class operators
+ *   (N = 16, doubly symmetric mask), else 1.
+ * dctf_filter_blocks_parity: Y[b] = H_dct . X[b] as dctf_filter_blocks, through
+ *   the four class operators: a quarter of the dense product's MFMA work.
+ *   Precisions as for dctf_filter_blocks (split-BF16: class inputs (u, v) =
+ *   (2a + pu, 2b + pv) with a <= 1 and b in {0, 1, 4, 5} in FP32 MFMA, a
+ *   superset of the dense path's FP32 set; FP32: each class's first column
+ *   in FP32 VALU).  Results agree with dctf_filter_blocks within its
+ *   tolerance, not bit for bit (other operands and summation order); each
+ *   block's result depends only on the block and the operator.  Buffers as
+ *   for dctf_filter_blocks.  Errors: DCTF_EINVAL, DCTF_EUNSUPPORTED (the
+ *   operator has no class operators), DCTF_EHIP.
+ */
+dctf_status dctf_operator_parity_classes(dctf_operator op, int *classes);
+dctf_status dctf_filter_blocks_parity(dctf_operator op, int prec, const float *in_dev, float *out_dev, int64_t B,
+                                      dctf_stream stream);
+
+/*
  * Y[b] = sum_r P_r X[b] Q_r^t for b = 0..B-1: the factored form above,
  * FP32 MFMA (v_mfma_f32_16x16x4_f32, two chained products per rank term,
  * on 16 x 16 quadrants at N = 32, FP32 accumulation).  It does 2 R N^3

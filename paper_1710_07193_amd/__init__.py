@@ -88,6 +88,8 @@ _SIGS = {
     "dctf_operator_rank": ([_P, _P], _I),
     "dctf_operator_factors_fp64": ([_P, _P, _P], _I),
     "dctf_filter_blocks_factored": ([_P, _P, _P, _I64, _P], _I),
+    "dctf_operator_parity_classes": ([_P, _P], _I),
+    "dctf_filter_blocks_parity": ([_P, _I, _P, _P, _I64, _P], _I),
     "dctf_batch_create": ([ctypes.POINTER(_Job), _I, _I, ctypes.POINTER(_P)], _I),
     "dctf_batch_run": ([_P, ctypes.c_uint, _P], _I),
     "dctf_batch_capture": ([_P, ctypes.c_uint, _P], _I),
@@ -277,6 +279,24 @@ def dctf_filter_blocks_factored(op: Operator, X: torch.Tensor, Y: torch.Tensor, 
     _check(_lib.dctf_filter_blocks_factored(op, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
                                             X.numel() // nn, _stream(stream)),
            "dctf_filter_blocks_factored")
+
+
+def dctf_operator_parity_classes(op: Operator) -> int:
+    """4 when the operator splits into parity-class operators (N = 16, mask
+    mirror-symmetric on both axes), else 1."""
+    c = ctypes.c_int()
+    _check(_lib.dctf_operator_parity_classes(op, ctypes.byref(c)), "dctf_operator_parity_classes")
+    return c.value
+
+
+def dctf_filter_blocks_parity(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    """Y[b] = H_dct . X[b] through the four parity-class operators (N = 16)."""
+    nn = op.N * op.N
+    if X.numel() % nn or Y.numel() != X.numel():
+        raise ValueError("X and Y must hold the same whole number of N*N blocks")
+    _check(_lib.dctf_filter_blocks_parity(op, prec, _dptr(X, torch.float32, "X"), _dptr(Y, torch.float32, "Y"),
+                                          X.numel() // nn, _stream(stream)),
+           "dctf_filter_blocks_parity")
 
 
 def dctf_filter_blocks_f64(op: Operator, X: torch.Tensor, Y: torch.Tensor, stream=None):

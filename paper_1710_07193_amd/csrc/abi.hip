@@ -203,7 +203,29 @@ int dctf::mask_rank_factors(const double *W, int kh, int kw, std::vector<double>
     return rank;
 }
 
-static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, dctf_operator *out)
+// Mirror-symmetric on both axes with odd sides: then the correlation window
+// is centred and the block's mirror images are filtered alike.  Entries may
+// differ from their mirror images by 1e-12 of the largest entry (a mask
+// averaged with its mirror images in floating point); the coupling between
+// parity classes that this leaves is of the same relative size, far below
+// FP32 rounding, and the class operators leave it out.
+static bool mask_doubly_symmetric(const double *W, int kh, int kw)
+{
+    if (kh % 2 == 0 || kw % 2 == 0)
+        return false;
+    double m = 0.0;
+    for (int e = 0; e < kh * kw; ++e)
+        m = std::max(m, std::fabs(W[e]));
+    const double tol = 1e-12 * m;
+    for (int i = 0; i < kh; ++i)
+        for (int j = 0; j < kw; ++j)
+            if (std::fabs(W[i * kw + j] - W[(kh - 1 - i) * kw + j]) > tol ||
+                std::fabs(W[i * kw + j] - W[i * kw + (kw - 1 - j)]) > tol)
+                return false;
+    return true;
+}
+
+static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, bool parity, dctf_operator *out)
 {
     const size_t NN = (size_t)N * N, N4 = NN * NN, F = frag_elems(N);
     // split-BF16 images exist for N = 8, 16 and 32; the pixel-domain set for N <= 16
@@ -235,6 +257,12 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     const size_t o_q64 = off;  off = align_up(off + sizeof(double) * rank * NN);
     const size_t o_p32 = off;  off = align_up(off + sizeof(float) * rank * NN);
     const size_t o_q32 = off;  off = align_up(off + sizeof(float) * rank * NN);
+    // parity-class images (N = 16, doubly symmetric masks): four N = 8 sets
+    parity = parity && N == 16;
+    size_t o_par = off;
+    const size_t par_bytes = align_up(sizeof(float) * (4096 + 64 + 512)) + 2 * align_up(sizeof(uint16_t) * 4096);
+    if (parity)
+        off += 4 * par_bytes;
 
     dctf_operator op = new (std::nothrow) dctf_operator_s();
     if (!op)
@@ -275,6 +303,20 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, d
     op->img.Q64 = reinterpret_cast<double *>(b + o_q64);
     op->img.P32 = reinterpret_cast<float *>(b + o_p32);
     op->img.Q32 = reinterpret_cast<float *>(b + o_q32);
+    op->parity = parity ? 1 : 0;
+    for (int c = 0; c < 4; ++c) {
+        DenseImages &P = op->par[c];
+        P = DenseImages{};
+        if (!parity)
+            continue;
+        char *q = b + o_par + c * par_bytes;
+        P.frag32 = reinterpret_cast<float *>(q);
+        P.h0 = P.frag32 + 4096;
+        P.frag_lf = P.h0 + 64;
+        q += align_up(sizeof(float) * (4096 + 64 + 512));
+        P.frag_hi = reinterpret_cast<uint16_t *>(q);
+        P.frag_lo = reinterpret_cast<uint16_t *>(q + align_up(sizeof(uint16_t) * 4096));
+    }
     *out = op;
     return DCTF_OK;
 }
@@ -299,12 +341,15 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
         if (st != DCTF_OK)
             return st;
     }
-    // the N = 32 split-BF16 images, from the FP64 operator just built
+    // the N = 32 split-BF16 images and the N = 16 parity-class images, from
+    // the FP64 operator just built
     for (int i = 0; i < n && (parts & kBuildDct); ++i) {
         const DenseImages &D = ops[i]->img.dct;
-        if (ops[i]->N != 32)
-            continue;
-        dctf_status st = hip_status(launch_split_n32(D.H64, D.frag_hi, D.frag_lo, D.frag_lf, s));
+        dctf_status st = DCTF_OK;
+        if (ops[i]->N == 32)
+            st = hip_status(launch_split_n32(D.H64, D.frag_hi, D.frag_lo, D.frag_lf, s));
+        else if (ops[i]->parity)
+            st = hip_status(launch_build_parity(D.H64, ops[i]->par, s));
         if (st != DCTF_OK)
             return st;
     }
@@ -330,7 +375,8 @@ extern "C" dctf_status dctf_build_operators(const dctf_mask_desc *masks, int n, 
     for (int i = 0; i < n && st == DCTF_OK; ++i) {
         const int kh = masks[i].kh, kw = masks[i].kw;
         const int rank = mask_rank_factors(masks[i].mask_host, kh, kw, fa[i], fb[i]);
-        st = alloc_operator(masks[i].N, kh, kw, masks[i].border, rank, &ops[i]);
+        st = alloc_operator(masks[i].N, kh, kw, masks[i].border, rank,
+                            mask_doubly_symmetric(masks[i].mask_host, kh, kw), &ops[i]);
         if (st == DCTF_OK)
             st = hip_status(hipMemcpyAsync(ops[i]->img.mask, masks[i].mask_host, sizeof(double) * kh * kw,
                                            hipMemcpyHostToDevice, s));
@@ -467,6 +513,34 @@ extern "C" dctf_status dctf_filter_blocks(dctf_operator op, int prec, const floa
         st = hip_status(launch_filter_n32(prec, a, s));
     else
         st = hip_status(launch_filter(op->N, prec, current_variant(op->N, prec), a, s));
+    timing_end(s, slot);
+    return st;
+}
+
+extern "C" dctf_status dctf_operator_parity_classes(dctf_operator op, int *classes)
+{
+    if (op == nullptr || classes == nullptr)
+        return DCTF_EINVAL;
+    *classes = op->parity ? 4 : 1;
+    return DCTF_OK;
+}
+
+extern "C" dctf_status dctf_filter_blocks_parity(dctf_operator op, int prec, const float *in_dev, float *out_dev,
+                                                 int64_t B, dctf_stream stream)
+{
+    if (op == nullptr || (prec != DCTF_PREC_FP32 && prec != DCTF_PREC_SPLIT_BF16))
+        return DCTF_EINVAL;
+    dctf_status st = validate_io(op->N, in_dev, out_dev, B);
+    if (st != DCTF_OK)
+        return st;
+    if (!op->parity)
+        return DCTF_EUNSUPPORTED;
+    if (B == 0)
+        return DCTF_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int slot;
+    timing_begin(s, &slot);
+    st = hip_status(launch_filter_n16_parity(prec, op->par, in_dev, out_dev, B, s));
     timing_end(s, slot);
     return st;
 }

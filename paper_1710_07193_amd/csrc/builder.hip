@@ -66,6 +66,27 @@ __device__ inline int src_index(int i, int d, int N, int border, bool *valid)
 template <int N>
 constexpr int chunk_rows() { return N >= 32 ? 1 : (N >= 16 ? 8 : (N == 8 ? 17 : 33)); }
 
+// Split-BF16 images of entry H[r][c] = h (h32 = fp32(h)) of an operator on
+// N x N blocks (N = 8 or 16): the low-frequency columns (DC included) go to
+// the FP32 MFMA image frag_lf (slot 2g + j of k-step j, 2 steps); every other
+// column is split into BF16 hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
+__device__ __forceinline__ void write_split_entry(const DenseImages &D, int N, int r, int c, double h, float h32)
+{
+    const int q = lf_slot(N, c);
+    uint16_t hi = 0, lo = 0;
+    if (q >= 0) {
+        const int t = r >> 4, m = r & 15;
+        const int steps = lf_count(N) / 4, lane = 16 * (q / steps) + m;
+        D.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;
+    } else {
+        hi = bf16_rne(h32);
+        lo = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(hi)));
+    }
+    const int fi = frag16_index(N, r, c);
+    D.frag_hi[fi] = hi;
+    D.frag_lo[fi] = lo;
+}
+
 template <int N>
 __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
 {
@@ -207,23 +228,7 @@ __device__ void build_op(const BuildDesc &d, int r0, double *lds, int domain)
             out.frag_lo[fi] = mid;
             out.frag_lo2[fi] = lo;
         } else if constexpr (N == 8 || N == 16) {
-            // Split path: low-frequency columns (DC included) go to the FP32
-            // MFMA image frag_lf; every other column is split into BF16
-            // hi = bf16(fp32(H)), lo = bf16(fp32(H - hi)).
-            const int q = lf_slot(N, c);
-            uint16_t hi = 0, lo = 0;
-            if (q >= 0) {
-                // slot 2g + j of k-step j (2 steps)
-                const int t = r >> 4, m = r & 15;
-                const int steps = lf_count(N) / 4, lane = 16 * (q / steps) + m;
-                out.frag_lf[(t * 64 + lane) * steps + q % steps] = h32;
-            } else {
-                hi = bf16_rne(h32);
-                lo = bf16_rne(__double2float_rn(h - (double)bf16_to_f32(hi)));
-            }
-            const int fi = frag16_index(N, r, c);
-            out.frag_hi[fi] = hi;
-            out.frag_lo[fi] = lo;
+            write_split_entry(out, N, r, c, h, h32);
         }
     }
 }
@@ -332,7 +337,42 @@ __global__ __launch_bounds__(kThreads) void k_build_factors(BuildArgs args)
     }
 }
 
+// Parity classes of an N = 16 operator (mask mirror-symmetric on both axes):
+// entry [r][c] of class (pu, pv), r = 8a + b and c = 8a' + b', is
+// H_dct[(2a + pu) 16 + 2b + pv][(2a' + pu) 16 + 2b' + pv], written into the
+// class's N = 8 images as the builder writes an N = 8 operator.
+struct ParityOut {
+    DenseImages par[4];
+};
+
+__global__ __launch_bounds__(kThreads) void k_build_parity(const double *H64, ParityOut out)
+{
+    const int e = blockIdx.x * kThreads + threadIdx.x;   // 4 classes x 64 x 64
+    if (e >= 4 * 4096)
+        return;
+    const int cls = e >> 12, r = (e >> 6) & 63, c = e & 63;
+    const int pu = cls >> 1, pv = cls & 1;
+    const int R = (2 * (r >> 3) + pu) * 16 + 2 * (r & 7) + pv;
+    const int C = (2 * (c >> 3) + pu) * 16 + 2 * (c & 7) + pv;
+    const double h = H64[R * 256 + C];
+    const float h32 = __double2float_rn(h);
+    const DenseImages &D = out.par[cls];
+    if (c == 0)
+        D.h0[r] = h32;
+    D.frag32[frag32_index(8, r, c)] = (c == 0) ? 0.0f : h32;
+    write_split_entry(D, 8, r, c, h, h32);
+}
+
 }  // namespace
+
+hipError_t launch_build_parity(const double *H64, const DenseImages *par, hipStream_t stream)
+{
+    ParityOut o;
+    for (int c = 0; c < 4; ++c)
+        o.par[c] = par[c];
+    hipLaunchKernelGGL(k_build_parity, dim3(4 * 4096 / kThreads), dim3(kThreads), 0, stream, H64, o);
+    return hipGetLastError();
+}
 
 hipError_t launch_build(const BuildArgs &args, hipStream_t stream)
 {

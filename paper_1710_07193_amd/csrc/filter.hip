@@ -305,6 +305,106 @@ hipError_t dispatch16_split(int variant, const FilterArgs &a, hipStream_t stream
     }
 }
 
+// -------------------------------------- N = 16, mirror-symmetric masks
+//
+// A mask that is mirror-symmetric on both axes (odd kh and kw) filters a
+// block and its mirror images alike, and the DCT basis vectors are even or
+// odd under a mirror: H_dct couples coefficient (u, v) only with those whose
+// row and column indices have the same parities (the DCT-domain form of the
+// paper's remark that symmetric masks need fewer products, Sec. II.B-C).  The
+// operator is then four 64 x 64 operators, one per parity class (pu, pv): a
+// quarter of the dense 256 x 256 product.
+//
+// A workgroup of four waves takes 16-block tiles; wave c = 2 pu + pv
+// multiplies class (pu, pv) of each block with the N = 8 tile code (its
+// operator in VGPRs, N = 8 fragment layout, class coefficient q = 8a + b for
+// (u, v) = (2a + pu, 2b + pv)).  The tile passes through LDS in class order:
+// every global load and store instruction covers 4 KiB of the tile
+// (thread t holds float4 k 256 + t: block 4k + t / 64, row (t / 4) % 16,
+// columns 4 (t % 4) .. +3, i.e. two coefficients of class (u % 2, 0) and two
+// of class (u % 2, 1)), written to and gathered from LDS as 8-byte pairs.
+// In LDS, class c of block n is 16 chunks of 16 bytes (class coefficients
+// 4 ch .. 4 ch + 3 in chunk ch), chunk ch stored at slot ch ^ n, so that the
+// 16-byte reads of a wave (lane (n, g) takes chunk 4i + g of block n, i.e.
+// class coefficients 16i + 4g .. +3 as the N = 8 tile code wants them) fall
+// in different banks.  Each wave writes its outputs over its own inputs (no
+// other wave touches that class), then the workgroup gathers the natural
+// order back for the stores.  The next tile's loads are in flight while the
+// current one is multiplied; a ragged tail goes through raw buffer
+// instructions over the tile's valid blocks (zeros in, stores dropped).
+struct ParArgs {
+    const float *in;
+    float *out;
+    int64_t B;
+    DenseImages par[4];
+};
+
+__device__ __forceinline__ int par_slot(int cls, int n, int ch) { return (cls * 16 + n) * 16 + (ch ^ n); }
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void k_filter_n16_par(ParArgs a, int64_t tiles, int64_t groups)
+{
+    __shared__ __attribute__((aligned(16))) float4 lds[4 * 16 * 16];   // [class][block][chunk slot], 16 KiB
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int cls = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t wg = blockIdx.x;
+    if (wg >= tiles)
+        return;
+    typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs8F32, OpRegs8BF16>::type Regs;
+    Regs R;
+    const DenseImages &P = a.par[cls];
+    if constexpr (PREC == DCTF_PREC_FP32)
+        load_op8(R, P.frag32, P.h0, lane);
+    else
+        load_op8(R, P.frag_hi, P.frag_lo, P.frag_lf, lane);
+    const int n = lane & 15, g = lane >> 4;
+    // loader role: float4 k of thread tid is block 4k + tid / 64, row u, columns v0 .. v0 + 3
+    const int u = (tid >> 2) & 15, pu = u & 1, ch = 2 * (u >> 1) + ((tid & 3) >> 1), half = tid & 1;
+    const int64_t my_tiles = (tiles - wg + groups - 1) / groups;
+    const int64_t last = wg + (my_tiles - 1) * groups;
+    float2 *lds2 = reinterpret_cast<float2 *>(lds);
+    float4 gl[4];
+    auto load = [&](int64_t t) {
+        const rsrc_t r = tile_rsrc(a.in, t * 16, a.B, 1024);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            gl[k] = buf_ld4<true>(r, (uint32_t)(k * 256 + tid) * 16u);
+    };
+    int64_t tile = wg;
+    load(tile);
+    for (int64_t it = 0; it < my_tiles; ++it) {
+        __syncthreads();   // the previous tile's gathers are done
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int nb = 4 * k + (tid >> 6);
+            lds2[2 * par_slot(2 * pu, nb, ch) + half] = make_float2(gl[k].x, gl[k].z);
+            lds2[2 * par_slot(2 * pu + 1, nb, ch) + half] = make_float2(gl[k].y, gl[k].w);
+        }
+        const int64_t nt = tile + groups;
+        load(nt < last ? nt : last);   // the last step loads its own tile again: every step loads
+        __syncthreads();
+        float4 x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            x[i] = lds[par_slot(cls, n, 4 * i + g)];
+        f32x4 acc[4];
+        tile8(R, x, lane, acc);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            lds[par_slot(cls, n, 4 * t + g)] = make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+        __syncthreads();
+        const rsrc_t o = tile_rsrc(a.out, tile * 16, a.B, 1024);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int nb = 4 * k + (tid >> 6);
+            const float2 e = lds2[2 * par_slot(2 * pu, nb, ch) + half];
+            const float2 f = lds2[2 * par_slot(2 * pu + 1, nb, ch) + half];
+            buf_st4<true>(o, (uint32_t)(k * 256 + tid) * 16u, f32x4{e.x, f.x, e.y, f.y});
+        }
+        tile += groups;
+    }
+}
+
 // ------------------------------------------------- N = 16, factored form
 //
 // Y = sum_r P_r X Q_r^t per block (the paper's A . BLOCK . B products with
@@ -646,6 +746,31 @@ int default_variant(int N, int prec)
     (void)N;
     (void)prec;
     return 0;
+}
+
+hipError_t launch_filter_n16_parity(int prec, const DenseImages *par, const float *in, float *out, int64_t B,
+                                    hipStream_t stream)
+{
+    if (B <= 0)
+        return hipSuccess;
+    ParArgs a;
+    a.in = in;
+    a.out = out;
+    a.B = B;
+    for (int c = 0; c < 4; ++c)
+        a.par[c] = par[c];
+    const int64_t tiles = (B + 15) / 16;
+    // two 4-wave workgroups per CU (three or four measured 7-10 % slower,
+    // split-BF16)
+    const int64_t want = (int64_t)cu_count() * 2;
+    const int64_t groups = tiles < want ? tiles : want;
+    if (prec == DCTF_PREC_FP32)
+        hipLaunchKernelGGL(k_filter_n16_par<DCTF_PREC_FP32>, dim3((unsigned)groups), dim3(256), 0, stream, a, tiles,
+                           groups);
+    else
+        hipLaunchKernelGGL(k_filter_n16_par<DCTF_PREC_SPLIT_BF16>, dim3((unsigned)groups), dim3(256), 0, stream, a,
+                           tiles, groups);
+    return hipGetLastError();
 }
 
 hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipStream_t stream)

@@ -88,6 +88,8 @@ def test_filter_and_batch_validation(lib):
     assert lib.dctf_operator_rank(None, None) == -1
     assert lib.dctf_operator_factors_fp64(None, None, None) == -1
     assert lib.dctf_filter_blocks_factored(None, None, None, 1, None) == -1
+    assert lib.dctf_operator_parity_classes(None, None) == -1
+    assert lib.dctf_filter_blocks_parity(None, 1, None, None, 1, None) == -1
     assert lib.dctf_operator_pixel_fp64(None, None) == -1
     assert lib.dctf_filter_blocks_f64(None, None, None, 1, None) == -1
     assert lib.dctf_filter_image(None, 0, None, None, 1, 1, 1, None) == -1

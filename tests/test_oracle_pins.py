@@ -363,6 +363,31 @@ def test_paper_symmetric_shortcut_eq12():
     assert np.abs(paper_route.filter_symmetric_zero(X, W) - oracle.filter_coeffs(X[None], W, Z)[0]).max() < 1e-9
 
 
+@pytest.mark.parametrize("N", [8, 16])
+@pytest.mark.parametrize("border", [Z, R])
+def test_doubly_symmetric_mask_decouples_parity_classes(N, border):
+    """A mask mirror-symmetric on both axes (odd sides) filters a block's
+    mirror images alike, and DCT basis vectors are even or odd under the
+    mirror (C J = D C, D = diag((-1)^k)): H_dct vanishes between coefficients
+    whose row (or column) indices differ in parity, so it splits into four
+    parity-class operators.  Checked on the oracle's probe of the spatial
+    filter (not its own H): zero to rounding for symmetric masks, and clearly
+    nonzero when either mirror symmetry or the odd side is missing."""
+    rng = _rng(44)
+    A = rng.uniform(-1, 1, (7, 7))
+    B = A + A[::-1]
+    sym = (B + B[:, ::-1]) / 4
+    u = np.arange(N * N) // N
+    v = np.arange(N * N) % N
+    odd = ((u[:, None] + u[None, :]) % 2 == 1) | ((v[:, None] + v[None, :]) % 2 == 1)
+    for W in (sym, syn.gaussian_mask(5, sigma=1.0), syn.box_mask(3), sym[3:4]):
+        H = oracle.operator_probe(N, W, border)
+        assert np.abs(H[odd]).max() < 1e-13 * np.abs(H).max()
+    for W in ((A + A[:, ::-1]) / 2, (A + A[::-1]) / 2, np.ones((4, 4)) / 16):
+        H = oracle.operator_probe(N, W, border)
+        assert np.abs(H[odd]).max() > 1e-3
+
+
 # ------------------------------------------------- pixels, uint8, tiling
 
 def test_u8_rounding_rule():
