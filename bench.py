@@ -378,7 +378,8 @@ def fp64_filter(dctf, torch, stream, X, N, steps, warmup):
 def n16_frames(dctf, torch, stream, steps, warmup):
     """32 seeded 3840x2160 frames in 16x16 blocks (1,036,800 blocks) through
     one 7x7 asymmetric mask with zero border, in both precisions, the
-    factored FP32 path for that mask and for a separable 7x7 Gaussian, and
+    factored FP32 path for that mask and for a separable 7x7 Gaussian (and
+    the Gaussian through the dense and the parity-class filters), and
     image-level (cross-block) filtering with the same mask."""
     import numpy as np
 
@@ -408,9 +409,15 @@ def n16_frames(dctf, torch, stream, steps, warmup):
         ent = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
                "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
         if tag == "gauss7x7":
+            # the same symmetric mask: dense operator, and its four parity-class operators
+            ent["parity_classes"] = dctf.dctf_operator_parity_classes(o)
             for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
                 ent["dense_%s_ms" % pname] = timed_steps(
                     torch, lambda: dctf.dctf_filter_blocks(o, p, X, Y, stream), steps, warmup, stream)
+                pms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_parity(o, p, X, Y, stream), steps, warmup,
+                                  stream, settle_first=True)
+                ent["parity_%s_ms" % pname] = pms
+                ent["parity_%s_GBps" % pname] = B * N * N * 8 / (pms * 1e-3) / 1e9
         res["factored_" + tag] = ent
     res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
