@@ -513,6 +513,19 @@ dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w, int64_t pi
                                 float *coeffs_dev, dctf_stream stream);
 
 /*
+ * The same for nimg images of h x w pixels in one launch (N = 8, 16, 32; one
+ * launch per image for the other block sizes): image i starts img_stride
+ * bytes after image i - 1 (nimg > 1: img_stride >= (h - 1) * pitch + w), and
+ * its blocks follow image i - 1's in coeffs_dev (nimg * ceil(h/N)*ceil(w/N)
+ * blocks of N*N floats, the layout the raster calls take).  h, w or nimg = 0
+ * is a no-op.  Errors: DCTF_EINVAL (null, misaligned, negative sizes, bad
+ * pitch or stride, images overlapping the coefficients), DCTF_EUNSUPPORTED,
+ * DCTF_EHIP.
+ */
+dctf_status dctf_forward_dct_u8_images(const uint8_t *img_dev, int h, int w, int64_t pitch, int64_t img_stride,
+                                       int64_t nimg, int N, float *coeffs_dev, dctf_stream stream);
+
+/*
  * Verify kernel: inverse DCT (eq. 3) of each coefficient block in FP32, then
  * the uint8 conversion of Sec. III (round half up, saturate to [0, 255]).
  *   pix_dev      B*N*N bytes out (block-contiguous, row-major inside a block).

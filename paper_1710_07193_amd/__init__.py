@@ -100,6 +100,7 @@ _SIGS = {
     "dctf_filter_batch_noalloc": ([ctypes.POINTER(_Job), _I, _I, _P], _I),
     "dctf_filter_batch_f64": ([ctypes.POINTER(_JobF64), _I, _P], _I),
     "dctf_forward_dct_u8": ([_P, _I, _I, _I64, _I, _P, _P], _I),
+    "dctf_forward_dct_u8_images": ([_P, _I, _I, _I64, _I64, _I64, _I, _P, _P], _I),
     "dctf_idct_u8_verify": ([_I, _P, _I64, _P, _P, _P, _P], _I),
     "dctf_stream_copy": ([_P, _P, _I64, _P], _I),
     "dctf_variant_count": ([_I, _I], _I),
@@ -560,6 +561,25 @@ def dctf_forward_dct_u8(img: torch.Tensor, N: int, coeffs: torch.Tensor, stream=
     _check(_lib.dctf_forward_dct_u8(_P(img.data_ptr()), h, w, img.stride(0), N,
                                     _dptr(coeffs, torch.float32, "coeffs"), _stream(stream)),
            "dctf_forward_dct_u8")
+
+
+def dctf_forward_dct_u8_images(imgs: torch.Tensor, N: int, coeffs: torch.Tensor, stream=None):
+    """uint8 images (n, h, w) on the device -> their coefficient blocks, one
+    image after another, in one launch.  Rows may be views of wider buffers
+    (row pitch imgs.stride(1), image stride imgs.stride(0))."""
+    if not isinstance(imgs, torch.Tensor) or not imgs.is_cuda or imgs.dtype != torch.uint8:
+        raise TypeError("imgs must be a uint8 device tensor")
+    if imgs.dim() != 3:
+        raise ValueError("imgs must be 3-D (n, h, w)")
+    n, h, w = imgs.shape
+    if imgs.stride(2) != 1 or imgs.stride(1) < w:
+        raise ValueError("image rows must be contiguous, with a row pitch of at least the width")
+    nblk = -(-h // N) * -(-w // N)
+    if coeffs.numel() != n * nblk * N * N:
+        raise ValueError("coeffs must hold %d blocks" % (n * nblk))
+    _check(_lib.dctf_forward_dct_u8_images(_P(imgs.data_ptr()), h, w, imgs.stride(1), imgs.stride(0), n, N,
+                                           _dptr(coeffs, torch.float32, "coeffs"), _stream(stream)),
+           "dctf_forward_dct_u8_images")
 
 
 def dctf_idct_u8_verify(N: int, Y: torch.Tensor, pix: torch.Tensor, expected=None, counters=None,

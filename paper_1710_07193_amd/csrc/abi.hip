@@ -1565,7 +1565,32 @@ extern "C" dctf_status dctf_forward_dct_u8(const uint8_t *img_dev, int h, int w,
         return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
     if (img_dev == nullptr || coeffs_dev == nullptr || h < 1 || w < 1 || pitch < w || !aligned16(coeffs_dev))
         return DCTF_EINVAL;
-    return hip_status(launch_forward_dct_u8(img_dev, h, w, pitch, N, coeffs_dev,
+    return hip_status(launch_forward_dct_u8(img_dev, h, w, pitch, 0, 1, N, coeffs_dev,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+extern "C" dctf_status dctf_forward_dct_u8_images(const uint8_t *img_dev, int h, int w, int64_t pitch,
+                                                  int64_t img_stride, int64_t nimg, int N, float *coeffs_dev,
+                                                  dctf_stream stream)
+{
+    if (!supported_op_n(N))
+        return (N > 0 && N <= 64) ? DCTF_EUNSUPPORTED : DCTF_EINVAL;
+    if (nimg < 0 || h < 0 || w < 0)
+        return DCTF_EINVAL;
+    if (nimg == 0 || h == 0 || w == 0)
+        return DCTF_OK;
+    if (img_dev == nullptr || coeffs_dev == nullptr || pitch < w || !aligned16(coeffs_dev))
+        return DCTF_EINVAL;
+    const int64_t span = (int64_t)(h - 1) * pitch + w;
+    if (nimg > 1 && img_stride < span)
+        return DCTF_EINVAL;
+    const int64_t bpi = (int64_t)((h + N - 1) / N) * ((w + N - 1) / N);
+    if (nimg > INT64_MAX / (bpi * N * N * 4) || nimg > INT64_MAX / std::max<int64_t>(img_stride, 1))
+        return DCTF_EINVAL;
+    const int64_t istr = nimg > 1 ? img_stride : 0;
+    if (ranges_overlap(img_dev, (size_t)((nimg - 1) * istr + span), coeffs_dev, (size_t)(nimg * bpi * N * N * 4)))
+        return DCTF_EINVAL;
+    return hip_status(launch_forward_dct_u8(img_dev, h, w, pitch, istr, nimg, N, coeffs_dev,
                                             static_cast<hipStream_t>(stream)));
 }
 

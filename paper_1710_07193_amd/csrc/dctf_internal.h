@@ -373,8 +373,9 @@ void variant_io(int N, int prec, int variant, int *io, bool *nt);
 hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,
                                  const uint8_t *expected, unsigned long long *counters,
                                  hipStream_t stream);
-hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
-                                 float *coeffs, hipStream_t stream);
+// nimg images img_stride bytes apart -> their blocks one image after another
+hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int64_t img_stride,
+                                 int64_t nimg, int N, float *coeffs, hipStream_t stream);
 hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_t stream);
 
 // Device properties cached per device.

@@ -147,11 +147,14 @@ __device__ __forceinline__ f64x4v mfma_f64x4(double a, double b, f64x4v c)
 // stored.  A unit inside the image reads its four pixels per lane and tile
 // row as one 32-bit load when the image and its pitch are 4-byte aligned
 // (aligned4), others pixel by pixel with clamped indices.  FP64 products and
-// sums, rounded once to FP32.
+// sums, rounded once to FP32.  Several images (img_stride bytes apart, upi
+// units each) go through one launch: the units are numbered across them, and
+// image i's blocks follow image i - 1's in the output.
 template <int N, int NB>
 __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *img, int h, int w, int64_t pitch,
                                                                float *coeffs, int64_t bh, int64_t bw, int64_t ubw,
-                                                               int64_t units, int aligned4)
+                                                               int64_t units, int aligned4, int64_t upi,
+                                                               int64_t img_stride)
 {
     constexpr int S = N < 16 ? 16 : N, NT = S / 16;
     __shared__ double sC[N * N];
@@ -198,19 +201,23 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
             else
                 soff[P][Q] = (16 * P + n) * N + 16 * Q + 4 * g;
         }
+    const int64_t ubh = upi / ubw, bpi_floats = bh * bw * (N * N);
     for (int64_t unit0 = wave * NB; unit0 < units; unit0 += waves * NB) {
-        const int64_t uy0 = unit0 / ubw, ux0 = unit0 % ubw;
+        const int64_t im0 = unit0 / upi, r0 = unit0 - im0 * upi;
+        const int64_t uy0 = r0 / ubw, ux0 = r0 % ubw;
         // px[b][I][J] byte s = pixel (16 I + n, 16 J + 4g + s) of unit unit0 + b: four pixels
         // per register, so that many units' loads fit in flight
         uint32_t px[NB][NT][NT];
         {
-            int64_t uy = uy0, ux = ux0;
+            int64_t im = im0, uy = uy0, ux = ux0;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const bool live = unit0 + b < units;
-                const int64_t ly = live ? uy : 0, lx = live ? ux : 0;   // a unit past the end reads unit 0
+                // a unit past the end reads unit 0
+                const int64_t ly = live ? uy : 0, lx = live ? ux : 0, li = live ? im : 0;
+                const uint8_t *ibase = img + li * img_stride;
                 if (aligned4 && (ly + 1) * S <= h && (lx + 1) * S <= w) {   // uniform over the wave
-                    const uint8_t *base = img + ly * S * pitch + lx * S;
+                    const uint8_t *base = ibase + ly * S * pitch + lx * S;
 #pragma unroll
                     for (int I = 0; I < NT; ++I)
 #pragma unroll
@@ -228,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
                             for (int k = 0; k < 4; ++k) {
                                 int64_t col = lx * S + (N == 32 && J == 1 ? 28 - 4 * g : 16 * J + 4 * g) + k;
                                 col = col < w ? col : w - 1;
-                                v |= (uint32_t)img[row * pitch + col] << (8 * k);
+                                v |= (uint32_t)ibase[row * pitch + col] << (8 * k);
                             }
                             px[b][I][J] = v;
                         }
@@ -236,18 +243,24 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
                 }
                 if (++ux == ubw) {
                     ux = 0;
-                    ++uy;
+                    if (++uy == ubh) {
+                        uy = 0;
+                        ++im;
+                    }
                 }
             }
         }
-        int64_t uy = uy0, ux = ux0;
+        int64_t im = im0, uy = uy0, ux = ux0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const bool live = unit0 + b < units;
-            const int64_t cy = uy, cx = ux;
+            const int64_t ci = im, cy = uy, cx = ux;
             if (++ux == ubw) {
                 ux = 0;
-                ++uy;
+                if (++uy == ubh) {
+                    uy = 0;
+                    ++im;
+                }
             }
             f64x4v t[NT][NT];   // t[I][V]; N = 32: t[I][P], columns v = 2 sigma(n) + P
             if constexpr (N == 32) {
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_dct_mfma(const uint8_t *im
             }
             if (!live)
                 continue;
-            float *out = coeffs + (N == 8 ? (2 * cy * bw + 2 * cx) * 64 : (cy * bw + cx) * (N * N));
+            float *out = coeffs + ci * bpi_floats + (N == 8 ? (2 * cy * bw + 2 * cx) * 64 : (cy * bw + cx) * (N * N));
             const bool mine = N != 8 || (2 * cy + (n >> 3) < bh && 2 * cx + (g >> 1) < bw);
             if constexpr (N == 32) {
 #pragma unroll
@@ -896,13 +909,13 @@ hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int N,
-                                 float *coeffs, hipStream_t stream)
+hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch, int64_t img_stride,
+                                 int64_t nimg, int N, float *coeffs, hipStream_t stream)
 {
     if (N == 8 || N == 16 || N == 32) {
         const int64_t bh = (h + N - 1) / N, bw = (w + N - 1) / N;
         const int64_t ubh = N == 8 ? (bh + 1) / 2 : bh, ubw = N == 8 ? (bw + 1) / 2 : bw;
-        const int64_t units = ubh * ubw;
+        const int64_t upi = ubh * ubw, units = upi * nimg;
         const int aligned4 = ((uintptr_t)img & 3u) == 0 && (pitch & 3) == 0;
         auto launch = [&](auto kernel, int nb, int slot_id) {
             static std::atomic<int> resident[4];
@@ -918,7 +931,7 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
             const int64_t need = (units + 4 * nb - 1) / (4 * nb);
             groups = groups < need ? groups : need;
             hipLaunchKernelGGL(kernel, dim3((unsigned)groups), dim3(kThreads), 0, stream, img, h, w, pitch, coeffs,
-                               bh, bw, ubw, units, aligned4);
+                               bh, bw, ubw, units, aligned4, upi, img_stride);
         };
         // images too small to give every resident wave a few steps of kFdctNb
         // units (one 2048 x 2048 image at N = 8 is 16,384 units) take two units
@@ -938,9 +951,14 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
     const int threads = N * N > kThreads ? N * N : kThreads;   // <= kMaxDctThreads (N <= 32)
     const int per = threads / (N * N);
     const int64_t groups = (nblocks + per - 1) / per;
-    hipLaunchKernelGGL(k_forward_dct_u8, dim3((unsigned)groups), dim3(threads), 0, stream, img, h, w,
-                       pitch, N, coeffs, nblocks);
-    return hipGetLastError();
+    for (int64_t i = 0; i < nimg; ++i) {   // small blocks: one launch per image
+        hipLaunchKernelGGL(k_forward_dct_u8, dim3((unsigned)groups), dim3(threads), 0, stream, img + i * img_stride,
+                           h, w, pitch, N, coeffs + i * nblocks * N * N, nblocks);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_idct_u8_verify(int N, const float *Y, int64_t B, uint8_t *pix,

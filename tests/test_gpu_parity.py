@@ -290,6 +290,48 @@ def test_forward_dct_strided_image(dctf, N, h, w, pad):
     assert np.all(diff[big] <= 2 * np.spacing(np.abs(ref[big]).astype(np.float32)))
 
 
+@pytest.mark.parametrize("N,h,w,n,pad", [(8, 130, 204, 5, 40), (8, 64, 64, 700, 0), (16, 100, 75, 9, 13),
+                                          (32, 70, 97, 4, 3), (4, 33, 20, 6, 0), (8, 1, 1, 3, 0)])
+def test_forward_dct_many_images_in_one_call(dctf, N, h, w, n, pad):
+    """n images in one launch (image stride with padding rows, odd and even
+    block counts, ragged sides, many units across image boundaries):
+    bit-identical to one call per image, and every block of the first and
+    last images against the oracle."""
+    imgs = np.stack([syn.image_u8(600 + i, h, w) for i in range(n)])
+    rows = h + (1 if pad else 0)
+    buf = torch.zeros((n, rows, w + pad), dtype=torch.uint8, device="cuda")
+    buf[:, :h, :w] = dev(imgs)
+    view = buf[:, :h, :w]
+    nb = -(-h // N) * -(-w // N)
+    X = torch.full((n * nb * N * N,), float("nan"), dtype=torch.float32, device="cuda")
+    dctf.dctf_forward_dct_u8_images(view, N, X)
+    one = torch.empty(nb * N * N, dtype=torch.float32, device="cuda")
+    for i in range(n):
+        dctf.dctf_forward_dct_u8(view[i], N, one)
+        torch.cuda.synchronize()
+        assert torch.equal(X[i * nb * N * N:(i + 1) * nb * N * N], one), i
+    for i in (0, n - 1):
+        ref = oracle.coeffs_fp32(oracle.tile_u8(imgs[i], N)).reshape(-1)
+        got = X[i * nb * N * N:(i + 1) * nb * N * N].cpu().numpy()
+        assert np.abs(got.astype(np.float64) - ref).max() <= 4 * np.spacing(np.float32(255 * N))
+
+
+def test_forward_dct_many_images_argument_errors(dctf):
+    lib = dctf.raw_library()
+    img = torch.zeros(4 * 64 * 64, dtype=torch.uint8, device="cuda")
+    X = torch.zeros(4 * 64 * 64, dtype=torch.float32, device="cuda")
+    f = lib.dctf_forward_dct_u8_images
+    pi, px = img.data_ptr(), X.data_ptr()
+    assert f(pi, 64, 64, 64, 4096, 4, 8, px, None) == 0
+    assert f(pi, 64, 64, 64, 4000, 4, 8, px, None) == -1       # images overlap
+    assert f(pi, 64, 64, 60, 4096, 4, 8, px, None) == -1       # pitch < w
+    assert f(pi, 64, 64, 64, 4096, -1, 8, px, None) == -1      # nimg < 0
+    assert f(pi, 64, 64, 64, 4096, 0, 8, px, None) == 0        # no-op
+    assert f(pi, 64, 64, 64, 4096, 4, 8, px + 4, None) == -1   # alignment
+    assert f(pi, 64, 64, 64, 4096, 4, 8, pi, None) == -1       # images overlap the coefficients
+    assert f(pi, 64, 64, 64, 4096, 4, 5, px, None) == -2       # block size
+
+
 @pytest.mark.parametrize("N", [2, 4, 8, 16, 32])
 def test_verify_kernel_all_sizes_strided(dctf, N):
     """Every block size, with enough blocks that each workgroup walks several
