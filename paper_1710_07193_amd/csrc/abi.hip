@@ -342,13 +342,14 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
             return st;
     }
     // the N = 32 split-BF16 images and the N = 16 parity-class images, from
-    // the FP64 operator just built
+    // the FP64 operator just built (batches, which rebuild only what they
+    // read, leave the parity classes alone)
     for (int i = 0; i < n && (parts & kBuildDct); ++i) {
         const DenseImages &D = ops[i]->img.dct;
         dctf_status st = DCTF_OK;
         if (ops[i]->N == 32)
             st = hip_status(launch_split_n32(D.H64, D.frag_hi, D.frag_lo, D.frag_lf, s));
-        else if (ops[i]->parity)
+        else if (ops[i]->parity && (parts & kBuildParity))
             st = hip_status(launch_build_parity(D.H64, ops[i]->par, s));
         if (st != DCTF_OK)
             return st;

@@ -146,7 +146,8 @@ constexpr unsigned kBuildDct = 1u;       // H_dct images (dense filter, batches,
 constexpr unsigned kBuildPix = 2u;       // pixel-domain images (filter + inverse DCT)
 constexpr unsigned kBuildFactors = 4u;   // rank factors P_r, Q_r (factored filter)
 constexpr unsigned kBuildPixPix = 8u;    // pixel-to-pixel images (N = 8 one-pass uint8 filter)
-constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors | kBuildPixPix;
+constexpr unsigned kBuildParity = 16u;   // parity-class images (N = 16, symmetric masks), from H_dct
+constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors | kBuildPixPix | kBuildParity;
 
 struct BuildArgs {
     BuildDesc d[kMaxBuildPerLaunch];

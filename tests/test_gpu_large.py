@@ -96,6 +96,25 @@ def test_filter_blocks_past_2_31(dctf, N, B, prec):
             dctf.dctf_set_variant(N, prec, 0)
 
 
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_parity_classes_past_2_31(dctf, prec):
+    """The parity-class filter (N = 16, a mirror-symmetric 7x7 Gaussian) over
+    more than 2^31 elements: the blocks on either side of each boundary and
+    random ones against the oracle."""
+    N, B = 16, 2 ** 23 + 5
+    W = syn.gaussian_mask(7, sigma=1.5)
+    op = dctf.dctf_build_operator(W, N, R)
+    assert dctf.dctf_operator_parity_classes(op) == 4
+    X = big_coeffs(N, B, 53)
+    assert X.numel() > 2 ** 31
+    Y = torch.full_like(X, float("nan"))
+    dctf.dctf_filter_blocks_parity(op, prec, X, Y)
+    torch.cuda.synchronize()
+    idx = boundary_blocks(N * N, B, 4, 117)
+    err = np.abs(sample(Y, N, idx) - oracle.filter_coeffs(sample(X, N, idx), W, R)).max()
+    assert err <= TOL[prec], err
+
+
 def test_factored_past_2_31(dctf):
     N, B = 16, 2 ** 23 + 5
     W = syn.gaussian_mask(5)
