@@ -812,82 +812,96 @@ def main():
 
     if not args.no_extras:
         extras = {}
-        # the same step replayed from a captured HIP graph, one event pair per replay
-        side_stream = torch.cuda.Stream()
-        torch.cuda.synchronize()
-        with torch.cuda.stream(side_stream):
-            dctf.dctf_batch_capture(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, side_stream)
-            per_replay = replay_times(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
-                                      args.steps, args.warmup, side_stream, settle_first=True)
-        extras["graph_replay"] = {"replays": len(per_replay), "ms_median": float(np.median(per_replay)),
-                                  "ms_p99": float(np.percentile(per_replay, 99)),
-                                  "blocks_per_s_median": B / (float(np.median(per_replay)) * 1e-3)}
-        # the other precision on the same jobs (split-BF16 vs FP32 speedup)
-        other = dctf.DCTF_PREC_FP32 if prec == dctf.DCTF_PREC_SPLIT_BF16 else dctf.DCTF_PREC_SPLIT_BF16
-        ob = dctf.dctf_batch_create(jobs, other)
-        oms = timed_steps(torch, lambda: dctf.dctf_batch_run(ob, dctf.DCTF_RUN_REBUILD_OPERATORS, stream),
-                          args.steps, args.warmup, stream, settle_first=True)
-        extras["fp32" if other == dctf.DCTF_PREC_FP32 else "split_bf16"] = {
-            "ms_per_step": oms, "blocks_per_s": B / (oms * 1e-3),
-            "split_over_fp32_speedup": (oms / ms) if other == dctf.DCTF_PREC_FP32 else (ms / oms)}
-        del ob
-        # all blocks through the single 5x5 asymmetric inseparable mask (one operator),
-        # once per border mode and precision
-        for bname, border in (("zero", dctf.DCTF_BORDER_ZERO), ("replicate", dctf.DCTF_BORDER_REPLICATE)):
-            op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, border)
-            for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
-                sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
-                                  args.steps, args.warmup, stream, settle_first=True)
-                extras["mask5x5_%s_single_op_%s" % (bname, pname)] = {
-                    "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
-                    "GBps": alg_bytes / (sms * 1e-3) / 1e9,
-                    "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
-        progress("graph replay, other precision, single-operator runs")
-        extras["small_workloads"] = small_workloads(dctf, torch, stream)
-        extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup, args.images,
-                                             args.side)
-        progress("small workloads, pixel outputs")
-        extras["image_level"] = image_level(dctf, torch, stream, X, Y, args.images, args.side, N,
-                                            max(10, args.steps // 5), max(5, args.warmup // 6))
-        progress("image-level filtering")
-        extras["fp64"] = fp64_filter(dctf, torch, stream, X, N, max(10, args.steps // 2), max(5, args.warmup // 3))
-        # optional verify kernel: inverse DCT + uint8 of every output block
-        pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
-        vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream, settle_first=True)
-        extras["verify_kernel_ms"] = vms
         out["extras"] = extras
         extras["cold_restart"] = cold
-        del pix
-        extras["forward_dct_ingest"] = forward_dct_ingest(dctf, torch, stream, args.images, args.side, N, Y, 5, 2)
-        progress("FP64 filter, verify kernel, forward DCT")
-        extras["n16_frames"] = n16_frames(dctf, torch, stream, max(10, args.steps // 5), max(5, args.warmup // 6))
-        extras["n32_frames"] = n32_frames(dctf, torch, stream, max(5, args.steps // 10), 3)
-        progress("N = 16 and N = 32 frames")
+        try:
+            # the same step replayed from a captured HIP graph, one event pair per replay
+            side_stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side_stream):
+                dctf.dctf_batch_capture(batch, dctf.DCTF_RUN_REBUILD_OPERATORS, side_stream)
+                per_replay = replay_times(torch, lambda: dctf.dctf_batch_launch_graph(batch, side_stream),
+                                          args.steps, args.warmup, side_stream, settle_first=True)
+            extras["graph_replay"] = {"replays": len(per_replay), "ms_median": float(np.median(per_replay)),
+                                      "ms_p99": float(np.percentile(per_replay, 99)),
+                                      "blocks_per_s_median": B / (float(np.median(per_replay)) * 1e-3)}
+            # the other precision on the same jobs (split-BF16 vs FP32 speedup)
+            other = dctf.DCTF_PREC_FP32 if prec == dctf.DCTF_PREC_SPLIT_BF16 else dctf.DCTF_PREC_SPLIT_BF16
+            ob = dctf.dctf_batch_create(jobs, other)
+            oms = timed_steps(torch, lambda: dctf.dctf_batch_run(ob, dctf.DCTF_RUN_REBUILD_OPERATORS, stream),
+                              args.steps, args.warmup, stream, settle_first=True)
+            extras["fp32" if other == dctf.DCTF_PREC_FP32 else "split_bf16"] = {
+                "ms_per_step": oms, "blocks_per_s": B / (oms * 1e-3),
+                "split_over_fp32_speedup": (oms / ms) if other == dctf.DCTF_PREC_FP32 else (ms / oms)}
+            del ob
+            # all blocks through the single 5x5 asymmetric inseparable mask (one operator),
+            # once per border mode and precision
+            for bname, border in (("zero", dctf.DCTF_BORDER_ZERO), ("replicate", dctf.DCTF_BORDER_REPLICATE)):
+                op5 = dctf.dctf_build_operator(syn.asym_mask_5x5(), N, border)
+                for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+                    sms = timed_steps(torch, lambda: dctf.dctf_filter_blocks(op5, p, X, Y, stream),
+                                      args.steps, args.warmup, stream, settle_first=True)
+                    extras["mask5x5_%s_single_op_%s" % (bname, pname)] = {
+                        "ms_per_launch": sms, "blocks_per_s": B / (sms * 1e-3),
+                        "GBps": alg_bytes / (sms * 1e-3) / 1e9,
+                        "variant": dctf.dctf_variant_name(N, p, dctf.dctf_get_variant(N, p))}
+            progress("graph replay, other precision, single-operator runs")
+            extras["small_workloads"] = small_workloads(dctf, torch, stream)
+            extras["pixels_out"] = pixel_outputs(dctf, torch, stream, X, N, args.steps, args.warmup, args.images,
+                                                 args.side)
+            progress("small workloads, pixel outputs")
+            extras["image_level"] = image_level(dctf, torch, stream, X, Y, args.images, args.side, N,
+                                                max(10, args.steps // 5), max(5, args.warmup // 6))
+            progress("image-level filtering")
+            extras["fp64"] = fp64_filter(dctf, torch, stream, X, N, max(10, args.steps // 2), max(5, args.warmup // 3))
+            # optional verify kernel: inverse DCT + uint8 of every output block
+            pix = torch.empty(X.numel(), dtype=torch.uint8, device="cuda")
+            vms = timed_steps(torch, lambda: dctf.dctf_idct_u8_verify(N, Y, pix, None, None), 5, 1, stream, settle_first=True)
+            extras["verify_kernel_ms"] = vms
+            del pix
+            extras["forward_dct_ingest"] = forward_dct_ingest(dctf, torch, stream, args.images, args.side, N, Y, 5, 2)
+            progress("FP64 filter, verify kernel, forward DCT")
+            extras["n16_frames"] = n16_frames(dctf, torch, stream, max(10, args.steps // 5), max(5, args.warmup // 6))
+            extras["n32_frames"] = n32_frames(dctf, torch, stream, max(5, args.steps // 10), 3)
+            progress("N = 16 and N = 32 frames")
+        except Exception as e:   # a failing extra must not cost the headline line
+            extras["error"] = "%s: %s" % (type(e).__name__, e)
+            progress("extras stopped: %s" % extras["error"])
 
     if args.serve_seconds > 0:
-        del X, Y
-        torch.cuda.empty_cache()
-        sweep, sstats = serving_sweep(dctf, torch, [1000.0, 10000.0, 50000.0, 100000.0, 150000.0, 200000.0],
-                                      args.serve_seconds)
-        # headline: the highest offered rate the server kept up with: no queue built up, i.e. the
-        # last request completed within 1 ms of its arrival
-        kept = [r for r in sweep if r["span_s"] - r["offered_s"] <= 1e-3]
-        head = kept[-1] if kept else sweep[0]
-        out["p99_latency_ms"] = head["p99_ms"]
-        out["serving"] = {"at_rate_req_s": head["rate_req_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
-                          "sweep": sweep, "stats": sstats,
-                          "config": "Poisson arrivals; each request's sides drawn uniformly over multiples of 8 "
-                                    "in [256,4096], ceil(h/N)*ceil(w/N) blocks; N=8 (80%)/16 (20%); 32 masks K in "
-                                    "{3,5,7,9}; coefficients device-resident (prefixes of a 4096^2 image per N); "
-                                    "arena 8 GiB, 4 batches in flight, <=64 requests per batch"}
-        progress("serving sweep")
+        try:
+            del X, Y
+            torch.cuda.empty_cache()
+            sweep, sstats = serving_sweep(dctf, torch, [1000.0, 10000.0, 50000.0, 100000.0, 150000.0, 200000.0],
+                                          args.serve_seconds)
+            # headline: the highest offered rate the server kept up with: no queue built up, i.e. the
+            # last request completed within 1 ms of its arrival
+            kept = [r for r in sweep if r["span_s"] - r["offered_s"] <= 1e-3]
+            head = kept[-1] if kept else sweep[0]
+            out["p99_latency_ms"] = head["p99_ms"]
+            out["serving"] = {"at_rate_req_s": head["rate_req_s"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+                              "sweep": sweep, "stats": sstats,
+                              "config": "Poisson arrivals; each request's sides drawn uniformly over multiples of 8 "
+                                        "in [256,4096], ceil(h/N)*ceil(w/N) blocks; N=8 (80%)/16 (20%); 32 masks K in "
+                                        "{3,5,7,9}; coefficients device-resident (prefixes of a 4096^2 image per N); "
+                                        "arena 8 GiB, 4 batches in flight, <=64 requests per batch"}
+            progress("serving sweep")
+        except Exception as e:   # as above
+            out["serving"] = {"error": "%s: %s" % (type(e).__name__, e)}
+            progress("serving sweep stopped: %s" % out["serving"]["error"])
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.images, args.side, pool, draws, args.cpu_seconds, N)
-        progress("CPU oracle baseline")
-        out["accuracy"] = headline_accuracy(head_sample, pool, draws, args.side, N, gpu_near_half, B)
-        progress("accuracy of the headline output against the oracle")
-        out["cpu_context"] = cpu_context(torch, args.images, args.side, pool, draws, N)
+        try:
+            out["cpu_baseline"] = cpu_baseline(args.images, args.side, pool, draws, args.cpu_seconds, N)
+            progress("CPU oracle baseline")
+            out["accuracy"] = headline_accuracy(head_sample, pool, draws, args.side, N, gpu_near_half, B)
+            progress("accuracy of the headline output against the oracle")
+            out["cpu_context"] = cpu_context(torch, args.images, args.side, pool, draws, N)
+        except Exception as e:   # as above
+            out.setdefault("cpu_baseline", None)
+            out.setdefault("accuracy", None)
+            out["cpu_error"] = "%s: %s" % (type(e).__name__, e)
+            progress("CPU legs stopped: %s" % out["cpu_error"])
     else:
         out["cpu_baseline"] = None
         out["accuracy"] = None
