@@ -916,7 +916,8 @@ hipError_t launch_forward_dct_u8(const uint8_t *img, int h, int w, int64_t pitch
         const int64_t bh = (h + N - 1) / N, bw = (w + N - 1) / N;
         const int64_t ubh = N == 8 ? (bh + 1) / 2 : bh, ubw = N == 8 ? (bw + 1) / 2 : bw;
         const int64_t upi = ubh * ubw, units = upi * nimg;
-        const int aligned4 = ((uintptr_t)img & 3u) == 0 && (pitch & 3) == 0;
+        // 32-bit pixel loads need every image's rows 4-byte aligned
+        const int aligned4 = ((uintptr_t)img & 3u) == 0 && (pitch & 3) == 0 && (nimg == 1 || (img_stride & 3) == 0);
         auto launch = [&](auto kernel, int nb, int slot_id) {
             static std::atomic<int> resident[4];
             std::atomic<int> &slot = resident[slot_id];

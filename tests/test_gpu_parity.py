@@ -291,17 +291,25 @@ def test_forward_dct_strided_image(dctf, N, h, w, pad):
 
 
 @pytest.mark.parametrize("N,h,w,n,pad", [(8, 130, 204, 5, 40), (8, 64, 64, 700, 0), (16, 100, 75, 9, 13),
-                                          (32, 70, 97, 4, 3), (4, 33, 20, 6, 0), (8, 1, 1, 3, 0)])
+                                          (32, 70, 97, 4, 3), (4, 33, 20, 6, 0), (8, 1, 1, 3, 0),
+                                          (8, 64, 64, 5, -1)])
 def test_forward_dct_many_images_in_one_call(dctf, N, h, w, n, pad):
     """n images in one launch (image stride with padding rows, odd and even
-    block counts, ragged sides, many units across image boundaries):
+    block counts, ragged sides, many units across image boundaries; pad -1:
+    aligned rows but an image stride that is not a multiple of 4):
     bit-identical to one call per image, and every block of the first and
     last images against the oracle."""
     imgs = np.stack([syn.image_u8(600 + i, h, w) for i in range(n)])
-    rows = h + (1 if pad else 0)
-    buf = torch.zeros((n, rows, w + pad), dtype=torch.uint8, device="cuda")
-    buf[:, :h, :w] = dev(imgs)
-    view = buf[:, :h, :w]
+    if pad < 0:
+        # images h * w + 1 bytes apart: the pixel rows of images 1.. are not 4-byte aligned
+        flat = torch.zeros(n * (h * w + 1), dtype=torch.uint8, device="cuda")
+        view = torch.as_strided(flat, (n, h, w), (h * w + 1, w, 1))
+        view.copy_(dev(imgs))
+    else:
+        rows = h + (1 if pad else 0)
+        buf = torch.zeros((n, rows, w + pad), dtype=torch.uint8, device="cuda")
+        buf[:, :h, :w] = dev(imgs)
+        view = buf[:, :h, :w]
     nb = -(-h // N) * -(-w // N)
     X = torch.full((n * nb * N * N,), float("nan"), dtype=torch.float32, device="cuda")
     dctf.dctf_forward_dct_u8_images(view, N, X)
