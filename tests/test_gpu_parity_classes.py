@@ -44,7 +44,9 @@ def sym(A):
 RNG = np.random.default_rng(71)
 MASKS = {"gauss7": syn.gaussian_mask(7, sigma=1.5), "box3": syn.box_mask(3),
          "sym5": sym(RNG.uniform(-1, 1, (5, 5))), "sym7": sym(RNG.uniform(-1, 1, (7, 7))),
-         "row1x9": sym(RNG.uniform(-1, 1, (1, 9))), "gauss33": syn.gaussian_mask(33, sigma=5.0)}
+         "row1x9": sym(RNG.uniform(-1, 1, (1, 9))), "col9x1": sym(RNG.uniform(-1, 1, (9, 1))),
+         "gauss33": syn.gaussian_mask(33, sigma=5.0), "delta1": np.ones((1, 1)),
+         "laplace3": np.array([[0.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 0.0]])}
 
 
 def natural_coeffs(B, seed):
