@@ -479,7 +479,9 @@ def n32_frames(dctf, torch, stream, steps, warmup):
     N = 32 kernels (1024 x 1024 operator streamed from L2).  FP32: bound by
     FP32 MFMA (2 * 1024^2 flop per block).  Split-BF16: 3 * 2 * 1024^2 BF16
     flop per block (the 16 FP32 low-frequency columns are 1.6 % of it)
-    against the BF16 MFMA peak; HBM would allow 8 KiB per block at 8 TB/s."""
+    against the BF16 MFMA peak; HBM would allow 8 KiB per block at 8 TB/s.
+    A separable 7x7 Gaussian also runs through the factored path and, being
+    mirror-symmetric, through the dense and the parity-class filters."""
     import numpy as np
 
     import synthetic as syn
@@ -510,8 +512,19 @@ def n32_frames(dctf, torch, stream, steps, warmup):
         rank = dctf.dctf_operator_rank(o)
         fms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_factored(o, X, Y, stream), steps, warmup, stream,
                           settle_first=True)
-        res["factored_" + tag] = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
-                                  "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
+        ent = {"rank": rank, "ms_per_launch": fms, "GBps": B * N * N * 8 / (fms * 1e-3) / 1e9,
+               "fp32_mfma_TFLOPs": B * 4.0 * rank * N ** 3 / (fms * 1e-3) / 1e12}
+        if tag == "gauss7x7":
+            # the same symmetric mask: dense operator, and its four 256 x 256 parity-class operators
+            ent["parity_classes"] = dctf.dctf_operator_parity_classes(o)
+            for pname, p in (("split", dctf.DCTF_PREC_SPLIT_BF16), ("fp32", dctf.DCTF_PREC_FP32)):
+                ent["dense_%s_ms" % pname] = timed_steps(
+                    torch, lambda: dctf.dctf_filter_blocks(o, p, X, Y, stream), steps, warmup, stream)
+                pms = timed_steps(torch, lambda: dctf.dctf_filter_blocks_parity(o, p, X, Y, stream), steps, warmup,
+                                  stream, settle_first=True)
+                ent["parity_%s_ms" % pname] = pms
+                ent["parity_%s_GBps" % pname] = B * N * N * 8 / (pms * 1e-3) / 1e9
+        res["factored_" + tag] = ent
     res["verify"] = verify_frames(dctf, torch, stream, Y, N, steps, warmup)
     res["fp64"] = fp64_frames(dctf, torch, stream, op, X, N, steps, warmup)
     del X, Y

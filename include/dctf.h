@@ -219,18 +219,21 @@ dctf_status dctf_filter_blocks(dctf_operator op, int prec, const float *in_dev, 
  * and v1 + v2 are even (the DCT-domain form of the paper's observation that
  * symmetric masks need fewer products, Sec. II.B-C, eq. 12 and the remark
  * after eq. 20).  H_dct is then four (N^2/4) x (N^2/4) operators, one per
- * parity class (u % 2, v % 2).  At N = 16 the builder forms these four 64 x 64
- * operators (in FP64, taken from H_dct) when the mask has the symmetry to
- * 1e-12 of its largest entry (the coupling that such a difference leaves
- * between classes is of the same relative size and is left out).
+ * parity class (u % 2, v % 2).  At N = 16 and N = 32 the builder forms these
+ * four operators (64 x 64 and 256 x 256, in FP64, taken from H_dct) when the
+ * mask has the symmetry to 1e-12 of its largest entry (the coupling that
+ * such a difference leaves between classes is of the same relative size and
+ * is left out).  Class coefficient (a, b), a, b < N/2, is (u, v) =
+ * (2a + pu, 2b + pv); a class is then filtered as blocks of side N/2.
  *
  * dctf_operator_parity_classes: 4 when the operator has the class operators
- *   (N = 16, doubly symmetric mask), else 1.
+ *   (N = 16 or 32, doubly symmetric mask), else 1.
  * dctf_filter_blocks_parity: Y[b] = H_dct . X[b] as dctf_filter_blocks, through
  *   the four class operators: a quarter of the dense product's MFMA work.
- *   Precisions as for dctf_filter_blocks (split-BF16: class inputs (u, v) =
- *   (2a + pu, 2b + pv) with a <= 1 and b in {0, 1, 4, 5} in FP32 MFMA, a
- *   superset of the dense path's FP32 set; FP32: each class's first column
+ *   Precisions as for dctf_filter_blocks (split-BF16: the class inputs that
+ *   the N/2 dense path keeps in FP32 MFMA, i.e. N = 16: a <= 1 and b in
+ *   {0, 1, 4, 5}; N = 32: the first 8 (a, b) in zigzag order; in either case
+ *   a superset of the dense path's FP32 set; FP32: each class's first column
  *   in FP32 VALU).  Results agree with dctf_filter_blocks within its
  *   tolerance, not bit for bit (other operands and summation order); each
  *   block's result depends only on the block and the operator.  Buffers as

@@ -283,7 +283,7 @@ def dctf_filter_blocks_factored(op: Operator, X: torch.Tensor, Y: torch.Tensor, 
 
 
 def dctf_operator_parity_classes(op: Operator) -> int:
-    """4 when the operator splits into parity-class operators (N = 16, mask
+    """4 when the operator splits into parity-class operators (N = 16 or 32, mask
     mirror-symmetric on both axes), else 1."""
     c = ctypes.c_int()
     _check(_lib.dctf_operator_parity_classes(op, ctypes.byref(c)), "dctf_operator_parity_classes")
@@ -291,7 +291,7 @@ def dctf_operator_parity_classes(op: Operator) -> int:
 
 
 def dctf_filter_blocks_parity(op: Operator, prec: int, X: torch.Tensor, Y: torch.Tensor, stream=None):
-    """Y[b] = H_dct . X[b] through the four parity-class operators (N = 16)."""
+    """Y[b] = H_dct . X[b] through the four parity-class operators (N = 16 or 32)."""
     nn = op.N * op.N
     if X.numel() % nn or Y.numel() != X.numel():
         raise ValueError("X and Y must hold the same whole number of N*N blocks")

@@ -257,10 +257,13 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, b
     const size_t o_q64 = off;  off = align_up(off + sizeof(double) * rank * NN);
     const size_t o_p32 = off;  off = align_up(off + sizeof(float) * rank * NN);
     const size_t o_q32 = off;  off = align_up(off + sizeof(float) * rank * NN);
-    // parity-class images (N = 16, doubly symmetric masks): four N = 8 sets
-    parity = parity && N == 16;
+    // parity-class images (N = 16 and 32, doubly symmetric masks): four sets
+    // of the N / 2 block size's images (K = N^2 / 4 class coefficients)
+    parity = parity && (N == 16 || N == 32);
+    const size_t K = NN / 4;
     size_t o_par = off;
-    const size_t par_bytes = align_up(sizeof(float) * (4096 + 64 + 512)) + 2 * align_up(sizeof(uint16_t) * 4096);
+    const size_t par_f32 = align_up(sizeof(float) * (K * K + K + K * lf_count(N / 2)));
+    const size_t par_bytes = par_f32 + 2 * align_up(sizeof(uint16_t) * K * K);
     if (parity)
         off += 4 * par_bytes;
 
@@ -311,11 +314,11 @@ static dctf_status alloc_operator(int N, int kh, int kw, int border, int rank, b
             continue;
         char *q = b + o_par + c * par_bytes;
         P.frag32 = reinterpret_cast<float *>(q);
-        P.h0 = P.frag32 + 4096;
-        P.frag_lf = P.h0 + 64;
-        q += align_up(sizeof(float) * (4096 + 64 + 512));
+        P.h0 = P.frag32 + K * K;
+        P.frag_lf = P.h0 + K;
+        q += par_f32;
         P.frag_hi = reinterpret_cast<uint16_t *>(q);
-        P.frag_lo = reinterpret_cast<uint16_t *>(q + align_up(sizeof(uint16_t) * 4096));
+        P.frag_lo = reinterpret_cast<uint16_t *>(q + align_up(sizeof(uint16_t) * K * K));
     }
     *out = op;
     return DCTF_OK;
@@ -349,8 +352,8 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
         dctf_status st = DCTF_OK;
         if (ops[i]->N == 32)
             st = hip_status(launch_split_n32(D.H64, D.frag_hi, D.frag_lo, D.frag_lf, s));
-        else if (ops[i]->parity && (parts & kBuildParity))
-            st = hip_status(launch_build_parity(D.H64, ops[i]->par, s));
+        if (st == DCTF_OK && ops[i]->parity && (parts & kBuildParity))
+            st = hip_status(launch_build_parity(ops[i]->N, D.H64, ops[i]->par, s));
         if (st != DCTF_OK)
             return st;
     }
@@ -541,7 +544,8 @@ extern "C" dctf_status dctf_filter_blocks_parity(dctf_operator op, int prec, con
     hipStream_t s = static_cast<hipStream_t>(stream);
     int slot;
     timing_begin(s, &slot);
-    st = hip_status(launch_filter_n16_parity(prec, op->par, in_dev, out_dev, B, s));
+    st = hip_status(op->N == 16 ? launch_filter_n16_parity(prec, op->par, in_dev, out_dev, B, s)
+                                : launch_filter_n32_parity(prec, op->par, in_dev, out_dev, B, s));
     timing_end(s, slot);
     return st;
 }

@@ -337,40 +337,46 @@ __global__ __launch_bounds__(kThreads) void k_build_factors(BuildArgs args)
     }
 }
 
-// Parity classes of an N = 16 operator (mask mirror-symmetric on both axes):
-// entry [r][c] of class (pu, pv), r = 8a + b and c = 8a' + b', is
-// H_dct[(2a + pu) 16 + 2b + pv][(2a' + pu) 16 + 2b' + pv], written into the
-// class's N = 8 images as the builder writes an N = 8 operator.
+// Parity classes of an N = 16 or 32 operator (mask mirror-symmetric on both
+// axes): with M = N / 2, entry [r][c] of class (pu, pv), r = M a + b and
+// c = M a' + b', is H_dct[(2a + pu) N + 2b + pv][(2a' + pu) N + 2b' + pv],
+// written into the class's images as the builder writes an operator on
+// M x M blocks.
 struct ParityOut {
     DenseImages par[4];
 };
 
+template <int N>
 __global__ __launch_bounds__(kThreads) void k_build_parity(const double *H64, ParityOut out)
 {
-    const int e = blockIdx.x * kThreads + threadIdx.x;   // 4 classes x 64 x 64
-    if (e >= 4 * 4096)
+    constexpr int M = N / 2, K = M * M;
+    const int e = blockIdx.x * kThreads + threadIdx.x;   // 4 classes x K x K
+    if (e >= 4 * K * K)
         return;
-    const int cls = e >> 12, r = (e >> 6) & 63, c = e & 63;
+    const int cls = e / (K * K), r = (e / K) % K, c = e % K;
     const int pu = cls >> 1, pv = cls & 1;
-    const int R = (2 * (r >> 3) + pu) * 16 + 2 * (r & 7) + pv;
-    const int C = (2 * (c >> 3) + pu) * 16 + 2 * (c & 7) + pv;
-    const double h = H64[R * 256 + C];
+    const int R = (2 * (r / M) + pu) * N + 2 * (r % M) + pv;
+    const int C = (2 * (c / M) + pu) * N + 2 * (c % M) + pv;
+    const double h = H64[(size_t)R * (N * N) + C];
     const float h32 = __double2float_rn(h);
     const DenseImages &D = out.par[cls];
     if (c == 0)
         D.h0[r] = h32;
-    D.frag32[frag32_index(8, r, c)] = (c == 0) ? 0.0f : h32;
-    write_split_entry(D, 8, r, c, h, h32);
+    D.frag32[frag32_index(M, r, c)] = (c == 0) ? 0.0f : h32;
+    write_split_entry(D, M, r, c, h, h32);
 }
 
 }  // namespace
 
-hipError_t launch_build_parity(const double *H64, const DenseImages *par, hipStream_t stream)
+hipError_t launch_build_parity(int N, const double *H64, const DenseImages *par, hipStream_t stream)
 {
     ParityOut o;
     for (int c = 0; c < 4; ++c)
         o.par[c] = par[c];
-    hipLaunchKernelGGL(k_build_parity, dim3(4 * 4096 / kThreads), dim3(kThreads), 0, stream, H64, o);
+    if (N == 16)
+        hipLaunchKernelGGL(k_build_parity<16>, dim3(4 * 4096 / kThreads), dim3(kThreads), 0, stream, H64, o);
+    else
+        hipLaunchKernelGGL(k_build_parity<32>, dim3(4 * 65536 / kThreads), dim3(kThreads), 0, stream, H64, o);
     return hipGetLastError();
 }
 

@@ -120,13 +120,14 @@ struct dctf_operator_s {
     void *base;   // owning device allocation
     size_t bytes;
     dctf::OpImages img;
-    // N = 16, masks mirror-symmetric on both axes (odd kh, kw): H_dct couples
-    // only coefficients whose row indices and whose column indices have equal
-    // parity, so it splits into four 64 x 64 operators, one per class
-    // (pu, pv) of coefficients (u, v) with u % 2 = pu, v % 2 = pv; par[2 pu
-    // + pv] holds class (pu, pv) in the N = 8 fragment images (frag32, h0,
-    // frag_hi, frag_lo, frag_lf), class coefficient q = 8a + b standing for
-    // (u, v) = (2a + pu, 2b + pv).  parity = 1 when they exist.
+    // N = 16 and 32, masks mirror-symmetric on both axes (odd kh, kw): H_dct
+    // couples only coefficients whose row indices and whose column indices
+    // have equal parity, so it splits into four (N^2 / 4)-square operators,
+    // one per class (pu, pv) of coefficients (u, v) with u % 2 = pu,
+    // v % 2 = pv; par[2 pu + pv] holds class (pu, pv) in the fragment images
+    // of the N / 2 block size (frag32, h0, frag_hi, frag_lo, frag_lf), class
+    // coefficient q = (N / 2) a + b standing for (u, v) = (2a + pu, 2b + pv).
+    // parity = 1 when they exist.
     int parity;
     dctf::DenseImages par[4];
 };
@@ -161,9 +162,9 @@ inline size_t frag_lf_elems(int N) { return (N >= 8) ? (size_t)N * N * lf_count(
 
 // builder.hip
 hipError_t launch_build(const BuildArgs &args, hipStream_t stream);
-// The parity-class images (OpImages::par) of an N = 16 operator from its
-// FP64 H_dct (256 x 256, row-major).
-hipError_t launch_build_parity(const double *H64, const DenseImages *par, hipStream_t stream);
+// The parity-class images (dctf_operator_s::par) of an N = 16 or 32 operator
+// from its FP64 H_dct (N^2 x N^2, row-major).
+hipError_t launch_build_parity(int N, const double *H64, const DenseImages *par, hipStream_t stream);
 
 // Rank factorisation of a kh x kw mask (host, FP64): W = sum_r a_r b_r^t with
 // a_r (kh values) and b_r (kw values) appended to a and b.  Returns the rank
@@ -279,8 +280,11 @@ struct FilterArgs {
     const float *H32;
 };
 hipError_t launch_filter(int N, int prec, int variant, const FilterArgs &a, hipStream_t stream);
-// The N = 16 filter through the four parity-class operators (OpImages::par).
+// The N = 16 / N = 32 filters through the four parity-class operators
+// (dctf_operator_s::par).
 hipError_t launch_filter_n16_parity(int prec, const DenseImages *par, const float *in, float *out, int64_t B,
+                                    hipStream_t stream);
+hipError_t launch_filter_n32_parity(int prec, const DenseImages *par, const float *in, float *out, int64_t B,
                                     hipStream_t stream);
 // n32.hip — the N = 32 filter, operator streamed from L2: FP32 MFMA (frag32
 // and h0 of the DCT-domain images) or split-BF16 (frag_hi / frag_lo in the

@@ -405,6 +405,65 @@ __global__ __launch_bounds__(256, 2) void k_filter_n16_par(ParArgs a, int64_t ti
     }
 }
 
+// -------------------------------------- N = 32, mirror-symmetric masks
+//
+// The same parity classes at N = 32: four 256 x 256 operators, the size of
+// an N = 16 operator, so each class runs through the N = 16 weight-stationary
+// tile loop (8 waves holding the class operator in VGPRs) with a loader that
+// gathers the class's 256 coefficients of each of a tile's 16 blocks (four
+// 32-bit loads per class chunk of four, every other float of a block row; the
+// workgroup of the other column parity reads the floats in between, from the
+// same cache lines) and stores that write the results back to their places
+// (32-bit stores, the other half of each row written by that workgroup).  Workgroup w takes class (w / 8) % 4 and, within it, the place
+// (w / 32) 8 + w % 8: the four classes of a tile are on the same XCD (its
+// L2 serves the rows the four read) and next to each other in launch order.
+// FP32: 32-bit class loads, two tiles ahead; split-BF16 (more operator
+// registers): float4 loads of whole 32-byte row pieces, one tile ahead.
+constexpr int kPar32In[2] = {2, 3};
+constexpr int kPar32Depth[2] = {2, 1};
+struct RefPar32 {
+    const float *in;
+    float *out;
+    int64_t B;
+    int64_t blk0;
+    int op;
+    int cls;
+};
+
+template <int PREC>
+__global__ __launch_bounds__(512) void k_filter_n32_par(ParArgs a, int64_t tiles, int64_t per_class)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int w = blockIdx.x;
+    const int cls = (w >> 3) & 3;
+    const int64_t wg = (int64_t)(w >> 5) * 8 + (w & 7), G = per_class;
+    if (wg >= tiles)
+        return;
+    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split];
+    typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
+    Regs R;
+    const int64_t count = (tiles - wg + G - 1) / G;
+    auto ref = [&](int64_t t) {
+        RefPar32 r;
+        r.in = a.in;
+        r.out = a.out;
+        r.B = a.B;
+        r.blk0 = (wg + t * G) * 16;
+        r.op = 0;
+        r.cls = cls;
+        return r;
+    };
+    const DenseImages &P = a.par[cls];
+    auto op_load = [&](int) {
+        if constexpr (PREC == DCTF_PREC_FP32)
+            load_op16(R, P.frag32, P.h0, wave, lane);
+        else
+            load_op16(R, P.frag_hi, P.frag_lo, P.frag_lf, wave, lane);
+    };
+    run_tiles16<PREC, kPar32Depth[PREC], RefPar32, kPar32In[PREC], 3>(count, ref, op_load, R, smem);
+}
+
 // ------------------------------------------------- N = 16, factored form
 //
 // Y = sum_r P_r X Q_r^t per block (the paper's A . BLOCK . B products with
@@ -770,6 +829,32 @@ hipError_t launch_filter_n16_parity(int prec, const DenseImages *par, const floa
     else
         hipLaunchKernelGGL(k_filter_n16_par<DCTF_PREC_SPLIT_BF16>, dim3((unsigned)groups), dim3(256), 0, stream, a,
                            tiles, groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_n32_parity(int prec, const DenseImages *par, const float *in, float *out, int64_t B,
+                                    hipStream_t stream)
+{
+    if (B <= 0)
+        return hipSuccess;
+    ParArgs a;
+    a.in = in;
+    a.out = out;
+    a.B = B;
+    for (int c = 0; c < 4; ++c)
+        a.par[c] = par[c];
+    const int64_t tiles = (B + 15) / 16;
+    // one 8-wave workgroup per CU, a quarter of them per class, in groups of 8
+    int64_t per_class = ((int64_t)cu_count() / 4 + 7) / 8 * 8;
+    const int64_t need = (tiles + 7) / 8 * 8;
+    per_class = per_class < need ? per_class : need;
+    const unsigned grid = (unsigned)(4 * per_class);
+    if (prec == DCTF_PREC_FP32)
+        hipLaunchKernelGGL((k_filter_n32_par<DCTF_PREC_FP32>), dim3(grid), dim3(512), 0, stream, a, tiles,
+                           per_class);
+    else
+        hipLaunchKernelGGL((k_filter_n32_par<DCTF_PREC_SPLIT_BF16>), dim3(grid), dim3(512), 0, stream,
+                           a, tiles, per_class);
     return hipGetLastError();
 }
 

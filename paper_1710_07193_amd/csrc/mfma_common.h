@@ -727,6 +727,24 @@ struct Stage16<1> {
     u32x4 raw;
 };
 
+// IN = 2, 3: one parity class (pu, pv) of N = 32 blocks as blocks of 256
+// coefficients in class order (q = 16a + b for (u, v) = (2a + pu, 2b + pv)):
+// class chunk c (coefficients 4c .. 4c + 3) is every other float of the 8
+// from column 8(c % 4) of row 2(c / 4) + pu.  IN = 2 loads the four with
+// 32-bit loads; IN = 3 loads all 8 as two float4s (half the load
+// instructions and cache-line lookups, twice the registers) and picks the
+// class's four when the tile is written to LDS.
+template <>
+struct Stage16<2> {
+    float4 v[2];
+};
+
+template <>
+struct Stage16<3> {
+    float4 v[2][2];
+    int pv;
+};
+
 __device__ __forceinline__ void stage16_chunks(const Stage16<0> &S, const float *, float, float4 v[2])
 {
     v[0] = S.v[0];
@@ -740,10 +758,24 @@ __device__ __forceinline__ void stage16_chunks(const Stage16<1> &S, const float 
     dequant8(S.raw, qv, dc, v[0], v[1]);
 }
 
+__device__ __forceinline__ void stage16_chunks(const Stage16<2> &S, const float *, float, float4 v[2])
+{
+    v[0] = S.v[0];
+    v[1] = S.v[1];
+}
+
+__device__ __forceinline__ void stage16_chunks(const Stage16<3> &S, const float *, float, float4 v[2])
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        v[h] = S.pv ? make_float4(S.v[h][0].y, S.v[h][0].w, S.v[h][1].y, S.v[h][1].w)
+                    : make_float4(S.v[h][0].x, S.v[h][0].z, S.v[h][1].x, S.v[h][1].z);
+}
+
 template <int IN>
 __device__ __forceinline__ void stage16_pos(int tid, int h, int &b, int &c)
 {
-    if constexpr (IN == 0) {
+    if constexpr (IN != 1) {
         const int q = tid + 512 * h;
         b = q >> 6;
         c = q & 63;
@@ -760,6 +792,34 @@ __device__ __forceinline__ void stage16_load_q(Stage16<1> &S, rsrc_t r, int tid)
     // int16 block: 512 bytes; thread q: coefficients 8(q % 32) .. +7 of block q / 32
     S.raw = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
                                           r, (uint32_t)((tid >> 5) * 512 + 16 * (tid & 31)), 0, 2));
+}
+
+// class cls = 2 pu + pv of a tile of 16 N = 32 blocks (4 KiB each)
+__device__ __forceinline__ void stage16_load_cls(Stage16<2> &S, rsrc_t r, int tid, int cls)
+{
+    const int pu = cls >> 1, pv = cls & 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h, c = q & 63;
+        const uint32_t off = (uint32_t)((q >> 6) * 4096 + ((2 * (c >> 2) + pu) * 32 + 8 * (c & 3) + pv) * 4);
+        S.v[h] = make_float4(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)),
+                             __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off + 8, 0, 0)),
+                             __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off + 16, 0, 0)),
+                             __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off + 24, 0, 0)));
+    }
+}
+
+__device__ __forceinline__ void stage16_load_cls(Stage16<3> &S, rsrc_t r, int tid, int cls)
+{
+    const int pu = cls >> 1;
+    S.pv = cls & 1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + 512 * h, c = q & 63;
+        const uint32_t off = (uint32_t)((q >> 6) * 4096 + ((2 * (c >> 2) + pu) * 32 + 8 * (c & 3)) * 4);
+        S.v[h][0] = buf_ld4<false>(r, off);
+        S.v[h][1] = buf_ld4<false>(r, off + 16);
+    }
 }
 
 __device__ __forceinline__ void stage16_load(Stage16<0> &S, rsrc_t r, int tid)
@@ -902,11 +962,13 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // the end, through empty resources), so the compiler's memory-counter waits
 // let the D tiles ahead stay in flight.
 // IN = 0: FP32 coefficients from r.in; IN = 1: int16 coefficients from
-// r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term.
+// r.qin, dequantised with qtab (N*N factors) and dc_offset on the DC term;
+// IN = 2: parity class r.cls of N = 32 blocks from r.in (Stage16<2>).
 // OUT = 0: FP32 results to r.out; OUT = 1: uint8 pixels to r.pix (the
 // operator is then the pixel-domain one); OUT = 2: the same pixels into the
 // raster images at r.pix (r.h x r.w, row pitch r.pitch, r.Bw blocks per row,
-// r.bpi blocks and r.img_stride bytes per image).
+// r.bpi blocks and r.img_stride bytes per image); OUT = 3: FP32 results of
+// parity class r.cls back to their places in the N = 32 blocks at r.out.
 template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, typename RefFn,
           typename OpFn, typename Regs>
 __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
@@ -939,8 +1001,10 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
     auto stage = [&](Stage16<IN> &S, const Ref &r) {
         if constexpr (IN == 0)
             stage16_load(S, tile_rsrc(r.in, r.blk0, r.B, 1024), tid);
-        else
+        else if constexpr (IN == 1)
             stage16_load_q(S, tile_rsrc(r.qin, r.blk0, r.B, 512), tid);
+        else
+            stage16_load_cls(S, tile_rsrc(r.in, r.blk0, r.B, 4096), tid, r.cls);
     };
     // Output offsets of the lane (block n, rows 32 wave + 4g .. and + 16).
     const uint32_t out_off = (uint32_t)(n * (OUT == 0 ? 1024 : 256) + (OUT == 0 ? 4 : 1) * (32 * wave + 4 * g));
@@ -995,6 +1059,17 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
             const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 1024);
             buf_st4<false>(o, out_off, acc[0]);
             buf_st4<false>(o, out_off + 64, acc[1]);
+        } else if constexpr (OUT == 3) {
+            // output rows 32 wave + 16t + 4g + r of the class are (a, b) =
+            // (2 wave + t, 4g + r), i.e. (u, v) = (4 wave + 2t + pu, 8g + 2r + pv)
+            const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 4096);
+            const uint32_t off3 =
+                (uint32_t)(n * 4096 + ((4 * wave + (rc.cls >> 1)) * 32 + 8 * g + (rc.cls & 1)) * 4);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[t][r]), o, off3 + 256 * t + 8 * r, 0, 0);
         } else if constexpr (OUT == 1) {
             const rsrc_t o = tile_rsrc(rc.pix, rc.blk0, rc.B, 256);
             __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]), o,

@@ -97,11 +97,12 @@ def test_filter_blocks_past_2_31(dctf, N, B, prec):
 
 
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
-def test_parity_classes_past_2_31(dctf, prec):
-    """The parity-class filter (N = 16, a mirror-symmetric 7x7 Gaussian) over
-    more than 2^31 elements: the blocks on either side of each boundary and
+@pytest.mark.parametrize("N", [16, 32])
+def test_parity_classes_past_2_31(dctf, N, prec):
+    """The parity-class filter (a mirror-symmetric 7x7 Gaussian) over more
+    than 2^31 elements: the blocks on either side of each boundary and
     random ones against the oracle."""
-    N, B = 16, 2 ** 23 + 5
+    B = 2 ** 31 // (N * N) + 5
     W = syn.gaussian_mask(7, sigma=1.5)
     op = dctf.dctf_build_operator(W, N, R)
     assert dctf.dctf_operator_parity_classes(op) == 4
