@@ -897,9 +897,11 @@ __global__ __launch_bounds__(kThreads) void k_idct_u8_verify8(const float *Y, in
 hipError_t launch_stream_copy(const float *in, float *out, int64_t n, hipStream_t stream)
 {
     const int64_t n4 = n / 4;
-    // twice the workgroups a CU holds (8): the queued ones fill the gaps as
-    // others end (1 GiB: 5.98 TB/s, against 5.88 with exactly the resident 8)
-    int64_t groups = (int64_t)cu_count() * 16;
+    // up to one step per wave: a launch of many short-lived workgroups keeps
+    // more loads in flight as waves end than a few long grid-stride loops
+    // (1 GiB, 4 KiB per wave and step: 6.23 TB/s at 256 workgroups per CU
+    // (one step), 6.15 at 64, 5.98 at 16, 5.88 at the resident 8)
+    int64_t groups = (int64_t)cu_count() * 256;
     const int64_t need = (n4 + 1023) / 1024;   // 4 waves x 256 float4 per group and step
     groups = groups < need ? groups : need;
     if (groups <= 0)
