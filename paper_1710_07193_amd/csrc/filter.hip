@@ -418,9 +418,12 @@ __global__ __launch_bounds__(256, 2) void k_filter_n16_par(ParArgs a, int64_t ti
 // (w / 32) 8 + w % 8: the four classes of a tile are on the same XCD (its
 // L2 serves the rows the four read) and next to each other in launch order.
 // FP32: 32-bit class loads, two tiles ahead; split-BF16 (more operator
-// registers): float4 loads of whole 32-byte row pieces, one tile ahead.
+// registers): float4 loads of whole 32-byte row pieces, one tile ahead,
+// written to LDS after the tile's MFMA work rather than halfway through it
+// (a whole tile's work for the loads to land in).
 constexpr int kPar32In[2] = {2, 3};
 constexpr int kPar32Depth[2] = {2, 1};
+constexpr bool kPar32Late[2] = {false, true};
 struct RefPar32 {
     const float *in;
     float *out;
@@ -461,7 +464,8 @@ __global__ __launch_bounds__(512) void k_filter_n32_par(ParArgs a, int64_t tiles
         else
             load_op16(R, P.frag_hi, P.frag_lo, P.frag_lf, wave, lane);
     };
-    run_tiles16<PREC, kPar32Depth[PREC], RefPar32, kPar32In[PREC], 3>(count, ref, op_load, R, smem);
+    run_tiles16<PREC, kPar32Depth[PREC], RefPar32, kPar32In[PREC], 3, false, kPar32Late[PREC]>(count, ref, op_load, R,
+                                                                                            smem);
 }
 
 // ------------------------------------------------- N = 16, factored form

@@ -969,8 +969,8 @@ __device__ __forceinline__ void tile16(const OpRegs16BF16 &R, const uint16_t *lh
 // raster images at r.pix (r.h x r.w, row pitch r.pitch, r.Bw blocks per row,
 // r.bpi blocks and r.img_stride bytes per image); OUT = 3: FP32 results of
 // parity class r.cls back to their places in the N = 32 blocks at r.out.
-template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, typename RefFn,
-          typename OpFn, typename Regs>
+template <int PREC, int D, typename Ref, int IN = 0, int OUT = 0, bool MULTI_OP = false, bool LATE_PUT = false,
+          typename RefFn, typename OpFn, typename Regs>
 __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_load, Regs &R, char *smem,
                                             const float *qtab = nullptr, float dc_offset = 0.0f)
 {
@@ -1046,9 +1046,11 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
         f32x4 acc[2];
         // the next tile's stage goes into the other buffer (free since the
         // last barrier) halfway through this tile's MFMA work (single-operator
-        // loops; with operator reloads the registers are too tight for it)
+        // loops; with operator reloads the registers are too tight for it, and
+        // LATE_PUT defers it to the end of the tile, which gives loads issued
+        // one tile ahead the whole tile's work to land)
         auto mid = [&]() {
-            if (!MULTI_OP && !last)
+            if (!MULTI_OP && !LATE_PUT && !last)
                 put(S[(p + 1) % D], buf ^ 1);
         };
         if constexpr (PREC == DCTF_PREC_FP32)
@@ -1089,7 +1091,7 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
             }
         }
         if (!last) {
-            if constexpr (MULTI_OP)
+            if constexpr (MULTI_OP || LATE_PUT)
                 put(S[(p + 1) % D], buf ^ 1);
             __syncthreads();
         }
