@@ -344,7 +344,7 @@ static dctf_status launch_rebuild(const dctf_operator *ops, int n, hipStream_t s
         if (st != DCTF_OK)
             return st;
     }
-    // the N = 32 split-BF16 images and the N = 16 parity-class images, from
+    // the N = 32 split-BF16 images and the N = 16 and 32 parity-class images, from
     // the FP64 operator just built (batches, which rebuild only what they
     // read, leave the parity classes alone)
     for (int i = 0; i < n && (parts & kBuildDct); ++i) {

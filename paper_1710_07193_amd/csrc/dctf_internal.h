@@ -147,7 +147,7 @@ constexpr unsigned kBuildDct = 1u;       // H_dct images (dense filter, batches,
 constexpr unsigned kBuildPix = 2u;       // pixel-domain images (filter + inverse DCT)
 constexpr unsigned kBuildFactors = 4u;   // rank factors P_r, Q_r (factored filter)
 constexpr unsigned kBuildPixPix = 8u;    // pixel-to-pixel images (N = 8 one-pass uint8 filter)
-constexpr unsigned kBuildParity = 16u;   // parity-class images (N = 16, symmetric masks), from H_dct
+constexpr unsigned kBuildParity = 16u;   // parity-class images (N = 16 and 32, symmetric masks), from H_dct
 constexpr unsigned kBuildAll = kBuildDct | kBuildPix | kBuildFactors | kBuildPixPix | kBuildParity;
 
 struct BuildArgs {
