@@ -443,7 +443,8 @@ __global__ __launch_bounds__(512) void k_filter_n32_par(ParArgs a, int64_t tiles
     const int64_t wg = (int64_t)(w >> 5) * 8 + (w & 7), G = per_class;
     if (wg >= tiles)
         return;
-    __shared__ __attribute__((aligned(16))) char smem[PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split];
+    // the two tile buffers, then 2 KiB per wave for the results on their way out
+    __shared__ __attribute__((aligned(16))) char smem[(PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split) + 8 * 2048];
     typedef typename std::conditional<PREC == DCTF_PREC_FP32, OpRegs16F32, OpRegs16BF16>::type Regs;
     Regs R;
     const int64_t count = (tiles - wg + G - 1) / G;

@@ -1062,16 +1062,28 @@ __device__ __forceinline__ void run_tiles16(int64_t count, RefFn ref, OpFn op_lo
             buf_st4<false>(o, out_off, acc[0]);
             buf_st4<false>(o, out_off + 64, acc[1]);
         } else if constexpr (OUT == 3) {
-            // output rows 32 wave + 16t + 4g + r of the class are (a, b) =
-            // (2 wave + t, 4g + r), i.e. (u, v) = (4 wave + 2t + pu, 8g + 2r + pv)
-            const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 4096);
-            const uint32_t off3 =
-                (uint32_t)(n * 4096 + ((4 * wave + (rc.cls >> 1)) * 32 + 8 * g + (rc.cls & 1)) * 4);
+            // The wave's results are the class rows a = 2 wave + t (all 16 b)
+            // of the 16 blocks: 32 row pieces.  They pass through the wave's
+            // own 2 KiB of LDS (row piece 16 t + n, lane (n, g) holding
+            // b = 4g .. 4g + 3; LDS accesses of a wave complete in order, so
+            // no barrier) and leave with 16 lanes per row piece: b = j at
+            // (u, v) = (4 wave + 2t + pu, 2j + pv), four rows per store
+            // instruction instead of sixteen.
+            float *ost = reinterpret_cast<float *>(smem + (PREC == DCTF_PREC_FP32 ? kSmem16F32 : kSmem16Split)) +
+                         wave * 512;
 #pragma unroll
             for (int t = 0; t < 2; ++t)
+                *reinterpret_cast<f32x4 *>(ost + (16 * t + n) * 16 + 4 * g) = acc[t];
+            __builtin_amdgcn_wave_barrier();
+            const rsrc_t o = tile_rsrc(rc.out, rc.blk0, rc.B, 4096);
+            const int j = lane & 15;
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[t][r]), o, off3 + 256 * t + 8 * r, 0, 0);
+            for (int i = 0; i < 8; ++i) {
+                const int rp = 4 * i + (lane >> 4), t = rp >> 4, blk = rp & 15;
+                const uint32_t off = (uint32_t)(blk * 4096 + ((4 * wave + 2 * t + (rc.cls >> 1)) * 32 + 2 * j + (rc.cls & 1)) * 4);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ost[rp * 16 + j]), o, off, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
         } else if constexpr (OUT == 1) {
             const rsrc_t o = tile_rsrc(rc.pix, rc.blk0, rc.B, 256);
             __builtin_amdgcn_raw_buffer_store_b32(pack_u8x4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]), o,
