@@ -1,5 +1,5 @@
 """Single calls captured into a HIP graph (torch.cuda.graph on the capture
-stream) and replayed: the block filter (N = 8, 16), the parity-class filter,
+stream) and replayed: the block filter (N = 8, 16, 32), the parity-class filter (N = 16, 32),
 the one-pass uint8 filter, the raster pixel output and the multi-image
 forward DCT.  Each replay follows eager work that overwrites the outputs,
 and must reproduce the eager result bit for bit (the calls enqueue kernel
@@ -46,7 +46,7 @@ def replay_matches(fn, outs):
             assert torch.equal(o, e), r
 
 
-@pytest.mark.parametrize("N", [8, 16])
+@pytest.mark.parametrize("N", [8, 16, 32])
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
 def test_filter_blocks_in_a_graph(dctf, N, prec):
     op = dctf.dctf_build_operator(syn.random_mask(np.random.default_rng(3), 5, 5), N, 1)
@@ -55,10 +55,11 @@ def test_filter_blocks_in_a_graph(dctf, N, prec):
     replay_matches(lambda s: dctf.dctf_filter_blocks(op, prec, X, Y, s), [Y])
 
 
+@pytest.mark.parametrize("N", [16, 32])
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
-def test_parity_filter_in_a_graph(dctf, prec):
-    op = dctf.dctf_build_operator(syn.gaussian_mask(7, sigma=1.5), 16, 0)
-    X = torch.randn(2003 * 256, device="cuda") * 20
+def test_parity_filter_in_a_graph(dctf, N, prec):
+    op = dctf.dctf_build_operator(syn.gaussian_mask(7, sigma=1.5), N, 0)
+    X = torch.randn(2003 * N * N, device="cuda") * 20
     Y = torch.empty_like(X)
     replay_matches(lambda s: dctf.dctf_filter_blocks_parity(op, prec, X, Y, s), [Y])
 
