@@ -1,4 +1,4 @@
-"""Concurrent use of the library: one operator filtering on several streams
+"""Concurrent use of the library: one operator filtering (dense and parity-class) on several streams
 at once, calls from several host threads (ctypes releases the GIL, so the
 calls overlap), and operators built concurrently.  Every result must be
 bit-identical to the same call made alone on one stream.
@@ -50,6 +50,34 @@ def test_one_operator_on_several_streams(dctf, N):
                 Y = torch.empty_like(X)
                 with torch.cuda.stream(s):
                     dctf.dctf_filter_blocks(op, prec, X, Y, s)
+                outs[rep, prec, i] = Y
+    torch.cuda.synchronize()
+    for (rep, prec, i), Y in outs.items():
+        assert torch.equal(Y, ref[prec, i]), (rep, prec, i)
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_parity_filter_on_several_streams(dctf, N):
+    """The parity-class filter of one symmetric operator on four streams at
+    once: each result bit-identical to the same call alone."""
+    op = dctf.dctf_build_operator(syn.gaussian_mask(7, sigma=1.5), N, R)
+    assert dctf.dctf_operator_parity_classes(op) == 4
+    Xs = inputs(4, N, 512, 740)
+    ref = {}
+    for prec in (FP32, SPLIT):
+        for i, X in enumerate(Xs):
+            Y = torch.empty_like(X)
+            dctf.dctf_filter_blocks_parity(op, prec, X, Y)
+            ref[prec, i] = Y
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in Xs]
+    outs = {}
+    for rep in range(3):
+        for prec in (FP32, SPLIT):
+            for i, (X, s) in enumerate(zip(Xs, streams)):
+                Y = torch.empty_like(X)
+                with torch.cuda.stream(s):
+                    dctf.dctf_filter_blocks_parity(op, prec, X, Y, s)
                 outs[rep, prec, i] = Y
     torch.cuda.synchronize()
     for (rep, prec, i), Y in outs.items():
