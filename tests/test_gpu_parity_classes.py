@@ -100,12 +100,12 @@ def test_parity_filter_matches_oracle(dctf, N, mask, border, prec):
 @pytest.mark.parametrize("prec", [FP32, SPLIT])
 @pytest.mark.parametrize("N", [16, 32])
 def test_parity_filter_small_and_empty(dctf, N, prec):
-    """B = 0 writes nothing; B = 1, 15, 17 (one partial tile or a tile and a
-    block): only the first B blocks are written."""
+    """B = 0 writes nothing; B = 1, 15, 16, 17, 32, 33 (a partial tile, whole
+    tiles, whole tiles and a block): only the first B blocks are written."""
     W = MASKS["gauss7"]
     op = dctf.dctf_build_operator(W, N, R)
     X = natural_coeffs(40, 9, N)
-    for B in (0, 1, 15, 17):
+    for B in (0, 1, 15, 16, 17, 32, 33):
         Y = torch.full((40 * N * N,), 7.0, device="cuda")
         dctf.dctf_filter_blocks_parity(op, prec, X[:B * N * N], Y[:B * N * N])
         torch.cuda.synchronize()
